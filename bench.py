@@ -1,0 +1,166 @@
+"""Benchmark: 4K RGB homogeneous diffusion inpainting by multilevel ORAS on one
+MI355X.
+
+One step = one full solve (all levels, every kernel of the path, the float64
+stop tests and the final residual certificate) of a 3840 x 2160 x 3 float32
+frame with a 4 % i.i.d. Bernoulli mask shared by the channels, 64 x 64
+blocks with overlap 4, four levels (coarsest 1/8). Inputs are synthetic
+(paper_2110_03946_amd.synth) and already resident in HBM when the timed
+region starts.
+
+Prints one JSON line. Besides the driver's fields it carries
+  roofline      the finest-level ORAS sweep (the dominant kernel): its
+                average duration from HIP events bracketing every such
+                launch on the solver's stream during the timed region, the
+                algorithmic float32 work per launch, and the peak it is
+                held against;
+  cpu_baseline  the float64 CPU oracle on the same frame (all 3 channels);
+  max_err_grey  max |u - u_oracle| over the frame on the 0-255 scale;
+  p50_ms/p99_ms latency of the timed solves.
+
+Usage: python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+H, W, C = 2160, 3840, 3
+DENSITY = 0.04
+METRIC = "4K RGB frames/s at ≤0.5 grey-level err vs FP64; HBM GB/s frac; p99 ms"
+
+# MI355X (gfx950) figures used for the roofline.
+N_CU = 256
+CLOCK_HZ = 2.4e9
+HBM_PEAK_GBS = 8000.0
+# float32 FMA on the vector ALU without packed instructions:
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+VALU_F32_PEAK_TFLOPS = N_CU * 4 * 16 * 2 * CLOCK_HZ / 1e12
+# algorithmic float32 flops per block pixel: residual (4 differences + 3
+# sums) and, per CG step, the 5-point matvec (3 sums + multiply-subtract),
+# two dot products (2 + 2) and three axpys (2 + 2 + 2)
+FLOPS_RESIDUAL = 7
+FLOPS_PER_CG_STEP = 15
+
+
+def solver_params() -> dict:
+    """Solver parameters of the benchmark workload (64 x 64 blocks, overlap
+    4, coarsest level 1/8); the stop tolerance keeps the max error below
+    0.5 grey levels on this workload class."""
+    return dict(block=64, overlap=4, levels=4, local_iters=16, robin_alpha=0.25,
+                coarse_sweeps=2, coarsest_sweeps=3, rel_tol=5e-4, min_sweeps=2,
+                max_sweeps=30, check_every=1, final_residual=1)
+
+
+def sweep_work(p: dict):
+    """Algorithmic flops and bytes of one finest-level sweep launch."""
+    from paper_2110_03946_amd import ddi
+    nby = ddi.block_count(H, p["block"], p["overlap"])
+    nbx = ddi.block_count(W, p["block"], p["overlap"])
+    bpx = nby * nbx * C * min(p["block"], H) * min(p["block"], W)  # block pixels
+    flops = bpx * (FLOPS_RESIDUAL + FLOPS_PER_CG_STEP * p["local_iters"])
+    # u with a one-pixel halo and the mask per block, owned u written once
+    halo = (min(p["block"], H) + 2) * (min(p["block"], W) + 2)
+    bytes_ = nby * nbx * C * (halo * 4 + min(p["block"], H) * min(p["block"], W)) + C * H * W * 8
+    return flops, bytes_, bpx
+
+
+def cpu_baseline(f, c, u_gpu):
+    import oracle
+    t0 = time.perf_counter()
+    ex, info = oracle.solve_exact(f.astype(np.float64), c, return_info=True)
+    t = time.perf_counter() - t0
+    err = float(np.abs(u_gpu.astype(np.float64) - ex).max())
+    return {"value": 1.0 / t, "unit": "frames/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": "the full 3840x2160x3 frame: float64 CG on the reduced system to "
+                      f"relative residual 1e-12 per channel ({[i['iters'] for i in info]} "
+                      f"iterations), {t:.1f} s"}, err
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this solver has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2110_03946_amd import build, ddi, synth
+    if not os.path.exists(build.LIB):
+        build.build()
+    if not torch.cuda.is_available():
+        print("no GPU", file=sys.stderr)
+        sys.exit(1)
+
+    f_np, c_np = synth.make_workload(H, W, C, DENSITY, "bernoulli", workload=1)
+    f = torch.from_numpy(f_np).cuda()
+    c = torch.from_numpy(c_np).cuda()
+    u = torch.empty_like(f)
+    prm = solver_params()
+    plan = ddi.Plan(H, W, C, timing=1, **prm)
+
+    for _ in range(args.warmup):
+        plan.solve(f, c, u)
+    torch.cuda.synchronize()
+    lat, sweep_ms, nsweeps, sweeps_per_solve, rels = [], 0.0, 0, [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        _, st = plan.solve(f, c, u)
+        lat.append((time.perf_counter() - ts) * 1e3)
+        sweep_ms += st["sweep_ms"]
+        nsweeps += st["sweeps"]
+        sweeps_per_solve.append(st["sweeps"])
+        rels.append(st["rel_residual"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fps = args.steps / elapsed
+
+    flops, bytes_, bpx = sweep_work(prm)
+    avg_sweep_s = sweep_ms / max(nsweeps, 1) / 1e3
+    tflops = flops / avg_sweep_s / 1e12
+    roofline = {"bound": "alu", "achieved": round(tflops, 3),
+                "peak": round(VALU_F32_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                "frac": round(tflops / VALU_F32_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "k_sweep<64> (finest-level ORAS sweep)",
+                "avg_launch_us": round(avg_sweep_s * 1e6, 2),
+                "hbm_gbs": round(bytes_ / avg_sweep_s / 1e9, 1)}
+
+    u_np = u.cpu().numpy()
+    out = {"metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "4K RGB 3840x2160x3 f32, 4% Bernoulli mask shared by the "
+                                  "channels, multilevel ORAS (64x64 blocks, overlap 4, "
+                                  "4 levels: coarsest 1/8), CG local solves",
+                      **prm},
+           "p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "sweeps_per_solve": sorted(set(sweeps_per_solve)),
+           "rel_residual_max": max(rels),
+           "roofline": roofline}
+    if not args.no_cpu:
+        cb, err = cpu_baseline(f_np, c_np, u_np)
+        out["cpu_baseline"] = cb
+        out["max_err_grey"] = round(err, 4)
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

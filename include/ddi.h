@@ -1,0 +1,220 @@
+/*
+ * ddi.h -- C ABI of the MI355X (gfx950) multilevel ORAS solver for
+ * homogeneous diffusion inpainting.
+ *
+ * Method: Kaemper & Weickert, "Domain decomposition algorithms for real-time
+ * homogeneous diffusion inpainting in 4K" (arXiv 2110.03946).
+ *   - The problem (Sec. 2, eqs. 5-6): per colour channel solve A u = b with
+ *     A = C - (I - C) L and b = C f, where L is the 5-point Laplacian with
+ *     reflecting image boundaries and C the 0/1 diagonal of the mask. Known
+ *     pixels keep their value; unknown pixels satisfy the discrete Laplace
+ *     equation.
+ *   - The solver (Sec. 3 eqs. 7-10, Sec. 4): optimised restricted additive
+ *     Schwarz over overlapping square blocks, each local problem solved by a
+ *     few conjugate-gradient steps, with a Robin interface condition, a
+ *     Boolean partition of unity, and a coarse-to-fine start from dyadically
+ *     subsampled masks and values.
+ *
+ * Conventions for every entry point:
+ *   - Images are planar, dense, row-major float32: channel k, row y, column x
+ *     sits at index (k * height + y) * width + x. The mask is one dense
+ *     height x width uint8 plane (1 = known pixel, 0 = to be inpainted)
+ *     shared by all channels. Grey values are expected in [0, 255] but any
+ *     finite values work.
+ *   - Pointers named f, c, u, r, ... are DEVICE pointers (HIP global memory,
+ *     e.g. the data_ptr() of a torch tensor on a ROCm device). They remain
+ *     owned by the caller; the library never frees them. Input and output
+ *     buffers must not overlap.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued on it; calls that return results on the host
+ *     synchronise that stream.
+ *   - Every call returns DDI_OK (0) or a negative DDI_E* code; ddi_strerror
+ *     turns it into text. On DDI_EHIP, ddi_last_hip_error gives the HIP
+ *     error code of the failing runtime call.
+ *   - Nothing here is thread-safe for one plan; use one plan per stream.
+ */
+#ifndef DDI_H
+#define DDI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define DDI_OK          0
+#define DDI_EINVAL     (-1)  /* bad size, parameter or pointer; mask byte > 1 */
+#define DDI_ESINGULAR  (-2)  /* no known pixel: A is singular (Sec. 2 needs K nonempty) */
+#define DDI_ENOMEM     (-3)  /* device allocation failed */
+#define DDI_ENOCONV    (-4)  /* max_sweeps reached before rel_tol */
+#define DDI_EHIP       (-5)  /* a HIP runtime call failed */
+#define DDI_ENODEV     (-6)  /* no usable gfx950 device */
+
+/* Largest block edge (pixels) the on-chip local solver supports. */
+#define DDI_MAX_BLOCK 64
+
+/*
+ * Solver parameters. Fill with ddi_default_params, then override.
+ *   block          S: edge of a square block, overlap included (Sec. 4),
+ *                  2 <= S <= DDI_MAX_BLOCK. Blocks are cut to the image
+ *                  when the image is smaller.
+ *   overlap        o: pixels shared by neighbouring blocks, 0 <= o < S.
+ *                  Block k starts at min(k (S - o), n - S).
+ *   levels         resolution levels of the coarse-to-fine scheme (Sec. 4),
+ *                  >= 1; level l has size ceil(n / 2^l).
+ *   local_iters    k: CG steps per local solve (Sec. 4), >= 1.
+ *   robin_alpha    weight of an interface neighbour in the local diagonal
+ *                  (ORAS, Sec. 3): 1 = RAS (homogeneous Dirichlet at the
+ *                  block interface), towards 0 = Neumann. 0 < alpha <= 1.
+ *   coarse_sweeps  ORAS sweeps on each level between the coarsest and the
+ *                  finest, >= 0.
+ *   coarsest_sweeps ORAS sweeps on the coarsest level, >= 0.
+ *   rel_tol        stop on the finest level once ||b - A u||_2 <= rel_tol
+ *                  ||b||_2 holds in every channel (float64 norms), >= 0.
+ *   min_sweeps     finest-level sweeps before the first stop test, >= 0.
+ *   max_sweeps     cap on finest-level sweeps, >= min_sweeps.
+ *   check_every    sweeps between stop tests, >= 1.
+ *   final_residual 1: recompute ||b - A u|| of the returned u (float64) for
+ *                  the stats; 0: report the last stop-test residual.
+ *   timing         1: bracket every finest-level sweep with HIP events and
+ *                  report their summed device time in the stats.
+ */
+typedef struct ddi_params {
+    int block;
+    int overlap;
+    int levels;
+    int local_iters;
+    float robin_alpha;
+    int coarse_sweeps;
+    int coarsest_sweeps;
+    double rel_tol;
+    int min_sweeps;
+    int max_sweeps;
+    int check_every;
+    int final_residual;
+    int timing;
+} ddi_params;
+
+/*
+ * Result of a solve.
+ *   sweeps        ORAS sweeps run on the finest level.
+ *   converged     1 if rel_tol was met.
+ *   rel_residual  max over channels of ||b - A u||_2 / ||b||_2 (float64)
+ *                 for the returned u (final_residual = 1), or for the
+ *                 iterate of the last stop test (final_residual = 0).
+ *   ms            device time of the solve from HIP events, milliseconds.
+ *   sweep_ms      with timing = 1: summed device time of the finest-level
+ *                 sweeps (the solver's dominant kernel), milliseconds.
+ */
+typedef struct ddi_stats {
+    int sweeps;
+    int converged;
+    double rel_residual;
+    double ms;
+    double sweep_ms;
+} ddi_stats;
+
+typedef struct ddi_plan ddi_plan;
+
+/* Fill *p with the defaults: S = 64, o = 4, 4 levels, k = 16, alpha = 0.25,
+ * 2 sweeps per coarser level, 3 on the coarsest, rel_tol = 1e-4,
+ * min_sweeps = 2, max_sweeps = 50, check_every = 1, final_residual = 1,
+ * timing = 0. */
+int ddi_default_params(ddi_params* p);
+
+/* Check *p for one image size without touching the GPU. */
+int ddi_check_params(int height, int width, int channels, const ddi_params* p);
+
+/*
+ * Create a plan for height x width images with `channels` channels sharing
+ * one mask. Allocates every device buffer the solve needs (level pyramid,
+ * ping-pong iterate, reduction partials) once; ddi_solve allocates nothing.
+ * p == NULL uses the defaults. The plan keeps `stream`.
+ * Errors: DDI_EINVAL (sizes or params), DDI_ENOMEM, DDI_ENODEV, DDI_EHIP.
+ */
+int ddi_create(ddi_plan** out, int height, int width, int channels,
+               const ddi_params* p, void* stream);
+
+/*
+ * Inpaint: multilevel ORAS (Sec. 3-4) for all channels of f with mask c,
+ * writing the result to u. f: channels x height x width float32; c: height x
+ * width uint8; u: like f, fully written, with u = f bit for bit on the mask.
+ * Synchronises the plan's stream (stop tests read float64 norms).
+ * Errors: DDI_EINVAL (null pointer, mask byte > 1), DDI_ESINGULAR (empty
+ * mask), DDI_ENOCONV (u then holds the last iterate and *st is filled),
+ * DDI_EHIP. st may be NULL.
+ */
+int ddi_solve(ddi_plan* plan, const float* f, const uint8_t* c, float* u,
+              ddi_stats* st);
+
+/* Release the plan and its device buffers. NULL is a no-op. */
+int ddi_destroy(ddi_plan* plan);
+
+/* Text for an error code (static storage). */
+const char* ddi_strerror(int code);
+
+/* HIP error code of the last DDI_EHIP in this process (0 if none). */
+int ddi_last_hip_error(void);
+
+/* Geometry of the block grid the solver uses on an n-pixel axis: number of
+ * blocks, and origin / owned range [lo, hi) of block k (k < count). Host
+ * only; lets callers and tests check the partition of unity (eq. 10). */
+int ddi_block_count(int n, int block, int overlap);
+int ddi_block_range(int n, int block, int overlap, int k, int* origin,
+                    int* own_lo, int* own_hi);
+
+/* ---- the steps of the path, exposed one by one -------------------------
+ * Each enqueues on `stream`; those returning host values synchronise it.
+ * They allocate device scratch per call (unlike ddi_solve).
+ */
+
+/*
+ * Residual r = b - A u of eq. 7 (the masked 5-point stencil), for all
+ * channels: r_p = f_p - u_p on the mask, sum over in-image 4-neighbours q
+ * of (u_q - u_p) elsewhere. r may be NULL (norms only). rsq (host,
+ * `channels` doubles, may be NULL) receives sum_p r_p^2 per channel,
+ * accumulated in float64.
+ */
+int ddi_residual(const float* f, const uint8_t* c, const float* u, int height,
+                 int width, int channels, float* r, double* rsq, void* stream);
+
+/*
+ * One dyadic subsampling step (Sec. 4): coarse pixel (I, J) covers the
+ * in-image fine pixels (2I + a, 2J + b), a, b in {0, 1}; it is known iff one
+ * of them is, and its value is the float64 mean of the known fine values,
+ * rounded to float32 (0 where unknown). fc: channels x ceil(h/2) x ceil(w/2)
+ * float32, cc: ceil(h/2) x ceil(w/2) uint8.
+ */
+int ddi_coarsen(const float* f, const uint8_t* c, int height, int width,
+                int channels, float* fc, uint8_t* cc, void* stream);
+
+/*
+ * Coarse-to-fine initialisation (Sec. 4): u = f on the mask, elsewhere the
+ * bilinear interpolation of the coarse grid uc (channels x hc x wc) at the
+ * fine pixel centre (y/2 - 1/4, x/2 - 1/4), clamped to the coarse grid.
+ * Requires hc = ceil(height/2), wc = ceil(width/2).
+ */
+int ddi_prolong(const float* uc, int hc, int wc, const float* f,
+                const uint8_t* c, int height, int width, int channels,
+                float* u, void* stream);
+
+/*
+ * One ORAS iteration (Sec. 3, eqs. 7-9) on all channels, u_in -> u_out:
+ * the residual of u_in restricted to each block, k CG steps on the block's
+ * local matrix with Robin weight alpha at the interface, and the sum of the
+ * restricted corrections over the Boolean partition of unity. u_in must
+ * equal f on the mask (then u_out does too). rsq (host, may be NULL)
+ * receives sum_p r_p^2 of u_in per channel in float64.
+ */
+int ddi_oras_sweep(const float* u_in, const uint8_t* c, float* u_out,
+                   int height, int width, int channels, int block,
+                   int overlap, float robin_alpha, int local_iters,
+                   double* rsq, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDI_H */

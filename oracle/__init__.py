@@ -22,7 +22,7 @@ Contents
   coarsen          dyadic mask/value subsampling (Sec. 4).
   prolong          bilinear coarse-to-fine interpolation (a reading: the
                    paper does not say how the coarse solution initialises the
-                   finer level).
+                   finer level); fine_start re-imposes u = f on the mask.
   block_origins, owner_bounds
                    overlapping block grid and the Boolean partition of unity
                    (Sec. 3 eq. 10, Sec. 4 block size / overlap).
@@ -290,6 +290,15 @@ def prolong(uc, h: int, w: int) -> np.ndarray:
     return out
 
 
+def fine_start(uc, f, c) -> np.ndarray:
+    """Initial guess of a finer level (Sec. 4): the coarse solution
+    interpolated by prolong(), with u = f re-imposed on the mask."""
+    f = np.asarray(f, dtype=np.float64)
+    c = np.asarray(c)
+    h, w = c.shape
+    return np.where(c == 1, f, prolong(uc, h, w))
+
+
 # ---------------------------------------------------------------------------
 # Domain decomposition (Sec. 3, Sec. 4)
 # ---------------------------------------------------------------------------
@@ -461,7 +470,7 @@ def ml_oras(f, c, levels: int, size: int, overlap: int, alpha: float,
         if u is None:
             u = np.where(cl == 1, fl, 0.0)
         else:
-            u = np.where(cl == 1, fl, prolong(u, *cl.shape))
+            u = fine_start(u, fl, cl)
         for _ in range(sweeps[lev]):
             u, _ = oras_step(u, fl, cl, size, overlap, alpha, k)
     return u

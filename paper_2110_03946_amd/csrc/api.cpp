@@ -1,0 +1,494 @@
+// Solver driver and C ABI (include/ddi.h) of the multilevel ORAS inpainting
+// library. Host code only: it owns the device buffers of a plan and
+// enqueues the kernels of kernels.hip on the plan's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ddi.h"
+#include "internal.h"
+
+using namespace ddi;
+
+namespace {
+
+int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return DDI_EHIP;
+}
+
+#define DDI_HIP(call)                                  \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return hip_fail(e_);     \
+    } while (0)
+
+BlockGrid make_grid(int h, int w, int block, int overlap) {
+    BlockGrid g;
+    g.h = h;
+    g.w = w;
+    g.bh = std::min(block, h);
+    g.bw = std::min(block, w);
+    g.nby = block_count(h, block, overlap);
+    g.nbx = block_count(w, block, overlap);
+    g.sy = g.nby > 1 ? block - overlap : std::max(g.bh, 1);
+    g.sx = g.nbx > 1 ? block - overlap : std::max(g.bw, 1);
+    return g;
+}
+
+SweepArgs make_sweep(int h, int w, int channels, int block, int overlap, float alpha, int k) {
+    SweepArgs a;
+    a.g = make_grid(h, w, block, overlap);
+    a.channels = channels;
+    a.cpitch = (int64_t)h * w;
+    a.alpha = alpha;
+    a.k = k;
+    return a;
+}
+
+int check_device() {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return DDI_ENODEV;
+    int dev = 0;
+    DDI_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    DDI_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return DDI_ENODEV;
+    return DDI_OK;
+}
+
+int check_dims(int h, int w, int channels) {
+    if (h < 1 || w < 1 || channels < 1 || channels > 4) return DDI_EINVAL;
+    if ((int64_t)h * w > (int64_t)1 << 30) return DDI_EINVAL;
+    return DDI_OK;
+}
+
+struct Level {
+    int h = 0, w = 0;
+    const float* f = nullptr;
+    const uint8_t* c = nullptr;
+    float* fown = nullptr;
+    uint8_t* cown = nullptr;
+    float* u[2] = {nullptr, nullptr};
+    bool own_u0 = false;
+    SweepArgs sw;
+};
+
+// Device scratch a step call needs, freed on scope exit.
+struct Scratch {
+    void* p = nullptr;
+    ~Scratch() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+struct ddi_plan {
+    int h = 0, w = 0, C = 0;
+    ddi_params p;
+    hipStream_t s = nullptr;
+    std::vector<Level> lv;
+    double* part = nullptr;
+    size_t part_n = 0;
+    double* red = nullptr;   // [C + 2] stats, then [C] norms
+    double* host = nullptr;  // pinned mirror of red
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<hipEvent_t> sweep_ev;  // 2 per finest-level sweep (timing)
+};
+
+extern "C" {
+
+int ddi_default_params(ddi_params* p) {
+    if (!p) return DDI_EINVAL;
+    p->block = 64;
+    p->overlap = 4;
+    p->levels = 4;
+    p->local_iters = 16;
+    p->robin_alpha = 0.25f;
+    p->coarse_sweeps = 2;
+    p->coarsest_sweeps = 3;
+    p->rel_tol = 1e-4;
+    p->min_sweeps = 2;
+    p->max_sweeps = 50;
+    p->check_every = 1;
+    p->final_residual = 1;
+    p->timing = 0;
+    return DDI_OK;
+}
+
+int ddi_check_params(int height, int width, int channels, const ddi_params* p) {
+    int e = check_dims(height, width, channels);
+    if (e) return e;
+    if (!p) return DDI_EINVAL;
+    if (p->block < 2 || p->block > DDI_MAX_BLOCK) return DDI_EINVAL;
+    if (p->overlap < 0 || p->overlap >= p->block) return DDI_EINVAL;
+    if (p->levels < 1 || p->levels > 16) return DDI_EINVAL;
+    if (p->local_iters < 1) return DDI_EINVAL;
+    if (!(p->robin_alpha > 0.f && p->robin_alpha <= 1.f)) return DDI_EINVAL;
+    if (p->coarse_sweeps < 0 || p->coarsest_sweeps < 0) return DDI_EINVAL;
+    if (!(p->rel_tol >= 0.0)) return DDI_EINVAL;
+    if (p->min_sweeps < 0 || p->max_sweeps < p->min_sweeps) return DDI_EINVAL;
+    if (p->check_every < 1) return DDI_EINVAL;
+    return DDI_OK;
+}
+
+int ddi_destroy(ddi_plan* plan) {
+    if (!plan) return DDI_OK;
+    for (Level& l : plan->lv) {
+        if (l.fown) (void)hipFree(l.fown);
+        if (l.cown) (void)hipFree(l.cown);
+        for (int i = 0; i < 2; ++i)
+            if (l.u[i] && (i == 1 || l.own_u0)) (void)hipFree(l.u[i]);
+    }
+    if (plan->part) (void)hipFree(plan->part);
+    if (plan->red) (void)hipFree(plan->red);
+    if (plan->host) (void)hipHostFree(plan->host);
+    if (plan->e0) (void)hipEventDestroy(plan->e0);
+    if (plan->e1) (void)hipEventDestroy(plan->e1);
+    for (hipEvent_t e : plan->sweep_ev) (void)hipEventDestroy(e);
+    delete plan;
+    return DDI_OK;
+}
+
+int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_params* p,
+               void* stream) {
+    if (!out) return DDI_EINVAL;
+    *out = nullptr;
+    ddi_params prm;
+    if (p)
+        prm = *p;
+    else
+        ddi_default_params(&prm);
+    int e = ddi_check_params(height, width, channels, &prm);
+    if (e) return e;
+    e = check_device();
+    if (e) return e;
+
+    ddi_plan* P = new (std::nothrow) ddi_plan;
+    if (!P) return DDI_ENOMEM;
+    P->h = height;
+    P->w = width;
+    P->C = channels;
+    P->p = prm;
+    P->s = (hipStream_t)stream;
+
+    // levels: stop halving once the level is a single pixel
+    int L = 1;
+    while (L < prm.levels) {
+        int hl = height, wl = width;
+        for (int i = 0; i < L; ++i) {
+            hl = (hl + 1) / 2;
+            wl = (wl + 1) / 2;
+        }
+        if (hl == 1 && wl == 1) break;
+        ++L;
+    }
+    P->lv.resize(L);
+    size_t part_n = 0;
+    int hl = height, wl = width;
+    for (int l = 0; l < L; ++l) {
+        Level& lev = P->lv[l];
+        lev.h = hl;
+        lev.w = wl;
+        lev.sw = make_sweep(hl, wl, channels, prm.block, prm.overlap, prm.robin_alpha,
+                            prm.local_iters);
+        const size_t n = (size_t)hl * wl;
+        const size_t nf = n * channels;
+        auto fail = [&](hipError_t err) {
+            ddi_destroy(P);
+            if (err == hipErrorOutOfMemory) return DDI_ENOMEM;
+            return hip_fail(err);
+        };
+        hipError_t err;
+        if (l > 0) {
+            if ((err = hipMalloc(&lev.fown, nf * sizeof(float))) != hipSuccess) return fail(err);
+            if ((err = hipMalloc(&lev.cown, n)) != hipSuccess) return fail(err);
+            if ((err = hipMalloc(&lev.u[0], nf * sizeof(float))) != hipSuccess) return fail(err);
+            lev.own_u0 = true;
+            lev.f = lev.fown;
+            lev.c = lev.cown;
+        }
+        if ((err = hipMalloc(&lev.u[1], nf * sizeof(float))) != hipSuccess) return fail(err);
+        part_n = std::max(part_n, (size_t)sweep_partials(lev.sw) * channels);
+        const size_t res_wg = (size_t)((wl + 63) / 64) * ((hl + 31) / 32);
+        part_n = std::max(part_n, res_wg * channels);
+        hl = (hl + 1) / 2;
+        wl = (wl + 1) / 2;
+    }
+    // statistics partials: coarsen grid (level 0 -> 1) or the stats grid
+    {
+        const size_t hc = (height + 1) / 2, wc = (width + 1) / 2;
+        const size_t nwg = std::max<size_t>((hc * wc + 255) / 256, 1024);
+        part_n = std::max(part_n, nwg * (channels + 2));
+    }
+    P->part_n = part_n;
+    hipError_t err;
+    if ((err = hipMalloc(&P->part, part_n * sizeof(double))) != hipSuccess) {
+        ddi_destroy(P);
+        return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
+    }
+    const size_t nred = 2 * channels + 2;
+    if ((err = hipMalloc(&P->red, nred * sizeof(double))) != hipSuccess ||
+        (err = hipHostMalloc(&P->host, nred * sizeof(double), hipHostMallocDefault)) !=
+            hipSuccess ||
+        (err = hipEventCreate(&P->e0)) != hipSuccess ||
+        (err = hipEventCreate(&P->e1)) != hipSuccess) {
+        ddi_destroy(P);
+        return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
+    }
+    if (prm.timing) {
+        P->sweep_ev.assign(2 * (size_t)prm.max_sweeps, nullptr);
+        for (hipEvent_t& ev : P->sweep_ev) {
+            if ((err = hipEventCreate(&ev)) != hipSuccess) {
+                ddi_destroy(P);
+                return hip_fail(err);
+            }
+        }
+    }
+    *out = P;
+    return DDI_OK;
+}
+
+// Reduce `nrows` x C partials to per-channel sums in red[off..off+C), copy the
+// first `ncopy` doubles of red to the pinned host mirror and wait.
+static int reduce_and_read(ddi_plan* P, int nrows, int off, int ncopy) {
+    DDI_HIP(launch_reduce(P->part, nrows, P->C, P->C, P->red + off, P->s));
+    DDI_HIP(hipMemcpyAsync(P->host, P->red, ncopy * sizeof(double), hipMemcpyDeviceToHost, P->s));
+    DDI_HIP(hipStreamSynchronize(P->s));
+    return DDI_OK;
+}
+
+// max over channels of sqrt(rsq / ||b||^2); the stats occupy host[0..C+2).
+static double rel_from_host(const ddi_plan* P, const double* rsq) {
+    double worst = 0.0;
+    for (int k = 0; k < P->C; ++k) {
+        const double b2 = P->host[k];
+        double rel;
+        if (b2 > 0.0)
+            rel = std::sqrt(rsq[k] / b2);
+        else
+            rel = rsq[k] > 0.0 ? INFINITY : 0.0;
+        worst = std::max(worst, rel);
+    }
+    return worst;
+}
+
+int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats* st) {
+    if (!P || !f || !c || !u) return DDI_EINVAL;
+    const int C = P->C;
+    const int L = (int)P->lv.size();
+    const ddi_params& prm = P->p;
+    Level& L0 = P->lv[0];
+    L0.f = f;
+    L0.c = c;
+    L0.u[0] = u;
+    if (st) std::memset(st, 0, sizeof(*st));
+
+    DDI_HIP(hipEventRecord(P->e0, P->s));
+
+    // ---- level pyramid (Sec. 4) and input statistics ----
+    int nwg = 0;
+    if (L > 1)
+        DDI_HIP(launch_coarsen(f, c, P->h, P->w, C, P->lv[1].fown, P->lv[1].cown, P->part, &nwg,
+                               P->s));
+    else
+        DDI_HIP(launch_stats(f, c, P->h, P->w, C, P->part, &nwg, P->s));
+    DDI_HIP(launch_reduce(P->part, nwg, C + 2, C + 2, P->red, P->s));
+    for (int l = 1; l + 1 < L; ++l) {
+        Level& a = P->lv[l];
+        Level& b = P->lv[l + 1];
+        DDI_HIP(launch_coarsen(a.f, a.c, a.h, a.w, C, b.fown, b.cown, nullptr, nullptr, P->s));
+    }
+
+    // ---- coarsest level, then coarse-to-fine ----
+    const int top = L - 1;
+    DDI_HIP(launch_init(P->lv[top].f, P->lv[top].c, P->lv[top].h, P->lv[top].w, C,
+                        P->lv[top].u[0], P->s));
+    int cur = 0;
+    for (int l = top; l >= 1; --l) {
+        Level& lev = P->lv[l];
+        const int n = (l == top) ? prm.coarsest_sweeps : prm.coarse_sweeps;
+        for (int i = 0; i < n; ++i) {
+            DDI_HIP(launch_sweep(lev.u[cur], lev.c, lev.u[1 - cur], P->part, lev.sw, P->s));
+            cur ^= 1;
+        }
+        Level& fine = P->lv[l - 1];
+        DDI_HIP(launch_prolong(lev.u[cur], lev.h, lev.w, fine.f, fine.c, fine.h, fine.w, C,
+                               fine.u[0], P->s));
+        cur = 0;
+    }
+
+    // ---- finest level with the stop test ----
+    bool validated = false, converged = false;
+    double rel = INFINITY;
+    int sweeps = 0;
+    auto validate = [&]() -> int {
+        validated = true;
+        if (P->host[C + 1] > 0.0) return DDI_EINVAL;
+        if (P->host[C] <= 0.0) return DDI_ESINGULAR;
+        return DDI_OK;
+    };
+    const int nb = sweep_partials(L0.sw);
+    const bool timing = !P->sweep_ev.empty();
+    while (sweeps < prm.max_sweeps) {
+        if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * sweeps], P->s));
+        DDI_HIP(launch_sweep(L0.u[cur], L0.c, L0.u[1 - cur], P->part, L0.sw, P->s));
+        if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * sweeps + 1], P->s));
+        cur ^= 1;
+        ++sweeps;
+        if (sweeps >= prm.min_sweeps && (sweeps - prm.min_sweeps) % prm.check_every == 0) {
+            int e = reduce_and_read(P, nb, C + 2, 2 * C + 2);
+            if (e) return e;
+            if (!validated && (e = validate())) return e;
+            rel = rel_from_host(P, P->host + C + 2);  // residual of the sweep's input
+            if (rel <= prm.rel_tol) {
+                converged = true;
+                break;
+            }
+        }
+    }
+
+    // ---- final residual of the returned iterate; move it into u ----
+    if (prm.final_residual || cur == 1 || !validated) {
+        int rwg = 0;
+        DDI_HIP(launch_residual(f, c, L0.u[cur], P->h, P->w, C, nullptr,
+                                cur == 1 ? u : nullptr, P->part, &rwg, P->s));
+        int e = reduce_and_read(P, rwg, C + 2, 2 * C + 2);
+        if (e) return e;
+        if (!validated && (e = validate())) return e;
+        if (prm.final_residual) {
+            rel = rel_from_host(P, P->host + C + 2);
+            converged = rel <= prm.rel_tol || converged;
+        }
+    }
+    DDI_HIP(hipEventRecord(P->e1, P->s));
+    DDI_HIP(hipEventSynchronize(P->e1));
+    float ms = 0.f;
+    DDI_HIP(hipEventElapsedTime(&ms, P->e0, P->e1));
+    double sweep_ms = 0.0;
+    for (int i = 0; timing && i < sweeps; ++i) {
+        float t = 0.f;
+        DDI_HIP(hipEventElapsedTime(&t, P->sweep_ev[2 * i], P->sweep_ev[2 * i + 1]));
+        sweep_ms += t;
+    }
+    if (st) {
+        st->sweeps = sweeps;
+        st->converged = converged ? 1 : 0;
+        st->rel_residual = rel;
+        st->ms = ms;
+        st->sweep_ms = sweep_ms;
+    }
+    return converged ? DDI_OK : DDI_ENOCONV;
+}
+
+const char* ddi_strerror(int code) {
+    switch (code) {
+        case DDI_OK: return "ok";
+        case DDI_EINVAL: return "invalid argument";
+        case DDI_ESINGULAR: return "mask has no known pixel (singular system)";
+        case DDI_ENOMEM: return "out of device memory";
+        case DDI_ENOCONV: return "no convergence within max_sweeps";
+        case DDI_EHIP: return "HIP runtime error";
+        case DDI_ENODEV: return "no gfx950 device";
+        default: return "unknown error";
+    }
+}
+
+int ddi_last_hip_error(void) { return g_last_hip; }
+
+int ddi_block_count(int n, int block, int overlap) {
+    if (n < 1 || block < 1 || overlap < 0 || overlap >= block) return DDI_EINVAL;
+    return block_count(n, block, overlap);
+}
+
+int ddi_block_range(int n, int block, int overlap, int k, int* origin, int* own_lo,
+                    int* own_hi) {
+    const int nb = ddi_block_count(n, block, overlap);
+    if (nb < 0 || k < 0 || k >= nb) return DDI_EINVAL;
+    const BlockGrid g = make_grid(n, n, block, overlap);
+    int lo, hi;
+    owner_range(k, nb, g.sx, n, g.bw, &lo, &hi);
+    if (origin) *origin = block_origin(k, g.sx, n, g.bw);
+    if (own_lo) *own_lo = lo;
+    if (own_hi) *own_hi = hi;
+    return DDI_OK;
+}
+
+// ---- steps one by one ----
+
+int ddi_residual(const float* f, const uint8_t* c, const float* u, int height, int width,
+                 int channels, float* r, double* rsq, void* stream) {
+    int e = check_dims(height, width, channels);
+    if (e) return e;
+    if (!f || !c || !u) return DDI_EINVAL;
+    if ((e = check_device())) return e;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nwg = (size_t)((width + 63) / 64) * ((height + 31) / 32);
+    Scratch part, red;
+    DDI_HIP(hipMalloc(&part.p, nwg * channels * sizeof(double)));
+    DDI_HIP(hipMalloc(&red.p, channels * sizeof(double)));
+    int n = 0;
+    DDI_HIP(launch_residual(f, c, u, height, width, channels, r, nullptr, (double*)part.p, &n, s));
+    DDI_HIP(launch_reduce((double*)part.p, n, channels, channels, (double*)red.p, s));
+    if (rsq) {
+        DDI_HIP(hipMemcpyAsync(rsq, red.p, channels * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    DDI_HIP(hipStreamSynchronize(s));
+    return DDI_OK;
+}
+
+int ddi_coarsen(const float* f, const uint8_t* c, int height, int width, int channels,
+                float* fc, uint8_t* cc, void* stream) {
+    int e = check_dims(height, width, channels);
+    if (e) return e;
+    if (!f || !c || !fc || !cc) return DDI_EINVAL;
+    if ((e = check_device())) return e;
+    DDI_HIP(launch_coarsen(f, c, height, width, channels, fc, cc, nullptr, nullptr,
+                           (hipStream_t)stream));
+    return DDI_OK;
+}
+
+int ddi_prolong(const float* uc, int hc, int wc, const float* f, const uint8_t* c, int height,
+                int width, int channels, float* u, void* stream) {
+    int e = check_dims(height, width, channels);
+    if (e) return e;
+    if (!uc || !f || !c || !u) return DDI_EINVAL;
+    if (hc != (height + 1) / 2 || wc != (width + 1) / 2) return DDI_EINVAL;
+    if ((e = check_device())) return e;
+    DDI_HIP(launch_prolong(uc, hc, wc, f, c, height, width, channels, u, (hipStream_t)stream));
+    return DDI_OK;
+}
+
+int ddi_oras_sweep(const float* u_in, const uint8_t* c, float* u_out, int height, int width,
+                   int channels, int block, int overlap, float robin_alpha, int local_iters,
+                   double* rsq, void* stream) {
+    int e = check_dims(height, width, channels);
+    if (e) return e;
+    if (!u_in || !c || !u_out || u_in == u_out) return DDI_EINVAL;
+    if (block < 2 || block > DDI_MAX_BLOCK || overlap < 0 || overlap >= block) return DDI_EINVAL;
+    if (!(robin_alpha > 0.f && robin_alpha <= 1.f) || local_iters < 1) return DDI_EINVAL;
+    if ((e = check_device())) return e;
+    hipStream_t s = (hipStream_t)stream;
+    const SweepArgs a = make_sweep(height, width, channels, block, overlap, robin_alpha,
+                                   local_iters);
+    const int nb = sweep_partials(a);
+    Scratch part, red;
+    DDI_HIP(hipMalloc(&part.p, (size_t)nb * channels * sizeof(double)));
+    DDI_HIP(hipMalloc(&red.p, channels * sizeof(double)));
+    DDI_HIP(launch_sweep(u_in, c, u_out, (double*)part.p, a, s));
+    DDI_HIP(launch_reduce((double*)part.p, nb, channels, channels, (double*)red.p, s));
+    if (rsq) {
+        DDI_HIP(hipMemcpyAsync(rsq, red.p, channels * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    DDI_HIP(hipStreamSynchronize(s));
+    return DDI_OK;
+}
+
+}  // extern "C"

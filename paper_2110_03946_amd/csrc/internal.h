@@ -1,0 +1,108 @@
+// Internal declarations shared by the kernels (kernels.hip) and the solver
+// driver / C ABI (api.cpp). Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ddi {
+
+// Overlapping block grid of one resolution level (Sec. 4: a block spans
+// `size` pixels including the overlap, neighbours share `overlap` pixels,
+// the last block is shifted back to end at the image border).
+struct BlockGrid {
+    int h, w;       // level size in pixels
+    int bh, bw;     // block height / width after clamping to the image
+    int sy, sx;     // strides: bh - overlap_y, bw - overlap_x (>= 1)
+    int nby, nbx;   // number of blocks per axis
+};
+
+// Arguments of one ORAS sweep (Sec. 3, eqs. 7-9) over all channels.
+struct SweepArgs {
+    BlockGrid g;
+    int channels;
+    int64_t cpitch;   // elements between channel planes (= h * w)
+    float alpha;      // Robin interface weight, 1 = RAS
+    int k;            // local CG steps
+};
+
+__host__ __device__ inline int block_origin(int k, int stride, int n, int size) {
+    int o = k * stride;
+    return o < n - size ? o : n - size;
+}
+
+// Pixels [lo, hi) along one axis owned by block k (Boolean partition of
+// unity, eq. 10): the overlap with each neighbour is split in the middle,
+// the lower half (rounded up) going to the lower block.
+__host__ __device__ inline void owner_range(int k, int nb, int stride, int n,
+                                            int size, int* lo, int* hi) {
+    int o = block_origin(k, stride, n, size);
+    if (k == 0) {
+        *lo = 0;
+    } else {
+        int op = block_origin(k - 1, stride, n, size);
+        *lo = o + (op + size - o + 1) / 2;
+    }
+    if (k == nb - 1) {
+        *hi = n;
+    } else {
+        int on = block_origin(k + 1, stride, n, size);
+        *hi = on + (o + size - on + 1) / 2;
+    }
+}
+
+// Number of blocks of length `size` with overlap `ov` covering n pixels.
+__host__ __device__ inline int block_count(int n, int size, int ov) {
+    if (size >= n) return 1;
+    int stride = size - ov;
+    return (n - ov + stride - 1) / stride;
+}
+
+// ---- launchers (kernels.hip); all asynchronous on `s` ----
+
+// Largest block edge the sweep kernel holds on chip (one wave64 per block:
+// lanes are columns, rows live in registers).
+constexpr int kMaxBlock = 64;
+
+hipError_t launch_sweep(const float* uin, const uint8_t* mask, float* uout,
+                        double* partial, const SweepArgs& a, hipStream_t s);
+
+// Coarsening (Sec. 4). When `stats` is non-null it also writes per-workgroup
+// partials [nwg][channels + 2]: sum over known pixels of f^2 per channel,
+// number of known pixels, number of mask bytes > 1. Returns the number of
+// workgroups in *nwg.
+hipError_t launch_coarsen(const float* f, const uint8_t* c, int h, int w,
+                          int channels, float* fc, uint8_t* cc,
+                          double* stats, int* nwg, hipStream_t s);
+
+// Same statistics without coarsening (single-level solves).
+hipError_t launch_stats(const float* f, const uint8_t* c, int h, int w,
+                        int channels, double* stats, int* nwg, hipStream_t s);
+
+// u = c ? f : 0 (start on the coarsest level).
+hipError_t launch_init(const float* f, const uint8_t* c, int h, int w,
+                       int channels, float* u, hipStream_t s);
+
+// u = c ? f : bilinear(uc) (coarse-to-fine initialisation, Sec. 4).
+hipError_t launch_prolong(const float* uc, int hc, int wc, const float* f,
+                          const uint8_t* c, int h, int w, int channels,
+                          float* u, hipStream_t s);
+
+// Residual r = b - A u (eq. 7): per-workgroup partial sums of r^2 per
+// channel into partial[nwg][channels]; optionally writes r and/or copies u
+// into ucopy. Returns the number of workgroups in *nwg.
+hipError_t launch_residual(const float* f, const uint8_t* c, const float* u,
+                           int h, int w, int channels, float* r,
+                           float* ucopy, double* partial, int* nwg,
+                           hipStream_t s);
+
+// out[j] = sum_i partial[i * stride + j] for j < ncols, fixed order.
+hipError_t launch_reduce(const double* partial, int nrows, int stride,
+                         int ncols, double* out, hipStream_t s);
+
+// Partials per channel written by one sweep: one per block.
+inline int sweep_partials(const SweepArgs& a) {
+    return a.g.nby * a.g.nbx;
+}
+
+}  // namespace ddi

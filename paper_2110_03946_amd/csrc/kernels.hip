@@ -1,0 +1,579 @@
+// HIP kernels for gfx950 (CDNA4, wave64) of multilevel ORAS inpainting.
+//
+//   k_sweep     one ORAS iteration (Sec. 3 eqs. 7-9): block residual, k-step
+//               local CG with the Robin interface weight, owned write-back.
+//               One wave64 per (block, channel): lanes are block columns, the
+//               block's rows live in registers, horizontal neighbours come
+//               from DPP lane shifts, CG dot products are wave reductions
+//               (DPP row shifts + readlane). No LDS barriers.
+//   k_coarsen   dyadic subsampling of mask and known values (Sec. 4).
+//   k_stats     ||C f||^2 per channel, known-pixel count, bad mask bytes.
+//   k_init      u = c ? f : 0 on the coarsest level.
+//   k_prolong   u = c ? f : bilinear(coarse u) (Sec. 4 coarse-to-fine start).
+//   k_residual  r = b - A u (eq. 7), float64 partial norms; column-walking
+//               waves keep the vertical stencil in registers.
+//   k_reduce    fixed-order float64 sums of per-workgroup partials.
+//
+// All reductions run in a fixed order, so results are bitwise reproducible.
+#include "internal.h"
+
+namespace ddi {
+namespace {
+
+// ---------------------------------------------------------------------------
+// wave64 helpers
+// ---------------------------------------------------------------------------
+
+// GCN DPP controls: wave_shr:1 moves data one lane up (lane i receives lane
+// i - 1), wave_shl:1 one lane down; row_shr:n shifts inside 16-lane rows.
+// With bound_ctrl set, lanes whose source does not exist receive 0.
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+
+// Value held by lane i - 1 (0 in lane 0).
+__device__ __forceinline__ float from_left(float x) { return dpp<kDppWaveShr1>(x); }
+// Value held by lane i + 1 (0 in lane 63).
+__device__ __forceinline__ float from_right(float x) { return dpp<kDppWaveShl1>(x); }
+
+__device__ __forceinline__ float readlane(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// Sum over the 64 lanes, returned uniformly (fixed order).
+__device__ __forceinline__ float wave_sum(float x) {
+    x += dpp<0x111>(x);  // row_shr:1
+    x += dpp<0x112>(x);  // row_shr:2
+    x += dpp<0x114>(x);  // row_shr:4
+    x += dpp<0x118>(x);  // row_shr:8 -> lane 15 of each row holds the row sum
+    return (readlane(x, 15) + readlane(x, 31)) + (readlane(x, 47) + readlane(x, 63));
+}
+
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Mask of one block column, built from the bits of the unknown pixels.
+// Float storage (1 = unknown) for short columns; the bits themselves for
+// 64-row columns, where registers are scarce.
+template <int RPW, bool BITS>
+struct ColMask;
+
+template <int RPW>
+struct ColMask<RPW, false> {
+    float m[RPW];
+    __device__ __forceinline__ void load(uint32_t lo, uint32_t hi) {
+#pragma unroll
+        for (int y = 0; y < RPW; ++y)
+            m[y] = (((y < 32 ? lo : hi) >> (y & 31)) & 1u) ? 1.f : 0.f;
+    }
+    __device__ __forceinline__ float apply(int y, float q) const { return q * m[y]; }
+};
+
+template <int RPW>
+struct ColMask<RPW, true> {
+    uint32_t b[2];
+    __device__ __forceinline__ void load(uint32_t lo, uint32_t hi) { b[0] = lo; b[1] = hi; }
+    __device__ __forceinline__ float apply(int y, float q) const {
+        // all-ones where the pixel is unknown, zero elsewhere
+        const int sel = (int)(b[y >> 5] << (31 - (y & 31))) >> 31;
+        return __int_as_float(__float_as_int(q) & sel);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// One ORAS sweep
+// ---------------------------------------------------------------------------
+//
+// Block b = (by, bx) of channel ch covers rows [y0, y0 + bh) and columns
+// [x0, x0 + bw); lane l holds column x0 + l (lanes >= bw idle). Row y of the
+// block is register index y (RPW >= bh; RAGGED when bh < RPW).
+//
+// Local matrix (one row per unknown pixel p of the block): diagonal = number
+// of in-image neighbours inside the block + alpha * number of in-image
+// neighbours outside it; -1 towards every unknown neighbour inside the
+// block. Known pixels are homogeneous Dirichlet (their correction is 0).
+// This is R_i A R_i^T of eq. 7 for alpha = 1 (RAS) and the Robin-modified
+// ORAS matrix otherwise (Sec. 3). The diagonal depends only on the position:
+// dmid for inner rows (per lane), dtop / dbot for the first / last row.
+//
+// LDS: the block's u with a one-pixel halo is staged first (the halo copies
+// the nearest image pixel where the image ends, which is exactly the
+// reflecting boundary of eq. 3); the same memory then parks the CG vector
+// q = A p between the matvec and the update when QLDS is set (64-row blocks
+// do not fit v, r, p and q in 256 VGPRs).
+constexpr int kTileW = kMaxBlock + 2;
+
+template <int RPW, bool RAGGED, bool QLDS, bool MBITS>
+__global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
+                                              const uint8_t* __restrict__ mask,
+                                              float* __restrict__ uout,
+                                              double* __restrict__ partial,
+                                              SweepArgs a) {
+    __shared__ __attribute__((aligned(16))) float lds[(RPW + 2) * kTileW];
+
+    const int lane = threadIdx.x;
+    const BlockGrid g = a.g;
+    const int nblk = g.nby * g.nbx;
+    const int ch = blockIdx.x / nblk;
+    const int b = blockIdx.x - ch * nblk;
+    const int by = b / g.nbx;
+    const int bx = b - by * g.nbx;
+    const int y0 = block_origin(by, g.sy, g.h, g.bh);
+    const int x0 = block_origin(bx, g.sx, g.w, g.bw);
+    int oylo, oyhi, oxlo, oxhi;
+    owner_range(by, g.nby, g.sy, g.h, g.bh, &oylo, &oyhi);
+    owner_range(bx, g.nbx, g.sx, g.w, g.bw, &oxlo, &oxhi);
+
+    const int64_t W = g.w;
+    const float* __restrict__ U = uin + ch * a.cpitch;
+    const bool on = lane < g.bw;
+    const int x = x0 + lane;
+    const int nrows = RAGGED ? g.bh : RPW;
+    const bool has_top = y0 > 0;
+    const bool has_bot = y0 + nrows < g.h;
+    const bool has_left = x0 > 0;
+    const bool has_right = x0 + g.bw < g.w;
+
+    // ---- stage u (rows y0-1 .. y0+nrows, columns x0-1 .. x0+bw) ----
+    uint32_t mlo = 0u, mhi = 0u;  // bit y: pixel (y0 + y, x) is unknown
+    {
+        // lanes 0 and 1 also fetch the left and right halo columns
+        const int hx = (lane == 0) ? max(x0 - 1, 0) : min(x0 + g.bw, g.w - 1);
+        const int hcol = (lane == 0) ? 0 : g.bw + 1;
+#pragma unroll 8
+        for (int t = -1; t <= nrows; ++t) {
+            const int yy = min(max(y0 + t, 0), g.h - 1);
+            const int64_t row = (int64_t)yy * W;
+            if (on) lds[(t + 1) * kTileW + lane + 1] = U[row + x];
+            if (lane < 2) lds[(t + 1) * kTileW + hcol] = U[row + hx];
+            if (on && t >= 0 && t < nrows && mask[row + x] == 0) {
+                if (t < 32) mlo |= 1u << t; else mhi |= 1u << (t - 32);
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- residual of u_in on the block (eq. 7) and its owned norm ----
+    float r[RPW];
+    double rsq = 0.0;
+    {
+        const int ylo = oylo - y0, yhi = oyhi - y0;
+        const bool own_col = on && x >= oxlo && x < oxhi;
+        const float* col = lds + lane + 1;
+        float uup = col[0];
+        float uy = col[kTileW];
+#pragma unroll
+        for (int y = 0; y < RPW; ++y) {
+            const float udn = col[(y + 2) * kTileW];
+            const float ul = col[(y + 1) * kTileW - 1];
+            const float ur = col[(y + 1) * kTileW + 1];
+            const bool unk = ((y < 32 ? mlo : mhi) >> (y & 31)) & 1u;
+            const float ry =
+                unk ? ((uup - uy) + (udn - uy)) + ((ul - uy) + (ur - uy)) : 0.f;
+            r[y] = ry;
+            if (own_col && y >= ylo && y < yhi) rsq += (double)ry * (double)ry;
+            uup = uy;
+            uy = udn;
+        }
+    }
+    rsq = wave_sum_d(rsq);
+    if (lane == 0) partial[(int64_t)b * a.channels + ch] = rsq;
+
+    ColMask<RPW, MBITS> mk;
+    mk.load(mlo, mhi);
+
+    // ---- local CG (Sec. 4) from v = 0 ----
+    const float al = a.alpha;
+    const float wl = (lane > 0) ? 1.f : (has_left ? al : 0.f);
+    const float wr = (lane < g.bw - 1) ? 1.f : (has_right ? al : 0.f);
+    const float dmid = 2.f + wl + wr;
+    const float dtop = dmid - 1.f + (has_top ? al : 0.f);
+    const float dbot = dmid - 1.f + (has_bot ? al : 0.f);
+
+    float v[RPW], p[RPW];
+    float rho_l0 = 0.f, rho_l1 = 0.f;
+#pragma unroll
+    for (int y = 0; y < RPW; ++y) {
+        v[y] = 0.f;
+        p[y] = r[y];
+        if (y & 1) rho_l1 += r[y] * r[y]; else rho_l0 += r[y] * r[y];
+    }
+    float rho = wave_sum(rho_l0 + rho_l1);
+
+    __syncthreads();  // the staged tile is dead; its LDS now holds q
+    float4* qs = reinterpret_cast<float4*>(lds);
+    float qreg[QLDS ? 1 : RPW];
+    for (int it = 0; it < a.k; ++it) {
+        if (!(rho > 0.f)) break;
+        // q = A_loc p, pq = p . q
+        float pq0 = 0.f, pq1 = 0.f;
+        float q4[4];
+        // keep the last-row test inside the loop (64 hoisted compares would
+        // exhaust the scalar registers)
+        int last = nrows - 1;
+        if constexpr (RAGGED) asm volatile("" : "+s"(last));
+#pragma unroll
+        for (int y = 0; y < RPW; ++y) {
+            float s = ((y > 0) ? p[y - 1] : 0.f) + ((y < RPW - 1) ? p[y + 1] : 0.f);
+            s += from_left(p[y]);
+            s += from_right(p[y]);
+            float d;
+            if (!RAGGED) {
+                d = (y == 0) ? dtop : ((y == RPW - 1) ? dbot : dmid);
+            } else {
+                d = dmid;
+                if (y == 0) d = dtop;
+                if (y == last) d = (y == 0) ? dtop + dbot - dmid : dbot;
+            }
+            const float q = mk.apply(y, d * p[y] - s);
+            if (y & 1) pq1 += p[y] * q; else pq0 += p[y] * q;
+            if constexpr (QLDS) {
+                q4[y & 3] = q;
+                if ((y & 3) == 3)
+                    qs[(y >> 2) * 64 + lane] = make_float4(q4[0], q4[1], q4[2], q4[3]);
+            } else {
+                qreg[y] = q;
+            }
+        }
+        const float pq = wave_sum(pq0 + pq1);
+        if (!(pq > 0.f)) break;
+        const float alpha = rho / pq;
+        float rr0 = 0.f, rr1 = 0.f;
+        float4 qn;
+        if constexpr (QLDS) qn = qs[lane];
+#pragma unroll
+        for (int y = 0; y < RPW; ++y) {
+            float q;
+            if constexpr (QLDS) {
+                // one float4 group in flight ahead of the one in use
+                if ((y & 3) == 0) {
+                    q4[0] = qn.x; q4[1] = qn.y; q4[2] = qn.z; q4[3] = qn.w;
+                    if (y + 4 < RPW) qn = qs[((y >> 2) + 1) * 64 + lane];
+                }
+                q = q4[y & 3];
+            } else {
+                q = qreg[y];
+            }
+            v[y] += alpha * p[y];
+            r[y] -= alpha * q;
+            if (y & 1) rr1 += r[y] * r[y]; else rr0 += r[y] * r[y];
+            if constexpr (QLDS) {
+                if ((y & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        const float rr = wave_sum(rr0 + rr1);
+        const float beta = rr / rho;
+        rho = rr;
+#pragma unroll
+        for (int y = 0; y < RPW; ++y) p[y] = r[y] + beta * p[y];
+    }
+
+    // ---- restricted prolongation: u_out = u_in + v on owned pixels (eq. 9)
+    if (on && x >= oxlo && x < oxhi) {
+        float* __restrict__ UO = uout + ch * a.cpitch;
+#pragma unroll
+        for (int y = 0; y < RPW; ++y) {
+            const int yy = y0 + y;
+            if ((!RAGGED || y < nrows) && yy >= oylo && yy < oyhi) {
+                const int64_t idx = (int64_t)yy * W + x;
+                UO[idx] = U[idx] + v[y];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Level transfer and statistics
+// ---------------------------------------------------------------------------
+
+constexpr int kTpb = 256;
+
+// Fixed-order block reduction of NV doubles per thread into out[0..NV).
+template <int NV>
+__device__ void block_reduce(double (&val)[NV], double* out) {
+    __shared__ double sm[kTpb];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        sm[threadIdx.x] = val[j];
+        __syncthreads();
+        for (int s = kTpb / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[j] = sm[0];
+        __syncthreads();
+    }
+}
+
+
+template <int NC>
+__global__ __launch_bounds__(kTpb) void k_coarsen(const float* __restrict__ f,
+                                                  const uint8_t* __restrict__ c,
+                                                  int h, int w, float* __restrict__ fc,
+                                                  uint8_t* __restrict__ cc, int hc, int wc,
+                                                  double* __restrict__ stats) {
+    const int64_t n = (int64_t)hc * wc;
+    const int64_t idx = (int64_t)blockIdx.x * kTpb + threadIdx.x;
+    double st[NC + 2];
+#pragma unroll
+    for (int j = 0; j < NC + 2; ++j) st[j] = 0.0;
+    if (idx < n) {
+        const int I = (int)(idx / wc), J = (int)(idx - (int64_t)I * wc);
+        double s[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) s[k] = 0.0;
+        int cnt = 0;
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2) {
+#pragma unroll
+            for (int b2 = 0; b2 < 2; ++b2) {
+                const int i = 2 * I + a2, j = 2 * J + b2;
+                if (i < h && j < w) {
+                    const int64_t fi = (int64_t)i * w + j;
+                    const uint8_t cv = c[fi];
+                    if (cv != 0) {
+                        ++cnt;
+#pragma unroll
+                        for (int k = 0; k < NC; ++k) {
+                            const double fv = f[k * (int64_t)h * w + fi];
+                            s[k] += fv;
+                            st[k] += fv * fv;
+                        }
+                    }
+                    st[NC] += cv != 0 ? 1.0 : 0.0;
+                    st[NC + 1] += cv > 1 ? 1.0 : 0.0;
+                }
+            }
+        }
+        cc[idx] = cnt > 0 ? 1 : 0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+            fc[k * n + idx] = cnt > 0 ? (float)(s[k] / (double)cnt) : 0.f;
+    }
+    if (stats) block_reduce<NC + 2>(st, stats + (int64_t)blockIdx.x * (NC + 2));
+}
+
+template <int NC>
+__global__ __launch_bounds__(kTpb) void k_stats(const float* __restrict__ f,
+                                                const uint8_t* __restrict__ c, int64_t n,
+                                                double* __restrict__ stats) {
+    double st[NC + 2];
+#pragma unroll
+    for (int j = 0; j < NC + 2; ++j) st[j] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kTpb + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kTpb) {
+        const uint8_t cv = c[i];
+        if (cv != 0) {
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                const double fv = f[k * n + i];
+                st[k] += fv * fv;
+            }
+        }
+        st[NC] += cv != 0 ? 1.0 : 0.0;
+        st[NC + 1] += cv > 1 ? 1.0 : 0.0;
+    }
+    block_reduce<NC + 2>(st, stats + (int64_t)blockIdx.x * (NC + 2));
+}
+
+__global__ __launch_bounds__(kTpb) void k_init(const float* __restrict__ f,
+                                               const uint8_t* __restrict__ c, int64_t n,
+                                               int channels, float* __restrict__ u) {
+    const int64_t i = (int64_t)blockIdx.x * kTpb + threadIdx.x;
+    if (i >= n) return;
+    const bool known = c[i] != 0;
+    for (int k = 0; k < channels; ++k) u[k * n + i] = known ? f[k * n + i] : 0.f;
+}
+
+__global__ __launch_bounds__(kTpb) void k_prolong(const float* __restrict__ uc, int hc, int wc,
+                                                  const float* __restrict__ f,
+                                                  const uint8_t* __restrict__ c, int h, int w,
+                                                  int channels, float* __restrict__ u) {
+    const int64_t n = (int64_t)h * w;
+    const int64_t i = (int64_t)blockIdx.x * kTpb + threadIdx.x;
+    if (i >= n) return;
+    const int y = (int)(i / w), x = (int)(i - (int64_t)y * w);
+    if (c[i] != 0) {
+        for (int k = 0; k < channels; ++k) u[k * n + i] = f[k * n + i];
+        return;
+    }
+    // fine pixel centre in coarse coordinates: y/2 - 1/4, clamped
+    double ty = fmin(fmax(0.5 * y - 0.25, 0.0), (double)(hc - 1));
+    double tx = fmin(fmax(0.5 * x - 0.25, 0.0), (double)(wc - 1));
+    const int i0 = (int)ty, j0 = (int)tx;
+    const int i1 = min(i0 + 1, hc - 1), j1 = min(j0 + 1, wc - 1);
+    const double ay = ty - i0, ax = tx - j0;
+    const int64_t nc = (int64_t)hc * wc;
+    for (int k = 0; k < channels; ++k) {
+        const float* C = uc + k * nc;
+        const double u00 = C[(int64_t)i0 * wc + j0], u01 = C[(int64_t)i0 * wc + j1];
+        const double u10 = C[(int64_t)i1 * wc + j0], u11 = C[(int64_t)i1 * wc + j1];
+        const double v = (1.0 - ay) * ((1.0 - ax) * u00 + ax * u01) +
+                         ay * ((1.0 - ax) * u10 + ax * u11);
+        u[k * n + i] = (float)v;
+    }
+}
+
+// Residual r = b - A u: one wave walks 64 columns down kResRows rows,
+// keeping the rows above and below in registers; workgroups are single
+// waves so that blockIdx maps to (column strip, row strip, channel).
+constexpr int kResRows = 32;
+
+__global__ __launch_bounds__(64) void k_residual(const float* __restrict__ f,
+                                                 const uint8_t* __restrict__ c,
+                                                 const float* __restrict__ u, int h, int w,
+                                                 int channels, float* __restrict__ r,
+                                                 float* __restrict__ ucopy,
+                                                 double* __restrict__ partial) {
+    const int lane = threadIdx.x;
+    const int x0 = blockIdx.x * 64;
+    const int y0 = blockIdx.y * kResRows;
+    const int ch = blockIdx.z;
+    const int64_t n = (int64_t)h * w;
+    const float* U = u + ch * n;
+    const float* F = f + ch * n;
+    const int x = x0 + lane;
+    const bool on = x < w;
+    const int bw = min(64, w - x0);
+    const int y1 = min(y0 + kResRows, h);
+    double acc = 0.0;
+    float ucur = on ? U[(int64_t)y0 * w + x] : 0.f;
+    float uup = (on && y0 > 0) ? U[(int64_t)(y0 - 1) * w + x] : ucur;
+    for (int y = y0; y < y1; ++y) {
+        const int64_t row = (int64_t)y * w;
+        const float udn = (on && y + 1 < h) ? U[row + w + x] : ucur;
+        float ul = from_left(ucur);
+        float ur = from_right(ucur);
+        if (lane == 0) ul = x0 > 0 ? U[row + x0 - 1] : ucur;
+        if (lane == bw - 1) ur = (x0 + bw < w) ? U[row + x0 + bw] : ucur;
+        if (on) {
+            const bool known = c[row + x] != 0;
+            const float ry = known ? F[row + x] - ucur
+                                   : ((uup - ucur) + (udn - ucur)) + ((ul - ucur) + (ur - ucur));
+            acc += (double)ry * (double)ry;
+            if (r) r[ch * n + row + x] = ry;
+            if (ucopy) ucopy[ch * n + row + x] = ucur;
+        }
+        uup = ucur;
+        ucur = udn;
+    }
+    acc = wave_sum_d(acc);
+    if (lane == 0)
+        partial[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * channels + ch] = acc;
+}
+
+__global__ __launch_bounds__(kTpb) void k_reduce(const double* __restrict__ partial, int nrows,
+                                                 int stride, double* __restrict__ out) {
+    const int j = blockIdx.x;
+    double s[1] = {0.0};
+    for (int i = threadIdx.x; i < nrows; i += kTpb) s[0] += partial[(int64_t)i * stride + j];
+    block_reduce<1>(s, out + j);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <int RPW, bool QLDS, bool MBITS>
+static hipError_t sweep_rpw(const float* uin, const uint8_t* mask, float* uout,
+                            double* partial, const SweepArgs& a, hipStream_t s) {
+    const int grid = a.g.nby * a.g.nbx * a.channels;
+    if (a.g.bh == RPW)
+        hipLaunchKernelGGL((k_sweep<RPW, false, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
+                           uin, mask, uout, partial, a);
+    else
+        hipLaunchKernelGGL((k_sweep<RPW, true, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
+                           uin, mask, uout, partial, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const float* uin, const uint8_t* mask, float* uout,
+                        double* partial, const SweepArgs& a, hipStream_t s) {
+    const int bh = a.g.bh;
+    if (a.g.bw < 1 || a.g.bw > kMaxBlock || bh < 1 || bh > kMaxBlock) return hipErrorInvalidValue;
+    if (bh > 32) return sweep_rpw<64, true, true>(uin, mask, uout, partial, a, s);
+    if (bh > 16) return sweep_rpw<32, false, false>(uin, mask, uout, partial, a, s);
+    if (bh > 8) return sweep_rpw<16, false, false>(uin, mask, uout, partial, a, s);
+    return sweep_rpw<8, false, false>(uin, mask, uout, partial, a, s);
+}
+
+static int grid1d(int64_t n) { return (int)((n + kTpb - 1) / kTpb); }
+
+hipError_t launch_coarsen(const float* f, const uint8_t* c, int h, int w, int channels,
+                          float* fc, uint8_t* cc, double* stats, int* nwg, hipStream_t s) {
+    const int hc = (h + 1) / 2, wc = (w + 1) / 2;
+    const int grid = grid1d((int64_t)hc * wc);
+    if (nwg) *nwg = grid;
+    switch (channels) {
+#define DDI_CASE(NC)                                                                       \
+    case NC:                                                                               \
+        hipLaunchKernelGGL(k_coarsen<NC>, dim3(grid), dim3(kTpb), 0, s, f, c, h, w, fc, cc, \
+                           hc, wc, stats);                                                 \
+        break;
+        DDI_CASE(1) DDI_CASE(2) DDI_CASE(3) DDI_CASE(4)
+#undef DDI_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const float* f, const uint8_t* c, int h, int w, int channels,
+                        double* stats, int* nwg, hipStream_t s) {
+    const int64_t n = (int64_t)h * w;
+    int grid = grid1d(n);
+    if (grid > 1024) grid = 1024;
+    if (nwg) *nwg = grid;
+    switch (channels) {
+#define DDI_CASE(NC)                                                                   \
+    case NC:                                                                           \
+        hipLaunchKernelGGL(k_stats<NC>, dim3(grid), dim3(kTpb), 0, s, f, c, n, stats); \
+        break;
+        DDI_CASE(1) DDI_CASE(2) DDI_CASE(3) DDI_CASE(4)
+#undef DDI_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const float* f, const uint8_t* c, int h, int w, int channels, float* u,
+                       hipStream_t s) {
+    const int64_t n = (int64_t)h * w;
+    hipLaunchKernelGGL(k_init, dim3(grid1d(n)), dim3(kTpb), 0, s, f, c, n, channels, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(const float* uc, int hc, int wc, const float* f, const uint8_t* c,
+                          int h, int w, int channels, float* u, hipStream_t s) {
+    const int64_t n = (int64_t)h * w;
+    hipLaunchKernelGGL(k_prolong, dim3(grid1d(n)), dim3(kTpb), 0, s, uc, hc, wc, f, c, h, w,
+                       channels, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const float* f, const uint8_t* c, const float* u, int h, int w,
+                           int channels, float* r, float* ucopy, double* partial, int* nwg,
+                           hipStream_t s) {
+    dim3 grid((w + 63) / 64, (h + kResRows - 1) / kResRows, channels);
+    if (nwg) *nwg = (int)(grid.x * grid.y);
+    hipLaunchKernelGGL(k_residual, grid, dim3(64), 0, s, f, c, u, h, w, channels, r, ucopy,
+                       partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partial, int nrows, int stride, int ncols, double* out,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(ncols), dim3(kTpb), 0, s, partial, nrows, stride, out);
+    return hipGetLastError();
+}
+
+}  // namespace ddi

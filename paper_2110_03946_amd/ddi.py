@@ -1,0 +1,301 @@
+"""ctypes binding of libddi.so (include/ddi.h).
+
+Argument marshalling only: every step runs in the HIP kernels of the
+library. Tensors are torch tensors on the ROCm device (torch supplies device
+memory and the current stream); shapes follow the C ABI:
+  f, u : (channels, height, width) float32, contiguous
+  c    : (height, width) uint8, contiguous, 1 = known pixel
+There is no CPU fallback: if the library is not built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+DDI_OK = 0
+DDI_EINVAL = -1
+DDI_ESINGULAR = -2
+DDI_ENOMEM = -3
+DDI_ENOCONV = -4
+DDI_EHIP = -5
+DDI_ENODEV = -6
+MAX_BLOCK = 64
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("overlap", ctypes.c_int),
+                ("levels", ctypes.c_int), ("local_iters", ctypes.c_int),
+                ("robin_alpha", ctypes.c_float), ("coarse_sweeps", ctypes.c_int),
+                ("coarsest_sweeps", ctypes.c_int), ("rel_tol", ctypes.c_double),
+                ("min_sweeps", ctypes.c_int), ("max_sweeps", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("final_residual", ctypes.c_int),
+                ("timing", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("ms", ctypes.c_double),
+                ("sweep_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class DDIError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = lib().ddi_strerror(code).decode()
+        if code == DDI_EHIP:
+            msg += f" (hip error {lib().ddi_last_hip_error()})"
+        super().__init__(f"{what}: {msg} [{code}]" if what else f"{msg} [{code}]")
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def lib():
+    """Load libddi.so (built in tree by ``python -m paper_2110_03946_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            raise RuntimeError(
+                f"{_build.LIB} is not built; run `python -m paper_2110_03946_amd.build` "
+                "(the solver has no CPU fallback)")
+        L = ctypes.CDLL(_build.LIB)
+        vp, i, d, f = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_float
+        ip = ctypes.POINTER(ctypes.c_int)
+        sig = {
+            "ddi_default_params": (i, [ctypes.POINTER(Params)]),
+            "ddi_check_params": (i, [i, i, i, ctypes.POINTER(Params)]),
+            "ddi_create": (i, [ctypes.POINTER(vp), i, i, i, ctypes.POINTER(Params), vp]),
+            "ddi_solve": (i, [vp, vp, vp, vp, ctypes.POINTER(Stats)]),
+            "ddi_destroy": (i, [vp]),
+            "ddi_strerror": (ctypes.c_char_p, [i]),
+            "ddi_last_hip_error": (i, []),
+            "ddi_block_count": (i, [i, i, i]),
+            "ddi_block_range": (i, [i, i, i, i, ip, ip, ip]),
+            "ddi_residual": (i, [vp, vp, vp, i, i, i, vp, vp, vp]),
+            "ddi_coarsen": (i, [vp, vp, i, i, i, vp, vp, vp]),
+            "ddi_prolong": (i, [vp, i, i, vp, vp, i, i, i, vp, vp]),
+            "ddi_oras_sweep": (i, [vp, vp, vp, i, i, i, i, i, f, i, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list[str]:
+    """Function names declared in include/ddi.h."""
+    hdr = os.path.join(_build.ROOT, "include", "ddi.h")
+    txt = open(hdr).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w[\w\s\*]*?\b(ddi_\w+)\s*\(", txt, re.M)))
+
+
+def _check(rc: int, what: str):
+    if rc != DDI_OK:
+        raise DDIError(rc, what)
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    _check(lib().ddi_default_params(ctypes.byref(p)), "ddi_default_params")
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def check_params(h: int, w: int, channels: int, p: Params) -> int:
+    return lib().ddi_check_params(h, w, channels, ctypes.byref(p))
+
+
+def block_count(n: int, block: int, overlap: int) -> int:
+    return lib().ddi_block_count(n, block, overlap)
+
+
+def block_range(n: int, block: int, overlap: int, k: int):
+    o, lo, hi = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().ddi_block_range(n, block, overlap, k, ctypes.byref(o), ctypes.byref(lo),
+                                 ctypes.byref(hi)), "ddi_block_range")
+    return o.value, lo.value, hi.value
+
+
+# ---------------------------------------------------------------------------
+# device-tensor helpers (torch only as the owner of device memory / streams)
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _img(t, name, channels=None, hw=None):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3:
+        raise ValueError(f"{name} must be (channels, height, width)")
+    if channels is not None and t.shape[0] != channels:
+        raise ValueError(f"{name} has {t.shape[0]} channels, expected {channels}")
+    if hw is not None and tuple(t.shape[1:]) != tuple(hw):
+        raise ValueError(f"{name} is {tuple(t.shape[1:])}, expected {tuple(hw)}")
+    return t
+
+
+def _mask(t, hw=None):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError("c must be a torch tensor on the GPU")
+    if t.dtype != torch.uint8 or not t.is_contiguous() or t.dim() != 2:
+        raise TypeError("c must be a contiguous (height, width) uint8 tensor")
+    if hw is not None and tuple(t.shape) != tuple(hw):
+        raise ValueError(f"c is {tuple(t.shape)}, expected {tuple(hw)}")
+    return t
+
+
+class Plan:
+    """A solver plan for one image size (ddi_create / ddi_solve / ddi_destroy)."""
+
+    def __init__(self, height: int, width: int, channels: int = 3,
+                 params: Params | None = None, stream=None, **overrides):
+        if params is None:
+            params = default_params(**overrides)
+        elif overrides:
+            for k, v in overrides.items():
+                setattr(params, k, v)
+        self.height, self.width, self.channels = height, width, channels
+        self.params = params
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().ddi_create(ctypes.byref(h), height, width, channels,
+                                ctypes.byref(params), _stream(stream)), "ddi_create")
+        self._h = h
+
+    def solve(self, f, c, u=None, allow_noconv: bool = False):
+        """Inpaint f (C, H, W) with mask c (H, W) into u; returns (u, stats)."""
+        torch = _torch()
+        hw = (self.height, self.width)
+        f = _img(f, "f", self.channels, hw)
+        c = _mask(c, hw)
+        if u is None:
+            u = torch.empty_like(f)
+        else:
+            u = _img(u, "u", self.channels, hw)
+        st = Stats()
+        rc = lib().ddi_solve(self._h, _ptr(f), _ptr(c), _ptr(u), ctypes.byref(st))
+        if rc != DDI_OK and not (allow_noconv and rc == DDI_ENOCONV):
+            raise DDIError(rc, "ddi_solve")
+        return u, st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ddi_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(f, c, **params):
+    """One-shot inpainting: creates a plan, solves, destroys it."""
+    f3 = _img(f, "f")
+    with Plan(f3.shape[1], f3.shape[2], f3.shape[0], **params) as plan:
+        return plan.solve(f3, c)
+
+
+def residual(f, c, u, r=None, stream=None):
+    """r = b - A u (eq. 7); returns (r or None, per-channel sum of r^2)."""
+    f = _img(f, "f")
+    C, H, W = f.shape
+    c = _mask(c, (H, W))
+    u = _img(u, "u", C, (H, W))
+    if r is not None:
+        r = _img(r, "r", C, (H, W))
+    rsq = np.zeros(C, dtype=np.float64)
+    _check(lib().ddi_residual(_ptr(f), _ptr(c), _ptr(u), H, W, C,
+                              _ptr(r) if r is not None else None,
+                              rsq.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+           "ddi_residual")
+    return r, rsq
+
+
+def coarsen(f, c, stream=None):
+    """One dyadic subsampling step (Sec. 4); returns (fc, cc)."""
+    torch = _torch()
+    f = _img(f, "f")
+    C, H, W = f.shape
+    c = _mask(c, (H, W))
+    hc, wc = (H + 1) // 2, (W + 1) // 2
+    fc = torch.empty((C, hc, wc), dtype=torch.float32, device=f.device)
+    cc = torch.empty((hc, wc), dtype=torch.uint8, device=f.device)
+    _check(lib().ddi_coarsen(_ptr(f), _ptr(c), H, W, C, _ptr(fc), _ptr(cc), _stream(stream)),
+           "ddi_coarsen")
+    return fc, cc
+
+
+def prolong(uc, f, c, u=None, stream=None):
+    """Coarse-to-fine start: u = f on the mask, bilinear(uc) elsewhere."""
+    torch = _torch()
+    f = _img(f, "f")
+    C, H, W = f.shape
+    c = _mask(c, (H, W))
+    uc = _img(uc, "uc", C)
+    if u is None:
+        u = torch.empty_like(f)
+    _check(lib().ddi_prolong(_ptr(uc), uc.shape[1], uc.shape[2], _ptr(f), _ptr(c), H, W, C,
+                             _ptr(u), _stream(stream)), "ddi_prolong")
+    return u
+
+
+def oras_sweep(u_in, c, block: int, overlap: int, alpha: float, k: int, u_out=None,
+               stream=None):
+    """One ORAS iteration (Sec. 3 eqs. 7-9); returns (u_out, per-channel ||r||^2 of u_in)."""
+    torch = _torch()
+    u_in = _img(u_in, "u_in")
+    C, H, W = u_in.shape
+    c = _mask(c, (H, W))
+    if u_out is None:
+        u_out = torch.empty_like(u_in)
+    rsq = np.zeros(C, dtype=np.float64)
+    _check(lib().ddi_oras_sweep(_ptr(u_in), _ptr(c), _ptr(u_out), H, W, C, block, overlap,
+                                float(alpha), k, rsq.ctypes.data_as(ctypes.c_void_p),
+                                _stream(stream)), "ddi_oras_sweep")
+    return u_out, rsq

@@ -1,0 +1,74 @@
+"""The C ABI library: loads without a GPU, exports every declared symbol, and
+its host-side logic (parameters, block grid, partition of unity) is right.
+No compute call is made here."""
+import ctypes
+import json
+import os
+
+import pytest
+
+import oracle
+from paper_2110_03946_amd import ddi
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_library_loads_and_exports_header_symbols():
+    names = ddi.header_symbols()
+    assert len(names) >= 13
+    L = ddi.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_default_params_valid():
+    p = ddi.default_params()
+    assert p.block == 64 and p.overlap == 4 and 0 < p.robin_alpha <= 1
+    assert ddi.check_params(2160, 3840, 3, p) == ddi.DDI_OK
+
+
+@pytest.mark.parametrize("field,value", [
+    ("block", 1), ("block", 65), ("overlap", -1), ("overlap", 64), ("levels", 0),
+    ("local_iters", 0), ("robin_alpha", 0.0), ("robin_alpha", 1.5),
+    ("coarse_sweeps", -1), ("rel_tol", -1.0), ("check_every", 0), ("max_sweeps", 1)])
+def test_bad_params_rejected(field, value):
+    p = ddi.default_params()
+    setattr(p, field, value)
+    assert ddi.check_params(64, 64, 1, p) == ddi.DDI_EINVAL
+
+
+@pytest.mark.parametrize("h,w,ch", [(0, 5, 1), (5, 0, 1), (5, 5, 0), (5, 5, 5)])
+def test_bad_dims_rejected(h, w, ch):
+    assert ddi.check_params(h, w, ch, ddi.default_params()) == ddi.DDI_EINVAL
+
+
+def test_paper_block_count():
+    g = json.load(open(os.path.join(GOLDEN, "block_count.json")))
+    n = (ddi.block_count(g["height"], g["block_size"], g["overlap"]) *
+         ddi.block_count(g["width"], g["block_size"], g["overlap"]) * g["channels"])
+    assert n == g["local_problems"]
+
+
+@pytest.mark.parametrize("n,S,o", [(256, 64, 4), (3840, 64, 4), (2160, 64, 4), (100, 32, 6),
+                                   (33, 32, 6), (20, 32, 6), (1000, 48, 9), (65, 64, 1),
+                                   (270, 64, 4), (7, 4, 3), (1, 64, 4)])
+def test_block_grid_matches_oracle(n, S, o):
+    """The library's block grid and owner map equal the oracle's reading of
+    Sec. 4 / eq. 10 (and therefore form a partition of unity)."""
+    org, s = oracle.block_origins(n, S, o)
+    lo, hi = oracle.owner_bounds(org, s, n)
+    assert ddi.block_count(n, S, o) == len(org)
+    for k in range(len(org)):
+        assert ddi.block_range(n, S, o, k) == (org[k], lo[k], hi[k])
+
+
+def test_strerror_and_nodev_without_gpu():
+    for code in (0, -1, -2, -3, -4, -5, -6, -99):
+        assert ddi.lib().ddi_strerror(code)
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    p = ddi.default_params()
+    rc = ddi.lib().ddi_create(ctypes.byref(h), 64, 64, 1, ctypes.byref(p), None)
+    assert rc == ddi.DDI_ENODEV and not h.value
