@@ -57,21 +57,46 @@ def solver_params() -> dict:
     4, coarsest level 1/8); the stop tolerance keeps the max error below
     0.5 grey levels on this workload class."""
     return dict(block=64, overlap=4, levels=4, local_iters=16, robin_alpha=0.25,
-                coarse_sweeps=2, coarsest_sweeps=3, rel_tol=5e-4, min_sweeps=2,
-                max_sweeps=30, check_every=1, final_residual=1)
+                coarse_sweeps=1, coarsest_sweeps=1, coarse_local_iters=4, local_tol=0.002,
+                rel_tol=5e-4, min_sweeps=2, max_sweeps=30, check_every=1, final_residual=0)
 
 
-def sweep_work(p: dict):
-    """Algorithmic flops and bytes of one finest-level sweep launch."""
+def sweep_work(p: dict, sweeps: int, cg_steps: float):
+    """Algorithmic flops and HBM bytes of the finest-level sweeps of a solve
+    (`sweeps` launches, `cg_steps` block CG steps actually run)."""
     from paper_2110_03946_amd import ddi
     nby = ddi.block_count(H, p["block"], p["overlap"])
     nbx = ddi.block_count(W, p["block"], p["overlap"])
-    bpx = nby * nbx * C * min(p["block"], H) * min(p["block"], W)  # block pixels
-    flops = bpx * (FLOPS_RESIDUAL + FLOPS_PER_CG_STEP * p["local_iters"])
-    # u with a one-pixel halo and the mask per block, owned u written once
-    halo = (min(p["block"], H) + 2) * (min(p["block"], W) + 2)
-    bytes_ = nby * nbx * C * (halo * 4 + min(p["block"], H) * min(p["block"], W)) + C * H * W * 8
-    return flops, bytes_, bpx
+    bh, bw = min(p["block"], H), min(p["block"], W)
+    blocks = nby * nbx * C
+    flops = bh * bw * (blocks * sweeps * FLOPS_RESIDUAL + cg_steps * FLOPS_PER_CG_STEP)
+    # per launch: every block reads its u tile with a one-pixel halo and 16
+    # bytes of transposed mask per column; the owned pixels (each pixel once)
+    # are written back
+    bytes_ = sweeps * (blocks * ((bh + 2) * (bw + 2) * 4 + bw * 16) + C * H * W * 4)
+    return flops, bytes_
+
+
+def summarize_trace(path: str) -> str:
+    """Per (kernel, grid) duration table of a rocprofv3 --kernel-trace CSV:
+    the same kernel runs on every level of the pyramid, and the grid size
+    tells the levels apart (the finest-level sweep has 6912 workgroups)."""
+    import csv
+    import collections
+    groups = collections.defaultdict(list)
+    for row in csv.DictReader(open(path)):
+        name = row["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0]
+        name = name.replace("void ", "")
+        grid = (int(row["Grid_Size_X"]) * int(row["Grid_Size_Y"]) * int(row["Grid_Size_Z"]) //
+                max(1, int(row["Workgroup_Size_X"]) * int(row["Workgroup_Size_Y"]) *
+                    int(row["Workgroup_Size_Z"])))
+        groups[(name, grid)].append(int(row["End_Timestamp"]) - int(row["Start_Timestamp"]))
+    total = sum(sum(v) for v in groups.values())
+    out = ["| kernel | workgroups | calls | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    for (name, grid), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        out.append(f"| {name} | {grid} | {len(v)} | {sum(v) / len(v) / 1e3:.2f} | "
+                   f"{min(v) / 1e3:.2f} | {max(v) / 1e3:.2f} | {100 * sum(v) / total:.1f} |")
+    return "\n".join(out)
 
 
 def cpu_baseline(f, c, u_gpu):
@@ -92,7 +117,12 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--summarize-trace", metavar="CSV",
+                    help="print a per-kernel, per-grid table of a rocprofv3 kernel trace and exit")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this solver has no "
               "multi-GPU path", file=sys.stderr)
@@ -116,7 +146,7 @@ def main():
     for _ in range(args.warmup):
         plan.solve(f, c, u)
     torch.cuda.synchronize()
-    lat, sweep_ms, nsweeps, sweeps_per_solve, rels = [], 0.0, 0, [], []
+    lat, sweep_ms, nsweeps, sweeps_per_solve, rels, steps = [], 0.0, 0, [], [], 0.0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
@@ -124,21 +154,38 @@ def main():
         lat.append((time.perf_counter() - ts) * 1e3)
         sweep_ms += st["sweep_ms"]
         nsweeps += st["sweeps"]
+        steps += st["cg_steps"]
         sweeps_per_solve.append(st["sweeps"])
         rels.append(st["rel_residual"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     fps = args.steps / elapsed
 
-    flops, bytes_, bpx = sweep_work(prm)
+    flops, bytes_ = sweep_work(prm, nsweeps, steps)
     avg_sweep_s = sweep_ms / max(nsweeps, 1) / 1e3
-    tflops = flops / avg_sweep_s / 1e12
-    roofline = {"bound": "alu", "achieved": round(tflops, 3),
-                "peak": round(VALU_F32_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(tflops / VALU_F32_PEAK_TFLOPS, 4), "traffic": None,
+    tflops = flops / (sweep_ms / 1e3) / 1e12
+    gbs = bytes_ / (sweep_ms / 1e3) / 1e9
+    # the kernel's bound is set by its arithmetic intensity against the
+    # machine's ridge point (peak flops / peak bytes per second)
+    intensity = flops / bytes_
+    ridge = VALU_F32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if intensity >= ridge:
+        roofline = {"bound": "alu", "achieved": round(tflops, 3),
+                    "peak": round(VALU_F32_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                    "frac": round(tflops / VALU_F32_PEAK_TFLOPS, 4)}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    roofline.update({"traffic": None,
                 "kernel": "k_sweep<64> (finest-level ORAS sweep)",
                 "avg_launch_us": round(avg_sweep_s * 1e6, 2),
-                "hbm_gbs": round(bytes_ / avg_sweep_s / 1e9, 1)}
+                "flops_per_byte": round(intensity, 2), "ridge_flops_per_byte": round(ridge, 2),
+                "valu_tflops": round(tflops, 3),
+                "valu_frac": round(tflops / VALU_F32_PEAK_TFLOPS, 4),
+                "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                "cg_steps_per_block_sweep": round(steps / max(nsweeps, 1) /
+                                                  (ddi.block_count(H, prm["block"], prm["overlap"]) *
+                                                   ddi.block_count(W, prm["block"], prm["overlap"]) * C), 2)})
 
     u_np = u.cpu().numpy()
     out = {"metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,

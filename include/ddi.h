@@ -79,7 +79,18 @@ extern "C" {
  *   final_residual 1: recompute ||b - A u|| of the returned u (float64) for
  *                  the stats; 0: report the last stop-test residual.
  *   timing         1: bracket every finest-level sweep with HIP events and
- *                  report their summed device time in the stats.
+ *                  report their summed device time and CG step count in the
+ *                  stats (costs one small kernel per solve).
+ *   coarse_block   block edge on the coarser levels (0 = block); small
+ *                  levels solve faster with more, smaller blocks.
+ *   coarse_overlap overlap on the coarser levels (-1 = overlap).
+ *   coarse_local_iters CG steps per local solve on the coarser levels
+ *                  (0 = local_iters).
+ *   local_tol      absolute stop of the local CG (grey levels): a block
+ *                  stops early once its mean square local residual is at
+ *                  most local_tol^2 (0 = always local_iters steps). Blocks
+ *                  that are already converged then cost no CG work; the
+ *                  fixed point of the iteration is unchanged.
  */
 typedef struct ddi_params {
     int block;
@@ -95,6 +106,10 @@ typedef struct ddi_params {
     int check_every;
     int final_residual;
     int timing;
+    int coarse_block;
+    int coarse_overlap;
+    int coarse_local_iters;
+    float local_tol;
 } ddi_params;
 
 /*
@@ -107,6 +122,9 @@ typedef struct ddi_params {
  *   ms            device time of the solve from HIP events, milliseconds.
  *   sweep_ms      with timing = 1: summed device time of the finest-level
  *                 sweeps (the solver's dominant kernel), milliseconds.
+ *   cg_steps      with timing = 1: local CG steps run by the finest-level
+ *                 sweeps, summed over blocks and channels (fewer than blocks
+ *                 x local_iters when local_tol stops blocks early).
  */
 typedef struct ddi_stats {
     int sweeps;
@@ -114,6 +132,7 @@ typedef struct ddi_stats {
     double rel_residual;
     double ms;
     double sweep_ms;
+    double cg_steps;
 } ddi_stats;
 
 typedef struct ddi_plan ddi_plan;
@@ -121,7 +140,8 @@ typedef struct ddi_plan ddi_plan;
 /* Fill *p with the defaults: S = 64, o = 4, 4 levels, k = 16, alpha = 0.25,
  * 2 sweeps per coarser level, 3 on the coarsest, rel_tol = 1e-4,
  * min_sweeps = 2, max_sweeps = 50, check_every = 1, final_residual = 1,
- * timing = 0. */
+ * timing = 0, coarse_block = 0, coarse_overlap = -1, coarse_local_iters = 0,
+ * local_tol = 0. */
 int ddi_default_params(ddi_params* p);
 
 /* Check *p for one image size without touching the GPU. */

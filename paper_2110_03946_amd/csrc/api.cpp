@@ -42,8 +42,10 @@ BlockGrid make_grid(int h, int w, int block, int overlap) {
     return g;
 }
 
-SweepArgs make_sweep(int h, int w, int channels, int block, int overlap, float alpha, int k) {
+SweepArgs make_sweep(int h, int w, int channels, int block, int overlap, float alpha, int k,
+                     float local_tol = 0.f) {
     SweepArgs a;
+    a.local_tol2 = local_tol * local_tol;
     a.g = make_grid(h, w, block, overlap);
     a.channels = channels;
     a.cpitch = (int64_t)h * w;
@@ -76,6 +78,7 @@ struct Level {
     float* fown = nullptr;
     uint8_t* cown = nullptr;
     float* u[2] = {nullptr, nullptr};
+    uint64_t* mbits = nullptr;  // column-transposed unknown-pixel bits
     bool own_u0 = false;
     SweepArgs sw;
 };
@@ -97,10 +100,12 @@ struct ddi_plan {
     std::vector<Level> lv;
     double* part = nullptr;
     size_t part_n = 0;
-    double* red = nullptr;   // [C + 2] stats, then [C] norms
+    double* red = nullptr;   // [C + 2] stats, [C] norms, [C] CG step totals
     double* host = nullptr;  // pinned mirror of red
+    double* cgcnt = nullptr; // timing: CG steps per finest-level block
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<hipEvent_t> sweep_ev;  // 2 per finest-level sweep (timing)
+    int last_sweeps = -1;              // finest-level sweeps of the previous solve
 };
 
 extern "C" {
@@ -120,6 +125,10 @@ int ddi_default_params(ddi_params* p) {
     p->check_every = 1;
     p->final_residual = 1;
     p->timing = 0;
+    p->coarse_block = 0;
+    p->coarse_overlap = -1;
+    p->coarse_local_iters = 0;
+    p->local_tol = 0.f;
     return DDI_OK;
 }
 
@@ -136,6 +145,13 @@ int ddi_check_params(int height, int width, int channels, const ddi_params* p) {
     if (!(p->rel_tol >= 0.0)) return DDI_EINVAL;
     if (p->min_sweeps < 0 || p->max_sweeps < p->min_sweeps) return DDI_EINVAL;
     if (p->check_every < 1) return DDI_EINVAL;
+    const int cb = p->coarse_block ? p->coarse_block : p->block;
+    const int co = p->coarse_overlap >= 0 ? p->coarse_overlap : p->overlap;
+    if (p->coarse_block != 0 && (p->coarse_block < 2 || p->coarse_block > DDI_MAX_BLOCK))
+        return DDI_EINVAL;
+    if (p->coarse_overlap < -1 || co >= cb) return DDI_EINVAL;
+    if (p->coarse_local_iters < 0) return DDI_EINVAL;
+    if (!(p->local_tol >= 0.f) || p->local_tol > 1e6f) return DDI_EINVAL;
     return DDI_OK;
 }
 
@@ -144,11 +160,13 @@ int ddi_destroy(ddi_plan* plan) {
     for (Level& l : plan->lv) {
         if (l.fown) (void)hipFree(l.fown);
         if (l.cown) (void)hipFree(l.cown);
+        if (l.mbits) (void)hipFree(l.mbits);
         for (int i = 0; i < 2; ++i)
             if (l.u[i] && (i == 1 || l.own_u0)) (void)hipFree(l.u[i]);
     }
     if (plan->part) (void)hipFree(plan->part);
     if (plan->red) (void)hipFree(plan->red);
+    if (plan->cgcnt) (void)hipFree(plan->cgcnt);
     if (plan->host) (void)hipHostFree(plan->host);
     if (plan->e0) (void)hipEventDestroy(plan->e0);
     if (plan->e1) (void)hipEventDestroy(plan->e1);
@@ -197,8 +215,15 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
         Level& lev = P->lv[l];
         lev.h = hl;
         lev.w = wl;
-        lev.sw = make_sweep(hl, wl, channels, prm.block, prm.overlap, prm.robin_alpha,
-                            prm.local_iters);
+        if (l == 0) {
+            lev.sw = make_sweep(hl, wl, channels, prm.block, prm.overlap, prm.robin_alpha,
+                                prm.local_iters, prm.local_tol);
+        } else {
+            const int cb = prm.coarse_block ? prm.coarse_block : prm.block;
+            const int co = prm.coarse_overlap >= 0 ? prm.coarse_overlap : prm.overlap;
+            const int ck = prm.coarse_local_iters ? prm.coarse_local_iters : prm.local_iters;
+            lev.sw = make_sweep(hl, wl, channels, cb, co, prm.robin_alpha, ck, prm.local_tol);
+        }
         const size_t n = (size_t)hl * wl;
         const size_t nf = n * channels;
         auto fail = [&](hipError_t err) {
@@ -216,8 +241,11 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
             lev.c = lev.cown;
         }
         if ((err = hipMalloc(&lev.u[1], nf * sizeof(float))) != hipSuccess) return fail(err);
+        if ((err = hipMalloc(&lev.mbits, (size_t)mask_bit_groups(hl) * wl * sizeof(uint64_t))) !=
+            hipSuccess)
+            return fail(err);
         part_n = std::max(part_n, (size_t)sweep_partials(lev.sw) * channels);
-        const size_t res_wg = (size_t)((wl + 63) / 64) * ((hl + 31) / 32);
+        const size_t res_wg = (size_t)residual_partials(hl, wl);
         part_n = std::max(part_n, res_wg * channels);
         hl = (hl + 1) / 2;
         wl = (wl + 1) / 2;
@@ -234,7 +262,7 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
         ddi_destroy(P);
         return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
     }
-    const size_t nred = 2 * channels + 2;
+    const size_t nred = 3 * channels + 2;
     if ((err = hipMalloc(&P->red, nred * sizeof(double))) != hipSuccess ||
         (err = hipHostMalloc(&P->host, nred * sizeof(double), hipHostMallocDefault)) !=
             hipSuccess ||
@@ -244,6 +272,11 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
         return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
     }
     if (prm.timing) {
+        const size_t nc = (size_t)sweep_partials(P->lv[0].sw) * channels;
+        if ((err = hipMalloc(&P->cgcnt, nc * sizeof(double))) != hipSuccess) {
+            ddi_destroy(P);
+            return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
+        }
         P->sweep_ev.assign(2 * (size_t)prm.max_sweeps, nullptr);
         for (hipEvent_t& ev : P->sweep_ev) {
             if ((err = hipEventCreate(&ev)) != hipSuccess) {
@@ -306,23 +339,32 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
         Level& b = P->lv[l + 1];
         DDI_HIP(launch_coarsen(a.f, a.c, a.h, a.w, C, b.fown, b.cown, nullptr, nullptr, P->s));
     }
+    for (Level& lev : P->lv) DDI_HIP(launch_mask_bits(lev.c, lev.h, lev.w, lev.mbits, P->s));
 
     // ---- coarsest level, then coarse-to-fine ----
+    // The finest level ping-pongs between u (index 0) and the plan's buffer
+    // (index 1). It starts in the buffer that makes the expected final
+    // iterate -- as many sweeps as the previous solve needed -- land in u,
+    // so that usually no copy is needed at the end.
+    const int expect = P->last_sweeps >= 0 ? P->last_sweeps : std::max(prm.min_sweeps, 1);
+    const int start0 = std::min(expect, prm.max_sweeps) & 1;
     const int top = L - 1;
+    int cur = (top == 0) ? start0 : 0;
     DDI_HIP(launch_init(P->lv[top].f, P->lv[top].c, P->lv[top].h, P->lv[top].w, C,
-                        P->lv[top].u[0], P->s));
-    int cur = 0;
+                        P->lv[top].u[cur], P->s));
     for (int l = top; l >= 1; --l) {
         Level& lev = P->lv[l];
         const int n = (l == top) ? prm.coarsest_sweeps : prm.coarse_sweeps;
         for (int i = 0; i < n; ++i) {
-            DDI_HIP(launch_sweep(lev.u[cur], lev.c, lev.u[1 - cur], P->part, lev.sw, P->s));
+            DDI_HIP(launch_sweep(lev.u[cur], lev.mbits, lev.u[1 - cur], P->part, nullptr, lev.sw,
+                                 P->s));
             cur ^= 1;
         }
         Level& fine = P->lv[l - 1];
+        const int dst = (l == 1) ? start0 : 0;
         DDI_HIP(launch_prolong(lev.u[cur], lev.h, lev.w, fine.f, fine.c, fine.h, fine.w, C,
-                               fine.u[0], P->s));
-        cur = 0;
+                               fine.u[dst], P->s));
+        cur = dst;
     }
 
     // ---- finest level with the stop test ----
@@ -337,9 +379,11 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
     };
     const int nb = sweep_partials(L0.sw);
     const bool timing = !P->sweep_ev.empty();
+    double* steps = P->cgcnt;
+    if (steps) DDI_HIP(launch_clear(steps, nb * C, P->s));
     while (sweeps < prm.max_sweeps) {
         if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * sweeps], P->s));
-        DDI_HIP(launch_sweep(L0.u[cur], L0.c, L0.u[1 - cur], P->part, L0.sw, P->s));
+        DDI_HIP(launch_sweep(L0.u[cur], L0.mbits, L0.u[1 - cur], P->part, steps, L0.sw, P->s));
         if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * sweeps + 1], P->s));
         cur ^= 1;
         ++sweeps;
@@ -355,8 +399,10 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
         }
     }
 
+    P->last_sweeps = sweeps;
+
     // ---- final residual of the returned iterate; move it into u ----
-    if (prm.final_residual || cur == 1 || !validated) {
+    if (prm.final_residual || !validated) {
         int rwg = 0;
         DDI_HIP(launch_residual(f, c, L0.u[cur], P->h, P->w, C, nullptr,
                                 cur == 1 ? u : nullptr, P->part, &rwg, P->s));
@@ -367,9 +413,19 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
             rel = rel_from_host(P, P->host + C + 2);
             converged = rel <= prm.rel_tol || converged;
         }
+    } else if (cur == 1) {
+        DDI_HIP(hipMemcpyAsync(u, L0.u[1], (size_t)C * P->h * P->w * sizeof(float),
+                               hipMemcpyDeviceToDevice, P->s));
+    }
+    if (steps) {
+        DDI_HIP(launch_reduce(steps, nb, C, C, P->red + 2 * C + 2, P->s));
+        DDI_HIP(hipMemcpyAsync(P->host + 2 * C + 2, P->red + 2 * C + 2, C * sizeof(double),
+                               hipMemcpyDeviceToHost, P->s));
     }
     DDI_HIP(hipEventRecord(P->e1, P->s));
     DDI_HIP(hipEventSynchronize(P->e1));
+    double nsteps = 0.0;
+    for (int k = 0; steps && k < C; ++k) nsteps += P->host[2 * C + 2 + k];
     float ms = 0.f;
     DDI_HIP(hipEventElapsedTime(&ms, P->e0, P->e1));
     double sweep_ms = 0.0;
@@ -384,6 +440,7 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
         st->rel_residual = rel;
         st->ms = ms;
         st->sweep_ms = sweep_ms;
+        st->cg_steps = nsteps;
     }
     return converged ? DDI_OK : DDI_ENOCONV;
 }
@@ -430,7 +487,7 @@ int ddi_residual(const float* f, const uint8_t* c, const float* u, int height, i
     if (!f || !c || !u) return DDI_EINVAL;
     if ((e = check_device())) return e;
     hipStream_t s = (hipStream_t)stream;
-    const size_t nwg = (size_t)((width + 63) / 64) * ((height + 31) / 32);
+    const size_t nwg = (size_t)residual_partials(height, width);
     Scratch part, red;
     DDI_HIP(hipMalloc(&part.p, nwg * channels * sizeof(double)));
     DDI_HIP(hipMalloc(&red.p, channels * sizeof(double)));
@@ -479,10 +536,12 @@ int ddi_oras_sweep(const float* u_in, const uint8_t* c, float* u_out, int height
     const SweepArgs a = make_sweep(height, width, channels, block, overlap, robin_alpha,
                                    local_iters);
     const int nb = sweep_partials(a);
-    Scratch part, red;
+    Scratch part, red, mb;
     DDI_HIP(hipMalloc(&part.p, (size_t)nb * channels * sizeof(double)));
     DDI_HIP(hipMalloc(&red.p, channels * sizeof(double)));
-    DDI_HIP(launch_sweep(u_in, c, u_out, (double*)part.p, a, s));
+    DDI_HIP(hipMalloc(&mb.p, (size_t)mask_bit_groups(height) * width * sizeof(uint64_t)));
+    DDI_HIP(launch_mask_bits(c, height, width, (uint64_t*)mb.p, s));
+    DDI_HIP(launch_sweep(u_in, (const uint64_t*)mb.p, u_out, (double*)part.p, nullptr, a, s));
     DDI_HIP(launch_reduce((double*)part.p, nb, channels, channels, (double*)red.p, s));
     if (rsq) {
         DDI_HIP(hipMemcpyAsync(rsq, red.p, channels * sizeof(double), hipMemcpyDeviceToHost, s));

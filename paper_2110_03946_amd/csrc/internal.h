@@ -24,6 +24,7 @@ struct SweepArgs {
     int64_t cpitch;   // elements between channel planes (= h * w)
     float alpha;      // Robin interface weight, 1 = RAS
     int k;            // local CG steps
+    float local_tol2; // stop CG once r.r <= local_tol2 * block pixels (0: k steps)
 };
 
 __host__ __device__ inline int block_origin(int k, int stride, int n, int size) {
@@ -64,8 +65,21 @@ __host__ __device__ inline int block_count(int n, int size, int ov) {
 // lanes are columns, rows live in registers).
 constexpr int kMaxBlock = 64;
 
-hipError_t launch_sweep(const float* uin, const uint8_t* mask, float* uout,
-                        double* partial, const SweepArgs& a, hipStream_t s);
+// One ORAS sweep u_in -> u_out. `mbits` is the column-transposed mask of
+// launch_mask_bits for the same level. When cg_steps is non-null, block b
+// of channel ch adds the number of CG steps it ran to cg_steps[b * C + ch].
+hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
+                        double* partial, double* cg_steps, const SweepArgs& a,
+                        hipStream_t s);
+
+// Row groups of the transposed mask: ceil(h / 64) plus one zero group.
+inline int mask_bit_groups(int h) { return (h + 63) / 64 + 1; }
+
+// mbits[g * w + x], bit j = pixel (64 g + j, x) is unknown.
+hipError_t launch_mask_bits(const uint8_t* c, int h, int w, uint64_t* mbits, hipStream_t s);
+
+// p[0..n) = 0.
+hipError_t launch_clear(double* p, int n, hipStream_t s);
 
 // Coarsening (Sec. 4). When `stats` is non-null it also writes per-workgroup
 // partials [nwg][channels + 2]: sum over known pixels of f^2 per channel,
@@ -95,6 +109,9 @@ hipError_t launch_residual(const float* f, const uint8_t* c, const float* u,
                            int h, int w, int channels, float* r,
                            float* ucopy, double* partial, int* nwg,
                            hipStream_t s);
+
+// Workgroups (partial rows) of launch_residual for an h x w plane.
+int residual_partials(int h, int w);
 
 // out[j] = sum_i partial[i * stride + j] for j < ncols, fixed order.
 hipError_t launch_reduce(const double* partial, int nrows, int stride,

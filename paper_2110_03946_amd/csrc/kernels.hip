@@ -60,6 +60,19 @@ __device__ __forceinline__ double wave_sum_d(double x) {
     return x;
 }
 
+// Workgroups are handed to the 8 XCDs of the chip round-robin (workgroup i
+// runs on XCD i mod 8). Renumber them so that XCD j works through one
+// contiguous range of the logical order: neighbouring blocks, which share
+// halo and overlap cache lines, then meet in the same L2. Bijective for any
+// count n.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int q = n / kXcds, rem = n - q * kXcds;
+    const int j = b % kXcds, i = b / kXcds;
+    return j * q + min(j, rem) + i;
+}
+
 // Mask of one block column, built from the bits of the unknown pixels.
 // Float storage (1 = unknown) for short columns; the bits themselves for
 // 64-row columns, where registers are scarce.
@@ -113,17 +126,19 @@ constexpr int kTileW = kMaxBlock + 2;
 
 template <int RPW, bool RAGGED, bool QLDS, bool MBITS>
 __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
-                                              const uint8_t* __restrict__ mask,
+                                              const uint64_t* __restrict__ mbits,
                                               float* __restrict__ uout,
                                               double* __restrict__ partial,
+                                              double* __restrict__ cg_steps,
                                               SweepArgs a) {
     __shared__ __attribute__((aligned(16))) float lds[(RPW + 2) * kTileW];
 
     const int lane = threadIdx.x;
     const BlockGrid g = a.g;
     const int nblk = g.nby * g.nbx;
-    const int ch = blockIdx.x / nblk;
-    const int b = blockIdx.x - ch * nblk;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int ch = lb / nblk;
+    const int b = lb - ch * nblk;
     const int by = b / g.nbx;
     const int bx = b - by * g.nbx;
     const int y0 = block_origin(by, g.sy, g.h, g.bh);
@@ -132,7 +147,6 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
     owner_range(by, g.nby, g.sy, g.h, g.bh, &oylo, &oyhi);
     owner_range(bx, g.nbx, g.sx, g.w, g.bw, &oxlo, &oxhi);
 
-    const int64_t W = g.w;
     const float* __restrict__ U = uin + ch * a.cpitch;
     const bool on = lane < g.bw;
     const int x = x0 + lane;
@@ -142,22 +156,55 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
     const bool has_left = x0 > 0;
     const bool has_right = x0 + g.bw < g.w;
 
-    // ---- stage u (rows y0-1 .. y0+nrows, columns x0-1 .. x0+bw) ----
-    uint32_t mlo = 0u, mhi = 0u;  // bit y: pixel (y0 + y, x) is unknown
+    // ---- stage u (rows y0-1 .. y0+RPW, columns x0-1 .. x0+bw) ----
+    // Rows and columns are clamped to the image: a clamped halo copies the
+    // border pixel, i.e. the reflecting boundary. All loads are issued
+    // before the first LDS write (no branches between them). Offsets are
+    // 32-bit element indices into one channel plane (planes hold < 2^30
+    // pixels), so each load is one scalar base plus a vector offset.
     {
-        // lanes 0 and 1 also fetch the left and right halo columns
-        const int hx = (lane == 0) ? max(x0 - 1, 0) : min(x0 + g.bw, g.w - 1);
-        const int hcol = (lane == 0) ? 0 : g.bw + 1;
-#pragma unroll 8
-        for (int t = -1; t <= nrows; ++t) {
-            const int yy = min(max(y0 + t, 0), g.h - 1);
-            const int64_t row = (int64_t)yy * W;
-            if (on) lds[(t + 1) * kTileW + lane + 1] = U[row + x];
-            if (lane < 2) lds[(t + 1) * kTileW + hcol] = U[row + hx];
-            if (on && t >= 0 && t < nrows && mask[row + x] == 0) {
-                if (t < 32) mlo |= 1u << t; else mhi |= 1u << (t - 32);
-            }
+        const uint32_t xc = on ? x : x0;
+        float col[RPW + 2];
+#pragma unroll
+        for (int t = 0; t < RPW + 2; ++t) {
+            const uint32_t yy = min(max(y0 + t - 1, 0), g.h - 1);
+            col[t] = U[yy * (uint32_t)g.w + xc];
         }
+        // halo columns: lane l fetches row l - 1 (and rows 63, 64 in a
+        // second pass for lanes 0, 1)
+        const uint32_t xl = max(x0 - 1, 0), xr = min(x0 + g.bw, g.w - 1);
+        const int t1 = lane, t2 = 64 + lane;
+        const uint32_t r1 = (uint32_t)min(max(y0 + t1 - 1, 0), g.h - 1) * (uint32_t)g.w;
+        const float hl1 = U[r1 + xl], hr1 = U[r1 + xr];
+        float hl2 = 0.f, hr2 = 0.f;
+        if (t2 < RPW + 2) {
+            const uint32_t r2 = (uint32_t)min(max(y0 + t2 - 1, 0), g.h - 1) * (uint32_t)g.w;
+            hl2 = U[r2 + xl];
+            hr2 = U[r2 + xr];
+        }
+        if (on) {
+#pragma unroll
+            for (int t = 0; t < RPW + 2; ++t) lds[t * kTileW + lane + 1] = col[t];
+        }
+        if (t1 < RPW + 2) {
+            lds[t1 * kTileW] = hl1;
+            lds[t1 * kTileW + g.bw + 1] = hr1;
+        }
+        if (t2 < RPW + 2) {
+            lds[t2 * kTileW] = hl2;
+            lds[t2 * kTileW + g.bw + 1] = hr2;
+        }
+    }
+    // unknown-pixel bits of this column: bit y <-> row y0 + y
+    uint32_t mlo = 0u, mhi = 0u;
+    if (on) {
+        const int gy = y0 >> 6, sh = y0 & 63;
+        const uint64_t* mb = mbits + (uint32_t)gy * (uint32_t)g.w + (uint32_t)x;
+        uint64_t bits = mb[0] >> sh;
+        if (sh) bits |= mb[g.w] << (64 - sh);
+        if (nrows < 64) bits &= (1ull << nrows) - 1ull;
+        mlo = (uint32_t)bits;
+        mhi = (uint32_t)(bits >> 32);
     }
     __syncthreads();
 
@@ -198,21 +245,26 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
     const float dtop = dmid - 1.f + (has_top ? al : 0.f);
     const float dbot = dmid - 1.f + (has_bot ? al : 0.f);
 
-    float v[RPW], p[RPW];
+    // w = u_in + v: the correction is accumulated straight into the block's
+    // own values, so the write-back needs no second read of u_in
+    float w[RPW], p[RPW];
     float rho_l0 = 0.f, rho_l1 = 0.f;
 #pragma unroll
     for (int y = 0; y < RPW; ++y) {
-        v[y] = 0.f;
+        w[y] = lds[(y + 1) * kTileW + lane + 1];
         p[y] = r[y];
         if (y & 1) rho_l1 += r[y] * r[y]; else rho_l0 += r[y] * r[y];
     }
     float rho = wave_sum(rho_l0 + rho_l1);
+    // optional absolute stop: mean square local residual below local_tol^2
+    const float rho_stop = a.local_tol2 * (float)(g.bh * g.bw);
 
     __syncthreads();  // the staged tile is dead; its LDS now holds q
     float4* qs = reinterpret_cast<float4*>(lds);
     float qreg[QLDS ? 1 : RPW];
-    for (int it = 0; it < a.k; ++it) {
-        if (!(rho > 0.f)) break;
+    int it = 0;
+    for (; it < a.k; ++it) {
+        if (!(rho > rho_stop)) break;
         // q = A_loc p, pq = p . q
         float pq0 = 0.f, pq1 = 0.f;
         float q4[4];
@@ -244,7 +296,10 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
             }
         }
         const float pq = wave_sum(pq0 + pq1);
-        if (!(pq > 0.f)) break;
+        if (!(pq > 0.f)) {
+            ++it;  // the matvec of this step was done
+            break;
+        }
         const float alpha = rho / pq;
         float rr0 = 0.f, rr1 = 0.f;
         float4 qn;
@@ -262,7 +317,7 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
             } else {
                 q = qreg[y];
             }
-            v[y] += alpha * p[y];
+            w[y] += alpha * p[y];
             r[y] -= alpha * q;
             if (y & 1) rr1 += r[y] * r[y]; else rr0 += r[y] * r[y];
             if constexpr (QLDS) {
@@ -276,18 +331,50 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
         for (int y = 0; y < RPW; ++y) p[y] = r[y] + beta * p[y];
     }
 
+    // executed CG steps, accumulated in this block's own slot (one wave per
+    // block and launch, launches in stream order: no race)
+    if (cg_steps && lane == 0) cg_steps[(int64_t)b * a.channels + ch] += (double)it;
+
     // ---- restricted prolongation: u_out = u_in + v on owned pixels (eq. 9)
     if (on && x >= oxlo && x < oxhi) {
         float* __restrict__ UO = uout + ch * a.cpitch;
 #pragma unroll
         for (int y = 0; y < RPW; ++y) {
             const int yy = y0 + y;
-            if ((!RAGGED || y < nrows) && yy >= oylo && yy < oyhi) {
-                const int64_t idx = (int64_t)yy * W + x;
-                UO[idx] = U[idx] + v[y];
-            }
+            if ((!RAGGED || y < nrows) && yy >= oylo && yy < oyhi)
+                UO[(uint32_t)yy * (uint32_t)g.w + (uint32_t)x] = w[y];
         }
     }
+}
+
+// Zero fill (a kernel rather than hipMemsetAsync, so that the solve can be
+// captured into a graph).
+__global__ void k_clear(double* __restrict__ p, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// Column-transposed unknown-pixel bits of a mask: word (g, x) holds bit j
+// = 1 iff pixel (64 g + j, x) is unknown (0 beyond the image). One extra
+// all-zero group row follows the last one.
+__global__ __launch_bounds__(256) void k_mask_bits(const uint8_t* __restrict__ c, int h, int w,
+                                                   int groups, uint64_t* __restrict__ mbits) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int gy = blockIdx.y;
+    if (x >= w) return;
+    uint64_t bits = 0;
+    if (gy < groups - 1) {
+        uint8_t m[64];
+#pragma unroll
+        for (int j = 0; j < 64; ++j) {
+            const int y = min(gy * 64 + j, h - 1);
+            m[j] = c[(int64_t)y * w + x];
+        }
+#pragma unroll
+        for (int j = 0; j < 64; ++j)
+            if (gy * 64 + j < h && m[j] == 0) bits |= 1ull << j;
+    }
+    mbits[(int64_t)gy * w + x] = bits;
 }
 
 // ---------------------------------------------------------------------------
@@ -296,23 +383,25 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
 
 constexpr int kTpb = 256;
 
-// Fixed-order block reduction of NV doubles per thread into out[0..NV).
+// Fixed-order block reduction of NV doubles per thread into out[0..NV):
+// wave sums, then thread 0 adds the kTpb / 64 wave results in order.
 template <int NV>
 __device__ void block_reduce(double (&val)[NV], double* out) {
-    __shared__ double sm[kTpb];
+    __shared__ double sm[kTpb / 64][NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        sm[threadIdx.x] = val[j];
-        __syncthreads();
-        for (int s = kTpb / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[j] = sm[0];
-        __syncthreads();
+    for (int j = 0; j < NV; ++j) val[j] = wave_sum_d(val[j]);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) sm[threadIdx.x >> 6][j] = val[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < kTpb / 64; ++i) s += sm[i][threadIdx.x];
+        out[threadIdx.x] = s;
     }
 }
-
 
 template <int NC>
 __global__ __launch_bounds__(kTpb) void k_coarsen(const float* __restrict__ f,
@@ -393,81 +482,100 @@ __global__ __launch_bounds__(kTpb) void k_init(const float* __restrict__ f,
     for (int k = 0; k < channels; ++k) u[k * n + i] = known ? f[k * n + i] : 0.f;
 }
 
+// One thread per coarse cell (I, J) writes the fine pixels 2I + a, 2J + b.
+// Fine pixel y = 2I sits at coarse coordinate I - 1/4 and y = 2I + 1 at
+// I + 1/4 (clamped to the coarse grid), so each output mixes the cell with
+// its neighbour on that side with weights 3/4 and 1/4 per axis.
 __global__ __launch_bounds__(kTpb) void k_prolong(const float* __restrict__ uc, int hc, int wc,
                                                   const float* __restrict__ f,
                                                   const uint8_t* __restrict__ c, int h, int w,
                                                   int channels, float* __restrict__ u) {
-    const int64_t n = (int64_t)h * w;
-    const int64_t i = (int64_t)blockIdx.x * kTpb + threadIdx.x;
-    if (i >= n) return;
-    const int y = (int)(i / w), x = (int)(i - (int64_t)y * w);
-    if (c[i] != 0) {
-        for (int k = 0; k < channels; ++k) u[k * n + i] = f[k * n + i];
-        return;
-    }
-    // fine pixel centre in coarse coordinates: y/2 - 1/4, clamped
-    double ty = fmin(fmax(0.5 * y - 0.25, 0.0), (double)(hc - 1));
-    double tx = fmin(fmax(0.5 * x - 0.25, 0.0), (double)(wc - 1));
-    const int i0 = (int)ty, j0 = (int)tx;
-    const int i1 = min(i0 + 1, hc - 1), j1 = min(j0 + 1, wc - 1);
-    const double ay = ty - i0, ax = tx - j0;
-    const int64_t nc = (int64_t)hc * wc;
+    const int J = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int I = blockIdx.y * (kTpb / 64) + (threadIdx.x >> 6);
+    if (I >= hc || J >= wc) return;
+    const int64_t n = (int64_t)h * w, nc = (int64_t)hc * wc;
+    const int Im = max(I - 1, 0), Ip = min(I + 1, hc - 1);
+    const int Jm = max(J - 1, 0), Jp = min(J + 1, wc - 1);
     for (int k = 0; k < channels; ++k) {
         const float* C = uc + k * nc;
-        const double u00 = C[(int64_t)i0 * wc + j0], u01 = C[(int64_t)i0 * wc + j1];
-        const double u10 = C[(int64_t)i1 * wc + j0], u11 = C[(int64_t)i1 * wc + j1];
-        const double v = (1.0 - ay) * ((1.0 - ax) * u00 + ax * u01) +
-                         ay * ((1.0 - ax) * u10 + ax * u11);
-        u[k * n + i] = (float)v;
+        double q[3][3];
+        const int rr[3] = {Im, I, Ip}, cc[3] = {Jm, J, Jp};
+#pragma unroll
+        for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+            for (int b2 = 0; b2 < 3; ++b2) q[a2][b2] = C[(int64_t)rr[a2] * wc + cc[b2]];
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2) {
+            const int y = 2 * I + a2;
+            if (y >= h) break;
+            // coarse rows used by fine row y and the weight of the second
+            const int r0 = (a2 == 0) ? 0 : 1, r1 = (a2 == 0) ? 1 : 2;
+            const bool ey = (a2 == 0) ? (I > 0) : (I + 1 < hc);
+            const double ay = ey ? ((a2 == 0) ? 0.75 : 0.25) : 0.0;
+#pragma unroll
+            for (int b2 = 0; b2 < 2; ++b2) {
+                const int x = 2 * J + b2;
+                if (x >= w) break;
+                const int c0 = (b2 == 0) ? 0 : 1, c1 = (b2 == 0) ? 1 : 2;
+                const bool ex = (b2 == 0) ? (J > 0) : (J + 1 < wc);
+                const double ax = ex ? ((b2 == 0) ? 0.75 : 0.25) : 0.0;
+                const int64_t i = (int64_t)y * w + x;
+                float out;
+                if (c[i] != 0) {
+                    out = f[k * n + i];
+                } else {
+                    const double v = (1.0 - ay) * ((1.0 - ax) * q[r0][c0] + ax * q[r0][c1]) +
+                                     ay * ((1.0 - ax) * q[r1][c0] + ax * q[r1][c1]);
+                    out = (float)v;
+                }
+                u[k * n + i] = out;
+            }
+        }
     }
 }
 
-// Residual r = b - A u: one wave walks 64 columns down kResRows rows,
-// keeping the rows above and below in registers; workgroups are single
-// waves so that blockIdx maps to (column strip, row strip, channel).
-constexpr int kResRows = 32;
+// Residual r = b - A u: one thread per pixel of a 64 x kResRows tile (the
+// vertical neighbours of a row are the rows the neighbouring waves of the
+// tile load, so they come from cache). Offsets are 32-bit indices into one
+// channel plane.
+constexpr int kResRows = 4;
 
-__global__ __launch_bounds__(64) void k_residual(const float* __restrict__ f,
-                                                 const uint8_t* __restrict__ c,
-                                                 const float* __restrict__ u, int h, int w,
-                                                 int channels, float* __restrict__ r,
-                                                 float* __restrict__ ucopy,
-                                                 double* __restrict__ partial) {
-    const int lane = threadIdx.x;
-    const int x0 = blockIdx.x * 64;
-    const int y0 = blockIdx.y * kResRows;
+__global__ __launch_bounds__(64 * kResRows) void k_residual(
+    const float* __restrict__ f, const uint8_t* __restrict__ c, const float* __restrict__ u,
+    int h, int w, int channels, float* __restrict__ r, float* __restrict__ ucopy,
+    double* __restrict__ partial) {
+    const int lane = threadIdx.x & 63;
+    const int x = blockIdx.x * 64 + lane;
+    const int y = blockIdx.y * kResRows + (threadIdx.x >> 6);
     const int ch = blockIdx.z;
     const int64_t n = (int64_t)h * w;
-    const float* U = u + ch * n;
-    const float* F = f + ch * n;
-    const int x = x0 + lane;
-    const bool on = x < w;
-    const int bw = min(64, w - x0);
-    const int y1 = min(y0 + kResRows, h);
+    const float* __restrict__ U = u + ch * n;
     double acc = 0.0;
-    float ucur = on ? U[(int64_t)y0 * w + x] : 0.f;
-    float uup = (on && y0 > 0) ? U[(int64_t)(y0 - 1) * w + x] : ucur;
-    for (int y = y0; y < y1; ++y) {
-        const int64_t row = (int64_t)y * w;
-        const float udn = (on && y + 1 < h) ? U[row + w + x] : ucur;
-        float ul = from_left(ucur);
-        float ur = from_right(ucur);
-        if (lane == 0) ul = x0 > 0 ? U[row + x0 - 1] : ucur;
-        if (lane == bw - 1) ur = (x0 + bw < w) ? U[row + x0 + bw] : ucur;
-        if (on) {
-            const bool known = c[row + x] != 0;
-            const float ry = known ? F[row + x] - ucur
-                                   : ((uup - ucur) + (udn - ucur)) + ((ul - ucur) + (ur - ucur));
-            acc += (double)ry * (double)ry;
-            if (r) r[ch * n + row + x] = ry;
-            if (ucopy) ucopy[ch * n + row + x] = ucur;
-        }
-        uup = ucur;
-        ucur = udn;
+    if (x < w && y < h) {
+        const uint32_t W = w;
+        const uint32_t i = (uint32_t)y * W + x;
+        const float uc = U[i];
+        const float uu = y > 0 ? U[i - W] : uc;
+        const float ud = y + 1 < h ? U[i + W] : uc;
+        const float ul = x > 0 ? U[i - 1] : uc;
+        const float ur = x + 1 < w ? U[i + 1] : uc;
+        const bool known = c[i] != 0;
+        const float fv = known ? f[ch * n + i] : 0.f;
+        const float ry = known ? fv - uc : ((uu - uc) + (ud - uc)) + ((ul - uc) + (ur - uc));
+        acc = (double)ry * (double)ry;
+        if (r) r[ch * n + i] = ry;
+        if (ucopy) ucopy[ch * n + i] = uc;
     }
     acc = wave_sum_d(acc);
-    if (lane == 0)
-        partial[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * channels + ch] = acc;
+    __shared__ double sm[kResRows];
+    if (lane == 0) sm[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < kResRows; ++j) s += sm[j];
+        partial[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * channels + ch] = s;
+    }
 }
 
 __global__ __launch_bounds__(kTpb) void k_reduce(const double* __restrict__ partial, int nrows,
@@ -485,26 +593,40 @@ __global__ __launch_bounds__(kTpb) void k_reduce(const double* __restrict__ part
 // ---------------------------------------------------------------------------
 
 template <int RPW, bool QLDS, bool MBITS>
-static hipError_t sweep_rpw(const float* uin, const uint8_t* mask, float* uout,
-                            double* partial, const SweepArgs& a, hipStream_t s) {
+static hipError_t sweep_rpw(const float* uin, const uint64_t* mbits, float* uout,
+                            double* partial, double* cg_steps, const SweepArgs& a,
+                            hipStream_t s) {
     const int grid = a.g.nby * a.g.nbx * a.channels;
     if (a.g.bh == RPW)
         hipLaunchKernelGGL((k_sweep<RPW, false, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
-                           uin, mask, uout, partial, a);
+                           uin, mbits, uout, partial, cg_steps, a);
     else
         hipLaunchKernelGGL((k_sweep<RPW, true, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
-                           uin, mask, uout, partial, a);
+                           uin, mbits, uout, partial, cg_steps, a);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const float* uin, const uint8_t* mask, float* uout,
-                        double* partial, const SweepArgs& a, hipStream_t s) {
+hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
+                        double* partial, double* cg_steps, const SweepArgs& a,
+                        hipStream_t s) {
     const int bh = a.g.bh;
     if (a.g.bw < 1 || a.g.bw > kMaxBlock || bh < 1 || bh > kMaxBlock) return hipErrorInvalidValue;
-    if (bh > 32) return sweep_rpw<64, true, true>(uin, mask, uout, partial, a, s);
-    if (bh > 16) return sweep_rpw<32, false, false>(uin, mask, uout, partial, a, s);
-    if (bh > 8) return sweep_rpw<16, false, false>(uin, mask, uout, partial, a, s);
-    return sweep_rpw<8, false, false>(uin, mask, uout, partial, a, s);
+    if (bh > 32) return sweep_rpw<64, true, true>(uin, mbits, uout, partial, cg_steps, a, s);
+    if (bh > 16) return sweep_rpw<32, false, false>(uin, mbits, uout, partial, cg_steps, a, s);
+    if (bh > 8) return sweep_rpw<16, false, false>(uin, mbits, uout, partial, cg_steps, a, s);
+    return sweep_rpw<8, false, false>(uin, mbits, uout, partial, cg_steps, a, s);
+}
+
+hipError_t launch_clear(double* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_bits(const uint8_t* c, int h, int w, uint64_t* mbits, hipStream_t s) {
+    const int groups = mask_bit_groups(h);
+    hipLaunchKernelGGL(k_mask_bits, dim3((w + 255) / 256, groups), dim3(256), 0, s, c, h, w,
+                       groups, mbits);
+    return hipGetLastError();
 }
 
 static int grid1d(int64_t n) { return (int)((n + kTpb - 1) / kTpb); }
@@ -554,10 +676,13 @@ hipError_t launch_init(const float* f, const uint8_t* c, int h, int w, int chann
 
 hipError_t launch_prolong(const float* uc, int hc, int wc, const float* f, const uint8_t* c,
                           int h, int w, int channels, float* u, hipStream_t s) {
-    const int64_t n = (int64_t)h * w;
-    hipLaunchKernelGGL(k_prolong, dim3(grid1d(n)), dim3(kTpb), 0, s, uc, hc, wc, f, c, h, w,
-                       channels, u);
+    dim3 grid((wc + 63) / 64, (hc + kTpb / 64 - 1) / (kTpb / 64));
+    hipLaunchKernelGGL(k_prolong, grid, dim3(kTpb), 0, s, uc, hc, wc, f, c, h, w, channels, u);
     return hipGetLastError();
+}
+
+int residual_partials(int h, int w) {
+    return ((w + 63) / 64) * ((h + kResRows - 1) / kResRows);
 }
 
 hipError_t launch_residual(const float* f, const uint8_t* c, const float* u, int h, int w,
@@ -565,8 +690,8 @@ hipError_t launch_residual(const float* f, const uint8_t* c, const float* u, int
                            hipStream_t s) {
     dim3 grid((w + 63) / 64, (h + kResRows - 1) / kResRows, channels);
     if (nwg) *nwg = (int)(grid.x * grid.y);
-    hipLaunchKernelGGL(k_residual, grid, dim3(64), 0, s, f, c, u, h, w, channels, r, ucopy,
-                       partial);
+    hipLaunchKernelGGL(k_residual, grid, dim3(64 * kResRows), 0, s, f, c, u, h, w, channels, r,
+                       ucopy, partial);
     return hipGetLastError();
 }
 

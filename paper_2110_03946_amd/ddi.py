@@ -36,7 +36,9 @@ class Params(ctypes.Structure):
                 ("coarsest_sweeps", ctypes.c_int), ("rel_tol", ctypes.c_double),
                 ("min_sweeps", ctypes.c_int), ("max_sweeps", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("final_residual", ctypes.c_int),
-                ("timing", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("coarse_block", ctypes.c_int),
+                ("coarse_overlap", ctypes.c_int), ("coarse_local_iters", ctypes.c_int),
+                ("local_tol", ctypes.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -45,7 +47,7 @@ class Params(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int), ("converged", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("ms", ctypes.c_double),
-                ("sweep_ms", ctypes.c_double)]
+                ("sweep_ms", ctypes.c_double), ("cg_steps", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
