@@ -103,6 +103,8 @@ struct ddi_plan {
     double* red = nullptr;   // [C + 2] stats, [C] norms, [C] CG step totals
     double* host = nullptr;  // pinned mirror of red
     double* cgcnt = nullptr; // timing: CG steps per finest-level block
+    int* ctl = nullptr;      // device stop test: done, sweeps, error, -, rel (double)
+    void* hctl = nullptr;    // pinned mirror of ctl
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<hipEvent_t> sweep_ev;  // 2 per finest-level sweep (timing)
     int last_sweeps = -1;              // finest-level sweeps of the previous solve
@@ -167,6 +169,8 @@ int ddi_destroy(ddi_plan* plan) {
     if (plan->part) (void)hipFree(plan->part);
     if (plan->red) (void)hipFree(plan->red);
     if (plan->cgcnt) (void)hipFree(plan->cgcnt);
+    if (plan->ctl) (void)hipFree(plan->ctl);
+    if (plan->hctl) (void)hipHostFree(plan->hctl);
     if (plan->host) (void)hipHostFree(plan->host);
     if (plan->e0) (void)hipEventDestroy(plan->e0);
     if (plan->e1) (void)hipEventDestroy(plan->e1);
@@ -266,6 +270,8 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
     if ((err = hipMalloc(&P->red, nred * sizeof(double))) != hipSuccess ||
         (err = hipHostMalloc(&P->host, nred * sizeof(double), hipHostMallocDefault)) !=
             hipSuccess ||
+        (err = hipMalloc(&P->ctl, 64)) != hipSuccess ||
+        (err = hipHostMalloc(&P->hctl, 64, hipHostMallocDefault)) != hipSuccess ||
         (err = hipEventCreate(&P->e0)) != hipSuccess ||
         (err = hipEventCreate(&P->e1)) != hipSuccess) {
         ddi_destroy(P);
@@ -339,7 +345,18 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
         Level& b = P->lv[l + 1];
         DDI_HIP(launch_coarsen(a.f, a.c, a.h, a.w, C, b.fown, b.cown, nullptr, nullptr, P->s));
     }
-    for (Level& lev : P->lv) DDI_HIP(launch_mask_bits(lev.c, lev.h, lev.w, lev.mbits, P->s));
+    {
+        const uint8_t* cs[kMaxLevels];
+        uint64_t* mbs[kMaxLevels];
+        int hs[kMaxLevels], ws[kMaxLevels];
+        for (int l = 0; l < L; ++l) {
+            cs[l] = P->lv[l].c;
+            mbs[l] = P->lv[l].mbits;
+            hs[l] = P->lv[l].h;
+            ws[l] = P->lv[l].w;
+        }
+        DDI_HIP(launch_mask_bits_levels(L, cs, hs, ws, mbs, P->s));
+    }
 
     // ---- coarsest level, then coarse-to-fine ----
     // The finest level ping-pongs between u (index 0) and the plan's buffer
@@ -356,7 +373,8 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
         Level& lev = P->lv[l];
         const int n = (l == top) ? prm.coarsest_sweeps : prm.coarse_sweeps;
         for (int i = 0; i < n; ++i) {
-            DDI_HIP(launch_sweep(lev.u[cur], lev.mbits, lev.u[1 - cur], P->part, nullptr, lev.sw,
+            DDI_HIP(launch_sweep(lev.u[cur], lev.mbits, lev.u[1 - cur], P->part, nullptr, nullptr,
+                                 lev.sw,
                                  P->s));
             cur ^= 1;
         }
@@ -367,10 +385,14 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
         cur = dst;
     }
 
-    // ---- finest level with the stop test ----
+    // ---- finest level: sweeps with the stop test on the device ----
+    // Sweeps are enqueued ahead in batches; after each sweep where the stop
+    // test applies, k_decide runs it on the device, and once it passes the
+    // sweeps still enqueued exit at once. The host waits once per batch;
+    // the first batch is as long as the previous solve needed, so a solve
+    // like the previous one needs a single wait.
     bool validated = false, converged = false;
     double rel = INFINITY;
-    int sweeps = 0;
     auto validate = [&]() -> int {
         validated = true;
         if (P->host[C + 1] > 0.0) return DDI_EINVAL;
@@ -381,23 +403,48 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
     const bool timing = !P->sweep_ev.empty();
     double* steps = P->cgcnt;
     if (steps) DDI_HIP(launch_clear(steps, nb * C, P->s));
-    while (sweeps < prm.max_sweeps) {
-        if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * sweeps], P->s));
-        DDI_HIP(launch_sweep(L0.u[cur], L0.mbits, L0.u[1 - cur], P->part, steps, L0.sw, P->s));
-        if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * sweeps + 1], P->s));
-        cur ^= 1;
-        ++sweeps;
-        if (sweeps >= prm.min_sweeps && (sweeps - prm.min_sweeps) % prm.check_every == 0) {
-            int e = reduce_and_read(P, nb, C + 2, 2 * C + 2);
-            if (e) return e;
-            if (!validated && (e = validate())) return e;
-            rel = rel_from_host(P, P->host + C + 2);  // residual of the sweep's input
-            if (rel <= prm.rel_tol) {
-                converged = true;
-                break;
-            }
+    int* ctl = P->ctl;
+    double* drel = reinterpret_cast<double*>(ctl + 4);
+    DDI_HIP(launch_clear_int(ctl, 4, P->s));
+    const int start_cur = cur;
+    int enq = 0, sweeps = 0;
+    int batch = std::min(prm.max_sweeps, std::max(expect, prm.min_sweeps));
+    auto is_check = [&](int n) {
+        return n >= prm.min_sweeps && (n - prm.min_sweeps) % prm.check_every == 0;
+    };
+    while (enq < prm.max_sweeps) {
+        // a batch always ends with a stop test
+        int upto = std::min(prm.max_sweeps, std::max(enq + 1, batch));
+        while (upto < prm.max_sweeps && !is_check(upto)) ++upto;
+        for (; enq < upto; ++enq) {
+            const int c0 = start_cur ^ (enq & 1);
+            if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * enq], P->s));
+            DDI_HIP(launch_sweep(L0.u[c0], L0.mbits, L0.u[c0 ^ 1], P->part, steps, ctl, L0.sw,
+                                 P->s));
+            if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * enq + 1], P->s));
+            if (is_check(enq + 1) || enq + 1 == prm.max_sweeps)
+                DDI_HIP(launch_decide(P->part, nb, C, P->red, ctl, drel,
+                                      is_check(enq + 1) ? prm.rel_tol : -1.0, enq + 1, P->s));
         }
+        DDI_HIP(hipMemcpyAsync(P->hctl, ctl, 4 * sizeof(int) + sizeof(double),
+                               hipMemcpyDeviceToHost, P->s));
+        DDI_HIP(hipStreamSynchronize(P->s));
+        const int* hc = reinterpret_cast<const int*>(P->hctl);
+        validated = true;
+        if (hc[2] == 1) return DDI_EINVAL;
+        if (hc[2] == 2) return DDI_ESINGULAR;
+        double rel2;
+        std::memcpy(&rel2, hc + 4, sizeof(rel2));
+        rel = std::sqrt(rel2);
+        if (hc[0] != 0) {
+            sweeps = hc[1];
+            converged = true;
+            break;
+        }
+        sweeps = enq;
+        batch = enq + 2;
     }
+    cur = start_cur ^ (sweeps & 1);
 
     P->last_sweeps = sweeps;
 
@@ -541,7 +588,8 @@ int ddi_oras_sweep(const float* u_in, const uint8_t* c, float* u_out, int height
     DDI_HIP(hipMalloc(&red.p, channels * sizeof(double)));
     DDI_HIP(hipMalloc(&mb.p, (size_t)mask_bit_groups(height) * width * sizeof(uint64_t)));
     DDI_HIP(launch_mask_bits(c, height, width, (uint64_t*)mb.p, s));
-    DDI_HIP(launch_sweep(u_in, (const uint64_t*)mb.p, u_out, (double*)part.p, nullptr, a, s));
+    DDI_HIP(launch_sweep(u_in, (const uint64_t*)mb.p, u_out, (double*)part.p, nullptr, nullptr, a,
+                         s));
     DDI_HIP(launch_reduce((double*)part.p, nb, channels, channels, (double*)red.p, s));
     if (rsq) {
         DDI_HIP(hipMemcpyAsync(rsq, red.p, channels * sizeof(double), hipMemcpyDeviceToHost, s));

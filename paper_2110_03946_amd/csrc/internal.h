@@ -68,15 +68,33 @@ constexpr int kMaxBlock = 64;
 // One ORAS sweep u_in -> u_out. `mbits` is the column-transposed mask of
 // launch_mask_bits for the same level. When cg_steps is non-null, block b
 // of channel ch adds the number of CG steps it ran to cg_steps[b * C + ch].
+// When ctl is non-null and ctl[0] != 0 the sweep does nothing.
 hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
-                        double* partial, double* cg_steps, const SweepArgs& a,
+                        double* partial, double* cg_steps, const int* ctl, const SweepArgs& a,
                         hipStream_t s);
 
+// Device stop test after finest-level sweep n (see k_decide): reduces the
+// sweep's partials, stores max_k ||r_k||^2/||b_k||^2 in rel[0] and, when
+// the test passes or the input statistics are invalid (ctl[2] = 1 bad mask
+// byte, 2 empty mask), sets ctl[0] and records n in ctl[1].
+hipError_t launch_decide(const double* partial, int nb, int channels, const double* stats,
+                         int* ctl, double* rel, double tol, int n, hipStream_t s);
+
+// p[0..n) = 0 for ints.
+hipError_t launch_clear_int(int* p, int n, hipStream_t s);
+
 // Row groups of the transposed mask: ceil(h / 64) plus one zero group.
-inline int mask_bit_groups(int h) { return (h + 63) / 64 + 1; }
+__host__ __device__ inline int mask_bit_groups(int h) { return (h + 63) / 64 + 1; }
 
 // mbits[g * w + x], bit j = pixel (64 g + j, x) is unknown.
 hipError_t launch_mask_bits(const uint8_t* c, int h, int w, uint64_t* mbits, hipStream_t s);
+
+// Largest number of levels a plan holds.
+constexpr int kMaxLevels = 16;
+
+// The transposed masks of n levels in one launch.
+hipError_t launch_mask_bits_levels(int n, const uint8_t* const* c, const int* h, const int* w,
+                                   uint64_t* const* mbits, hipStream_t s);
 
 // p[0..n) = 0.
 hipError_t launch_clear(double* p, int n, hipStream_t s);

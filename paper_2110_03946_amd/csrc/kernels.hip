@@ -73,6 +73,14 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     return j * q + min(j, rem) + i;
 }
 
+// q where bit `bit` of `bits` is set, +0 elsewhere: a sign-extended bit
+// field (v_bfe_i32) ANDed with q. Branch-free, and opaque enough that the
+// compiler does not turn it into per-row lane masks held in scalar registers.
+__device__ __forceinline__ float mask_keep(uint32_t bits, int bit, float q) {
+    const int sel = __builtin_amdgcn_sbfe((int)bits, bit, 1);
+    return __int_as_float(__float_as_int(q) & sel);
+}
+
 // Mask of one block column, built from the bits of the unknown pixels.
 // Float storage (1 = unknown) for short columns; the bits themselves for
 // 64-row columns, where registers are scarce.
@@ -88,6 +96,7 @@ struct ColMask<RPW, false> {
             m[y] = (((y < 32 ? lo : hi) >> (y & 31)) & 1u) ? 1.f : 0.f;
     }
     __device__ __forceinline__ float apply(int y, float q) const { return q * m[y]; }
+    __device__ __forceinline__ void refresh() {}
 };
 
 template <int RPW>
@@ -95,10 +104,11 @@ struct ColMask<RPW, true> {
     uint32_t b[2];
     __device__ __forceinline__ void load(uint32_t lo, uint32_t hi) { b[0] = lo; b[1] = hi; }
     __device__ __forceinline__ float apply(int y, float q) const {
-        // all-ones where the pixel is unknown, zero elsewhere
-        const int sel = (int)(b[y >> 5] << (31 - (y & 31))) >> 31;
-        return __int_as_float(__float_as_int(q) & sel);
+        return mask_keep(b[y >> 5], y & 31, q);
     }
+    // Re-define the words once per CG step so that the 64 per-row bit
+    // extracts stay inside the loop instead of occupying 64 registers.
+    __device__ __forceinline__ void refresh() { asm volatile("" : "+v"(b[0]), "+v"(b[1])); }
 };
 
 // ---------------------------------------------------------------------------
@@ -130,8 +140,13 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
                                               float* __restrict__ uout,
                                               double* __restrict__ partial,
                                               double* __restrict__ cg_steps,
-                                              SweepArgs a) {
-    __shared__ __attribute__((aligned(16))) float lds[(RPW + 2) * kTileW];
+                                              const int* __restrict__ ctl, SweepArgs a) {
+    constexpr int TW = kTileW;  // floats per tile row in LDS
+    constexpr int CO = 1;       // tile column of block column 0
+    __shared__ __attribute__((aligned(16))) float lds[(RPW + 2) * TW];
+    // a solve that has already met its stop test skips the sweeps it had
+    // enqueued ahead (ctl[0] is set by k_decide)
+    if (ctl && ctl[0] != 0) return;
 
     const int lane = threadIdx.x;
     const BlockGrid g = a.g;
@@ -164,11 +179,25 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
     // pixels), so each load is one scalar base plus a vector offset.
     {
         const uint32_t xc = on ? x : x0;
+        const uint32_t Wd = g.w;
         float col[RPW + 2];
+        if constexpr (!RAGGED) {
+            // rows y0 .. y0+RPW-1 lie in the image; only the two halo rows
+            // can fall outside it (then they copy the border row)
+            uint32_t off = (uint32_t)y0 * Wd + xc;
+            col[0] = U[has_top ? off - Wd : off];
 #pragma unroll
-        for (int t = 0; t < RPW + 2; ++t) {
-            const uint32_t yy = min(max(y0 + t - 1, 0), g.h - 1);
-            col[t] = U[yy * (uint32_t)g.w + xc];
+            for (int t = 1; t <= RPW; ++t) {
+                col[t] = U[off];
+                if (t < RPW) off += Wd;
+            }
+            col[RPW + 1] = U[has_bot ? off + Wd : off];
+        } else {
+#pragma unroll
+            for (int t = 0; t < RPW + 2; ++t) {
+                const uint32_t yy = min(max(y0 + t - 1, 0), g.h - 1);
+                col[t] = U[yy * Wd + xc];
+            }
         }
         // halo columns: lane l fetches row l - 1 (and rows 63, 64 in a
         // second pass for lanes 0, 1)
@@ -184,15 +213,15 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
         }
         if (on) {
 #pragma unroll
-            for (int t = 0; t < RPW + 2; ++t) lds[t * kTileW + lane + 1] = col[t];
+            for (int t = 0; t < RPW + 2; ++t) lds[t * TW + lane + CO] = col[t];
         }
         if (t1 < RPW + 2) {
-            lds[t1 * kTileW] = hl1;
-            lds[t1 * kTileW + g.bw + 1] = hr1;
+            lds[t1 * TW + CO - 1] = hl1;
+            lds[t1 * TW + CO + g.bw] = hr1;
         }
         if (t2 < RPW + 2) {
-            lds[t2 * kTileW] = hl2;
-            lds[t2 * kTileW + g.bw + 1] = hr2;
+            lds[t2 * TW + CO - 1] = hl2;
+            lds[t2 * TW + CO + g.bw] = hr2;
         }
     }
     // unknown-pixel bits of this column: bit y <-> row y0 + y
@@ -202,37 +231,45 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
         const uint64_t* mb = mbits + (uint32_t)gy * (uint32_t)g.w + (uint32_t)x;
         uint64_t bits = mb[0] >> sh;
         if (sh) bits |= mb[g.w] << (64 - sh);
-        if (nrows < 64) bits &= (1ull << nrows) - 1ull;
+        if (nrows < 64) bits &= (1ull << (nrows & 63)) - 1ull;
         mlo = (uint32_t)bits;
         mhi = (uint32_t)(bits >> 32);
     }
     __syncthreads();
 
     // ---- residual of u_in on the block (eq. 7) and its owned norm ----
-    float r[RPW];
-    double rsq = 0.0;
+    // One pass over the rows also fills w = u_in (the iterate the local
+    // correction is added to) and rho = r.r. The owned-pixel norm is summed
+    // per lane over the block's rows in float32 (<= 64 terms) and in float64
+    // from there on (across lanes and blocks).
+    float r[RPW], w[RPW];
+    float rho_l0 = 0.f, rho_l1 = 0.f, own_l = 0.f;
     {
         const int ylo = oylo - y0, yhi = oyhi - y0;
-        const bool own_col = on && x >= oxlo && x < oxhi;
-        const float* col = lds + lane + 1;
+        const float* col = lds + lane + CO;
         float uup = col[0];
-        float uy = col[kTileW];
+        float uy = col[TW];
 #pragma unroll
         for (int y = 0; y < RPW; ++y) {
-            const float udn = col[(y + 2) * kTileW];
-            const float ul = col[(y + 1) * kTileW - 1];
-            const float ur = col[(y + 1) * kTileW + 1];
-            const bool unk = ((y < 32 ? mlo : mhi) >> (y & 31)) & 1u;
-            const float ry =
-                unk ? ((uup - uy) + (udn - uy)) + ((ul - uy) + (ur - uy)) : 0.f;
+            const float udn = col[(y + 2) * TW];
+            const float ul = col[(y + 1) * TW - 1];
+            const float ur = col[(y + 1) * TW + 1];
+            const float ry = mask_keep(y < 32 ? mlo : mhi, y & 31,
+                                       ((uup - uy) + (udn - uy)) + ((ul - uy) + (ur - uy)));
             r[y] = ry;
-            if (own_col && y >= ylo && y < yhi) rsq += (double)ry * (double)ry;
+            w[y] = uy;
+            const float rq = ry * ry;
+            if (y & 1) rho_l1 += rq; else rho_l0 += rq;
+            own_l += (y >= ylo && y < yhi) ? rq : 0.f;
             uup = uy;
             uy = udn;
         }
     }
-    rsq = wave_sum_d(rsq);
-    if (lane == 0) partial[(int64_t)b * a.channels + ch] = rsq;
+    {
+        const bool own_col = on && x >= oxlo && x < oxhi;
+        const double rsq = wave_sum_d(own_col ? (double)own_l : 0.0);
+        if (lane == 0) partial[(int64_t)b * a.channels + ch] = rsq;
+    }
 
     ColMask<RPW, MBITS> mk;
     mk.load(mlo, mhi);
@@ -247,14 +284,9 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
 
     // w = u_in + v: the correction is accumulated straight into the block's
     // own values, so the write-back needs no second read of u_in
-    float w[RPW], p[RPW];
-    float rho_l0 = 0.f, rho_l1 = 0.f;
+    float p[RPW];
 #pragma unroll
-    for (int y = 0; y < RPW; ++y) {
-        w[y] = lds[(y + 1) * kTileW + lane + 1];
-        p[y] = r[y];
-        if (y & 1) rho_l1 += r[y] * r[y]; else rho_l0 += r[y] * r[y];
-    }
+    for (int y = 0; y < RPW; ++y) p[y] = r[y];
     float rho = wave_sum(rho_l0 + rho_l1);
     // optional absolute stop: mean square local residual below local_tol^2
     const float rho_stop = a.local_tol2 * (float)(g.bh * g.bw);
@@ -265,6 +297,7 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
     int it = 0;
     for (; it < a.k; ++it) {
         if (!(rho > rho_stop)) break;
+        mk.refresh();
         // q = A_loc p, pq = p . q
         float pq0 = 0.f, pq1 = 0.f;
         float q4[4];
@@ -338,11 +371,12 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
     // ---- restricted prolongation: u_out = u_in + v on owned pixels (eq. 9)
     if (on && x >= oxlo && x < oxhi) {
         float* __restrict__ UO = uout + ch * a.cpitch;
+        uint32_t off = (uint32_t)y0 * (uint32_t)g.w + (uint32_t)x;
 #pragma unroll
         for (int y = 0; y < RPW; ++y) {
             const int yy = y0 + y;
-            if ((!RAGGED || y < nrows) && yy >= oylo && yy < oyhi)
-                UO[(uint32_t)yy * (uint32_t)g.w + (uint32_t)x] = w[y];
+            if ((!RAGGED || y < nrows) && yy >= oylo && yy < oyhi) UO[off] = w[y];
+            off += (uint32_t)g.w;
         }
     }
 }
@@ -473,6 +507,180 @@ __global__ __launch_bounds__(kTpb) void k_stats(const float* __restrict__ f,
     block_reduce<NC + 2>(st, stats + (int64_t)blockIdx.x * (NC + 2));
 }
 
+
+// Coarsening for widths divisible by 4: a thread makes coarse pixels
+// (I, 2t) and (I, 2t + 1) from fine rows 2I, 2I + 1 and columns 4t .. 4t+3
+// with one u32 mask load and one float4 per channel and row. Each
+// workgroup walks kCoarsenRows coarse rows, so the statistics partials stay
+// few. Same arithmetic as k_coarsen (float64 sum of <= 4 known values).
+constexpr int kCoarsenRows = 4;
+
+template <int NC>
+__global__ __launch_bounds__(kTpb) void k_coarsen4(const float* __restrict__ f,
+                                                   const uint8_t* __restrict__ c, int h, int w,
+                                                   float* __restrict__ fc,
+                                                   uint8_t* __restrict__ cc, int hc, int wc,
+                                                   double* __restrict__ stats) {
+    const int t = blockIdx.x * kTpb + threadIdx.x;  // pair of coarse columns
+    const int64_t n = (int64_t)h * w, ncs = (int64_t)hc * wc;
+    double st[NC + 2];
+#pragma unroll
+    for (int j = 0; j < NC + 2; ++j) st[j] = 0.0;
+    if (4 * t < w) {
+        for (int I = blockIdx.y * kCoarsenRows; I < min(hc, (blockIdx.y + 1) * kCoarsenRows);
+             ++I) {
+            uint32_t m[2] = {0u, 0u};
+            float4 fv[2][NC];
+#pragma unroll
+            for (int a2 = 0; a2 < 2; ++a2) {
+                const int y = 2 * I + a2;
+                if (y < h) {
+                    const int64_t i = (int64_t)y * w + 4 * t;
+                    m[a2] = *reinterpret_cast<const uint32_t*>(c + i);
+#pragma unroll
+                    for (int k = 0; k < NC; ++k)
+                        fv[a2][k] = m[a2] ? *reinterpret_cast<const float4*>(f + k * n + i)
+                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+            double s[2][NC];
+            int cnt[2] = {0, 0};
+#pragma unroll
+            for (int k = 0; k < NC; ++k) s[0][k] = s[1][k] = 0.0;
+#pragma unroll
+            for (int a2 = 0; a2 < 2; ++a2) {
+#pragma unroll
+                for (int b2 = 0; b2 < 4; ++b2) {
+                    const uint32_t cv = (m[a2] >> (8 * b2)) & 0xffu;
+                    const int J = b2 >> 1;
+                    if (cv != 0) {
+                        ++cnt[J];
+#pragma unroll
+                        for (int k = 0; k < NC; ++k) {
+                            const float4 q = fv[a2][k];
+                            const double v = b2 == 0 ? q.x : b2 == 1 ? q.y : b2 == 2 ? q.z : q.w;
+                            s[J][k] += v;
+                            st[k] += v * v;
+                        }
+                    }
+                    st[NC] += cv != 0 ? 1.0 : 0.0;
+                    st[NC + 1] += cv > 1 ? 1.0 : 0.0;
+                }
+            }
+            const int64_t o = (int64_t)I * wc + 2 * t;
+            *reinterpret_cast<uint16_t*>(cc + o) =
+                (uint16_t)((cnt[0] > 0 ? 1 : 0) | ((cnt[1] > 0 ? 1 : 0) << 8));
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                float2 out;
+                out.x = cnt[0] > 0 ? (float)(s[0][k] / (double)cnt[0]) : 0.f;
+                out.y = cnt[1] > 0 ? (float)(s[1][k] / (double)cnt[1]) : 0.f;
+                *reinterpret_cast<float2*>(fc + k * ncs + o) = out;
+            }
+        }
+    }
+    if (stats) block_reduce<NC + 2>(st, stats + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (NC + 2));
+}
+
+// Prolongation for widths divisible by 4: a thread writes fine pixels
+// (y, 4t .. 4t+3) of all channels with one u32 mask load, float4 loads of f
+// where the mask is set, and float4 stores. Fine x = 2J sits at coarse
+// column J - 1/4 and x = 2J + 1 at J + 1/4, so the four pixels read coarse
+// columns 2t - 1 .. 2t + 2 (clamped) of two coarse rows. Same float64
+// bilinear expression as k_prolong.
+template <int NC>
+__global__ __launch_bounds__(kTpb) void k_prolong4(const float* __restrict__ uc, int hc, int wc,
+                                                   const float* __restrict__ f,
+                                                   const uint8_t* __restrict__ c, int h, int w,
+                                                   float* __restrict__ u) {
+    const int t = blockIdx.x * kTpb + threadIdx.x;
+    const int y = blockIdx.y;
+    if (4 * t >= w) return;
+    const int64_t n = (int64_t)h * w, ncs = (int64_t)hc * wc;
+    const int64_t i = (int64_t)y * w + 4 * t;
+    const uint32_t m = *reinterpret_cast<const uint32_t*>(c + i);
+    // coarse rows (r0, r1) and the weight of r1
+    const int I = y >> 1;
+    int r0, r1;
+    double ay;
+    if ((y & 1) == 0) {
+        r0 = max(I - 1, 0); r1 = I; ay = I > 0 ? 0.75 : 0.0;
+        if (I == 0) r1 = 0;
+    } else {
+        r0 = I; r1 = min(I + 1, hc - 1); ay = I + 1 < hc ? 0.25 : 0.0;
+    }
+    // coarse columns 2t-1 .. 2t+2 clamped
+    int cj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cj[q] = min(max(2 * t - 1 + q, 0), wc - 1);
+    // per fine pixel b: first coarse column index (into cj) and weight of the second
+    const int J0 = 2 * t;
+    double ax[4];
+    int c0[4];
+    // x = 4t   -> coarse J0 - 1/4: (J0 - 1, J0), weight 0.75 (0 if J0 == 0)
+    c0[0] = 0; ax[0] = J0 > 0 ? 0.75 : 0.0;
+    // x = 4t+1 -> J0 + 1/4: (J0, J0 + 1), weight 0.25 (0 if J0 + 1 == wc)
+    c0[1] = 1; ax[1] = J0 + 1 < wc ? 0.25 : 0.0;
+    // x = 4t+2 -> J0 + 1 - 1/4: (J0, J0 + 1), weight 0.75
+    c0[2] = 1; ax[2] = 0.75;
+    // x = 4t+3 -> J0 + 1 + 1/4: (J0 + 1, J0 + 2), weight 0.25 (0 at the border)
+    c0[3] = 2; ax[3] = J0 + 2 < wc ? 0.25 : 0.0;
+    if (J0 == 0) c0[0] = 1;  // clamped: coordinate 0 -> column J0 only
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const float* C = uc + k * ncs;
+        double q0[4], q1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            q0[q] = C[(int64_t)r0 * wc + cj[q]];
+            q1[q] = C[(int64_t)r1 * wc + cj[q]];
+        }
+        const float4 fk = m ? *reinterpret_cast<const float4*>(f + k * n + i)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+        float o[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int a0 = c0[b], a1 = min(c0[b] + 1, 3);
+            const double v = (1.0 - ay) * ((1.0 - ax[b]) * q0[a0] + ax[b] * q0[a1]) +
+                             ay * ((1.0 - ax[b]) * q1[a0] + ax[b] * q1[a1]);
+            o[b] = (float)v;
+        }
+        float4 out;
+        out.x = (m & 0xffu) ? fk.x : o[0];
+        out.y = (m & 0xff00u) ? fk.y : o[1];
+        out.z = (m & 0xff0000u) ? fk.z : o[2];
+        out.w = (m & 0xff000000u) ? fk.w : o[3];
+        *reinterpret_cast<float4*>(u + k * n + i) = out;
+    }
+}
+
+// Column-transposed masks of several levels in one launch (grid.z = level).
+struct MaskBitsLevels {
+    const uint8_t* c[kMaxLevels];
+    uint64_t* mbits[kMaxLevels];
+    int h[kMaxLevels], w[kMaxLevels];
+};
+
+__global__ __launch_bounds__(256) void k_mask_bits_levels(MaskBitsLevels L) {
+    const int lv = blockIdx.z;
+    const int h = L.h[lv], w = L.w[lv];
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int gy = blockIdx.y;
+    const int groups = mask_bit_groups(h);
+    if (x >= w || gy >= groups) return;
+    const uint8_t* c = L.c[lv];
+    uint64_t bits = 0;
+    if (gy < groups - 1) {
+        uint8_t m[64];
+#pragma unroll
+        for (int j = 0; j < 64; ++j) m[j] = c[(int64_t)min(gy * 64 + j, h - 1) * w + x];
+#pragma unroll
+        for (int j = 0; j < 64; ++j)
+            if (gy * 64 + j < h && m[j] == 0) bits |= 1ull << j;
+    }
+    L.mbits[lv][(int64_t)gy * w + x] = bits;
+}
+
 __global__ __launch_bounds__(kTpb) void k_init(const float* __restrict__ f,
                                                const uint8_t* __restrict__ c, int64_t n,
                                                int channels, float* __restrict__ u) {
@@ -586,6 +794,67 @@ __global__ __launch_bounds__(kTpb) void k_reduce(const double* __restrict__ part
     block_reduce<1>(s, out + j);
 }
 
+// Stop test on the device after finest-level sweep number n (1-based),
+// launched only at the sweeps where the test applies. ctl[0] = done,
+// ctl[1] = the sweep after which the test passed, ctl[2] = error (1: mask
+// byte > 1, 2: empty mask). stats = [||b_k||^2 (k < C), known pixels, bad
+// mask bytes]. rel[0] receives max_k ||r_k||^2 / ||b_k||^2 of the sweep's
+// input. One workgroup sums the [block][channel] partials of all channels
+// in one pass, in a fixed order.
+constexpr int kDecideTpb = 1024;
+
+template <int NC>
+__global__ __launch_bounds__(kDecideTpb) void k_decide(const double* __restrict__ partial, int nb,
+                                                       const double* __restrict__ stats,
+                                                       int* __restrict__ ctl,
+                                                       double* __restrict__ rel, double tol2,
+                                                       int n) {
+    if (ctl[0] != 0) return;  // an earlier test passed: sweep n did not run
+    __shared__ double sm[kDecideTpb / 64][NC];
+    double v[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) v[k] = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kDecideTpb) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) v[k] += partial[(int64_t)i * NC + k];
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) v[k] = wave_sum_d(v[k]);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) sm[threadIdx.x >> 6][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double worst = 0.0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            double rsq = 0.0;
+            for (int j = 0; j < kDecideTpb / 64; ++j) rsq += sm[j][k];
+            const double b2 = stats[k];
+            const double q = b2 > 0.0 ? rsq / b2 : (rsq > 0.0 ? INFINITY : 0.0);
+            worst = fmax(worst, q);
+        }
+        rel[0] = worst;
+        int err = 0;
+        if (stats[NC + 1] > 0.0) err = 1;
+        else if (!(stats[NC] > 0.0)) err = 2;
+        if (err) {
+            ctl[2] = err;
+            ctl[1] = n;
+            ctl[0] = 1;
+        } else if (worst <= tol2) {
+            ctl[1] = n;
+            ctl[0] = 1;
+        }
+    }
+}
+
+__global__ void k_clear_int(int* __restrict__ p, int n) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -594,31 +863,69 @@ __global__ __launch_bounds__(kTpb) void k_reduce(const double* __restrict__ part
 
 template <int RPW, bool QLDS, bool MBITS>
 static hipError_t sweep_rpw(const float* uin, const uint64_t* mbits, float* uout,
-                            double* partial, double* cg_steps, const SweepArgs& a,
-                            hipStream_t s) {
+                            double* partial, double* cg_steps, const int* ctl,
+                            const SweepArgs& a, hipStream_t s) {
     const int grid = a.g.nby * a.g.nbx * a.channels;
     if (a.g.bh == RPW)
         hipLaunchKernelGGL((k_sweep<RPW, false, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
-                           uin, mbits, uout, partial, cg_steps, a);
+                           uin, mbits, uout, partial, cg_steps, ctl, a);
     else
         hipLaunchKernelGGL((k_sweep<RPW, true, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
-                           uin, mbits, uout, partial, cg_steps, a);
+                           uin, mbits, uout, partial, cg_steps, ctl, a);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
-                        double* partial, double* cg_steps, const SweepArgs& a,
+                        double* partial, double* cg_steps, const int* ctl, const SweepArgs& a,
                         hipStream_t s) {
     const int bh = a.g.bh;
     if (a.g.bw < 1 || a.g.bw > kMaxBlock || bh < 1 || bh > kMaxBlock) return hipErrorInvalidValue;
-    if (bh > 32) return sweep_rpw<64, true, true>(uin, mbits, uout, partial, cg_steps, a, s);
-    if (bh > 16) return sweep_rpw<32, false, false>(uin, mbits, uout, partial, cg_steps, a, s);
-    if (bh > 8) return sweep_rpw<16, false, false>(uin, mbits, uout, partial, cg_steps, a, s);
-    return sweep_rpw<8, false, false>(uin, mbits, uout, partial, cg_steps, a, s);
+    if (bh > 32) return sweep_rpw<64, true, true>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
+    if (bh > 16) return sweep_rpw<32, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
+    if (bh > 8) return sweep_rpw<16, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
+    return sweep_rpw<8, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
+}
+
+hipError_t launch_decide(const double* partial, int nb, int channels, const double* stats,
+                         int* ctl, double* rel, double tol, int n, hipStream_t s) {
+    const double tol2 = tol < 0.0 ? -1.0 : tol * tol;  // negative: never passes
+    switch (channels) {
+#define DDI_CASE(NC)                                                                          \
+    case NC:                                                                                  \
+        hipLaunchKernelGGL(k_decide<NC>, dim3(1), dim3(kDecideTpb), 0, s, partial, nb, stats, \
+                           ctl, rel, tol2, n);                                                \
+        break;
+        DDI_CASE(1) DDI_CASE(2) DDI_CASE(3) DDI_CASE(4)
+#undef DDI_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_int(int* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_int, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_clear(double* p, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_clear, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_bits_levels(int n, const uint8_t* const* c, const int* h, const int* w,
+                                  uint64_t* const* mbits, hipStream_t s) {
+    if (n < 1 || n > kMaxLevels) return hipErrorInvalidValue;
+    MaskBitsLevels L;
+    int gx = 1, gy = 1;
+    for (int i = 0; i < n; ++i) {
+        L.c[i] = c[i];
+        L.mbits[i] = mbits[i];
+        L.h[i] = h[i];
+        L.w[i] = w[i];
+        gx = max(gx, (w[i] + 255) / 256);
+        gy = max(gy, mask_bit_groups(h[i]));
+    }
+    hipLaunchKernelGGL(k_mask_bits_levels, dim3(gx, gy, n), dim3(256), 0, s, L);
     return hipGetLastError();
 }
 
@@ -631,9 +938,26 @@ hipError_t launch_mask_bits(const uint8_t* c, int h, int w, uint64_t* mbits, hip
 
 static int grid1d(int64_t n) { return (int)((n + kTpb - 1) / kTpb); }
 
+static bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
 hipError_t launch_coarsen(const float* f, const uint8_t* c, int h, int w, int channels,
                           float* fc, uint8_t* cc, double* stats, int* nwg, hipStream_t s) {
     const int hc = (h + 1) / 2, wc = (w + 1) / 2;
+    if (w % 4 == 0 && aligned(f, 16) && aligned(c, 4) && aligned(fc, 8) && aligned(cc, 2)) {
+        dim3 grid((w / 4 + kTpb - 1) / kTpb, (hc + kCoarsenRows - 1) / kCoarsenRows);
+        if (nwg) *nwg = (int)(grid.x * grid.y);
+        switch (channels) {
+#define DDI_CASE(NC)                                                                         \
+    case NC:                                                                                 \
+        hipLaunchKernelGGL(k_coarsen4<NC>, grid, dim3(kTpb), 0, s, f, c, h, w, fc, cc, hc, wc, \
+                           stats);                                                           \
+        break;
+            DDI_CASE(1) DDI_CASE(2) DDI_CASE(3) DDI_CASE(4)
+#undef DDI_CASE
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const int grid = grid1d((int64_t)hc * wc);
     if (nwg) *nwg = grid;
     switch (channels) {
@@ -676,6 +1000,19 @@ hipError_t launch_init(const float* f, const uint8_t* c, int h, int w, int chann
 
 hipError_t launch_prolong(const float* uc, int hc, int wc, const float* f, const uint8_t* c,
                           int h, int w, int channels, float* u, hipStream_t s) {
+    if (w % 4 == 0 && aligned(f, 16) && aligned(c, 4) && aligned(u, 16)) {
+        dim3 grid((w / 4 + kTpb - 1) / kTpb, h);
+        switch (channels) {
+#define DDI_CASE(NC)                                                                          \
+    case NC:                                                                                  \
+        hipLaunchKernelGGL(k_prolong4<NC>, grid, dim3(kTpb), 0, s, uc, hc, wc, f, c, h, w, u); \
+        break;
+            DDI_CASE(1) DDI_CASE(2) DDI_CASE(3) DDI_CASE(4)
+#undef DDI_CASE
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     dim3 grid((wc + 63) / 64, (hc + kTpb / 64 - 1) / (kTpb / 64));
     hipLaunchKernelGGL(k_prolong, grid, dim3(kTpb), 0, s, uc, hc, wc, f, c, h, w, channels, u);
     return hipGetLastError();
