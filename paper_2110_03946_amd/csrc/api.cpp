@@ -254,10 +254,10 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
         hl = (hl + 1) / 2;
         wl = (wl + 1) / 2;
     }
-    // statistics partials: coarsen grid (level 0 -> 1) or the stats grid
+    // statistics partials: the first coarsening (level 0 -> 1) or, for a
+    // single level, the statistics kernel (at most 1024 workgroups)
     {
-        const size_t hc = (height + 1) / 2, wc = (width + 1) / 2;
-        const size_t nwg = std::max<size_t>((hc * wc + 255) / 256, 1024);
+        const size_t nwg = std::max<size_t>((size_t)coarsen_partials(height, width), 1024);
         part_n = std::max(part_n, nwg * (channels + 2));
     }
     P->part_n = part_n;

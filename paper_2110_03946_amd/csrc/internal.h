@@ -107,6 +107,10 @@ hipError_t launch_coarsen(const float* f, const uint8_t* c, int h, int w,
                           int channels, float* fc, uint8_t* cc,
                           double* stats, int* nwg, hipStream_t s);
 
+// Workgroups (statistics partial rows) launch_coarsen uses for h x w,
+// whichever path it takes.
+int coarsen_partials(int h, int w);
+
 // Same statistics without coarsening (single-level solves).
 hipError_t launch_stats(const float* f, const uint8_t* c, int h, int w,
                         int channels, double* stats, int* nwg, hipStream_t s);

@@ -15,6 +15,8 @@
 //   k_reduce    fixed-order float64 sums of per-workgroup partials.
 //
 // All reductions run in a fixed order, so results are bitwise reproducible.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ddi {
@@ -61,16 +63,22 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 }
 
 // Workgroups are handed to the 8 XCDs of the chip round-robin (workgroup i
-// runs on XCD i mod 8). Renumber them so that XCD j works through one
-// contiguous range of the logical order: neighbouring blocks, which share
-// halo and overlap cache lines, then meet in the same L2. Bijective for any
-// count n.
+// runs on XCD i mod 8). Renumber them so that each XCD works through runs
+// of kXcdChunk consecutive blocks of the logical order (XCD j takes runs j,
+// j + 8, j + 16, ...): horizontal neighbours, which share halo and overlap
+// cache lines, meet in the same L2, while costly regions of the image are
+// still spread over all XCDs. A tail shorter than 8 runs keeps its order.
 constexpr int kXcds = 8;
+#ifndef DDI_XCD_CHUNK
+#define DDI_XCD_CHUNK 16
+#endif
+constexpr int kXcdChunk = DDI_XCD_CHUNK;
 
 __device__ __forceinline__ int xcd_remap(int b, int n) {
-    const int q = n / kXcds, rem = n - q * kXcds;
+    const int full = n - n % (kXcds * kXcdChunk);
+    if (b >= full) return b;
     const int j = b % kXcds, i = b / kXcds;
-    return j * q + min(j, rem) + i;
+    return (j + kXcds * (i / kXcdChunk)) * kXcdChunk + i % kXcdChunk;
 }
 
 // q where bit `bit` of `bits` is set, +0 elsewhere: a sign-extended bit
@@ -511,24 +519,23 @@ __global__ __launch_bounds__(kTpb) void k_stats(const float* __restrict__ f,
 // Coarsening for widths divisible by 4: a thread makes coarse pixels
 // (I, 2t) and (I, 2t + 1) from fine rows 2I, 2I + 1 and columns 4t .. 4t+3
 // with one u32 mask load and one float4 per channel and row. Each
-// workgroup walks kCoarsenRows coarse rows, so the statistics partials stay
-// few. Same arithmetic as k_coarsen (float64 sum of <= 4 known values).
-constexpr int kCoarsenRows = 4;
+// workgroup walks `rows` coarse rows (up to 4 on large levels, so the
+// statistics partials stay few; 1 on small ones, for parallelism). Same
+// arithmetic as k_coarsen (float64 sum of <= 4 known values).
 
 template <int NC>
 __global__ __launch_bounds__(kTpb) void k_coarsen4(const float* __restrict__ f,
                                                    const uint8_t* __restrict__ c, int h, int w,
                                                    float* __restrict__ fc,
                                                    uint8_t* __restrict__ cc, int hc, int wc,
-                                                   double* __restrict__ stats) {
+                                                   int rows, double* __restrict__ stats) {
     const int t = blockIdx.x * kTpb + threadIdx.x;  // pair of coarse columns
     const int64_t n = (int64_t)h * w, ncs = (int64_t)hc * wc;
     double st[NC + 2];
 #pragma unroll
     for (int j = 0; j < NC + 2; ++j) st[j] = 0.0;
     if (4 * t < w) {
-        for (int I = blockIdx.y * kCoarsenRows; I < min(hc, (blockIdx.y + 1) * kCoarsenRows);
-             ++I) {
+        for (int I = blockIdx.y * rows; I < min(hc, (blockIdx.y + 1) * rows); ++I) {
             uint32_t m[2] = {0u, 0u};
             float4 fv[2][NC];
 #pragma unroll
@@ -940,17 +947,32 @@ static int grid1d(int64_t n) { return (int)((n + kTpb - 1) / kTpb); }
 
 static bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
 
+static int coarsen4_rows(int hc, int gx) { return std::max(1, std::min(4, hc * gx / 2048)); }
+
+int coarsen_partials(int h, int w) {
+    const int hc = (h + 1) / 2, wc = (w + 1) / 2;
+    int n = grid1d((int64_t)hc * wc);  // fallback path
+    if (w % 4 == 0) {
+        const int gx = (w / 4 + kTpb - 1) / kTpb;
+        const int rows = coarsen4_rows(hc, gx);
+        n = std::max(n, gx * ((hc + rows - 1) / rows));
+    }
+    return n;
+}
+
 hipError_t launch_coarsen(const float* f, const uint8_t* c, int h, int w, int channels,
                           float* fc, uint8_t* cc, double* stats, int* nwg, hipStream_t s) {
     const int hc = (h + 1) / 2, wc = (w + 1) / 2;
     if (w % 4 == 0 && aligned(f, 16) && aligned(c, 4) && aligned(fc, 8) && aligned(cc, 2)) {
-        dim3 grid((w / 4 + kTpb - 1) / kTpb, (hc + kCoarsenRows - 1) / kCoarsenRows);
+        const int gx = (w / 4 + kTpb - 1) / kTpb;
+        const int rows = coarsen4_rows(hc, gx);
+        dim3 grid(gx, (hc + rows - 1) / rows);
         if (nwg) *nwg = (int)(grid.x * grid.y);
         switch (channels) {
 #define DDI_CASE(NC)                                                                         \
     case NC:                                                                                 \
         hipLaunchKernelGGL(k_coarsen4<NC>, grid, dim3(kTpb), 0, s, f, c, h, w, fc, cc, hc, wc, \
-                           stats);                                                           \
+                           rows, stats);                                                     \
         break;
             DDI_CASE(1) DDI_CASE(2) DDI_CASE(3) DDI_CASE(4)
 #undef DDI_CASE

@@ -216,6 +216,8 @@ def test_config0_256_grey(ddi):
     (1, 300, 500, 0.02, "bernoulli", {"block": 32, "overlap": 6, "local_iters": 8}),
     (3, 257, 255, 0.08, "clustered", {"levels": 3, "robin_alpha": 1.0}),
     (1, 64, 64, 0.1, "bernoulli", {"levels": 1}),
+    # tall and narrow: more coarsening workgroups than coarse pixels / 256
+    (1, 4096, 256, 0.05, "bernoulli", {"levels": 2}),
 ])
 def test_solve_parity(ddi, C, H, W, d, kind, prm):
     f, c = workload(C, H, W, d, kind, wl=5, idx=H + W)
