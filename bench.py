@@ -70,11 +70,25 @@ def sweep_work(p: dict, sweeps: int, cg_steps: float):
     bh, bw = min(p["block"], H), min(p["block"], W)
     blocks = nby * nbx * C
     flops = bh * bw * (blocks * sweeps * FLOPS_RESIDUAL + cg_steps * FLOPS_PER_CG_STEP)
-    # per launch: every block reads its u tile with a one-pixel halo and 16
-    # bytes of transposed mask per column; the owned pixels (each pixel once)
-    # are written back
-    bytes_ = sweeps * (blocks * ((bh + 2) * (bw + 2) * 4 + bw * 16) + C * H * W * 4)
+    # per launch: the iterate is read once and written once (float32), plus
+    # the transposed mask (one bit per pixel); re-reads of the tile overlap
+    # are not algorithmic (the L2 serves them)
+    bytes_ = sweeps * (C * H * W * 8 + H * W // 8)
     return flops, bytes_
+
+
+def measured_traffic():
+    """HBM bytes per finest-level sweep launch from the committed rocprofv3
+    counter summary, or None when the kernels changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_sweep_4k_rgb_traffic.json")
+    src = os.path.join(ROOT, "paper_2110_03946_amd", "csrc", "kernels.hip")
+    try:
+        d = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return d["hbm_bytes_per_launch"] if d.get("kernels_hip_sha256") == sha else None
 
 
 def summarize_trace(path: str) -> str:
@@ -117,6 +131,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 256 MiB device-to-device copy (the known-size "
+                         "reference for FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--summarize-trace", metavar="CSV",
                     help="print a per-kernel, per-grid table of a rocprofv3 kernel trace and exit")
     args = ap.parse_args()
@@ -129,6 +146,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        n = 64 << 20  # 64 Mi float32 = 256 MiB each way
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": 4 * n}), flush=True)
+        return
     from paper_2110_03946_amd import build, ddi, synth
     if not os.path.exists(build.LIB):
         build.build()
@@ -176,7 +202,7 @@ def main():
     else:
         roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    roofline.update({"traffic": None,
+    roofline.update({"traffic": measured_traffic(),
                 "kernel": "k_sweep<64> (finest-level ORAS sweep)",
                 "avg_launch_us": round(avg_sweep_s * 1e6, 2),
                 "flops_per_byte": round(intensity, 2), "ridge_flops_per_byte": round(ridge, 2),
