@@ -91,6 +91,10 @@ extern "C" {
  *                  most local_tol^2 (0 = always local_iters steps). Blocks
  *                  that are already converged then cost no CG work; the
  *                  fixed point of the iteration is unchanged.
+ *   use_graph      1: capture the solve (everything up to and including the
+ *                  first batch of finest-level sweeps) into a HIP graph on a
+ *                  stream the plan owns, and replay it on later solves with
+ *                  the same f, c and u pointers (ignored with timing = 1).
  */
 typedef struct ddi_params {
     int block;
@@ -110,6 +114,7 @@ typedef struct ddi_params {
     int coarse_overlap;
     int coarse_local_iters;
     float local_tol;
+    int use_graph;
 } ddi_params;
 
 /*
@@ -141,7 +146,7 @@ typedef struct ddi_plan ddi_plan;
  * 2 sweeps per coarser level, 3 on the coarsest, rel_tol = 1e-4,
  * min_sweeps = 2, max_sweeps = 50, check_every = 1, final_residual = 1,
  * timing = 0, coarse_block = 0, coarse_overlap = -1, coarse_local_iters = 0,
- * local_tol = 0. */
+ * local_tol = 0, use_graph = 0. */
 int ddi_default_params(ddi_params* p);
 
 /* Check *p for one image size without touching the GPU. */

@@ -108,6 +108,15 @@ struct ddi_plan {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<hipEvent_t> sweep_ev;  // 2 per finest-level sweep (timing)
     int last_sweeps = -1;              // finest-level sweeps of the previous solve
+    // graph mode: a plan-owned stream, and the instantiated graph of the
+    // solve's first batch with the key it was captured for
+    hipStream_t gs = nullptr;
+    hipEvent_t ev_in = nullptr;
+    hipGraphExec_t g_exec = nullptr;
+    const void* g_f = nullptr;
+    const void* g_c = nullptr;
+    const void* g_u = nullptr;
+    int g_start = -1, g_batch = -1;
 };
 
 extern "C" {
@@ -131,6 +140,7 @@ int ddi_default_params(ddi_params* p) {
     p->coarse_overlap = -1;
     p->coarse_local_iters = 0;
     p->local_tol = 0.f;
+    p->use_graph = 0;
     return DDI_OK;
 }
 
@@ -154,6 +164,7 @@ int ddi_check_params(int height, int width, int channels, const ddi_params* p) {
     if (p->coarse_overlap < -1 || co >= cb) return DDI_EINVAL;
     if (p->coarse_local_iters < 0) return DDI_EINVAL;
     if (!(p->local_tol >= 0.f) || p->local_tol > 1e6f) return DDI_EINVAL;
+    if (p->use_graph != 0 && p->use_graph != 1) return DDI_EINVAL;
     return DDI_OK;
 }
 
@@ -175,6 +186,9 @@ int ddi_destroy(ddi_plan* plan) {
     if (plan->e0) (void)hipEventDestroy(plan->e0);
     if (plan->e1) (void)hipEventDestroy(plan->e1);
     for (hipEvent_t e : plan->sweep_ev) (void)hipEventDestroy(e);
+    if (plan->g_exec) (void)hipGraphExecDestroy(plan->g_exec);
+    if (plan->ev_in) (void)hipEventDestroy(plan->ev_in);
+    if (plan->gs) (void)hipStreamDestroy(plan->gs);
     delete plan;
     return DDI_OK;
 }
@@ -277,11 +291,25 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
         ddi_destroy(P);
         return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
     }
+    if (prm.use_graph && !prm.timing) {
+        // a stream of our own (default priority): the caller's may be the
+        // legacy default stream, which cannot be captured
+        if ((err = hipStreamCreate(&P->gs)) != hipSuccess ||
+            (err = hipEventCreateWithFlags(&P->ev_in, hipEventDisableTiming)) != hipSuccess) {
+            ddi_destroy(P);
+            return hip_fail(err);
+        }
+    }
     if (prm.timing) {
         const size_t nc = (size_t)sweep_partials(P->lv[0].sw) * channels;
         if ((err = hipMalloc(&P->cgcnt, nc * sizeof(double))) != hipSuccess) {
             ddi_destroy(P);
             return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
+        }
+        if ((err = launch_clear(P->cgcnt, (int)nc, P->s)) != hipSuccess ||
+            (err = hipStreamSynchronize(P->s)) != hipSuccess) {
+            ddi_destroy(P);
+            return hip_fail(err);
         }
         P->sweep_ev.assign(2 * (size_t)prm.max_sweeps, nullptr);
         for (hipEvent_t& ev : P->sweep_ev) {
@@ -292,15 +320,6 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
         }
     }
     *out = P;
-    return DDI_OK;
-}
-
-// Reduce `nrows` x C partials to per-channel sums in red[off..off+C), copy the
-// first `ncopy` doubles of red to the pinned host mirror and wait.
-static int reduce_and_read(ddi_plan* P, int nrows, int off, int ncopy) {
-    DDI_HIP(launch_reduce(P->part, nrows, P->C, P->C, P->red + off, P->s));
-    DDI_HIP(hipMemcpyAsync(P->host, P->red, ncopy * sizeof(double), hipMemcpyDeviceToHost, P->s));
-    DDI_HIP(hipStreamSynchronize(P->s));
     return DDI_OK;
 }
 
@@ -319,31 +338,25 @@ static double rel_from_host(const ddi_plan* P, const double* rsq) {
     return worst;
 }
 
-int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats* st) {
-    if (!P || !f || !c || !u) return DDI_EINVAL;
+// Pyramid, input statistics, transposed masks, coarsest level and the
+// coarse-to-fine passes down to the start of the finest level, enqueued on
+// `s`. The finest level starts in buffer `start0` (0 = u).
+static int enqueue_front(ddi_plan* P, int start0, hipStream_t s) {
     const int C = P->C;
     const int L = (int)P->lv.size();
     const ddi_params& prm = P->p;
-    Level& L0 = P->lv[0];
-    L0.f = f;
-    L0.c = c;
-    L0.u[0] = u;
-    if (st) std::memset(st, 0, sizeof(*st));
-
-    DDI_HIP(hipEventRecord(P->e0, P->s));
-
-    // ---- level pyramid (Sec. 4) and input statistics ----
+    const Level& L0 = P->lv[0];
     int nwg = 0;
     if (L > 1)
-        DDI_HIP(launch_coarsen(f, c, P->h, P->w, C, P->lv[1].fown, P->lv[1].cown, P->part, &nwg,
-                               P->s));
+        DDI_HIP(launch_coarsen(L0.f, L0.c, P->h, P->w, C, P->lv[1].fown, P->lv[1].cown, P->part,
+                               &nwg, s));
     else
-        DDI_HIP(launch_stats(f, c, P->h, P->w, C, P->part, &nwg, P->s));
-    DDI_HIP(launch_reduce(P->part, nwg, C + 2, C + 2, P->red, P->s));
+        DDI_HIP(launch_stats(L0.f, L0.c, P->h, P->w, C, P->part, &nwg, s));
+    DDI_HIP(launch_reduce(P->part, nwg, C + 2, C + 2, P->red, s));
     for (int l = 1; l + 1 < L; ++l) {
         Level& a = P->lv[l];
         Level& b = P->lv[l + 1];
-        DDI_HIP(launch_coarsen(a.f, a.c, a.h, a.w, C, b.fown, b.cown, nullptr, nullptr, P->s));
+        DDI_HIP(launch_coarsen(a.f, a.c, a.h, a.w, C, b.fown, b.cown, nullptr, nullptr, s));
     }
     {
         const uint8_t* cs[kMaxLevels];
@@ -355,42 +368,137 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
             hs[l] = P->lv[l].h;
             ws[l] = P->lv[l].w;
         }
-        DDI_HIP(launch_mask_bits_levels(L, cs, hs, ws, mbs, P->s));
+        DDI_HIP(launch_mask_bits_levels(L, cs, hs, ws, mbs, s));
     }
-
-    // ---- coarsest level, then coarse-to-fine ----
-    // The finest level ping-pongs between u (index 0) and the plan's buffer
-    // (index 1). It starts in the buffer that makes the expected final
-    // iterate -- as many sweeps as the previous solve needed -- land in u,
-    // so that usually no copy is needed at the end.
-    const int expect = P->last_sweeps >= 0 ? P->last_sweeps : std::max(prm.min_sweeps, 1);
-    const int start0 = std::min(expect, prm.max_sweeps) & 1;
     const int top = L - 1;
     int cur = (top == 0) ? start0 : 0;
     DDI_HIP(launch_init(P->lv[top].f, P->lv[top].c, P->lv[top].h, P->lv[top].w, C,
-                        P->lv[top].u[cur], P->s));
+                        P->lv[top].u[cur], s));
     for (int l = top; l >= 1; --l) {
         Level& lev = P->lv[l];
         const int n = (l == top) ? prm.coarsest_sweeps : prm.coarse_sweeps;
         for (int i = 0; i < n; ++i) {
             DDI_HIP(launch_sweep(lev.u[cur], lev.mbits, lev.u[1 - cur], P->part, nullptr, nullptr,
-                                 lev.sw,
-                                 P->s));
+                                 lev.sw, s));
             cur ^= 1;
         }
         Level& fine = P->lv[l - 1];
         const int dst = (l == 1) ? start0 : 0;
         DDI_HIP(launch_prolong(lev.u[cur], lev.h, lev.w, fine.f, fine.c, fine.h, fine.w, C,
-                               fine.u[dst], P->s));
+                               fine.u[dst], s));
         cur = dst;
     }
+    return DDI_OK;
+}
 
-    // ---- finest level: sweeps with the stop test on the device ----
-    // Sweeps are enqueued ahead in batches; after each sweep where the stop
-    // test applies, k_decide runs it on the device, and once it passes the
-    // sweeps still enqueued exit at once. The host waits once per batch;
-    // the first batch is as long as the previous solve needed, so a solve
-    // like the previous one needs a single wait.
+static bool is_check(const ddi_params& prm, int n) {
+    return n >= prm.min_sweeps && (n - prm.min_sweeps) % prm.check_every == 0;
+}
+
+// Finest-level sweeps [from, to) starting from buffer start0, each followed
+// by the device stop test where it applies (and after the last allowed).
+static int enqueue_sweeps(ddi_plan* P, int from, int to, int start0, bool timing,
+                          hipStream_t s) {
+    const ddi_params& prm = P->p;
+    Level& L0 = P->lv[0];
+    const int nb = sweep_partials(L0.sw);
+    int* ctl = P->ctl;
+    double* drel = reinterpret_cast<double*>(ctl + 4);
+    for (int i = from; i < to; ++i) {
+        const int c0 = start0 ^ (i & 1);
+        if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * i], s));
+        DDI_HIP(launch_sweep(L0.u[c0], L0.mbits, L0.u[c0 ^ 1], P->part, timing ? P->cgcnt : nullptr,
+                             ctl, L0.sw, s));
+        if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * i + 1], s));
+        if (is_check(prm, i + 1) || i + 1 == prm.max_sweeps)
+            DDI_HIP(launch_decide(P->part, nb, P->C, P->red, ctl, drel,
+                                  is_check(prm, i + 1) ? prm.rel_tol : -1.0, i + 1, s));
+    }
+    return DDI_OK;
+}
+
+int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats* st) {
+    if (!P || !f || !c || !u) return DDI_EINVAL;
+    const int C = P->C;
+    const ddi_params& prm = P->p;
+    Level& L0 = P->lv[0];
+    L0.f = f;
+    L0.c = c;
+    L0.u[0] = u;
+    if (st) std::memset(st, 0, sizeof(*st));
+
+    const bool timing = !P->sweep_ev.empty();
+    const bool graph = P->gs != nullptr;
+    hipStream_t s = graph ? P->gs : P->s;
+    if (graph) {
+        // order the plan's stream after work the caller queued before
+        DDI_HIP(hipEventRecord(P->ev_in, P->s));
+        DDI_HIP(hipStreamWaitEvent(s, P->ev_in, 0));
+    }
+    DDI_HIP(hipEventRecord(P->e0, s));
+
+    // The finest level ping-pongs between u (index 0) and the plan's buffer
+    // (index 1). It starts in the buffer that makes the expected final
+    // iterate -- as many sweeps as the previous solve needed -- land in u,
+    // so that usually no copy is needed at the end. Sweeps are enqueued
+    // ahead in batches; after each sweep where the stop test applies,
+    // k_decide runs it on the device, and once it passes the sweeps still
+    // enqueued exit at once. The host waits once per batch; the first batch
+    // is as long as the previous solve needed.
+    const int expect = P->last_sweeps >= 0 ? P->last_sweeps : std::max(prm.min_sweeps, 1);
+    const int start0 = std::min(expect, prm.max_sweeps) & 1;
+    int batch = std::min(prm.max_sweeps, std::max(expect, prm.min_sweeps));
+    if (batch > 0) {
+        int upto = std::max(1, batch);
+        while (upto < prm.max_sweeps && !is_check(prm, upto)) ++upto;
+        batch = std::min(upto, prm.max_sweeps);
+    }
+
+    int enq = 0;
+    if (graph) {
+        // one graph per (f, c, u, start buffer, first batch); later solves
+        // with the same key replay it
+        const bool same = P->g_exec && P->g_f == f && P->g_c == c && P->g_u == u &&
+                          P->g_start == start0 && P->g_batch == batch;
+        if (!same) {
+            if (P->g_exec) {
+                (void)hipGraphExecDestroy(P->g_exec);
+                P->g_exec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            DDI_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            int e = enqueue_front(P, start0, s);
+            if (!e) {
+                hipError_t he = launch_clear_int(P->ctl, 4, s);
+                e = he != hipSuccess ? hip_fail(he) : enqueue_sweeps(P, 0, batch, start0, false, s);
+            }
+            hipError_t he = hipStreamEndCapture(s, &g);
+            if (e) {
+                if (g) (void)hipGraphDestroy(g);
+                return e;
+            }
+            if (he != hipSuccess) return hip_fail(he);
+            he = hipGraphInstantiate(&P->g_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (he != hipSuccess) {
+                P->g_exec = nullptr;
+                return hip_fail(he);
+            }
+            P->g_f = f;
+            P->g_c = c;
+            P->g_u = u;
+            P->g_start = start0;
+            P->g_batch = batch;
+        }
+        DDI_HIP(hipGraphLaunch(P->g_exec, s));
+        enq = batch;
+    } else {
+        int e = enqueue_front(P, start0, s);
+        if (e) return e;
+        DDI_HIP(launch_clear_int(P->ctl, 4, s));
+    }
+
+    // ---- finest level: wait for each batch, then enqueue more if needed ----
     bool validated = false, converged = false;
     double rel = INFINITY;
     auto validate = [&]() -> int {
@@ -399,36 +507,21 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
         if (P->host[C] <= 0.0) return DDI_ESINGULAR;
         return DDI_OK;
     };
-    const int nb = sweep_partials(L0.sw);
-    const bool timing = !P->sweep_ev.empty();
-    double* steps = P->cgcnt;
-    if (steps) DDI_HIP(launch_clear(steps, nb * C, P->s));
-    int* ctl = P->ctl;
-    double* drel = reinterpret_cast<double*>(ctl + 4);
-    DDI_HIP(launch_clear_int(ctl, 4, P->s));
-    const int start_cur = cur;
-    int enq = 0, sweeps = 0;
-    int batch = std::min(prm.max_sweeps, std::max(expect, prm.min_sweeps));
-    auto is_check = [&](int n) {
-        return n >= prm.min_sweeps && (n - prm.min_sweeps) % prm.check_every == 0;
-    };
-    while (enq < prm.max_sweeps) {
-        // a batch always ends with a stop test
-        int upto = std::min(prm.max_sweeps, std::max(enq + 1, batch));
-        while (upto < prm.max_sweeps && !is_check(upto)) ++upto;
-        for (; enq < upto; ++enq) {
-            const int c0 = start_cur ^ (enq & 1);
-            if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * enq], P->s));
-            DDI_HIP(launch_sweep(L0.u[c0], L0.mbits, L0.u[c0 ^ 1], P->part, steps, ctl, L0.sw,
-                                 P->s));
-            if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * enq + 1], P->s));
-            if (is_check(enq + 1) || enq + 1 == prm.max_sweeps)
-                DDI_HIP(launch_decide(P->part, nb, C, P->red, ctl, drel,
-                                      is_check(enq + 1) ? prm.rel_tol : -1.0, enq + 1, P->s));
+    int sweeps = 0;
+    int done_upto = enq;  // sweeps enqueued so far
+    bool first = true;
+    while (done_upto < prm.max_sweeps || (first && done_upto > 0)) {
+        if (!first || !graph) {
+            int upto = std::min(prm.max_sweeps, std::max(done_upto + 1, first ? batch : done_upto + 2));
+            while (upto < prm.max_sweeps && !is_check(prm, upto)) ++upto;
+            int e = enqueue_sweeps(P, done_upto, upto, start0, timing, s);
+            if (e) return e;
+            done_upto = upto;
         }
-        DDI_HIP(hipMemcpyAsync(P->hctl, ctl, 4 * sizeof(int) + sizeof(double),
-                               hipMemcpyDeviceToHost, P->s));
-        DDI_HIP(hipStreamSynchronize(P->s));
+        first = false;
+        DDI_HIP(hipMemcpyAsync(P->hctl, P->ctl, 4 * sizeof(int) + sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        DDI_HIP(hipStreamSynchronize(s));
         const int* hc = reinterpret_cast<const int*>(P->hctl);
         validated = true;
         if (hc[2] == 1) return DDI_EINVAL;
@@ -441,20 +534,22 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
             converged = true;
             break;
         }
-        sweeps = enq;
-        batch = enq + 2;
+        sweeps = done_upto;
+        if (done_upto >= prm.max_sweeps) break;
     }
-    cur = start_cur ^ (sweeps & 1);
-
+    int cur = start0 ^ (sweeps & 1);
     P->last_sweeps = sweeps;
 
     // ---- final residual of the returned iterate; move it into u ----
     if (prm.final_residual || !validated) {
         int rwg = 0;
         DDI_HIP(launch_residual(f, c, L0.u[cur], P->h, P->w, C, nullptr,
-                                cur == 1 ? u : nullptr, P->part, &rwg, P->s));
-        int e = reduce_and_read(P, rwg, C + 2, 2 * C + 2);
-        if (e) return e;
+                                cur == 1 ? u : nullptr, P->part, &rwg, s));
+        DDI_HIP(launch_reduce(P->part, rwg, C, C, P->red + C + 2, s));
+        DDI_HIP(hipMemcpyAsync(P->host, P->red, (2 * C + 2) * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        DDI_HIP(hipStreamSynchronize(s));
+        int e;
         if (!validated && (e = validate())) return e;
         if (prm.final_residual) {
             rel = rel_from_host(P, P->host + C + 2);
@@ -462,17 +557,19 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
         }
     } else if (cur == 1) {
         DDI_HIP(hipMemcpyAsync(u, L0.u[1], (size_t)C * P->h * P->w * sizeof(float),
-                               hipMemcpyDeviceToDevice, P->s));
+                               hipMemcpyDeviceToDevice, s));
     }
-    if (steps) {
-        DDI_HIP(launch_reduce(steps, nb, C, C, P->red + 2 * C + 2, P->s));
+    const int nb = sweep_partials(L0.sw);
+    if (timing) {
+        // the counters are cleared as they are read, ready for the next solve
+        DDI_HIP(launch_reduce(P->cgcnt, nb, C, C, P->red + 2 * C + 2, s, true));
         DDI_HIP(hipMemcpyAsync(P->host + 2 * C + 2, P->red + 2 * C + 2, C * sizeof(double),
-                               hipMemcpyDeviceToHost, P->s));
+                               hipMemcpyDeviceToHost, s));
     }
-    DDI_HIP(hipEventRecord(P->e1, P->s));
+    DDI_HIP(hipEventRecord(P->e1, s));
     DDI_HIP(hipEventSynchronize(P->e1));
     double nsteps = 0.0;
-    for (int k = 0; steps && k < C; ++k) nsteps += P->host[2 * C + 2 + k];
+    for (int k = 0; timing && k < C; ++k) nsteps += P->host[2 * C + 2 + k];
     float ms = 0.f;
     DDI_HIP(hipEventElapsedTime(&ms, P->e0, P->e1));
     double sweep_ms = 0.0;

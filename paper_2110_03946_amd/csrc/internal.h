@@ -135,9 +135,10 @@ hipError_t launch_residual(const float* f, const uint8_t* c, const float* u,
 // Workgroups (partial rows) of launch_residual for an h x w plane.
 int residual_partials(int h, int w);
 
-// out[j] = sum_i partial[i * stride + j] for j < ncols, fixed order.
+// out[j] = sum_i partial[i * stride + j] for j < ncols, fixed order; with
+// zero = true the partials are cleared after being read.
 hipError_t launch_reduce(const double* partial, int nrows, int stride,
-                         int ncols, double* out, hipStream_t s);
+                         int ncols, double* out, hipStream_t s, bool zero = false);
 
 // Partials per channel written by one sweep: one per block.
 inline int sweep_partials(const SweepArgs& a) {

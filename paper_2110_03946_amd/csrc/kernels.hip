@@ -793,11 +793,15 @@ __global__ __launch_bounds__(64 * kResRows) void k_residual(
     }
 }
 
-__global__ __launch_bounds__(kTpb) void k_reduce(const double* __restrict__ partial, int nrows,
-                                                 int stride, double* __restrict__ out) {
+__global__ __launch_bounds__(kTpb) void k_reduce(double* __restrict__ partial, int nrows,
+                                                 int stride, double* __restrict__ out, int zero) {
     const int j = blockIdx.x;
     double s[1] = {0.0};
-    for (int i = threadIdx.x; i < nrows; i += kTpb) s[0] += partial[(int64_t)i * stride + j];
+    for (int i = threadIdx.x; i < nrows; i += kTpb) {
+        double* p = partial + (int64_t)i * stride + j;
+        s[0] += *p;
+        if (zero) *p = 0.0;  // each element is read and cleared by one thread
+    }
     block_reduce<1>(s, out + j);
 }
 
@@ -1055,8 +1059,9 @@ hipError_t launch_residual(const float* f, const uint8_t* c, const float* u, int
 }
 
 hipError_t launch_reduce(const double* partial, int nrows, int stride, int ncols, double* out,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(ncols), dim3(kTpb), 0, s, partial, nrows, stride, out);
+                         hipStream_t s, bool zero) {
+    hipLaunchKernelGGL(k_reduce, dim3(ncols), dim3(kTpb), 0, s, const_cast<double*>(partial),
+                       nrows, stride, out, zero ? 1 : 0);
     return hipGetLastError();
 }
 

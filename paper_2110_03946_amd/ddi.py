@@ -38,7 +38,7 @@ class Params(ctypes.Structure):
                 ("check_every", ctypes.c_int), ("final_residual", ctypes.c_int),
                 ("timing", ctypes.c_int), ("coarse_block", ctypes.c_int),
                 ("coarse_overlap", ctypes.c_int), ("coarse_local_iters", ctypes.c_int),
-                ("local_tol", ctypes.c_float)]
+                ("local_tol", ctypes.c_float), ("use_graph", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

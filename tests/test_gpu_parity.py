@@ -279,3 +279,34 @@ def test_config1_4k_rgb_full_size(ddi):
     say("config1 oracle", st)
     err = check_solution(f, c, u)
     say("config1 max err", err)
+
+
+def test_graph_replays_match_eager(ddi):
+    """use_graph = 1 captures the solve into a HIP graph and replays it; every
+    replay (with eager work and synchronisations in between) must equal the
+    eager solve bit for bit, also after a re-capture for other buffers and
+    when the graph's first batch of sweeps is not enough."""
+    f, c = workload(3, 300, 400, 0.04, wl=8)
+    ft, ct = dev(f), dev(c)
+    say("graph: eager reference")
+    with ddi.Plan(300, 400, 3, levels=3) as plan:
+        ref, st_ref = plan.solve(ft, ct)
+        ref = host(ref)
+    with ddi.Plan(300, 400, 3, levels=3, use_graph=1) as plan:
+        u1 = torch.empty_like(ft)
+        u2 = torch.empty_like(ft)
+        for rep in range(4):
+            say("graph replay", rep)
+            out = u1 if rep < 3 else u2  # the last one re-captures
+            _, st = plan.solve(ft, ct, out)
+            junk = torch.randn(1 << 20, device="cuda").sum()  # eager work in between
+            torch.cuda.synchronize()
+            assert np.array_equal(host(out), ref), rep
+            assert st["sweeps"] == st_ref["sweeps"]
+        # a harder input needs more sweeps than the captured batch
+        f2, c2 = workload(3, 300, 400, 0.02, "clustered", wl=9)
+        say("graph: longer solve")
+        out, st2 = plan.solve(dev(f2), dev(c2), u1)
+        with ddi.Plan(300, 400, 3, levels=3) as p2:
+            ref2, _ = p2.solve(dev(f2), dev(c2))
+        assert np.array_equal(host(out), host(ref2))
