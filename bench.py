@@ -61,6 +61,13 @@ def solver_params() -> dict:
                 rel_tol=5e-4, min_sweeps=2, max_sweeps=30, check_every=1, final_residual=0)
 
 
+def batch_params(sizes):
+    """Per-image solver parameters of the batched workload (one Params per
+    (height, width))."""
+    from paper_2110_03946_amd import ddi
+    return [ddi.default_params(**solver_params()) for _ in sizes]
+
+
 def sweep_work(p: dict, sweeps: int, cg_steps: float):
     """Algorithmic flops and HBM bytes of the finest-level sweeps of a solve
     (`sweeps` launches, `cg_steps` block CG steps actually run)."""

@@ -177,6 +177,46 @@ int ddi_solve(ddi_plan* plan, const float* f, const uint8_t* c, float* u,
 /* Release the plan and its device buffers. NULL is a no-op. */
 int ddi_destroy(ddi_plan* plan);
 
+/* ---- batched solve ------------------------------------------------------
+ * Many images of uneven size solved together: every step of the scheme
+ * (coarsening, transposed masks, the sweeps of each level, prolongation,
+ * the stop tests) runs as one launch over the work items of all images, so
+ * that small images fill the GPU together and a batch costs the launches of
+ * one image. Each image keeps its own stop test; results equal those of
+ * ddi_solve on each image with the same parameters (the same kernels run on
+ * the same data), bit for bit.
+ */
+typedef struct ddi_batch ddi_batch;
+
+/*
+ * Create a batch plan for n images; image i is heights[i] x widths[i] with
+ * `channels` channels (shared by all). p is NULL (defaults), one params
+ * struct (n_params = 1) or one per image (n_params = n), e.g. picked per
+ * size by a tuner. min_sweeps, max_sweeps, check_every and timing must be
+ * equal across images (the finest-level sweeps run in lock step); use_graph
+ * is ignored. Allocates every device buffer once.
+ * Errors: DDI_EINVAL, DDI_ENOMEM, DDI_ENODEV, DDI_EHIP.
+ */
+int ddi_batch_create(ddi_batch** out, int n, const int* heights,
+                     const int* widths, int channels, const ddi_params* p,
+                     int n_params, void* stream);
+
+/*
+ * Inpaint all images: f[i], c[i], u[i] are device pointers laid out as for
+ * ddi_solve (host arrays of n pointers). st (n entries) and status (n codes:
+ * DDI_OK, DDI_EINVAL for a mask byte > 1, DDI_ESINGULAR, DDI_ENOCONV) may
+ * be NULL; st[i].ms and st[i].sweep_ms are those of the whole batch.
+ * Returns DDI_OK when every image converged, else the first image's error
+ * code in order (or DDI_EHIP / DDI_EINVAL for the call itself). Synchronises
+ * the stream.
+ */
+int ddi_batch_solve(ddi_batch* b, const float* const* f,
+                    const uint8_t* const* c, float* const* u, ddi_stats* st,
+                    int* status);
+
+/* Release the batch plan. NULL is a no-op. */
+int ddi_batch_destroy(ddi_batch* b);
+
 /* Text for an error code (static storage). */
 const char* ddi_strerror(int code);
 

@@ -9,25 +9,20 @@
 #include <new>
 #include <vector>
 
-#include "../../include/ddi.h"
-#include "internal.h"
+#include "plan.h"
 
 using namespace ddi;
 
 namespace {
-
 int g_last_hip = 0;
+}  // namespace
 
-int hip_fail(hipError_t e) {
+int ddi::hip_fail(hipError_t e) {
     g_last_hip = (int)e;
     return DDI_EHIP;
 }
 
-#define DDI_HIP(call)                                  \
-    do {                                               \
-        hipError_t e_ = (call);                        \
-        if (e_ != hipSuccess) return hip_fail(e_);     \
-    } while (0)
+namespace ddi {
 
 BlockGrid make_grid(int h, int w, int block, int overlap) {
     BlockGrid g;
@@ -43,7 +38,7 @@ BlockGrid make_grid(int h, int w, int block, int overlap) {
 }
 
 SweepArgs make_sweep(int h, int w, int channels, int block, int overlap, float alpha, int k,
-                     float local_tol = 0.f) {
+                     float local_tol) {
     SweepArgs a;
     a.local_tol2 = local_tol * local_tol;
     a.g = make_grid(h, w, block, overlap);
@@ -71,17 +66,10 @@ int check_dims(int h, int w, int channels) {
     return DDI_OK;
 }
 
-struct Level {
-    int h = 0, w = 0;
-    const float* f = nullptr;
-    const uint8_t* c = nullptr;
-    float* fown = nullptr;
-    uint8_t* cown = nullptr;
-    float* u[2] = {nullptr, nullptr};
-    uint64_t* mbits = nullptr;  // column-transposed unknown-pixel bits
-    bool own_u0 = false;
-    SweepArgs sw;
-};
+
+}  // namespace ddi
+
+namespace {
 
 // Device scratch a step call needs, freed on scope exit.
 struct Scratch {
@@ -93,31 +81,7 @@ struct Scratch {
 
 }  // namespace
 
-struct ddi_plan {
-    int h = 0, w = 0, C = 0;
-    ddi_params p;
-    hipStream_t s = nullptr;
-    std::vector<Level> lv;
-    double* part = nullptr;
-    size_t part_n = 0;
-    double* red = nullptr;   // [C + 2] stats, [C] norms, [C] CG step totals
-    double* host = nullptr;  // pinned mirror of red
-    double* cgcnt = nullptr; // timing: CG steps per finest-level block
-    int* ctl = nullptr;      // device stop test: done, sweeps, error, -, rel (double)
-    void* hctl = nullptr;    // pinned mirror of ctl
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    std::vector<hipEvent_t> sweep_ev;  // 2 per finest-level sweep (timing)
-    int last_sweeps = -1;              // finest-level sweeps of the previous solve
-    // graph mode: a plan-owned stream, and the instantiated graph of the
-    // solve's first batch with the key it was captured for
-    hipStream_t gs = nullptr;
-    hipEvent_t ev_in = nullptr;
-    hipGraphExec_t g_exec = nullptr;
-    const void* g_f = nullptr;
-    const void* g_c = nullptr;
-    const void* g_u = nullptr;
-    int g_start = -1, g_batch = -1;
-};
+
 
 extern "C" {
 

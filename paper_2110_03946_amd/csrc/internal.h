@@ -59,6 +59,52 @@ __host__ __device__ inline int block_count(int n, int size, int ov) {
     return (n - ov + stride - 1) / stride;
 }
 
+// One image's part of a batched sweep launch: its workgroups are the
+// logical range [wg0, wg0 + blocks * channels).
+struct SweepJob {
+    const float* uin;
+    const uint64_t* mbits;
+    float* uout;
+    double* partial;
+    double* cg_steps;
+    const int* ctl;
+    SweepArgs a;
+    int wg0;
+};
+
+// One image at one level for the batched level kernels (coarsening,
+// prolongation, initial guess, transposed masks). Unused fields are null.
+struct LevelJob {
+    const float* f;       // level data (the finer level for coarsening/prolongation)
+    const uint8_t* c;
+    float* fo;            // coarsening output
+    uint8_t* co;
+    const float* uc;      // prolongation input (coarse iterate)
+    float* u;             // prolongation / initial-guess output
+    uint64_t* mbits;      // transposed-mask output
+    double* stats;        // coarsening statistics partials (or null)
+    int h, w, hc, wc;     // fine and coarse sizes
+    int gx, rows;         // workgroup columns, coarse rows per workgroup
+    int wg0;              // first workgroup of the job in the launch
+};
+
+// One image's stop test in a batched k_decide launch.
+struct DecideJob {
+    const double* partial;
+    const double* stats;
+    int* ctl;
+    double* rel;
+    double tol2;  // squared tolerance, < 0: never passes
+    int nb;       // sweep partial rows (blocks)
+};
+
+// One image's column sums in a batched reduction.
+struct ReduceJob {
+    const double* partial;
+    double* out;
+    int nrows, stride;
+};
+
 // ---- launchers (kernels.hip); all asynchronous on `s` ----
 
 // Largest block edge the sweep kernel holds on chip (one wave64 per block:
@@ -139,6 +185,40 @@ int residual_partials(int h, int w);
 // zero = true the partials are cleared after being read.
 hipError_t launch_reduce(const double* partial, int nrows, int stride,
                          int ncols, double* out, hipStream_t s, bool zero = false);
+
+// ---- batched launchers: one launch for the jobs of many images; job
+// arrays live in device memory, sorted by wg0 (the first job at 0) ----
+
+// Register layout of the sweep for blocks of height bh.
+void sweep_instance(int bh, int* rpw, bool* ragged);
+// All jobs of one launch must share the sweep instance (rpw, ragged).
+hipError_t launch_sweep_batch(const SweepJob* jobs, int njobs, int total_wg, int rpw,
+                              bool ragged, hipStream_t s);
+// Width-4 coarsening / prolongation (every w % 4 == 0, aligned buffers).
+hipError_t launch_coarsen_batch(const LevelJob* jobs, int njobs, int total_wg, int channels,
+                                hipStream_t s);
+hipError_t launch_prolong_batch(const LevelJob* jobs, int njobs, int total_wg, int channels,
+                                hipStream_t s);
+hipError_t launch_init_batch(const LevelJob* jobs, int njobs, int total_wg, int channels,
+                             hipStream_t s);
+hipError_t launch_mask_bits_batch(const LevelJob* jobs, int njobs, int total_wg, hipStream_t s);
+// Stop tests after finest-level sweep n (see launch_decide), one per job.
+hipError_t launch_decide_batch(const DecideJob* jobs, int njobs, int channels, int n,
+                               hipStream_t s);
+hipError_t launch_reduce_batch(const ReduceJob* jobs, int njobs, int ncols, hipStream_t s);
+// Whether the width-4 coarsening / prolongation applies (w % 4 == 0 and
+// vector-aligned buffers); launch_coarsen / launch_prolong take it then.
+bool coarsen4_ok(const float* f, const uint8_t* c, const float* fc, const uint8_t* cc, int w);
+bool prolong4_ok(const float* f, const uint8_t* c, const float* u, int w);
+// Statistics rows launch_coarsen / launch_stats write for these arguments.
+int coarsen_rows(const float* f, const uint8_t* c, const float* fc, const uint8_t* cc, int h,
+                 int w);
+int stats_rows(int h, int w);
+// Workgroups of one job (h, w: the finer level) and its per-job geometry.
+int coarsen4_grid(int h, int w, int* gx, int* rows);
+int prolong4_grid(int h, int w, int* gx);
+int init_grid(int h, int w);
+int mask_bits_grid(int h, int w, int* gx);
 
 // Partials per channel written by one sweep: one per block.
 inline int sweep_partials(const SweepArgs& a) {

@@ -142,16 +142,18 @@ struct ColMask<RPW, true> {
 // do not fit v, r, p and q in 256 VGPRs).
 constexpr int kTileW = kMaxBlock + 2;
 
+// The sweep of logical block lb (channel-major over the block grid) of one
+// image, with the block's tile in `lds` ((RPW + 2) x kTileW floats).
 template <int RPW, bool RAGGED, bool QLDS, bool MBITS>
-__global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
-                                              const uint64_t* __restrict__ mbits,
-                                              float* __restrict__ uout,
-                                              double* __restrict__ partial,
-                                              double* __restrict__ cg_steps,
-                                              const int* __restrict__ ctl, SweepArgs a) {
+__device__ __forceinline__ void sweep_body(const float* __restrict__ uin,
+                                           const uint64_t* __restrict__ mbits,
+                                           float* __restrict__ uout,
+                                           double* __restrict__ partial,
+                                           double* __restrict__ cg_steps,
+                                           const int* __restrict__ ctl, const SweepArgs& a,
+                                           int lb, float* __restrict__ lds) {
     constexpr int TW = kTileW;  // floats per tile row in LDS
     constexpr int CO = 1;       // tile column of block column 0
-    __shared__ __attribute__((aligned(16))) float lds[(RPW + 2) * TW];
     // a solve that has already met its stop test skips the sweeps it had
     // enqueued ahead (ctl[0] is set by k_decide)
     if (ctl && ctl[0] != 0) return;
@@ -159,7 +161,6 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
     const int lane = threadIdx.x;
     const BlockGrid g = a.g;
     const int nblk = g.nby * g.nbx;
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int ch = lb / nblk;
     const int b = lb - ch * nblk;
     const int by = b / g.nbx;
@@ -396,6 +397,43 @@ __global__ void k_clear(double* __restrict__ p, int n) {
     if (i < n) p[i] = 0.0;
 }
 
+template <int RPW, bool RAGGED, bool QLDS, bool MBITS>
+__global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
+                                              const uint64_t* __restrict__ mbits,
+                                              float* __restrict__ uout,
+                                              double* __restrict__ partial,
+                                              double* __restrict__ cg_steps,
+                                              const int* __restrict__ ctl, SweepArgs a) {
+    __shared__ __attribute__((aligned(16))) float lds[(RPW + 2) * kTileW];
+    sweep_body<RPW, RAGGED, QLDS, MBITS>(uin, mbits, uout, partial, cg_steps, ctl, a,
+                                         xcd_remap(blockIdx.x, gridDim.x), lds);
+}
+
+// Index of the job whose workgroup range holds logical workgroup lb (jobs
+// sorted by wg0, jobs[0].wg0 == 0).
+template <class Job>
+__device__ __forceinline__ int find_job(const Job* __restrict__ jobs, int njobs, int lb) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].wg0 <= lb) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One ORAS sweep over the blocks of several images in one launch; the
+// logical workgroup order runs image after image, so the XCD interleave
+// keeps neighbouring blocks of an image together.
+template <int RPW, bool RAGGED, bool QLDS, bool MBITS>
+__global__ __launch_bounds__(64) void k_sweep_batch(const SweepJob* __restrict__ jobs,
+                                                    int njobs) {
+    __shared__ __attribute__((aligned(16))) float lds[(RPW + 2) * kTileW];
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const SweepJob& J = jobs[find_job(jobs, njobs, lb)];
+    sweep_body<RPW, RAGGED, QLDS, MBITS>(J.uin, J.mbits, J.uout, J.partial, J.cg_steps, J.ctl,
+                                         J.a, lb - J.wg0, lds);
+}
+
 // Column-transposed unknown-pixel bits of a mask: word (g, x) holds bit j
 // = 1 iff pixel (64 g + j, x) is unknown (0 beyond the image). One extra
 // all-zero group row follows the last one.
@@ -524,18 +562,19 @@ __global__ __launch_bounds__(kTpb) void k_stats(const float* __restrict__ f,
 // arithmetic as k_coarsen (float64 sum of <= 4 known values).
 
 template <int NC>
-__global__ __launch_bounds__(kTpb) void k_coarsen4(const float* __restrict__ f,
-                                                   const uint8_t* __restrict__ c, int h, int w,
-                                                   float* __restrict__ fc,
-                                                   uint8_t* __restrict__ cc, int hc, int wc,
-                                                   int rows, double* __restrict__ stats) {
-    const int t = blockIdx.x * kTpb + threadIdx.x;  // pair of coarse columns
+__device__ __forceinline__ void coarsen4_body(const float* __restrict__ f,
+                                              const uint8_t* __restrict__ c, int h, int w,
+                                              float* __restrict__ fc, uint8_t* __restrict__ cc,
+                                              int hc, int wc, int rows,
+                                              double* __restrict__ stats, int bx, int by,
+                                              int gx) {
+    const int t = bx * kTpb + threadIdx.x;  // pair of coarse columns
     const int64_t n = (int64_t)h * w, ncs = (int64_t)hc * wc;
     double st[NC + 2];
 #pragma unroll
     for (int j = 0; j < NC + 2; ++j) st[j] = 0.0;
     if (4 * t < w) {
-        for (int I = blockIdx.y * rows; I < min(hc, (blockIdx.y + 1) * rows); ++I) {
+        for (int I = by * rows; I < min(hc, (by + 1) * rows); ++I) {
             uint32_t m[2] = {0u, 0u};
             float4 fv[2][NC];
 #pragma unroll
@@ -550,10 +589,10 @@ __global__ __launch_bounds__(kTpb) void k_coarsen4(const float* __restrict__ f,
                                           : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
             }
-            double s[2][NC];
+            double sm[2][NC];
             int cnt[2] = {0, 0};
 #pragma unroll
-            for (int k = 0; k < NC; ++k) s[0][k] = s[1][k] = 0.0;
+            for (int k = 0; k < NC; ++k) sm[0][k] = sm[1][k] = 0.0;
 #pragma unroll
             for (int a2 = 0; a2 < 2; ++a2) {
 #pragma unroll
@@ -566,7 +605,7 @@ __global__ __launch_bounds__(kTpb) void k_coarsen4(const float* __restrict__ f,
                         for (int k = 0; k < NC; ++k) {
                             const float4 q = fv[a2][k];
                             const double v = b2 == 0 ? q.x : b2 == 1 ? q.y : b2 == 2 ? q.z : q.w;
-                            s[J][k] += v;
+                            sm[J][k] += v;
                             st[k] += v * v;
                         }
                     }
@@ -580,13 +619,33 @@ __global__ __launch_bounds__(kTpb) void k_coarsen4(const float* __restrict__ f,
 #pragma unroll
             for (int k = 0; k < NC; ++k) {
                 float2 out;
-                out.x = cnt[0] > 0 ? (float)(s[0][k] / (double)cnt[0]) : 0.f;
-                out.y = cnt[1] > 0 ? (float)(s[1][k] / (double)cnt[1]) : 0.f;
+                out.x = cnt[0] > 0 ? (float)(sm[0][k] / (double)cnt[0]) : 0.f;
+                out.y = cnt[1] > 0 ? (float)(sm[1][k] / (double)cnt[1]) : 0.f;
                 *reinterpret_cast<float2*>(fc + k * ncs + o) = out;
             }
         }
     }
-    if (stats) block_reduce<NC + 2>(st, stats + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (NC + 2));
+    if (stats) block_reduce<NC + 2>(st, stats + ((int64_t)by * gx + bx) * (NC + 2));
+}
+
+template <int NC>
+__global__ __launch_bounds__(kTpb) void k_coarsen4(const float* __restrict__ f,
+                                                   const uint8_t* __restrict__ c, int h, int w,
+                                                   float* __restrict__ fc,
+                                                   uint8_t* __restrict__ cc, int hc, int wc,
+                                                   int rows, double* __restrict__ stats) {
+    coarsen4_body<NC>(f, c, h, w, fc, cc, hc, wc, rows, stats, blockIdx.x, blockIdx.y,
+                      gridDim.x);
+}
+
+template <int NC>
+__global__ __launch_bounds__(kTpb) void k_coarsen4_batch(const LevelJob* __restrict__ jobs,
+                                                         int njobs) {
+    const int lb = blockIdx.x;
+    const LevelJob& J = jobs[find_job(jobs, njobs, lb)];
+    const int local = lb - J.wg0;
+    coarsen4_body<NC>(J.f, J.c, J.h, J.w, J.fo, J.co, J.hc, J.wc, J.rows, J.stats,
+                      local % J.gx, local / J.gx, J.gx);
 }
 
 // Prolongation for widths divisible by 4: a thread writes fine pixels
@@ -596,12 +655,11 @@ __global__ __launch_bounds__(kTpb) void k_coarsen4(const float* __restrict__ f,
 // columns 2t - 1 .. 2t + 2 (clamped) of two coarse rows. Same float64
 // bilinear expression as k_prolong.
 template <int NC>
-__global__ __launch_bounds__(kTpb) void k_prolong4(const float* __restrict__ uc, int hc, int wc,
-                                                   const float* __restrict__ f,
-                                                   const uint8_t* __restrict__ c, int h, int w,
-                                                   float* __restrict__ u) {
-    const int t = blockIdx.x * kTpb + threadIdx.x;
-    const int y = blockIdx.y;
+__device__ __forceinline__ void prolong4_body(const float* __restrict__ uc, int hc, int wc,
+                                              const float* __restrict__ f,
+                                              const uint8_t* __restrict__ c, int h, int w,
+                                              float* __restrict__ u, int bx, int y) {
+    const int t = bx * kTpb + threadIdx.x;
     if (4 * t >= w) return;
     const int64_t n = (int64_t)h * w, ncs = (int64_t)hc * wc;
     const int64_t i = (int64_t)y * w + 4 * t;
@@ -659,6 +717,58 @@ __global__ __launch_bounds__(kTpb) void k_prolong4(const float* __restrict__ uc,
         out.w = (m & 0xff000000u) ? fk.w : o[3];
         *reinterpret_cast<float4*>(u + k * n + i) = out;
     }
+}
+
+template <int NC>
+__global__ __launch_bounds__(kTpb) void k_prolong4(const float* __restrict__ uc, int hc, int wc,
+                                                   const float* __restrict__ f,
+                                                   const uint8_t* __restrict__ c, int h, int w,
+                                                   float* __restrict__ u) {
+    prolong4_body<NC>(uc, hc, wc, f, c, h, w, u, blockIdx.x, blockIdx.y);
+}
+
+template <int NC>
+__global__ __launch_bounds__(kTpb) void k_prolong4_batch(const LevelJob* __restrict__ jobs,
+                                                         int njobs) {
+    const int lb = blockIdx.x;
+    const LevelJob& J = jobs[find_job(jobs, njobs, lb)];
+    const int local = lb - J.wg0;
+    prolong4_body<NC>(J.uc, J.hc, J.wc, J.f, J.c, J.h, J.w, J.u, local % J.gx, local / J.gx);
+}
+
+// u = c ? f : 0 for several images (one grid1d range per job).
+__global__ __launch_bounds__(kTpb) void k_init_batch(const LevelJob* __restrict__ jobs, int njobs,
+                                                     int channels) {
+    const int lb = blockIdx.x;
+    const LevelJob& J = jobs[find_job(jobs, njobs, lb)];
+    const int64_t n = (int64_t)J.h * J.w;
+    const int64_t i = (int64_t)(lb - J.wg0) * kTpb + threadIdx.x;
+    if (i >= n) return;
+    const bool known = J.c[i] != 0;
+    for (int k = 0; k < channels; ++k) J.u[k * n + i] = known ? J.f[k * n + i] : 0.f;
+}
+
+// Transposed masks of several (image, level) pairs: job range = gx x groups.
+__global__ __launch_bounds__(256) void k_mask_bits_batch(const LevelJob* __restrict__ jobs,
+                                                         int njobs) {
+    const int lb = blockIdx.x;
+    const LevelJob& J = jobs[find_job(jobs, njobs, lb)];
+    const int local = lb - J.wg0;
+    const int h = J.h, w = J.w;
+    const int x = (local % J.gx) * 256 + threadIdx.x;
+    const int gy = local / J.gx;
+    const int groups = mask_bit_groups(h);
+    if (x >= w || gy >= groups) return;
+    uint64_t bits = 0;
+    if (gy < groups - 1) {
+        uint8_t m[64];
+#pragma unroll
+        for (int j = 0; j < 64; ++j) m[j] = J.c[(int64_t)min(gy * 64 + j, h - 1) * w + x];
+#pragma unroll
+        for (int j = 0; j < 64; ++j)
+            if (gy * 64 + j < h && m[j] == 0) bits |= 1ull << j;
+    }
+    J.mbits[(int64_t)gy * w + x] = bits;
 }
 
 // Column-transposed masks of several levels in one launch (grid.z = level).
@@ -805,6 +915,16 @@ __global__ __launch_bounds__(kTpb) void k_reduce(double* __restrict__ partial, i
     block_reduce<1>(s, out + j);
 }
 
+// Column sums of several images' partials: workgroup (job j, column k).
+__global__ __launch_bounds__(kTpb) void k_reduce_batch(const ReduceJob* __restrict__ jobs,
+                                                       int ncols) {
+    const ReduceJob& J = jobs[blockIdx.x / ncols];
+    const int j = blockIdx.x % ncols;
+    double s[1] = {0.0};
+    for (int i = threadIdx.x; i < J.nrows; i += kTpb) s[0] += J.partial[(int64_t)i * J.stride + j];
+    block_reduce<1>(s, J.out + j);
+}
+
 // Stop test on the device after finest-level sweep number n (1-based),
 // launched only at the sweeps where the test applies. ctl[0] = done,
 // ctl[1] = the sweep after which the test passed, ctl[2] = error (1: mask
@@ -815,11 +935,10 @@ __global__ __launch_bounds__(kTpb) void k_reduce(double* __restrict__ partial, i
 constexpr int kDecideTpb = 1024;
 
 template <int NC>
-__global__ __launch_bounds__(kDecideTpb) void k_decide(const double* __restrict__ partial, int nb,
-                                                       const double* __restrict__ stats,
-                                                       int* __restrict__ ctl,
-                                                       double* __restrict__ rel, double tol2,
-                                                       int n) {
+__device__ __forceinline__ void decide_body(const double* __restrict__ partial, int nb,
+                                            const double* __restrict__ stats,
+                                            int* __restrict__ ctl, double* __restrict__ rel,
+                                            double tol2, int n) {
     if (ctl[0] != 0) return;  // an earlier test passed: sweep n did not run
     __shared__ double sm[kDecideTpb / 64][NC];
     double v[NC];
@@ -859,6 +978,24 @@ __global__ __launch_bounds__(kDecideTpb) void k_decide(const double* __restrict_
             ctl[0] = 1;
         }
     }
+}
+
+template <int NC>
+__global__ __launch_bounds__(kDecideTpb) void k_decide(const double* __restrict__ partial, int nb,
+                                                       const double* __restrict__ stats,
+                                                       int* __restrict__ ctl,
+                                                       double* __restrict__ rel, double tol2,
+                                                       int n) {
+    decide_body<NC>(partial, nb, stats, ctl, rel, tol2, n);
+}
+
+// One stop test per image after finest-level sweep n: workgroup j tests
+// job j.
+template <int NC>
+__global__ __launch_bounds__(kDecideTpb) void k_decide_batch(const DecideJob* __restrict__ jobs,
+                                                             int n) {
+    const DecideJob& J = jobs[blockIdx.x];
+    decide_body<NC>(J.partial, J.nb, J.stats, J.ctl, J.rel, J.tol2, n);
 }
 
 __global__ void k_clear_int(int* __restrict__ p, int n) {
@@ -967,7 +1104,7 @@ int coarsen_partials(int h, int w) {
 hipError_t launch_coarsen(const float* f, const uint8_t* c, int h, int w, int channels,
                           float* fc, uint8_t* cc, double* stats, int* nwg, hipStream_t s) {
     const int hc = (h + 1) / 2, wc = (w + 1) / 2;
-    if (w % 4 == 0 && aligned(f, 16) && aligned(c, 4) && aligned(fc, 8) && aligned(cc, 2)) {
+    if (coarsen4_ok(f, c, fc, cc, w)) {
         const int gx = (w / 4 + kTpb - 1) / kTpb;
         const int rows = coarsen4_rows(hc, gx);
         dim3 grid(gx, (hc + rows - 1) / rows);
@@ -1026,7 +1163,7 @@ hipError_t launch_init(const float* f, const uint8_t* c, int h, int w, int chann
 
 hipError_t launch_prolong(const float* uc, int hc, int wc, const float* f, const uint8_t* c,
                           int h, int w, int channels, float* u, hipStream_t s) {
-    if (w % 4 == 0 && aligned(f, 16) && aligned(c, 4) && aligned(u, 16)) {
+    if (prolong4_ok(f, c, u, w)) {
         dim3 grid((w / 4 + kTpb - 1) / kTpb, h);
         switch (channels) {
 #define DDI_CASE(NC)                                                                          \
@@ -1062,6 +1199,117 @@ hipError_t launch_reduce(const double* partial, int nrows, int stride, int ncols
                          hipStream_t s, bool zero) {
     hipLaunchKernelGGL(k_reduce, dim3(ncols), dim3(kTpb), 0, s, const_cast<double*>(partial),
                        nrows, stride, out, zero ? 1 : 0);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batched launchers (one launch for the jobs of many images)
+// ---------------------------------------------------------------------------
+
+void sweep_instance(int bh, int* rpw, bool* ragged) {
+    *rpw = bh > 32 ? 64 : bh > 16 ? 32 : bh > 8 ? 16 : 8;
+    *ragged = bh != *rpw;
+}
+
+hipError_t launch_sweep_batch(const SweepJob* jobs, int njobs, int total_wg, int rpw,
+                              bool ragged, hipStream_t s) {
+    if (total_wg <= 0 || njobs <= 0) return hipSuccess;
+#define DDI_SB(R, G, Q, M)                                                                   \
+    hipLaunchKernelGGL((k_sweep_batch<R, G, Q, M>), dim3(total_wg), dim3(64), 0, s, jobs, njobs)
+    switch (rpw) {
+        case 64: if (ragged) DDI_SB(64, true, true, true); else DDI_SB(64, false, true, true); break;
+        case 32: if (ragged) DDI_SB(32, true, false, false); else DDI_SB(32, false, false, false); break;
+        case 16: if (ragged) DDI_SB(16, true, false, false); else DDI_SB(16, false, false, false); break;
+        case 8: if (ragged) DDI_SB(8, true, false, false); else DDI_SB(8, false, false, false); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef DDI_SB
+    return hipGetLastError();
+}
+
+bool coarsen4_ok(const float* f, const uint8_t* c, const float* fc, const uint8_t* cc, int w) {
+    return w % 4 == 0 && aligned(f, 16) && aligned(c, 4) && aligned(fc, 8) && aligned(cc, 2);
+}
+
+bool prolong4_ok(const float* f, const uint8_t* c, const float* u, int w) {
+    return w % 4 == 0 && aligned(f, 16) && aligned(c, 4) && aligned(u, 16);
+}
+
+int coarsen_rows(const float* f, const uint8_t* c, const float* fc, const uint8_t* cc, int h,
+                 int w) {
+    int gx, rows;
+    if (coarsen4_ok(f, c, fc, cc, w)) return coarsen4_grid(h, w, &gx, &rows);
+    return grid1d((int64_t)((h + 1) / 2) * ((w + 1) / 2));
+}
+
+int stats_rows(int h, int w) { return std::min(grid1d((int64_t)h * w), 1024); }
+
+int coarsen4_grid(int h, int w, int* gx, int* rows) {
+    const int hc = (h + 1) / 2;
+    *gx = (w / 4 + kTpb - 1) / kTpb;
+    *rows = coarsen4_rows(hc, *gx);
+    return *gx * ((hc + *rows - 1) / *rows);
+}
+
+int prolong4_grid(int h, int w, int* gx) {
+    *gx = (w / 4 + kTpb - 1) / kTpb;
+    return *gx * h;
+}
+
+int init_grid(int h, int w) { return grid1d((int64_t)h * w); }
+
+int mask_bits_grid(int h, int w, int* gx) {
+    *gx = (w + 255) / 256;
+    return *gx * mask_bit_groups(h);
+}
+
+#define DDI_NC_SWITCH(KERNEL, GRID, BLOCK, ...)                                           \
+    switch (channels) {                                                                  \
+        case 1: hipLaunchKernelGGL(KERNEL<1>, dim3(GRID), dim3(BLOCK), 0, s, __VA_ARGS__); break; \
+        case 2: hipLaunchKernelGGL(KERNEL<2>, dim3(GRID), dim3(BLOCK), 0, s, __VA_ARGS__); break; \
+        case 3: hipLaunchKernelGGL(KERNEL<3>, dim3(GRID), dim3(BLOCK), 0, s, __VA_ARGS__); break; \
+        case 4: hipLaunchKernelGGL(KERNEL<4>, dim3(GRID), dim3(BLOCK), 0, s, __VA_ARGS__); break; \
+        default: return hipErrorInvalidValue;                                            \
+    }
+
+hipError_t launch_coarsen_batch(const LevelJob* jobs, int njobs, int total_wg, int channels,
+                                hipStream_t s) {
+    if (total_wg <= 0) return hipSuccess;
+    DDI_NC_SWITCH(k_coarsen4_batch, total_wg, kTpb, jobs, njobs)
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_batch(const LevelJob* jobs, int njobs, int total_wg, int channels,
+                                hipStream_t s) {
+    if (total_wg <= 0) return hipSuccess;
+    DDI_NC_SWITCH(k_prolong4_batch, total_wg, kTpb, jobs, njobs)
+    return hipGetLastError();
+}
+
+hipError_t launch_decide_batch(const DecideJob* jobs, int njobs, int channels, int n,
+                               hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    DDI_NC_SWITCH(k_decide_batch, njobs, kDecideTpb, jobs, n)
+    return hipGetLastError();
+}
+#undef DDI_NC_SWITCH
+
+hipError_t launch_init_batch(const LevelJob* jobs, int njobs, int total_wg, int channels,
+                             hipStream_t s) {
+    if (total_wg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_batch, dim3(total_wg), dim3(kTpb), 0, s, jobs, njobs, channels);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_bits_batch(const LevelJob* jobs, int njobs, int total_wg, hipStream_t s) {
+    if (total_wg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mask_bits_batch, dim3(total_wg), dim3(256), 0, s, jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_batch(const ReduceJob* jobs, int njobs, int ncols, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_batch, dim3(njobs * ncols), dim3(kTpb), 0, s, jobs, ncols);
     return hipGetLastError();
 }
 

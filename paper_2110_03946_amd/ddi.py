@@ -91,6 +91,10 @@ def lib():
             "ddi_coarsen": (i, [vp, vp, i, i, i, vp, vp, vp]),
             "ddi_prolong": (i, [vp, i, i, vp, vp, i, i, i, vp, vp]),
             "ddi_oras_sweep": (i, [vp, vp, vp, i, i, i, i, i, f, i, vp, vp]),
+            "ddi_batch_create": (i, [ctypes.POINTER(vp), i, ip, ip, i, ctypes.POINTER(Params),
+                                     i, vp]),
+            "ddi_batch_solve": (i, [vp, vp, vp, vp, ctypes.POINTER(Stats), ip]),
+            "ddi_batch_destroy": (i, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -221,6 +225,76 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().ddi_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A batch plan for many images of uneven size (ddi_batch_create /
+    ddi_batch_solve / ddi_batch_destroy). `params` is one Params (or None
+    for the defaults, with keyword overrides) or a list with one Params per
+    image."""
+
+    def __init__(self, sizes, channels: int = 3, params=None, stream=None, **overrides):
+        self.sizes = [(int(h), int(w)) for h, w in sizes]
+        n = len(self.sizes)
+        self.channels = channels
+        if params is None:
+            plist = [default_params(**overrides)]
+        elif isinstance(params, Params):
+            plist = [params]
+        else:
+            plist = list(params)
+        for p in plist:
+            for k, v in overrides.items():
+                setattr(p, k, v)
+        self.params = plist
+        arr = (Params * len(plist))(*plist)
+        hs = (ctypes.c_int * n)(*[h for h, _ in self.sizes])
+        ws = (ctypes.c_int * n)(*[w for _, w in self.sizes])
+        h = ctypes.c_void_p()
+        _check(lib().ddi_batch_create(ctypes.byref(h), n, hs, ws, channels, arr, len(plist),
+                                      _stream(stream)), "ddi_batch_create")
+        self._h = h
+
+    def solve(self, fs, cs, us=None, allow_noconv: bool = False):
+        """Inpaint every (f, c) pair into us; returns (us, stats list, status list)."""
+        torch = _torch()
+        n = len(self.sizes)
+        if len(fs) != n or len(cs) != n:
+            raise ValueError(f"expected {n} images and masks")
+        fs = [_img(f, "f", self.channels, hw) for f, hw in zip(fs, self.sizes)]
+        cs = [_mask(c, hw) for c, hw in zip(cs, self.sizes)]
+        if us is None:
+            us = [torch.empty_like(f) for f in fs]
+        else:
+            us = [_img(u, "u", self.channels, hw) for u, hw in zip(us, self.sizes)]
+        P = ctypes.c_void_p * n
+        st = (Stats * n)()
+        status = (ctypes.c_int * n)()
+        rc = lib().ddi_batch_solve(self._h, P(*[t.data_ptr() for t in fs]),
+                                   P(*[t.data_ptr() for t in cs]),
+                                   P(*[t.data_ptr() for t in us]), st, status)
+        codes = list(status)
+        if rc != DDI_OK and not (allow_noconv and all(x in (DDI_OK, DDI_ENOCONV) for x in codes)
+                                 and rc == DDI_ENOCONV):
+            raise DDIError(rc, "ddi_batch_solve")
+        return us, [s.as_dict() for s in st], codes
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ddi_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __enter__(self):

@@ -26,12 +26,18 @@ Mask recipes, numpy ``default_rng(seed)``:
 
 Seed convention used by the tests and the benchmark: image seed
 ``1000 * workload + index``, mask seed ``image seed + 500``.
+
+Batch recipe (``batch_specs``), numpy ``default_rng(seed)``: n images, sizes
+uniform over 640x480, 1280x720, 1920x1080 and 3840x2160, mask densities
+uniform in [0.02, 0.10], exactly half of the masks clustered (a random half),
+the rest Bernoulli.
 """
 from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["make_image", "make_mask", "make_workload", "image_seed", "mask_seed"]
+__all__ = ["make_image", "make_mask", "make_workload", "image_seed", "mask_seed",
+           "batch_specs", "BATCH_SIZES"]
 
 
 def image_seed(workload: int, index: int = 0) -> int:
@@ -104,3 +110,22 @@ def make_workload(h: int, w: int, channels: int, density: float,
     f = make_image(h, w, channels, image_seed(workload, index))
     c = make_mask(h, w, density, kind, mask_seed(workload, index))
     return f, c
+
+
+# (height, width) of the batch recipe
+BATCH_SIZES = ((480, 640), (720, 1280), (1080, 1920), (2160, 3840))
+
+
+def batch_specs(n: int = 48, seed: int = 2, sizes=BATCH_SIZES,
+                densities=(0.02, 0.10)):
+    """List of n dicts (h, w, density, kind, index) for a batch of uneven
+    images; the data of entry i is make_workload(h, w, C, density, kind,
+    workload=seed, index=i)."""
+    rng = np.random.default_rng(seed)
+    pick = rng.integers(0, len(sizes), size=n)
+    dens = rng.uniform(densities[0], densities[1], size=n)
+    clustered = np.zeros(n, dtype=bool)
+    clustered[rng.permutation(n)[: n // 2]] = True
+    return [dict(h=int(sizes[k][0]), w=int(sizes[k][1]), density=float(d),
+                 kind="clustered" if cl else "bernoulli", index=i)
+            for i, (k, d, cl) in enumerate(zip(pick, dens, clustered))]
