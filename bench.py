@@ -1,12 +1,18 @@
-"""Benchmark: 4K RGB homogeneous diffusion inpainting by multilevel ORAS on one
+"""Benchmark: homogeneous diffusion inpainting by multilevel ORAS on one
 MI355X.
 
-One step = one full solve (all levels, every kernel of the path, the float64
-stop tests and the final residual certificate) of a 3840 x 2160 x 3 float32
-frame with a 4 % i.i.d. Bernoulli mask shared by the channels, 64 x 64
-blocks with overlap 4, four levels (coarsest 1/8). Inputs are synthetic
-(paper_2110_03946_amd.synth) and already resident in HBM when the timed
-region starts.
+Default workload (--workload 4k): one step = one full solve (all levels,
+every kernel of the path and the float64 stop tests) of a 3840 x 2160 x 3
+float32 frame with a 4 % i.i.d. Bernoulli mask shared by the channels, 64 x
+64 blocks with overlap 4, four levels (coarsest 1/8).
+
+--workload batch: one step = one batched solve of 48 RGB float32 images of
+uneven size (sizes uniform over 640x480 .. 3840x2160, mask densities uniform
+in 2-10 %, half of the masks clustered), each with the autotuned parameters
+of its class; it also times the plain single-image path on the same images.
+
+Inputs are synthetic (paper_2110_03946_amd.synth) and already resident in
+HBM when the timed region starts.
 
 Prints one JSON line. Besides the driver's fields it carries
   roofline      the finest-level ORAS sweep (the dominant kernel): its
@@ -14,11 +20,14 @@ Prints one JSON line. Besides the driver's fields it carries
                 launch on the solver's stream during the timed region, the
                 algorithmic float32 work per launch, and the peak it is
                 held against;
-  cpu_baseline  the float64 CPU oracle on the same frame (all 3 channels);
-  max_err_grey  max |u - u_oracle| over the frame on the 0-255 scale;
+  cpu_baseline  the float64 CPU oracle (4k: the same frame; batch: a sample
+                of the images, scaled to frames of the batch's mix);
+  max_err_grey  max |u - u_oracle| on the 0-255 scale (batch: over the
+                sample);
   p50_ms/p99_ms latency of the timed solves.
 
 Usage: python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu]
+                       [--workload 4k|batch]
 """
 from __future__ import annotations
 
@@ -61,27 +70,51 @@ def solver_params() -> dict:
                 rel_tol=5e-4, min_sweeps=2, max_sweeps=30, check_every=1, final_residual=0)
 
 
-def batch_params(sizes):
-    """Per-image solver parameters of the batched workload (one Params per
-    (height, width))."""
-    from paper_2110_03946_amd import ddi
-    return [ddi.default_params(**solver_params()) for _ in sizes]
+def batch_params(specs):
+    """Per-image solver parameters of the batched workload: the autotuner's
+    entry for each image's class (size, mask kind, density)."""
+    from paper_2110_03946_amd import autotune, ddi
+    table = autotune.load_table()
+    return [ddi.default_params(**autotune.params_for(table, s["h"], s["w"], s["kind"],
+                                                     s["density"])) for s in specs]
 
 
-def sweep_work(p: dict, sweeps: int, cg_steps: float):
+def sweep_work(p: dict, sweeps: int, cg_steps: float, h: int = H, w: int = W, ch: int = C):
     """Algorithmic flops and HBM bytes of the finest-level sweeps of a solve
-    (`sweeps` launches, `cg_steps` block CG steps actually run)."""
+    of an h x w x ch image (`sweeps` launches, `cg_steps` block CG steps
+    actually run)."""
     from paper_2110_03946_amd import ddi
-    nby = ddi.block_count(H, p["block"], p["overlap"])
-    nbx = ddi.block_count(W, p["block"], p["overlap"])
-    bh, bw = min(p["block"], H), min(p["block"], W)
-    blocks = nby * nbx * C
+    nby = ddi.block_count(h, p["block"], p["overlap"])
+    nbx = ddi.block_count(w, p["block"], p["overlap"])
+    bh, bw = min(p["block"], h), min(p["block"], w)
+    blocks = nby * nbx * ch
     flops = bh * bw * (blocks * sweeps * FLOPS_RESIDUAL + cg_steps * FLOPS_PER_CG_STEP)
     # per launch: the iterate is read once and written once (float32), plus
     # the transposed mask (one bit per pixel); re-reads of the tile overlap
     # are not algorithmic (the L2 serves them)
-    bytes_ = sweeps * (C * H * W * 8 + H * W // 8)
+    bytes_ = sweeps * (ch * h * w * 8 + h * w // 8)
     return flops, bytes_
+
+
+def roofline_of(flops: float, bytes_: float, sweep_ms: float, launches: int) -> dict:
+    """Roofline object of the finest-level sweep: achieved rate against the
+    bound its arithmetic intensity puts it under (ridge = peak flops / peak
+    bytes per second)."""
+    tflops = flops / (sweep_ms / 1e3) / 1e12
+    gbs = bytes_ / (sweep_ms / 1e3) / 1e9
+    intensity = flops / bytes_
+    ridge = VALU_F32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if intensity >= ridge:
+        r = {"bound": "alu", "achieved": round(tflops, 3), "peak": round(VALU_F32_PEAK_TFLOPS, 1),
+             "unit": "TFLOP/s", "frac": round(tflops / VALU_F32_PEAK_TFLOPS, 4)}
+    else:
+        r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    r.update({"avg_launch_us": round(sweep_ms / max(launches, 1) * 1e3, 2),
+              "flops_per_byte": round(intensity, 2), "ridge_flops_per_byte": round(ridge, 2),
+              "valu_tflops": round(tflops, 3), "valu_frac": round(tflops / VALU_F32_PEAK_TFLOPS, 4),
+              "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+    return r
 
 
 def measured_traffic():
@@ -132,12 +165,125 @@ def cpu_baseline(f, c, u_gpu):
                       f"iterations), {t:.1f} s"}, err
 
 
+BATCH_N, BATCH_SEED = 48, 2
+METRIC_BATCH = "batched uneven RGB frames/s at ≤0.5 grey-level err vs FP64"
+
+
+def run_batch(args):
+    """48 uneven RGB images in one batched solve per step (autotuned
+    parameters per image class), beside the plain single-image path."""
+    import torch
+    from paper_2110_03946_amd import ddi, synth
+    specs = synth.batch_specs(BATCH_N, BATCH_SEED)
+    print(f"[bench] generating {len(specs)} images", file=sys.stderr, flush=True)
+    data = [synth.make_workload(s["h"], s["w"], C, s["density"], s["kind"], workload=BATCH_SEED,
+                                index=s["index"]) for s in specs]
+    fs = [torch.from_numpy(f).cuda() for f, _ in data]
+    cs = [torch.from_numpy(c).cuda() for _, c in data]
+    us = [torch.empty_like(f) for f in fs]
+    prms = batch_params(specs)
+    for p in prms:
+        p.timing = 1
+        p.final_residual = 0
+    sizes = [(s["h"], s["w"]) for s in specs]
+    b = ddi.Batch(sizes, C, params=prms)
+    for _ in range(args.warmup):
+        b.solve(fs, cs, us)
+    torch.cuda.synchronize()
+    lat, sweep_ms, launches, flops, bytes_ = [], 0.0, 0, 0.0, 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        _, st, _ = b.solve(fs, cs, us)
+        lat.append((time.perf_counter() - ts) * 1e3)
+        sweep_ms += st[0]["sweep_ms"]
+        launches += max(x["sweeps"] for x in st)
+        for (h, w), p, x in zip(sizes, prms, st):
+            fl, by = sweep_work(p.as_dict(), x["sweeps"], x["cg_steps"], h, w)
+            flops += fl
+            bytes_ += by
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fps = args.steps * len(specs) / elapsed
+    sweeps = [x["sweeps"] for x in st]
+
+    # the plain single-image path on the same images and parameters
+    plans = []
+    for (h, w), p in zip(sizes, prms):
+        q = ddi.Params.from_buffer_copy(p)
+        q.timing = 0
+        plans.append(ddi.Plan(h, w, C, params=q))
+    for pl, f, c, u in zip(plans, fs, cs, us):
+        pl.solve(f, c, u)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 5)
+    single_lat = []
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        for pl, f, c, u in zip(plans, fs, cs, us):
+            ts = time.perf_counter()
+            pl.solve(f, c, u)
+            single_lat.append((time.perf_counter() - ts) * 1e3)
+    torch.cuda.synchronize()
+    single_fps = reps * len(specs) / (time.perf_counter() - t1)
+    for pl in plans:
+        pl.close()
+    b.solve(fs, cs, us)  # us hold the batched results again
+
+    roofline = roofline_of(flops, bytes_, sweep_ms, launches)
+    roofline.update({"traffic": None,
+                     "kernel": "k_sweep_batch<64> (finest-level ORAS sweep, all images)"})
+    npix = sum(h * w for h, w in sizes)
+    out = {"metric": METRIC_BATCH, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{len(specs)} RGB f32 images of uneven size "
+                                  "(640x480/1280x720/1920x1080/3840x2160), masks 2-10 %, half "
+                                  "clustered; batched multilevel ORAS, autotuned per class",
+                      "images": len(specs), "megapixels": round(npix / 1e6, 2)},
+           "p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "single_image_path": {"frames_per_s": round(single_fps, 2),
+                                 "p50_ms": round(float(np.percentile(single_lat, 50)), 3),
+                                 "p99_ms": round(float(np.percentile(single_lat, 99)), 3)},
+           "batch_speedup": round(fps / single_fps, 3),
+           "sweeps_per_image": [min(sweeps), max(sweeps)],
+           "roofline": roofline}
+    if not args.no_cpu:
+        import oracle
+        seen, sample = set(), []
+        for i, s in enumerate(specs):
+            if (s["h"], s["w"]) not in seen:
+                seen.add((s["h"], s["w"]))
+                sample.append(i)
+        t = 0.0
+        err = 0.0
+        for i in sample:
+            f, c = data[i]
+            t0 = time.perf_counter()
+            ex = oracle.solve_exact(f.astype(np.float64), c)
+            t += time.perf_counter() - t0
+            err = max(err, float(np.abs(us[i].cpu().numpy().astype(np.float64) - ex).max()))
+        spix = sum(specs[i]["h"] * specs[i]["w"] for i in sample)
+        out["cpu_baseline"] = {
+            "value": round(spix / t / (npix / len(specs)), 4), "unit": "frames/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"images {sample} (one per size, {spix / 1e6:.1f} Mpx, {t:.1f} s): float64 "
+                      "CG to relative residual 1e-12; pixel rate scaled to frames of the "
+                      "batch's mean size"}
+        out["max_err_grey"] = round(err, 4)
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--workload", choices=["4k", "batch"], default="4k")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB device-to-device copy (the known-size "
                          "reference for FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -168,6 +314,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "batch":
+        run_batch(args)
+        return
 
     f_np, c_np = synth.make_workload(H, W, C, DENSITY, "bernoulli", workload=1)
     f = torch.from_numpy(f_np).cuda()
@@ -195,30 +344,13 @@ def main():
     fps = args.steps / elapsed
 
     flops, bytes_ = sweep_work(prm, nsweeps, steps)
-    avg_sweep_s = sweep_ms / max(nsweeps, 1) / 1e3
-    tflops = flops / (sweep_ms / 1e3) / 1e12
-    gbs = bytes_ / (sweep_ms / 1e3) / 1e9
-    # the kernel's bound is set by its arithmetic intensity against the
-    # machine's ridge point (peak flops / peak bytes per second)
-    intensity = flops / bytes_
-    ridge = VALU_F32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if intensity >= ridge:
-        roofline = {"bound": "alu", "achieved": round(tflops, 3),
-                    "peak": round(VALU_F32_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-                    "frac": round(tflops / VALU_F32_PEAK_TFLOPS, 4)}
-    else:
-        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    roofline = roofline_of(flops, bytes_, sweep_ms, nsweeps)
     roofline.update({"traffic": measured_traffic(),
-                "kernel": "k_sweep<64> (finest-level ORAS sweep)",
-                "avg_launch_us": round(avg_sweep_s * 1e6, 2),
-                "flops_per_byte": round(intensity, 2), "ridge_flops_per_byte": round(ridge, 2),
-                "valu_tflops": round(tflops, 3),
-                "valu_frac": round(tflops / VALU_F32_PEAK_TFLOPS, 4),
-                "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                "cg_steps_per_block_sweep": round(steps / max(nsweeps, 1) /
-                                                  (ddi.block_count(H, prm["block"], prm["overlap"]) *
-                                                   ddi.block_count(W, prm["block"], prm["overlap"]) * C), 2)})
+                     "kernel": "k_sweep<64> (finest-level ORAS sweep)",
+                     "cg_steps_per_block_sweep": round(
+                         steps / max(nsweeps, 1) /
+                         (ddi.block_count(H, prm["block"], prm["overlap"]) *
+                          ddi.block_count(W, prm["block"], prm["overlap"]) * C), 2)})
 
     u_np = u.cpu().numpy()
     out = {"metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,

@@ -172,7 +172,7 @@ def test_batch_recipe_sample_vs_oracle(ddi):
     data = [synth.make_workload(s["h"], s["w"], C, s["density"], s["kind"], workload=3,
                                 index=s["index"]) for s in specs]
     say("batch recipe sample", [(s["h"], s["w"], s["kind"], round(s["density"], 3)) for s in specs])
-    prms = bench.batch_params([(s["h"], s["w"]) for s in specs])
+    prms = bench.batch_params(specs)
     with ddi.Batch([(s["h"], s["w"]) for s in specs], C, params=prms) as b:
         us, st, codes = b.solve([dev(f) for f, _ in data], [dev(c) for _, c in data])
     assert codes == [0] * len(data)
