@@ -55,6 +55,9 @@ extern "C" {
 /* Largest block edge (pixels) the on-chip local solver supports. */
 #define DDI_MAX_BLOCK 64
 
+/* Largest coarsest level (pixels) of the float64 coarse solve. */
+#define DDI_COARSE_MAX_PIXELS 8192
+
 /*
  * Solver parameters. Fill with ddi_default_params, then override.
  *   block          S: edge of a square block, overlap included (Sec. 4),
@@ -95,6 +98,14 @@ extern "C" {
  *                  first batch of finest-level sweeps) into a HIP graph on a
  *                  stream the plan owns, and replay it on later solves with
  *                  the same f, c and u pointers (ignored with timing = 1).
+ *   coarse_solver  0: coarsest_sweeps ORAS sweeps on the coarsest level;
+ *                  1: solve the coarsest level in float64 by conjugate
+ *                  gradients (one workgroup per channel; the coarsest level
+ *                  must have at most DDI_COARSE_MAX_PIXELS pixels -- add
+ *                  levels for large images).
+ *   coarse_cg_iters cap on CG steps of coarse_solver = 1, >= 1.
+ *   coarse_cg_tol  coarse_solver = 1 stops once ||b - A u||_2 <= tol ||b||_2
+ *                  on the coarsest level (float64), >= 0.
  */
 typedef struct ddi_params {
     int block;
@@ -115,6 +126,9 @@ typedef struct ddi_params {
     int coarse_local_iters;
     float local_tol;
     int use_graph;
+    int coarse_solver;
+    int coarse_cg_iters;
+    double coarse_cg_tol;
 } ddi_params;
 
 /*
@@ -146,10 +160,12 @@ typedef struct ddi_plan ddi_plan;
  * 2 sweeps per coarser level, 3 on the coarsest, rel_tol = 1e-4,
  * min_sweeps = 2, max_sweeps = 50, check_every = 1, final_residual = 1,
  * timing = 0, coarse_block = 0, coarse_overlap = -1, coarse_local_iters = 0,
- * local_tol = 0, use_graph = 0. */
+ * local_tol = 0, use_graph = 0, coarse_solver = 0, coarse_cg_iters = 500,
+ * coarse_cg_tol = 1e-10. */
 int ddi_default_params(ddi_params* p);
 
-/* Check *p for one image size without touching the GPU. */
+/* Check *p for one image size without touching the GPU (this includes the
+ * size of the coarsest level when coarse_solver = 1). */
 int ddi_check_params(int height, int width, int channels, const ddi_params* p);
 
 /*
@@ -277,6 +293,17 @@ int ddi_oras_sweep(const float* u_in, const uint8_t* c, float* u_out,
                    int height, int width, int channels, int block,
                    int overlap, float robin_alpha, int local_iters,
                    double* rsq, void* stream);
+
+/*
+ * Float64 solve of A u = b (Sec. 2, eq. 6) on a small grid, the solver of
+ * the coarsest level (coarse_solver = 1): conjugate gradients on the unknown
+ * pixels in float64, one workgroup per channel, from u = c ? f : 0 until
+ * ||b - A u||_2 <= tol ||b||_2 or max_iter steps; u (float32) receives the
+ * rounded iterate, f on the mask. height * width <= DDI_COARSE_MAX_PIXELS.
+ */
+int ddi_coarse_solve(const float* f, const uint8_t* c, int height, int width,
+                     int channels, float* u, int max_iter, double tol,
+                     void* stream);
 
 #ifdef __cplusplus
 }

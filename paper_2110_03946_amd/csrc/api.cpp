@@ -13,6 +13,8 @@
 
 using namespace ddi;
 
+static_assert(DDI_COARSE_MAX_PIXELS == kCoarseMaxPixels, "coarse solve size limit");
+
 namespace {
 int g_last_hip = 0;
 }  // namespace
@@ -60,6 +62,21 @@ int check_device() {
     return DDI_OK;
 }
 
+int level_count(int h, int w, int levels) {
+    // stop halving once the level is a single pixel
+    int L = 1;
+    while (L < levels) {
+        int hl = h, wl = w;
+        for (int i = 0; i < L; ++i) {
+            hl = (hl + 1) / 2;
+            wl = (wl + 1) / 2;
+        }
+        if (hl == 1 && wl == 1) break;
+        ++L;
+    }
+    return L;
+}
+
 int check_dims(int h, int w, int channels) {
     if (h < 1 || w < 1 || channels < 1 || channels > 4) return DDI_EINVAL;
     if ((int64_t)h * w > (int64_t)1 << 30) return DDI_EINVAL;
@@ -105,6 +122,9 @@ int ddi_default_params(ddi_params* p) {
     p->coarse_local_iters = 0;
     p->local_tol = 0.f;
     p->use_graph = 0;
+    p->coarse_solver = 0;
+    p->coarse_cg_iters = 500;
+    p->coarse_cg_tol = 1e-10;
     return DDI_OK;
 }
 
@@ -129,6 +149,16 @@ int ddi_check_params(int height, int width, int channels, const ddi_params* p) {
     if (p->coarse_local_iters < 0) return DDI_EINVAL;
     if (!(p->local_tol >= 0.f) || p->local_tol > 1e6f) return DDI_EINVAL;
     if (p->use_graph != 0 && p->use_graph != 1) return DDI_EINVAL;
+    if (p->coarse_solver != 0 && p->coarse_solver != 1) return DDI_EINVAL;
+    if (p->coarse_cg_iters < 1 || !(p->coarse_cg_tol >= 0.0)) return DDI_EINVAL;
+    if (p->coarse_solver == 1) {
+        int hl = height, wl = width;
+        for (int l = 1; l < level_count(height, width, p->levels); ++l) {
+            hl = (hl + 1) / 2;
+            wl = (wl + 1) / 2;
+        }
+        if ((int64_t)hl * wl > DDI_COARSE_MAX_PIXELS) return DDI_EINVAL;
+    }
     return DDI_OK;
 }
 
@@ -179,17 +209,7 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
     P->p = prm;
     P->s = (hipStream_t)stream;
 
-    // levels: stop halving once the level is a single pixel
-    int L = 1;
-    while (L < prm.levels) {
-        int hl = height, wl = width;
-        for (int i = 0; i < L; ++i) {
-            hl = (hl + 1) / 2;
-            wl = (wl + 1) / 2;
-        }
-        if (hl == 1 && wl == 1) break;
-        ++L;
-    }
+    const int L = level_count(height, width, prm.levels);
     P->lv.resize(L);
     size_t part_n = 0;
     int hl = height, wl = width;
@@ -336,11 +356,16 @@ static int enqueue_front(ddi_plan* P, int start0, hipStream_t s) {
     }
     const int top = L - 1;
     int cur = (top == 0) ? start0 : 0;
-    DDI_HIP(launch_init(P->lv[top].f, P->lv[top].c, P->lv[top].h, P->lv[top].w, C,
-                        P->lv[top].u[cur], s));
+    if (prm.coarse_solver == 1)
+        DDI_HIP(launch_coarse_cg(P->lv[top].f, P->lv[top].c, P->lv[top].h, P->lv[top].w, C,
+                                 P->lv[top].u[cur], prm.coarse_cg_iters, prm.coarse_cg_tol, s));
+    else
+        DDI_HIP(launch_init(P->lv[top].f, P->lv[top].c, P->lv[top].h, P->lv[top].w, C,
+                            P->lv[top].u[cur], s));
     for (int l = top; l >= 1; --l) {
         Level& lev = P->lv[l];
-        const int n = (l == top) ? prm.coarsest_sweeps : prm.coarse_sweeps;
+        const int n = (l == top) ? (prm.coarse_solver == 1 ? 0 : prm.coarsest_sweeps)
+                                 : prm.coarse_sweeps;
         for (int i = 0; i < n; ++i) {
             DDI_HIP(launch_sweep(lev.u[cur], lev.mbits, lev.u[1 - cur], P->part, nullptr, nullptr,
                                  lev.sw, s));
@@ -628,6 +653,18 @@ int ddi_prolong(const float* uc, int hc, int wc, const float* f, const uint8_t* 
     if (hc != (height + 1) / 2 || wc != (width + 1) / 2) return DDI_EINVAL;
     if ((e = check_device())) return e;
     DDI_HIP(launch_prolong(uc, hc, wc, f, c, height, width, channels, u, (hipStream_t)stream));
+    return DDI_OK;
+}
+
+int ddi_coarse_solve(const float* f, const uint8_t* c, int height, int width, int channels,
+                     float* u, int max_iter, double tol, void* stream) {
+    int e = check_dims(height, width, channels);
+    if (e) return e;
+    if (!f || !c || !u || max_iter < 1 || !(tol >= 0.0)) return DDI_EINVAL;
+    if ((int64_t)height * width > kCoarseMaxPixels) return DDI_EINVAL;
+    if ((e = check_device())) return e;
+    DDI_HIP(launch_coarse_cg(f, c, height, width, channels, u, max_iter, tol,
+                             (hipStream_t)stream));
     return DDI_OK;
 }
 

@@ -118,8 +118,8 @@ hipError_t run_sweeps(const std::vector<SweepLaunch>& ls, hipStream_t s) {
 // uploaded before the first launch is enqueued).
 struct Front {
     struct Step {
-        enum Kind { Coarsen, CoarsenOne, StatsOne, Reduce, MaskBits, Init, Sweep, Prolong,
-                    ProlongOne } kind;
+        enum Kind { Coarsen, CoarsenOne, StatsOne, Reduce, MaskBits, Init, CoarseCg, Sweep,
+                    Prolong, ProlongOne } kind;
         const void* jobs = nullptr;
         int njobs = 0, total_wg = 0;
         std::vector<SweepLaunch> sweeps;
@@ -128,6 +128,13 @@ struct Front {
     std::vector<Step> steps;
     std::vector<int> nwg;  // statistics rows per image
 };
+
+// ORAS sweeps an image runs on level l >= 1 of its pyramid.
+int coarse_sweeps_at(const ddi_plan* P, int l) {
+    const int L = (int)P->lv.size();
+    if (l != L - 1) return P->p.coarse_sweeps;
+    return P->p.coarse_solver == 1 ? 0 : P->p.coarsest_sweeps;
+}
 
 // Builds the front for images with start buffers start0 (finest level).
 // Pointers of level 0 must be set in the plans already.
@@ -233,16 +240,30 @@ void build_front(ddi_batch* B, const std::vector<int>& start0, Arena& A, Front& 
         F.steps.push_back(st);
     }
 
-    // start on each image's coarsest level
+    // start on each image's coarsest level: u = c ? f : 0, or its float64
+    // solve
     std::vector<int> cur(n, 0);
     {
         std::vector<LevelJob> jobs;
+        std::vector<CoarseJob> cg;
         int wg = 0;
         for (int i = 0; i < n; ++i) {
             ddi_plan* P = B->plans[i];
             const int top = (int)P->lv.size() - 1;
             cur[i] = top == 0 ? start0[i] : 0;
             const Level& lev = P->lv[top];
+            if (P->p.coarse_solver == 1) {
+                CoarseJob j{};
+                j.f = lev.f;
+                j.c = lev.c;
+                j.u = lev.u[cur[i]];
+                j.h = lev.h;
+                j.w = lev.w;
+                j.max_iter = P->p.coarse_cg_iters;
+                j.tol2 = P->p.coarse_cg_tol * P->p.coarse_cg_tol;
+                cg.push_back(j);
+                continue;
+            }
             LevelJob j{};
             j.f = lev.f;
             j.c = lev.c;
@@ -253,12 +274,21 @@ void build_front(ddi_batch* B, const std::vector<int>& start0, Arena& A, Front& 
             wg += init_grid(lev.h, lev.w);
             jobs.push_back(j);
         }
-        Front::Step st;
-        st.kind = Front::Step::Init;
-        st.jobs = A.put(jobs);
-        st.njobs = (int)jobs.size();
-        st.total_wg = wg;
-        F.steps.push_back(st);
+        if (!jobs.empty()) {
+            Front::Step st;
+            st.kind = Front::Step::Init;
+            st.jobs = A.put(jobs);
+            st.njobs = (int)jobs.size();
+            st.total_wg = wg;
+            F.steps.push_back(st);
+        }
+        if (!cg.empty()) {
+            Front::Step st;
+            st.kind = Front::Step::CoarseCg;
+            st.jobs = A.put(cg);
+            st.njobs = (int)cg.size();
+            F.steps.push_back(st);
+        }
     }
 
     // coarse levels, coarsest first: sweeps, then prolongation one level down
@@ -267,7 +297,7 @@ void build_front(ddi_batch* B, const std::vector<int>& start0, Arena& A, Front& 
         for (ddi_plan* P : B->plans) {
             const int L = (int)P->lv.size();
             if (L <= l) continue;
-            nmax = std::max(nmax, l == L - 1 ? P->p.coarsest_sweeps : P->p.coarse_sweeps);
+            nmax = std::max(nmax, coarse_sweeps_at(P, l));
         }
         for (int k = 0; k < nmax; ++k) {
             std::vector<SweepJob> jobs;
@@ -275,7 +305,7 @@ void build_front(ddi_batch* B, const std::vector<int>& start0, Arena& A, Front& 
                 ddi_plan* P = B->plans[i];
                 const int L = (int)P->lv.size();
                 if (L <= l) continue;
-                const int ni = l == L - 1 ? P->p.coarsest_sweeps : P->p.coarse_sweeps;
+                const int ni = coarse_sweeps_at(P, l);
                 if (k >= ni) continue;
                 Level& lev = P->lv[l];
                 SweepJob j{};
@@ -365,6 +395,9 @@ int enqueue_front(ddi_batch* B, const Front& F) {
                 break;
             case Front::Step::Init:
                 e = launch_init_batch((const LevelJob*)st.jobs, st.njobs, st.total_wg, C, s);
+                break;
+            case Front::Step::CoarseCg:
+                e = launch_coarse_cg_batch((const CoarseJob*)st.jobs, st.njobs, C, s);
                 break;
             case Front::Step::Sweep:
                 e = run_sweeps(st.sweeps, s);

@@ -88,6 +88,19 @@ struct LevelJob {
     int wg0;              // first workgroup of the job in the launch
 };
 
+// Largest level (pixels) the float64 coarsest-level solve takes: one
+// workgroup holds the level's search direction in LDS.
+constexpr int kCoarseMaxPixels = 8192;
+
+// One image's float64 coarsest-level solve in a batched launch.
+struct CoarseJob {
+    const float* f;
+    const uint8_t* c;
+    float* u;
+    int h, w, max_iter;
+    double tol2;  // squared relative tolerance
+};
+
 // One image's stop test in a batched k_decide launch.
 struct DecideJob {
     const double* partial;
@@ -219,6 +232,13 @@ int coarsen4_grid(int h, int w, int* gx, int* rows);
 int prolong4_grid(int h, int w, int* gx);
 int init_grid(int h, int w);
 int mask_bits_grid(int h, int w, int* gx);
+
+// Float64 CG solve of the coarsest level (h * w <= kCoarseMaxPixels), one
+// workgroup per channel: u = exact solution (rounded to float32) once
+// ||b - A u|| <= tol ||C f||, or after max_iter steps.
+hipError_t launch_coarse_cg(const float* f, const uint8_t* c, int h, int w, int channels,
+                            float* u, int max_iter, double tol, hipStream_t s);
+hipError_t launch_coarse_cg_batch(const CoarseJob* jobs, int njobs, int channels, hipStream_t s);
 
 // Partials per channel written by one sweep: one per block.
 inline int sweep_partials(const SweepArgs& a) {

@@ -1003,6 +1003,147 @@ __global__ void k_clear_int(int* __restrict__ p, int n) {
     if (i < n) p[i] = 0;
 }
 
+// ---------------------------------------------------------------------------
+// Float64 solve of the coarsest level (Sec. 2 system, eq. 6, on the coarse
+// grid): conjugate gradients on the unknown pixels, known pixels fixed at
+// their value, in one workgroup per channel. Thread t owns pixels t,
+// t + kCgTpb, ... of the level; the search direction lives in LDS for the
+// neighbour reads of the matvec; the two dot products of a step are
+// fixed-order block reductions. Starts from u = c ? f : 0 and stops once
+// ||r||^2 <= tol2 ||C f||^2 or after max_iter steps.
+// ---------------------------------------------------------------------------
+constexpr int kCgTpb = 1024;
+constexpr int kCgPer = kCoarseMaxPixels / kCgTpb;
+
+// Sum of v over the workgroup, returned to every thread (fixed order).
+__device__ __forceinline__ double cg_block_sum(double v, double* red) {
+    v = wave_sum_d(v);
+    const int wv = threadIdx.x >> 6;
+    __syncthreads();  // earlier readers of red are done
+    if ((threadIdx.x & 63) == 0) red[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kCgTpb / 64; ++i) s += red[i];
+    return s;
+}
+
+__device__ __forceinline__ void coarse_cg_body(const float* __restrict__ f,
+                                               const uint8_t* __restrict__ c, int h, int w,
+                                               float* __restrict__ u, int max_iter, double tol2,
+                                               int ch, double* __restrict__ sh,
+                                               double* __restrict__ red) {
+    const int n = h * w;
+    const float* F = f + (int64_t)ch * n;
+    float* U = u + (int64_t)ch * n;
+    const int t = threadIdx.x;
+    double x[kCgPer], r[kCgPer], p[kCgPer];
+    bool unk[kCgPer];
+    // in-image neighbours of each owned pixel: bit 0 up, 1 down, 2 left,
+    // 3 right
+    int nbm[kCgPer];
+    // start: u = c ? f : 0, staged for the residual's neighbour reads
+    double b2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < kCgPer; ++j) {
+        const int i = t + j * kCgTpb;
+        const bool in = i < n;
+        const bool known = in && c[i] != 0;
+        unk[j] = in && !known;
+        const int yy = in ? i / w : 0, xx = i - yy * w;
+        nbm[j] = (yy > 0 ? 1 : 0) | (yy < h - 1 ? 2 : 0) | (xx > 0 ? 4 : 0) | (xx < w - 1 ? 8 : 0);
+        x[j] = known ? (double)F[i] : 0.0;
+        b2 += known ? x[j] * x[j] : 0.0;
+        if (in) sh[i] = x[j];
+    }
+    b2 = cg_block_sum(b2, red);  // also orders the writes of sh before the reads
+    // r = b - A x: for an unknown pixel the sum over in-image neighbours of
+    // (x_q - x_p); 0 on the mask
+    double rho = 0.0;
+#pragma unroll
+    for (int j = 0; j < kCgPer; ++j) {
+        const int i = t + j * kCgTpb;
+        double rv = 0.0;
+        if (unk[j]) {
+            if (nbm[j] & 1) rv += sh[i - w] - x[j];
+            if (nbm[j] & 2) rv += sh[i + w] - x[j];
+            if (nbm[j] & 4) rv += sh[i - 1] - x[j];
+            if (nbm[j] & 8) rv += sh[i + 1] - x[j];
+        }
+        r[j] = rv;
+        p[j] = rv;
+        rho += rv * rv;
+    }
+    rho = cg_block_sum(rho, red);
+    const double stop = tol2 * b2;
+    for (int it = 0; it < max_iter && rho > stop; ++it) {
+        __syncthreads();  // all reads of sh from the previous step are done
+#pragma unroll
+        for (int j = 0; j < kCgPer; ++j) {
+            const int i = t + j * kCgTpb;
+            if (i < n) sh[i] = p[j];
+        }
+        __syncthreads();
+        double q[kCgPer];
+        double pq = 0.0;
+#pragma unroll
+        for (int j = 0; j < kCgPer; ++j) {
+            const int i = t + j * kCgTpb;
+            double qv = 0.0;
+            if (unk[j]) {
+                // (A p)_i = deg_i p_i - sum of the neighbours' p (p = 0 on
+                // the mask), deg_i = number of in-image neighbours
+                double s = 0.0, deg = 0.0;
+                if (nbm[j] & 1) { s += sh[i - w]; deg += 1.0; }
+                if (nbm[j] & 2) { s += sh[i + w]; deg += 1.0; }
+                if (nbm[j] & 4) { s += sh[i - 1]; deg += 1.0; }
+                if (nbm[j] & 8) { s += sh[i + 1]; deg += 1.0; }
+                qv = deg * p[j] - s;
+            }
+            q[j] = qv;
+            pq += p[j] * qv;
+        }
+        pq = cg_block_sum(pq, red);
+        if (!(pq > 0.0)) break;
+        const double alpha = rho / pq;
+        double rr = 0.0;
+#pragma unroll
+        for (int j = 0; j < kCgPer; ++j) {
+            x[j] += alpha * p[j];
+            r[j] -= alpha * q[j];
+            rr += r[j] * r[j];
+        }
+        rr = cg_block_sum(rr, red);
+        const double beta = rr / rho;
+        rho = rr;
+#pragma unroll
+        for (int j = 0; j < kCgPer; ++j) p[j] = r[j] + beta * p[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kCgPer; ++j) {
+        const int i = t + j * kCgTpb;
+        if (i < n) U[i] = (float)x[j];
+    }
+}
+
+__global__ __launch_bounds__(kCgTpb) void k_coarse_cg64(const float* __restrict__ f,
+                                                        const uint8_t* __restrict__ c, int h,
+                                                        int w, float* __restrict__ u,
+                                                        int max_iter, double tol2) {
+    __shared__ double sh[kCoarseMaxPixels];
+    __shared__ double red[kCgTpb / 64];
+    coarse_cg_body(f, c, h, w, u, max_iter, tol2, blockIdx.x, sh, red);
+}
+
+// Several images: workgroup (job j, channel k) = blockIdx.x = j * channels + k.
+__global__ __launch_bounds__(kCgTpb) void k_coarse_cg64_batch(const CoarseJob* __restrict__ jobs,
+                                                              int channels) {
+    __shared__ double sh[kCoarseMaxPixels];
+    __shared__ double red[kCgTpb / 64];
+    const CoarseJob& J = jobs[blockIdx.x / channels];
+    coarse_cg_body(J.f, J.c, J.h, J.w, J.u, J.max_iter, J.tol2, blockIdx.x % channels, sh, red);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1310,6 +1451,21 @@ hipError_t launch_mask_bits_batch(const LevelJob* jobs, int njobs, int total_wg,
 hipError_t launch_reduce_batch(const ReduceJob* jobs, int njobs, int ncols, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_reduce_batch, dim3(njobs * ncols), dim3(kTpb), 0, s, jobs, ncols);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_cg(const float* f, const uint8_t* c, int h, int w, int channels,
+                            float* u, int max_iter, double tol, hipStream_t s) {
+    if ((int64_t)h * w > kCoarseMaxPixels || channels < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_coarse_cg64, dim3(channels), dim3(kCgTpb), 0, s, f, c, h, w, u,
+                       max_iter, tol * tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_cg_batch(const CoarseJob* jobs, int njobs, int channels, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coarse_cg64_batch, dim3(njobs * channels), dim3(kCgTpb), 0, s, jobs,
+                       channels);
     return hipGetLastError();
 }
 

@@ -32,6 +32,8 @@ SweepArgs make_sweep(int h, int w, int channels, int block, int overlap, float a
                      float local_tol = 0.f);
 // DDI_OK when a gfx950 device is current.
 int check_device();
+// Levels a plan builds for h x w: `levels`, fewer once a level is 1 x 1.
+int level_count(int h, int w, int levels);
 // DDI_OK for 1 <= h, w; 1 <= channels <= 4; h * w <= 2^30.
 int check_dims(int h, int w, int channels);
 

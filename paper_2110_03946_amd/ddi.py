@@ -27,6 +27,7 @@ DDI_ENOCONV = -4
 DDI_EHIP = -5
 DDI_ENODEV = -6
 MAX_BLOCK = 64
+COARSE_MAX_PIXELS = 8192
 
 
 class Params(ctypes.Structure):
@@ -38,7 +39,9 @@ class Params(ctypes.Structure):
                 ("check_every", ctypes.c_int), ("final_residual", ctypes.c_int),
                 ("timing", ctypes.c_int), ("coarse_block", ctypes.c_int),
                 ("coarse_overlap", ctypes.c_int), ("coarse_local_iters", ctypes.c_int),
-                ("local_tol", ctypes.c_float), ("use_graph", ctypes.c_int)]
+                ("local_tol", ctypes.c_float), ("use_graph", ctypes.c_int),
+                ("coarse_solver", ctypes.c_int), ("coarse_cg_iters", ctypes.c_int),
+                ("coarse_cg_tol", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,6 +94,7 @@ def lib():
             "ddi_coarsen": (i, [vp, vp, i, i, i, vp, vp, vp]),
             "ddi_prolong": (i, [vp, i, i, vp, vp, i, i, i, vp, vp]),
             "ddi_oras_sweep": (i, [vp, vp, vp, i, i, i, i, i, f, i, vp, vp]),
+            "ddi_coarse_solve": (i, [vp, vp, i, i, i, vp, i, d, vp]),
             "ddi_batch_create": (i, [ctypes.POINTER(vp), i, ip, ip, i, ctypes.POINTER(Params),
                                      i, vp]),
             "ddi_batch_solve": (i, [vp, vp, vp, vp, ctypes.POINTER(Stats), ip]),
@@ -358,6 +362,19 @@ def prolong(uc, f, c, u=None, stream=None):
         u = torch.empty_like(f)
     _check(lib().ddi_prolong(_ptr(uc), uc.shape[1], uc.shape[2], _ptr(f), _ptr(c), H, W, C,
                              _ptr(u), _stream(stream)), "ddi_prolong")
+    return u
+
+
+def coarse_solve(f, c, max_iter: int = 500, tol: float = 1e-10, u=None, stream=None):
+    """Float64 CG solve of a small grid (the coarsest-level solver)."""
+    torch = _torch()
+    f = _img(f, "f")
+    C, H, W = f.shape
+    c = _mask(c, (H, W))
+    if u is None:
+        u = torch.empty_like(f)
+    _check(lib().ddi_coarse_solve(_ptr(f), _ptr(c), H, W, C, _ptr(u), max_iter, float(tol),
+                                  _stream(stream)), "ddi_coarse_solve")
     return u
 
 

@@ -37,6 +37,32 @@ def test_bad_params_rejected(field, value):
     assert ddi.check_params(64, 64, 1, p) == ddi.DDI_EINVAL
 
 
+def _header_struct_fields(name):
+    import re
+    txt = open(os.path.join(os.path.dirname(__file__), "..", "include", "ddi.h")).read()
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), txt, re.S).group(1)
+    return re.findall(r"^\s*(?:int|float|double)\s+(\w+);", body, re.M)
+
+
+def test_binding_structs_match_header():
+    assert [f for f, _ in ddi.Params._fields_] == _header_struct_fields("ddi_params")
+    assert [f for f, _ in ddi.Stats._fields_] == _header_struct_fields("ddi_stats")
+
+
+def test_coarse_solver_size_limit():
+    """The float64 coarsest-level solve takes at most 8192 pixels: 4K needs
+    6 levels (120 x 68) for it."""
+    p = ddi.default_params(coarse_solver=1, levels=4)
+    assert ddi.check_params(2160, 3840, 3, p) == ddi.DDI_EINVAL
+    p.levels = 6
+    assert ddi.check_params(2160, 3840, 3, p) == ddi.DDI_OK
+    p = ddi.default_params(coarse_solver=1, levels=1)
+    assert ddi.check_params(64, 128, 1, p) == ddi.DDI_OK
+    assert ddi.check_params(64, 129, 1, p) == ddi.DDI_EINVAL
+    p = ddi.default_params(coarse_cg_iters=0)
+    assert ddi.check_params(64, 64, 1, p) == ddi.DDI_EINVAL
+
+
 @pytest.mark.parametrize("h,w,ch", [(0, 5, 1), (5, 0, 1), (5, 5, 0), (5, 5, 5)])
 def test_bad_dims_rejected(h, w, ch):
     assert ddi.check_params(h, w, ch, ddi.default_params()) == ddi.DDI_EINVAL
