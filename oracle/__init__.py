@@ -30,6 +30,10 @@ Contents
                    that makes RAS into ORAS (Sec. 3).
   local_cg         k steps of conjugate gradients on a local system (Sec. 4).
   oras_step        one ORAS iteration, eqs. 7-9.
+  correction_step  one ORAS iteration on the residual-correction equation
+                   A d = r (d = 0 on the mask) that iterative refinement
+                   solves: the same local solves and partition of unity
+                   applied to a general right-hand side.
   ml_oras          coarse-to-fine multilevel ORAS (Sec. 4).
   inverse_inf_norm ||K_UU^{-1}||_inf, which turns a residual bound into a
                    guaranteed bound on the error of an inpainting.
@@ -449,6 +453,44 @@ def oras_step(u, f, c, size: int, overlap: int, alpha: float, k: int | None,
         out[ys:ye, xs:xe] += v[ys - y0:ye - y0, xs - x0:xe - x0]
         rsq += float(np.sum(r[ys:ye, xs:xe] ** 2))
     return out, rsq
+
+
+def correction_step(d, rhs, c, size: int, overlap: int, alpha: float, k: int | None,
+                    blocks=None):
+    """One (O)RAS iteration of Sec. 3 (eqs. 7-9) on A d = rhs, where A is the
+    matrix of eq. 6 and the mask rows carry d = 0 (rhs must vanish there).
+
+    This is the correction equation of iterative refinement: if u has
+    u = f on the mask and rhs = b - A u, then A (u + d) = b exactly when
+    A d = rhs, and one iteration here from d equals oras_step from u + d
+    minus u (the residual rhs - A d equals b - A (u + d)). Residual of d:
+    0 on the mask, rhs_p + sum over in-image 4-neighbours q of (d_q - d_p)
+    elsewhere.
+    """
+    d = np.asarray(d, dtype=np.float64)
+    rhs = np.asarray(rhs, dtype=np.float64)
+    c = np.asarray(c)
+    h, w = c.shape
+    oy, bh = block_origins(h, size, overlap)
+    ox, bw = block_origins(w, size, overlap)
+    ly, hy = owner_bounds(oy, bh, h)
+    lx, hx = owner_bounds(ox, bw, w)
+    if blocks is None:
+        blocks = [(i, j) for i in range(len(oy)) for j in range(len(ox))]
+    ld = np.zeros_like(d)
+    ld[:, :-1] += d[:, 1:] - d[:, :-1]
+    ld[:, 1:] += d[:, :-1] - d[:, 1:]
+    ld[:-1, :] += d[1:, :] - d[:-1, :]
+    ld[1:, :] += d[:-1, :] - d[1:, :]
+    r = np.where(c == 1, 0.0, rhs + ld)
+    out = d.copy()
+    for by, bx in blocks:
+        y0, x0 = oy[by], ox[bx]
+        M = local_matrix(c, y0, x0, bh, bw, alpha)
+        v = local_cg(M, r[y0:y0 + bh, x0:x0 + bw].reshape(-1), k).reshape(bh, bw)
+        ys, ye, xs, xe = ly[by], hy[by], lx[bx], hx[bx]
+        out[ys:ye, xs:xe] += v[ys - y0:ye - y0, xs - x0:xe - x0]
+    return out
 
 
 def ml_oras(f, c, levels: int, size: int, overlap: int, alpha: float,

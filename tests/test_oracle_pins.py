@@ -436,3 +436,54 @@ def test_multilevel_converges_to_exact():
     u_coarse_only = oracle.ml_oras(f, c, 3, 16, 4, 0.5, 10, [0, 3, 3])
     u_zero = np.where(c == 1, f, 0.0)
     assert np.abs(u_coarse_only - ue).max() < np.abs(u_zero - ue).max()
+
+
+# ---------------------------------------------------------------------------
+# correction equation of iterative refinement
+# ---------------------------------------------------------------------------
+
+def _corr_case(seed=5):
+    f, c = synth.make_workload(40, 52, 1, 0.08, "bernoulli", workload=20, index=seed)
+    f, c = f[0].astype(np.float64), c
+    rng = np.random.default_rng(seed)
+    u = np.where(c == 1, f, rng.uniform(0, 255, f.shape))
+    return f, c, u
+
+
+def test_correction_step_from_zero_is_oras_step():
+    """From d = 0 with rhs = b - A u, one correction iteration is the ORAS
+    iteration from u, shifted by u (the local problems see the same
+    residual)."""
+    f, c, u = _corr_case()
+    r = oracle.residual(f, c, u)
+    d = oracle.correction_step(np.zeros_like(u), r, c, 16, 4, 0.3, 6)
+    u1, _ = oracle.oras_step(u, f, c, 16, 4, 0.3, 6)
+    np.testing.assert_allclose(u + d, u1, atol=1e-9, rtol=0)
+
+
+def test_correction_step_general_start():
+    """From any d with d = 0 on the mask: u + correction_step(d, b - A u)
+    equals oras_step(u + d)."""
+    f, c, u = _corr_case(6)
+    rng = np.random.default_rng(1)
+    d = np.where(c == 1, 0.0, rng.normal(0, 10, u.shape))
+    r = oracle.residual(f, c, u)
+    d1 = oracle.correction_step(d, r, c, 12, 2, 1.0, 5)
+    u1, _ = oracle.oras_step(u + d, f, c, 12, 2, 1.0, 5)
+    np.testing.assert_allclose(u + d1, u1, atol=1e-9, rtol=0)
+
+
+def test_correction_step_fixed_point_and_convergence():
+    """The exact solution has rhs = 0 and stays a fixed point; iterating
+    the correction equation from d = 0 drives u + d to the exact solution."""
+    f, c, _ = _corr_case(7)
+    ex = oracle.solve_exact(f, c)
+    r0 = oracle.residual(f, c, ex)
+    d = oracle.correction_step(np.zeros_like(ex), r0, c, 16, 4, 0.3, 8)
+    assert np.abs(d).max() < 1e-8
+    u = np.where(c == 1, f, 0.0)
+    r = oracle.residual(f, c, u)
+    d = np.zeros_like(u)
+    for _ in range(60):
+        d = oracle.correction_step(d, r, c, 16, 4, 0.3, 8)
+    np.testing.assert_allclose(u + d, ex, atol=1e-6)
