@@ -106,6 +106,19 @@ extern "C" {
  *   coarse_cg_iters cap on CG steps of coarse_solver = 1, >= 1.
  *   coarse_cg_tol  coarse_solver = 1 stops once ||b - A u||_2 <= tol ||b||_2
  *                  on the coarsest level (float64), >= 0.
+ *   storage        0: the finest level iterates on u in float32 (ORAS sweeps
+ *                  on A u = b). 1: mixed precision with iterative
+ *                  refinement: after the coarse-to-fine start u_0 (float32),
+ *                  refinement step k forms r_k = b - A u_k from the float32
+ *                  u_k (stored in bfloat16, its norm in float64), runs
+ *                  inner_sweeps ORAS sweeps on the correction equation
+ *                  A d = r_k from d = 0 with d stored in bfloat16 (float32
+ *                  arithmetic), and sets u_{k+1} = u_k + d in float32. The
+ *                  stop test applies to r_k, so min_sweeps, max_sweeps and
+ *                  check_every count refinement steps, and the returned u_k
+ *                  is the iterate whose residual was tested. Single-image
+ *                  plans only.
+ *   inner_sweeps   correction sweeps per refinement step (storage = 1), >= 1.
  */
 typedef struct ddi_params {
     int block;
@@ -129,6 +142,8 @@ typedef struct ddi_params {
     int coarse_solver;
     int coarse_cg_iters;
     double coarse_cg_tol;
+    int storage;
+    int inner_sweeps;
 } ddi_params;
 
 /*
@@ -144,6 +159,8 @@ typedef struct ddi_params {
  *   cg_steps      with timing = 1: local CG steps run by the finest-level
  *                 sweeps, summed over blocks and channels (fewer than blocks
  *                 x local_iters when local_tol stops blocks early).
+ *   refinements   storage = 1: refinement steps taken (the finest-level
+ *                 sweeps are then refinements x inner_sweeps); 0 otherwise.
  */
 typedef struct ddi_stats {
     int sweeps;
@@ -152,6 +169,7 @@ typedef struct ddi_stats {
     double ms;
     double sweep_ms;
     double cg_steps;
+    int refinements;
 } ddi_stats;
 
 typedef struct ddi_plan ddi_plan;
@@ -161,7 +179,7 @@ typedef struct ddi_plan ddi_plan;
  * min_sweeps = 2, max_sweeps = 50, check_every = 1, final_residual = 1,
  * timing = 0, coarse_block = 0, coarse_overlap = -1, coarse_local_iters = 0,
  * local_tol = 0, use_graph = 0, coarse_solver = 0, coarse_cg_iters = 500,
- * coarse_cg_tol = 1e-10. */
+ * coarse_cg_tol = 1e-10, storage = 0, inner_sweeps = 2. */
 int ddi_default_params(ddi_params* p);
 
 /* Check *p for one image size without touching the GPU (this includes the
@@ -304,6 +322,29 @@ int ddi_oras_sweep(const float* u_in, const uint8_t* c, float* u_out,
 int ddi_coarse_solve(const float* f, const uint8_t* c, int height, int width,
                      int channels, float* u, int max_iter, double tol,
                      void* stream);
+
+/*
+ * The two steps of the mixed-precision refinement (storage = 1), exposed
+ * for tests. bfloat16 planes (d, rhs) are uint16 bit patterns laid out like
+ * u.
+ *
+ * ddi_refine_residual: u_next = u + d in float32 (d may be NULL: then u_next
+ * is not written and u itself is used), rhs = bfloat16(b - A u_next) of
+ * eq. 7 rounded to nearest even, rsq (host, channels doubles, may be NULL)
+ * = sum of (b - A u_next)^2 per channel in float64.
+ *
+ * ddi_correction_sweep: one ORAS iteration (Sec. 3, eqs. 7-9) on the
+ * refinement equation A d = rhs with d = 0 on the mask: the block residual
+ * rhs - A d_in (float32), k local CG steps, d_out = d_in + owned
+ * corrections rounded to bfloat16. d_in may be NULL (d = 0).
+ */
+int ddi_refine_residual(const float* f, const uint8_t* c, const float* u,
+                        const uint16_t* d, int height, int width, int channels,
+                        float* u_next, uint16_t* rhs, double* rsq, void* stream);
+int ddi_correction_sweep(const uint16_t* d_in, const uint16_t* rhs,
+                         const uint8_t* c, uint16_t* d_out, int height,
+                         int width, int channels, int block, int overlap,
+                         float robin_alpha, int local_iters, void* stream);
 
 #ifdef __cplusplus
 }

@@ -125,6 +125,8 @@ int ddi_default_params(ddi_params* p) {
     p->coarse_solver = 0;
     p->coarse_cg_iters = 500;
     p->coarse_cg_tol = 1e-10;
+    p->storage = 0;
+    p->inner_sweeps = 2;
     return DDI_OK;
 }
 
@@ -151,6 +153,8 @@ int ddi_check_params(int height, int width, int channels, const ddi_params* p) {
     if (p->use_graph != 0 && p->use_graph != 1) return DDI_EINVAL;
     if (p->coarse_solver != 0 && p->coarse_solver != 1) return DDI_EINVAL;
     if (p->coarse_cg_iters < 1 || !(p->coarse_cg_tol >= 0.0)) return DDI_EINVAL;
+    if (p->storage != 0 && p->storage != 1) return DDI_EINVAL;
+    if (p->inner_sweeps < 1) return DDI_EINVAL;
     if (p->coarse_solver == 1) {
         int hl = height, wl = width;
         for (int l = 1; l < level_count(height, width, p->levels); ++l) {
@@ -171,6 +175,9 @@ int ddi_destroy(ddi_plan* plan) {
         for (int i = 0; i < 2; ++i)
             if (l.u[i] && (i == 1 || l.own_u0)) (void)hipFree(l.u[i]);
     }
+    if (plan->r16) (void)hipFree(plan->r16);
+    for (uint16_t* d : plan->d16)
+        if (d) (void)hipFree(d);
     if (plan->part) (void)hipFree(plan->part);
     if (plan->red) (void)hipFree(plan->red);
     if (plan->cgcnt) (void)hipFree(plan->cgcnt);
@@ -275,7 +282,16 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
         ddi_destroy(P);
         return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
     }
-    if (prm.use_graph && !prm.timing) {
+    if (prm.storage == 1) {
+        const size_t nv = (size_t)channels * height * width * sizeof(uint16_t);
+        if ((err = hipMalloc(&P->r16, nv)) != hipSuccess ||
+            (err = hipMalloc(&P->d16[0], nv)) != hipSuccess ||
+            (err = hipMalloc(&P->d16[1], nv)) != hipSuccess) {
+            ddi_destroy(P);
+            return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
+        }
+    }
+    if (prm.use_graph && !prm.timing && prm.storage == 0) {
         // a stream of our own (default priority): the caller's may be the
         // legacy default stream, which cannot be captured
         if ((err = hipStreamCreate(&P->gs)) != hipSuccess ||
@@ -295,7 +311,8 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
             ddi_destroy(P);
             return hip_fail(err);
         }
-        P->sweep_ev.assign(2 * (size_t)prm.max_sweeps, nullptr);
+        const int per = prm.storage == 1 ? prm.inner_sweeps : 1;
+        P->sweep_ev.assign(2 * (size_t)std::max(prm.max_sweeps, 1) * per, nullptr);
         for (hipEvent_t& ev : P->sweep_ev) {
             if ((err = hipEventCreate(&ev)) != hipSuccess) {
                 ddi_destroy(P);
@@ -406,8 +423,121 @@ static int enqueue_sweeps(ddi_plan* P, int from, int to, int start0, bool timing
     return DDI_OK;
 }
 
+// storage = 1: the coarse-to-fine start, then refinement steps k = 0, 1,
+// ...: r_k = b - A u_k (bfloat16, float64 norm, device stop test), then
+// inner_sweeps correction sweeps on A d = r_k from d = 0 (bfloat16), and
+// u_{k+1} = u_k + d fused into the next residual pass. u_k lives in buffer
+// start0 ^ (k & 1) of the finest level; steps are enqueued ahead in batches
+// like the float32 sweeps, and exit at once after the stop test passed.
+static int solve_refine(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats* st) {
+    const int C = P->C;
+    const ddi_params& prm = P->p;
+    Level& L0 = P->lv[0];
+    const bool timing = !P->sweep_ev.empty();
+    hipStream_t s = P->s;
+    const int m = prm.inner_sweeps;
+    const int kmax = prm.max_sweeps;
+    DDI_HIP(hipEventRecord(P->e0, s));
+    const int expect = P->last_sweeps >= 0 ? P->last_sweeps : std::max(prm.min_sweeps, 1);
+    const int start0 = std::min(expect, kmax) & 1;
+    int e = enqueue_front(P, start0, s);
+    if (e) return e;
+    DDI_HIP(launch_clear_int(P->ctl, 4, s));
+    int* ctl = P->ctl;
+    double* drel = reinterpret_cast<double*>(ctl + 4);
+    const int nres = residual_partials(P->h, P->w);
+    auto enqueue_steps = [&](int from, int to) -> int {
+        for (int k = from; k < to; ++k) {
+            const int a = start0 ^ (k & 1);
+            const float* usrc = k == 0 ? L0.u[start0] : L0.u[a ^ 1];
+            const uint16_t* dk = k == 0 ? nullptr : P->d16[(m - 1) & 1];
+            DDI_HIP(launch_refine_residual(f, c, usrc, dk, P->h, P->w, C,
+                                           k == 0 ? nullptr : L0.u[a], P->r16, P->part, ctl,
+                                           nullptr, s));
+            const bool chk = is_check(prm, k);
+            if (chk || k == kmax)
+                DDI_HIP(launch_decide(P->part, nres, C, P->red, ctl, drel, chk ? prm.rel_tol : -1.0,
+                                      k, s));
+            if (k == kmax) break;
+            for (int j = 0; j < m; ++j) {
+                const int ev = k * m + j;
+                if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * ev], s));
+                DDI_HIP(launch_sweep_corr(j == 0 ? nullptr : P->d16[(j - 1) & 1], P->r16, L0.mbits,
+                                          P->d16[j & 1], P->part, timing ? P->cgcnt : nullptr, ctl,
+                                          L0.sw, s));
+                if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * ev + 1], s));
+            }
+        }
+        return DDI_OK;
+    };
+    int done = 0, k_end = kmax;
+    bool converged = false;
+    double rel = INFINITY;
+    int batch = std::min(kmax + 1, expect + 1);
+    while (done <= kmax) {
+        const int to = std::min(kmax + 1, done + batch);
+        if ((e = enqueue_steps(done, to))) return e;
+        done = to;
+        batch = 2;
+        DDI_HIP(hipMemcpyAsync(P->hctl, P->ctl, 4 * sizeof(int) + sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        DDI_HIP(hipStreamSynchronize(s));
+        const int* hc = reinterpret_cast<const int*>(P->hctl);
+        if (hc[2] == 1) return DDI_EINVAL;
+        if (hc[2] == 2) return DDI_ESINGULAR;
+        double rel2;
+        std::memcpy(&rel2, hc + 4, sizeof(rel2));
+        rel = std::sqrt(rel2);
+        if (hc[0] != 0) {
+            k_end = hc[1];
+            converged = true;
+            break;
+        }
+    }
+    P->last_sweeps = k_end;
+    const int cur = start0 ^ (k_end & 1);
+    if (cur == 1)
+        DDI_HIP(hipMemcpyAsync(u, L0.u[1], (size_t)C * P->h * P->w * sizeof(float),
+                               hipMemcpyDeviceToDevice, s));
+    if (timing) {
+        const int nb = sweep_partials(L0.sw);
+        DDI_HIP(launch_reduce(P->cgcnt, nb, C, C, P->red + 2 * C + 2, s, true));
+        DDI_HIP(hipMemcpyAsync(P->host + 2 * C + 2, P->red + 2 * C + 2, C * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    }
+    DDI_HIP(hipEventRecord(P->e1, s));
+    DDI_HIP(hipEventSynchronize(P->e1));
+    float ms = 0.f;
+    DDI_HIP(hipEventElapsedTime(&ms, P->e0, P->e1));
+    double sweep_ms = 0.0, nsteps = 0.0;
+    for (int i = 0; timing && i < k_end * m; ++i) {
+        float t = 0.f;
+        DDI_HIP(hipEventElapsedTime(&t, P->sweep_ev[2 * i], P->sweep_ev[2 * i + 1]));
+        sweep_ms += t;
+    }
+    for (int k = 0; timing && k < C; ++k) nsteps += P->host[2 * C + 2 + k];
+    if (st) {
+        st->sweeps = k_end * m;
+        st->refinements = k_end;
+        st->converged = converged ? 1 : 0;
+        st->rel_residual = rel;
+        st->ms = ms;
+        st->sweep_ms = sweep_ms;
+        st->cg_steps = nsteps;
+    }
+    return converged ? DDI_OK : DDI_ENOCONV;
+}
+
 int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats* st) {
     if (!P || !f || !c || !u) return DDI_EINVAL;
+    if (P->p.storage == 1) {
+        Level& L0 = P->lv[0];
+        L0.f = f;
+        L0.c = c;
+        L0.u[0] = u;
+        if (st) std::memset(st, 0, sizeof(*st));
+        return solve_refine(P, f, c, u, st);
+    }
     const int C = P->C;
     const ddi_params& prm = P->p;
     Level& L0 = P->lv[0];
@@ -665,6 +795,50 @@ int ddi_coarse_solve(const float* f, const uint8_t* c, int height, int width, in
     if ((e = check_device())) return e;
     DDI_HIP(launch_coarse_cg(f, c, height, width, channels, u, max_iter, tol,
                              (hipStream_t)stream));
+    return DDI_OK;
+}
+
+int ddi_refine_residual(const float* f, const uint8_t* c, const float* u, const uint16_t* d,
+                        int height, int width, int channels, float* u_next, uint16_t* rhs,
+                        double* rsq, void* stream) {
+    int e = check_dims(height, width, channels);
+    if (e) return e;
+    if (!f || !c || !u || !rhs || (d && !u_next)) return DDI_EINVAL;
+    if ((e = check_device())) return e;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nwg = (size_t)residual_partials(height, width);
+    Scratch part, red;
+    DDI_HIP(hipMalloc(&part.p, nwg * channels * sizeof(double)));
+    DDI_HIP(hipMalloc(&red.p, channels * sizeof(double)));
+    int n = 0;
+    DDI_HIP(launch_refine_residual(f, c, u, d, height, width, channels, u_next, rhs,
+                                   (double*)part.p, nullptr, &n, s));
+    DDI_HIP(launch_reduce((double*)part.p, n, channels, channels, (double*)red.p, s));
+    if (rsq)
+        DDI_HIP(hipMemcpyAsync(rsq, red.p, channels * sizeof(double), hipMemcpyDeviceToHost, s));
+    DDI_HIP(hipStreamSynchronize(s));
+    return DDI_OK;
+}
+
+int ddi_correction_sweep(const uint16_t* d_in, const uint16_t* rhs, const uint8_t* c,
+                         uint16_t* d_out, int height, int width, int channels, int block,
+                         int overlap, float robin_alpha, int local_iters, void* stream) {
+    int e = check_dims(height, width, channels);
+    if (e) return e;
+    if (!rhs || !c || !d_out || d_in == d_out) return DDI_EINVAL;
+    if (block < 2 || block > DDI_MAX_BLOCK || overlap < 0 || overlap >= block) return DDI_EINVAL;
+    if (!(robin_alpha > 0.f && robin_alpha <= 1.f) || local_iters < 1) return DDI_EINVAL;
+    if ((e = check_device())) return e;
+    hipStream_t s = (hipStream_t)stream;
+    const SweepArgs a = make_sweep(height, width, channels, block, overlap, robin_alpha,
+                                   local_iters);
+    Scratch part, mb;
+    DDI_HIP(hipMalloc(&part.p, (size_t)sweep_partials(a) * channels * sizeof(double)));
+    DDI_HIP(hipMalloc(&mb.p, (size_t)mask_bit_groups(height) * width * sizeof(uint64_t)));
+    DDI_HIP(launch_mask_bits(c, height, width, (uint64_t*)mb.p, s));
+    DDI_HIP(launch_sweep_corr(d_in, rhs, (const uint64_t*)mb.p, d_out, (double*)part.p, nullptr,
+                              nullptr, a, s));
+    DDI_HIP(hipStreamSynchronize(s));
     return DDI_OK;
 }
 

@@ -233,6 +233,23 @@ int prolong4_grid(int h, int w, int* gx);
 int init_grid(int h, int w);
 int mask_bits_grid(int h, int w, int* gx);
 
+// ---- bfloat16 storage with float32 iterative refinement ----
+
+// One ORAS sweep of the refinement equation A d = rhs (d = 0 on the mask):
+// din, rhs, dout bfloat16 planes like u (din == nullptr: d = 0); float32
+// arithmetic; otherwise as launch_sweep.
+hipError_t launch_sweep_corr(const uint16_t* din, const uint16_t* rhs, const uint64_t* mbits,
+                             uint16_t* dout, double* partial, double* cg_steps, const int* ctl,
+                             const SweepArgs& a, hipStream_t s);
+
+// unext = u + d (skipped when d == nullptr), rhs = bfloat16(b - A unext),
+// float64 partials of ||b - A unext||^2 laid out as launch_residual's (same
+// workgroup count). Does nothing once ctl[0] != 0.
+hipError_t launch_refine_residual(const float* f, const uint8_t* c, const float* u,
+                                  const uint16_t* d, int h, int w, int channels, float* unext,
+                                  uint16_t* rhs, double* partial, const int* ctl, int* nwg,
+                                  hipStream_t s);
+
 // Float64 CG solve of the coarsest level (h * w <= kCoarseMaxPixels), one
 // workgroup per channel: u = exact solution (rounded to float32) once
 // ||b - A u|| <= tol ||C f||, or after max_iter steps.

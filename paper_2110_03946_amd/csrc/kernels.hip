@@ -89,6 +89,15 @@ __device__ __forceinline__ float mask_keep(uint32_t bits, int bit, float q) {
     return __int_as_float(__float_as_int(q) & sel);
 }
 
+// bfloat16 storage of the correction equation: widen by a 16-bit shift,
+// narrow with round-to-nearest-even (inputs are finite).
+__device__ __forceinline__ float bf16_to_f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+__device__ __forceinline__ uint16_t f_to_bf16(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 // Mask of one block column, built from the bits of the unknown pixels.
 // Float storage (1 = unknown) for short columns; the bits themselves for
 // 64-row columns, where registers are scarce.
@@ -144,10 +153,19 @@ constexpr int kTileW = kMaxBlock + 2;
 
 // The sweep of logical block lb (channel-major over the block grid) of one
 // image, with the block's tile in `lds` ((RPW + 2) x kTileW floats).
-template <int RPW, bool RAGGED, bool QLDS, bool MBITS>
-__device__ __forceinline__ void sweep_body(const float* __restrict__ uin,
+//
+// CORR = false: the iterate u (float32) of A u = b; the block residual is
+// b - A u = L u on unknown pixels.
+// CORR = true: the correction d (bfloat16) of the refinement equation
+// A d = rhs (d = 0 on the mask, rhs = b - A u of the float32 iterate,
+// stored in bfloat16); the block residual is rhs - A d = rhs + L d on
+// unknown pixels. uin == nullptr stands for d = 0. Arithmetic is float32 in
+// both cases; only the loads widen and the stores narrow.
+template <int RPW, bool RAGGED, bool QLDS, bool MBITS, bool CORR = false>
+__device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
+                                           const uint16_t* __restrict__ rhs,
                                            const uint64_t* __restrict__ mbits,
-                                           float* __restrict__ uout,
+                                           void* __restrict__ uout_v,
                                            double* __restrict__ partial,
                                            double* __restrict__ cg_steps,
                                            const int* __restrict__ ctl, const SweepArgs& a,
@@ -171,7 +189,9 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ uin,
     owner_range(by, g.nby, g.sy, g.h, g.bh, &oylo, &oyhi);
     owner_range(bx, g.nbx, g.sx, g.w, g.bw, &oxlo, &oxhi);
 
-    const float* __restrict__ U = uin + ch * a.cpitch;
+    const float* __restrict__ U = CORR ? nullptr : (const float*)uin_v + ch * a.cpitch;
+    const uint16_t* __restrict__ U16 =
+        CORR && uin_v ? (const uint16_t*)uin_v + ch * a.cpitch : nullptr;
     const bool on = lane < g.bw;
     const int x = x0 + lane;
     const int nrows = RAGGED ? g.bh : RPW;
@@ -186,7 +206,7 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ uin,
     // before the first LDS write (no branches between them). Offsets are
     // 32-bit element indices into one channel plane (planes hold < 2^30
     // pixels), so each load is one scalar base plus a vector offset.
-    {
+    auto stage = [&](auto ld) {
         const uint32_t xc = on ? x : x0;
         const uint32_t Wd = g.w;
         float col[RPW + 2];
@@ -194,18 +214,18 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ uin,
             // rows y0 .. y0+RPW-1 lie in the image; only the two halo rows
             // can fall outside it (then they copy the border row)
             uint32_t off = (uint32_t)y0 * Wd + xc;
-            col[0] = U[has_top ? off - Wd : off];
+            col[0] = ld(has_top ? off - Wd : off);
 #pragma unroll
             for (int t = 1; t <= RPW; ++t) {
-                col[t] = U[off];
+                col[t] = ld(off);
                 if (t < RPW) off += Wd;
             }
-            col[RPW + 1] = U[has_bot ? off + Wd : off];
+            col[RPW + 1] = ld(has_bot ? off + Wd : off);
         } else {
 #pragma unroll
             for (int t = 0; t < RPW + 2; ++t) {
                 const uint32_t yy = min(max(y0 + t - 1, 0), g.h - 1);
-                col[t] = U[yy * Wd + xc];
+                col[t] = ld(yy * Wd + xc);
             }
         }
         // halo columns: lane l fetches row l - 1 (and rows 63, 64 in a
@@ -213,12 +233,12 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ uin,
         const uint32_t xl = max(x0 - 1, 0), xr = min(x0 + g.bw, g.w - 1);
         const int t1 = lane, t2 = 64 + lane;
         const uint32_t r1 = (uint32_t)min(max(y0 + t1 - 1, 0), g.h - 1) * (uint32_t)g.w;
-        const float hl1 = U[r1 + xl], hr1 = U[r1 + xr];
+        const float hl1 = ld(r1 + xl), hr1 = ld(r1 + xr);
         float hl2 = 0.f, hr2 = 0.f;
         if (t2 < RPW + 2) {
             const uint32_t r2 = (uint32_t)min(max(y0 + t2 - 1, 0), g.h - 1) * (uint32_t)g.w;
-            hl2 = U[r2 + xl];
-            hr2 = U[r2 + xr];
+            hl2 = ld(r2 + xl);
+            hr2 = ld(r2 + xr);
         }
         if (on) {
 #pragma unroll
@@ -232,6 +252,14 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ uin,
             lds[t2 * TW + CO - 1] = hl2;
             lds[t2 * TW + CO + g.bw] = hr2;
         }
+    };
+    if constexpr (!CORR) {
+        stage([&](uint32_t i) { return U[i]; });
+    } else {
+        if (U16)
+            stage([&](uint32_t i) { return bf16_to_f(U16[i]); });
+        else
+            stage([](uint32_t) { return 0.f; });
     }
     // unknown-pixel bits of this column: bit y <-> row y0 + y
     uint32_t mlo = 0u, mhi = 0u;
@@ -258,13 +286,19 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ uin,
         const float* col = lds + lane + CO;
         float uup = col[0];
         float uy = col[TW];
+        const uint16_t* R16 = nullptr;
+        if constexpr (CORR) R16 = rhs + ch * a.cpitch + (uint32_t)(on ? x : x0);
 #pragma unroll
         for (int y = 0; y < RPW; ++y) {
             const float udn = col[(y + 2) * TW];
             const float ul = col[(y + 1) * TW - 1];
             const float ur = col[(y + 1) * TW + 1];
-            const float ry = mask_keep(y < 32 ? mlo : mhi, y & 31,
-                                       ((uup - uy) + (udn - uy)) + ((ul - uy) + (ur - uy)));
+            float lap = ((uup - uy) + (udn - uy)) + ((ul - uy) + (ur - uy));
+            if constexpr (CORR) {
+                const uint32_t yy = RAGGED ? min(y0 + y, g.h - 1) : y0 + y;
+                lap = bf16_to_f(R16[yy * (uint32_t)g.w]) + lap;
+            }
+            const float ry = mask_keep(y < 32 ? mlo : mhi, y & 31, lap);
             r[y] = ry;
             w[y] = uy;
             const float rq = ry * ry;
@@ -379,13 +413,23 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ uin,
 
     // ---- restricted prolongation: u_out = u_in + v on owned pixels (eq. 9)
     if (on && x >= oxlo && x < oxhi) {
-        float* __restrict__ UO = uout + ch * a.cpitch;
         uint32_t off = (uint32_t)y0 * (uint32_t)g.w + (uint32_t)x;
+        if constexpr (!CORR) {
+            float* __restrict__ UO = (float*)uout_v + ch * a.cpitch;
 #pragma unroll
-        for (int y = 0; y < RPW; ++y) {
-            const int yy = y0 + y;
-            if ((!RAGGED || y < nrows) && yy >= oylo && yy < oyhi) UO[off] = w[y];
-            off += (uint32_t)g.w;
+            for (int y = 0; y < RPW; ++y) {
+                const int yy = y0 + y;
+                if ((!RAGGED || y < nrows) && yy >= oylo && yy < oyhi) UO[off] = w[y];
+                off += (uint32_t)g.w;
+            }
+        } else {
+            uint16_t* __restrict__ UO = (uint16_t*)uout_v + ch * a.cpitch;
+#pragma unroll
+            for (int y = 0; y < RPW; ++y) {
+                const int yy = y0 + y;
+                if ((!RAGGED || y < nrows) && yy >= oylo && yy < oyhi) UO[off] = f_to_bf16(w[y]);
+                off += (uint32_t)g.w;
+            }
         }
     }
 }
@@ -405,8 +449,23 @@ __global__ __launch_bounds__(64) void k_sweep(const float* __restrict__ uin,
                                               double* __restrict__ cg_steps,
                                               const int* __restrict__ ctl, SweepArgs a) {
     __shared__ __attribute__((aligned(16))) float lds[(RPW + 2) * kTileW];
-    sweep_body<RPW, RAGGED, QLDS, MBITS>(uin, mbits, uout, partial, cg_steps, ctl, a,
+    sweep_body<RPW, RAGGED, QLDS, MBITS>(uin, nullptr, mbits, uout, partial, cg_steps, ctl, a,
                                          xcd_remap(blockIdx.x, gridDim.x), lds);
+}
+
+// One sweep of the refinement equation A d = rhs with d and rhs in
+// bfloat16 (din == nullptr: d = 0).
+template <int RPW, bool RAGGED, bool QLDS, bool MBITS>
+__global__ __launch_bounds__(64) void k_sweep_corr(const uint16_t* __restrict__ din,
+                                                   const uint16_t* __restrict__ rhs,
+                                                   const uint64_t* __restrict__ mbits,
+                                                   uint16_t* __restrict__ dout,
+                                                   double* __restrict__ partial,
+                                                   double* __restrict__ cg_steps,
+                                                   const int* __restrict__ ctl, SweepArgs a) {
+    __shared__ __attribute__((aligned(16))) float lds[(RPW + 2) * kTileW];
+    sweep_body<RPW, RAGGED, QLDS, MBITS, true>(din, rhs, mbits, dout, partial, cg_steps, ctl, a,
+                                               xcd_remap(blockIdx.x, gridDim.x), lds);
 }
 
 // Index of the job whose workgroup range holds logical workgroup lb (jobs
@@ -430,8 +489,8 @@ __global__ __launch_bounds__(64) void k_sweep_batch(const SweepJob* __restrict__
     __shared__ __attribute__((aligned(16))) float lds[(RPW + 2) * kTileW];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const SweepJob& J = jobs[find_job(jobs, njobs, lb)];
-    sweep_body<RPW, RAGGED, QLDS, MBITS>(J.uin, J.mbits, J.uout, J.partial, J.cg_steps, J.ctl,
-                                         J.a, lb - J.wg0, lds);
+    sweep_body<RPW, RAGGED, QLDS, MBITS>(J.uin, nullptr, J.mbits, J.uout, J.partial, J.cg_steps,
+                                         J.ctl, J.a, lb - J.wg0, lds);
 }
 
 // Column-transposed unknown-pixel bits of a mask: word (g, x) holds bit j
@@ -903,6 +962,51 @@ __global__ __launch_bounds__(64 * kResRows) void k_residual(
     }
 }
 
+// Refinement step on the float32 iterate: u_next = u + d (d in bfloat16;
+// d == nullptr: u_next = u, not written), rhs = b - A u_next rounded to
+// bfloat16, and float64 partial norms of b - A u_next (float32 values) laid
+// out as k_residual's. Skipped once ctl[0] is set.
+__global__ __launch_bounds__(64 * kResRows) void k_refine_residual(
+    const float* __restrict__ f, const uint8_t* __restrict__ c, const float* __restrict__ u,
+    const uint16_t* __restrict__ d, int h, int w, int channels, float* __restrict__ unext,
+    uint16_t* __restrict__ rhs, double* __restrict__ partial, const int* __restrict__ ctl) {
+    if (ctl && ctl[0] != 0) return;
+    const int lane = threadIdx.x & 63;
+    const int x = blockIdx.x * 64 + lane;
+    const int y = blockIdx.y * kResRows + (threadIdx.x >> 6);
+    const int ch = blockIdx.z;
+    const int64_t n = (int64_t)h * w;
+    const float* __restrict__ U = u + ch * n;
+    const uint16_t* __restrict__ D = d ? d + ch * n : nullptr;
+    double acc = 0.0;
+    if (x < w && y < h) {
+        const uint32_t W = w;
+        const uint32_t i = (uint32_t)y * W + x;
+        auto val = [&](uint32_t j) { return D ? U[j] + bf16_to_f(D[j]) : U[j]; };
+        const float uc = val(i);
+        const float uu = y > 0 ? val(i - W) : uc;
+        const float ud = y + 1 < h ? val(i + W) : uc;
+        const float ul = x > 0 ? val(i - 1) : uc;
+        const float ur = x + 1 < w ? val(i + 1) : uc;
+        const bool known = c[i] != 0;
+        const float fv = known ? f[ch * n + i] : 0.f;
+        const float ry = known ? fv - uc : ((uu - uc) + (ud - uc)) + ((ul - uc) + (ur - uc));
+        acc = (double)ry * (double)ry;
+        rhs[ch * n + i] = f_to_bf16(ry);
+        if (D) unext[ch * n + i] = uc;
+    }
+    acc = wave_sum_d(acc);
+    __shared__ double sm[kResRows];
+    if (lane == 0) sm[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < kResRows; ++j) s += sm[j];
+        partial[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * channels + ch] = s;
+    }
+}
+
 __global__ __launch_bounds__(kTpb) void k_reduce(double* __restrict__ partial, int nrows,
                                                  int stride, double* __restrict__ out, int zero) {
     const int j = blockIdx.x;
@@ -1162,6 +1266,37 @@ static hipError_t sweep_rpw(const float* uin, const uint64_t* mbits, float* uout
         hipLaunchKernelGGL((k_sweep<RPW, true, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
                            uin, mbits, uout, partial, cg_steps, ctl, a);
     return hipGetLastError();
+}
+
+template <int RPW, bool QLDS, bool MBITS>
+static hipError_t sweep_corr_rpw(const uint16_t* din, const uint16_t* rhs,
+                                 const uint64_t* mbits, uint16_t* dout, double* partial,
+                                 double* cg_steps, const int* ctl, const SweepArgs& a,
+                                 hipStream_t s) {
+    const int grid = a.g.nby * a.g.nbx * a.channels;
+    if (a.g.bh == RPW)
+        hipLaunchKernelGGL((k_sweep_corr<RPW, false, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
+                           din, rhs, mbits, dout, partial, cg_steps, ctl, a);
+    else
+        hipLaunchKernelGGL((k_sweep_corr<RPW, true, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
+                           din, rhs, mbits, dout, partial, cg_steps, ctl, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_corr(const uint16_t* din, const uint16_t* rhs, const uint64_t* mbits,
+                             uint16_t* dout, double* partial, double* cg_steps, const int* ctl,
+                             const SweepArgs& a, hipStream_t s) {
+    const int bh = a.g.bh;
+    if (a.g.bw < 1 || a.g.bw > kMaxBlock || bh < 1 || bh > kMaxBlock) return hipErrorInvalidValue;
+    if (bh > 32)
+        return sweep_corr_rpw<64, true, true>(din, rhs, mbits, dout, partial, cg_steps, ctl, a, s);
+    if (bh > 16)
+        return sweep_corr_rpw<32, false, false>(din, rhs, mbits, dout, partial, cg_steps, ctl, a,
+                                                s);
+    if (bh > 8)
+        return sweep_corr_rpw<16, false, false>(din, rhs, mbits, dout, partial, cg_steps, ctl, a,
+                                                s);
+    return sweep_corr_rpw<8, false, false>(din, rhs, mbits, dout, partial, cg_steps, ctl, a, s);
 }
 
 hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
@@ -1466,6 +1601,17 @@ hipError_t launch_coarse_cg_batch(const CoarseJob* jobs, int njobs, int channels
     if (njobs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_coarse_cg64_batch, dim3(njobs * channels), dim3(kCgTpb), 0, s, jobs,
                        channels);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_residual(const float* f, const uint8_t* c, const float* u,
+                                  const uint16_t* d, int h, int w, int channels, float* unext,
+                                  uint16_t* rhs, double* partial, const int* ctl, int* nwg,
+                                  hipStream_t s) {
+    dim3 grid((w + 63) / 64, (h + kResRows - 1) / kResRows, channels);
+    if (nwg) *nwg = (int)(grid.x * grid.y);
+    hipLaunchKernelGGL(k_refine_residual, grid, dim3(64 * kResRows), 0, s, f, c, u, d, h, w,
+                       channels, unext, rhs, partial, ctl);
     return hipGetLastError();
 }
 

@@ -69,4 +69,8 @@ struct ddi_plan {
     const void* g_c = nullptr;
     const void* g_u = nullptr;
     int g_start = -1, g_batch = -1;
+    // storage = 1: bfloat16 right-hand side and ping-pong corrections of
+    // the refinement equation on the finest level
+    uint16_t* r16 = nullptr;
+    uint16_t* d16[2] = {nullptr, nullptr};
 };

@@ -41,7 +41,8 @@ class Params(ctypes.Structure):
                 ("coarse_overlap", ctypes.c_int), ("coarse_local_iters", ctypes.c_int),
                 ("local_tol", ctypes.c_float), ("use_graph", ctypes.c_int),
                 ("coarse_solver", ctypes.c_int), ("coarse_cg_iters", ctypes.c_int),
-                ("coarse_cg_tol", ctypes.c_double)]
+                ("coarse_cg_tol", ctypes.c_double), ("storage", ctypes.c_int),
+                ("inner_sweeps", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -50,7 +51,8 @@ class Params(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int), ("converged", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("ms", ctypes.c_double),
-                ("sweep_ms", ctypes.c_double), ("cg_steps", ctypes.c_double)]
+                ("sweep_ms", ctypes.c_double), ("cg_steps", ctypes.c_double),
+                ("refinements", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -95,6 +97,8 @@ def lib():
             "ddi_prolong": (i, [vp, i, i, vp, vp, i, i, i, vp, vp]),
             "ddi_oras_sweep": (i, [vp, vp, vp, i, i, i, i, i, f, i, vp, vp]),
             "ddi_coarse_solve": (i, [vp, vp, i, i, i, vp, i, d, vp]),
+            "ddi_refine_residual": (i, [vp, vp, vp, vp, i, i, i, vp, vp, vp, vp]),
+            "ddi_correction_sweep": (i, [vp, vp, vp, vp, i, i, i, i, i, f, i, vp]),
             "ddi_batch_create": (i, [ctypes.POINTER(vp), i, ip, ip, i, ctypes.POINTER(Params),
                                      i, vp]),
             "ddi_batch_solve": (i, [vp, vp, vp, vp, ctypes.POINTER(Stats), ip]),
@@ -376,6 +380,53 @@ def coarse_solve(f, c, max_iter: int = 500, tol: float = 1e-10, u=None, stream=N
     _check(lib().ddi_coarse_solve(_ptr(f), _ptr(c), H, W, C, _ptr(u), max_iter, float(tol),
                                   _stream(stream)), "ddi_coarse_solve")
     return u
+
+
+def _bf16(t, name, channels=None, hw=None):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.bfloat16 and
+            t.is_contiguous() and t.dim() == 3):
+        raise TypeError(f"{name} must be a contiguous (C, H, W) bfloat16 tensor on the GPU")
+    if channels is not None and t.shape[0] != channels:
+        raise ValueError(f"{name} has {t.shape[0]} channels, expected {channels}")
+    if hw is not None and tuple(t.shape[1:]) != tuple(hw):
+        raise ValueError(f"{name} is {tuple(t.shape[1:])}, expected {tuple(hw)}")
+    return t
+
+
+def refine_residual(f, c, u, d=None, stream=None):
+    """Refinement step: returns (u_next or None, rhs bfloat16, per-channel ||r||^2)."""
+    torch = _torch()
+    f = _img(f, "f")
+    C, H, W = f.shape
+    c = _mask(c, (H, W))
+    u = _img(u, "u", C, (H, W))
+    un = None
+    if d is not None:
+        d = _bf16(d, "d", C, (H, W))
+        un = torch.empty_like(u)
+    rhs = torch.empty((C, H, W), dtype=torch.bfloat16, device=f.device)
+    rsq = np.zeros(C, dtype=np.float64)
+    _check(lib().ddi_refine_residual(_ptr(f), _ptr(c), _ptr(u), _ptr(d) if d is not None else None,
+                                     H, W, C, _ptr(un) if un is not None else None, _ptr(rhs),
+                                     rsq.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+           "ddi_refine_residual")
+    return un, rhs, rsq
+
+
+def correction_sweep(d_in, rhs, c, block: int, overlap: int, alpha: float, k: int, stream=None):
+    """One ORAS iteration on A d = rhs (bfloat16 d and rhs); returns d_out."""
+    torch = _torch()
+    rhs = _bf16(rhs, "rhs")
+    C, H, W = rhs.shape
+    c = _mask(c, (H, W))
+    if d_in is not None:
+        d_in = _bf16(d_in, "d_in", C, (H, W))
+    d_out = torch.empty_like(rhs)
+    _check(lib().ddi_correction_sweep(_ptr(d_in) if d_in is not None else None, _ptr(rhs), _ptr(c),
+                                      _ptr(d_out), H, W, C, block, overlap, float(alpha), k,
+                                      _stream(stream)), "ddi_correction_sweep")
+    return d_out
 
 
 def oras_sweep(u_in, c, block: int, overlap: int, alpha: float, k: int, u_out=None,
