@@ -6,6 +6,10 @@ every kernel of the path and the float64 stop tests) of a 3840 x 2160 x 3
 float32 frame with a 4 % i.i.d. Bernoulli mask shared by the channels, 64 x
 64 blocks with overlap 4, four levels (coarsest 1/8).
 
+--workload precision: the 4K RGB frame with a 3 % Bernoulli mask, solved
+with bfloat16 storage of the correction, float32 iterative refinement and a
+float64 solve of the coarsest level; max error reported per channel.
+
 --workload batch: one step = one batched solve of 48 RGB float32 images of
 uneven size (sizes uniform over 640x480 .. 3840x2160, mask densities uniform
 in 2-10 %, half of the masks clustered), each with the autotuned parameters
@@ -27,7 +31,7 @@ Prints one JSON line. Besides the driver's fields it carries
   p50_ms/p99_ms latency of the timed solves.
 
 Usage: python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu]
-                       [--workload 4k|batch]
+                       [--workload 4k|batch|precision]
 """
 from __future__ import annotations
 
@@ -158,11 +162,114 @@ def cpu_baseline(f, c, u_gpu):
     t0 = time.perf_counter()
     ex, info = oracle.solve_exact(f.astype(np.float64), c, return_info=True)
     t = time.perf_counter() - t0
-    err = float(np.abs(u_gpu.astype(np.float64) - ex).max())
+    diff = np.abs(u_gpu.astype(np.float64) - ex)
+    per_ch = [float(diff[k].max()) for k in range(diff.shape[0])]
     return {"value": 1.0 / t, "unit": "frames/s", "cores": oracle.threads(), "kind": "oracle",
             "sample": "the full 3840x2160x3 frame: float64 CG on the reduced system to "
                       f"relative residual 1e-12 per channel ({[i['iters'] for i in info]} "
-                      f"iterations), {t:.1f} s"}, err
+                      f"iterations), {t:.1f} s"}, max(per_ch), per_ch
+
+
+def precision_params() -> dict:
+    """Parameters of the mixed-precision workload: bfloat16 correction
+    storage with float32 refinement steps of 2 correction sweeps, float64
+    solve of the coarsest level (6 levels: 120 x 68 for 4K)."""
+    return dict(block=64, overlap=4, levels=6, local_iters=16, robin_alpha=0.25,
+                coarse_sweeps=1, coarsest_sweeps=1, coarse_local_iters=4, local_tol=0.0005,
+                rel_tol=3e-5, min_sweeps=1, max_sweeps=40, check_every=1, final_residual=0,
+                coarse_solver=1, coarse_cg_iters=500, coarse_cg_tol=1e-10, storage=1,
+                inner_sweeps=2)
+
+
+PRECISION_DENSITY = 0.03
+METRIC_PRECISION = ("4K RGB frames/s, bf16 storage + f32 refinement, ≤0.5 grey-level err vs "
+                    "FP64 per channel")
+
+
+def correction_bytes(m: int, refinements: int, h: int = H, w: int = W, ch: int = C) -> int:
+    """Algorithmic HBM bytes of the correction sweeps of a mixed-precision
+    solve: every sweep reads the bfloat16 right-hand side and writes the
+    bfloat16 correction, all but the first of a step also read the previous
+    correction; plus the transposed mask."""
+    per_step = sum(ch * h * w * (4 if j == 0 else 6) + h * w // 8 for j in range(m))
+    return refinements * per_step
+
+
+def run_frame(args, workload: str):
+    """One 4K RGB frame per step: the float32 path (4k) or the mixed-precision
+    path (precision)."""
+    import torch
+    from paper_2110_03946_amd import ddi, synth
+    precision = workload == "precision"
+    density = PRECISION_DENSITY if precision else DENSITY
+    f_np, c_np = synth.make_workload(H, W, C, density, "bernoulli", workload=3 if precision else 1)
+    f = torch.from_numpy(f_np).cuda()
+    c = torch.from_numpy(c_np).cuda()
+    u = torch.empty_like(f)
+    prm = precision_params() if precision else solver_params()
+    plan = ddi.Plan(H, W, C, timing=1, **prm)
+
+    for _ in range(args.warmup):
+        plan.solve(f, c, u)
+    torch.cuda.synchronize()
+    lat, sweep_ms, nsweeps, sweeps_per_solve, rels, steps, refs = [], 0.0, 0, [], [], 0.0, 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        _, st = plan.solve(f, c, u)
+        lat.append((time.perf_counter() - ts) * 1e3)
+        sweep_ms += st["sweep_ms"]
+        nsweeps += st["sweeps"]
+        steps += st["cg_steps"]
+        refs += st["refinements"]
+        sweeps_per_solve.append(st["sweeps"])
+        rels.append(st["rel_residual"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fps = args.steps / elapsed
+
+    flops, bytes_ = sweep_work(prm, nsweeps, steps)
+    if precision:
+        bytes_ = correction_bytes(prm["inner_sweeps"], refs)
+    roofline = roofline_of(flops, bytes_, sweep_ms, nsweeps)
+    roofline.update({"traffic": None if precision else measured_traffic(),
+                     "kernel": ("k_sweep_corr<64> (finest-level correction sweep, bf16)"
+                                if precision else "k_sweep<64> (finest-level ORAS sweep)"),
+                     "cg_steps_per_block_sweep": round(
+                         steps / max(nsweeps, 1) /
+                         (ddi.block_count(H, prm["block"], prm["overlap"]) *
+                          ddi.block_count(W, prm["block"], prm["overlap"]) * C), 2)})
+
+    u_np = u.cpu().numpy()
+    if precision:
+        desc = ("4K RGB 3840x2160x3, 3% Bernoulli mask shared by the channels; bf16 storage of "
+                "the correction and its right-hand side with f32 arithmetic, f32 iterative "
+                "refinement (2 correction sweeps per step), f64 residual norm and f64 solve of "
+                "the coarsest level (6 levels: 120x68)")
+        dtype = "bf16 storage / f32 compute"
+    else:
+        desc = ("4K RGB 3840x2160x3 f32, 4% Bernoulli mask shared by the channels, multilevel "
+                "ORAS (64x64 blocks, overlap 4, 4 levels: coarsest 1/8), CG local solves")
+        dtype = "f32"
+    out = {"metric": METRIC_PRECISION if precision else METRIC, "value": round(fps, 2),
+           "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": {"workload": desc, **prm},
+           "p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "sweeps_per_solve": sorted(set(sweeps_per_solve)),
+           "rel_residual_max": max(rels),
+           "roofline": roofline}
+    if precision:
+        out["refinements_per_solve"] = round(refs / args.steps, 2)
+    if not args.no_cpu:
+        cb, err, per_ch = cpu_baseline(f_np, c_np, u_np)
+        out["cpu_baseline"] = cb
+        out["max_err_grey"] = round(err, 4)
+        out["max_err_grey_per_channel"] = [round(e, 4) for e in per_ch]
+    print(json.dumps(out), flush=True)
+    plan.close()
 
 
 BATCH_N, BATCH_SEED = 48, 2
@@ -283,7 +390,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--workload", choices=["4k", "batch"], default="4k")
+    ap.add_argument("--workload", choices=["4k", "batch", "precision"], default="4k")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB device-to-device copy (the known-size "
                          "reference for FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -318,60 +425,7 @@ def main():
         run_batch(args)
         return
 
-    f_np, c_np = synth.make_workload(H, W, C, DENSITY, "bernoulli", workload=1)
-    f = torch.from_numpy(f_np).cuda()
-    c = torch.from_numpy(c_np).cuda()
-    u = torch.empty_like(f)
-    prm = solver_params()
-    plan = ddi.Plan(H, W, C, timing=1, **prm)
-
-    for _ in range(args.warmup):
-        plan.solve(f, c, u)
-    torch.cuda.synchronize()
-    lat, sweep_ms, nsweeps, sweeps_per_solve, rels, steps = [], 0.0, 0, [], [], 0.0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        _, st = plan.solve(f, c, u)
-        lat.append((time.perf_counter() - ts) * 1e3)
-        sweep_ms += st["sweep_ms"]
-        nsweeps += st["sweeps"]
-        steps += st["cg_steps"]
-        sweeps_per_solve.append(st["sweeps"])
-        rels.append(st["rel_residual"])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    fps = args.steps / elapsed
-
-    flops, bytes_ = sweep_work(prm, nsweeps, steps)
-    roofline = roofline_of(flops, bytes_, sweep_ms, nsweeps)
-    roofline.update({"traffic": measured_traffic(),
-                     "kernel": "k_sweep<64> (finest-level ORAS sweep)",
-                     "cg_steps_per_block_sweep": round(
-                         steps / max(nsweeps, 1) /
-                         (ddi.block_count(H, prm["block"], prm["overlap"]) *
-                          ddi.block_count(W, prm["block"], prm["overlap"]) * C), 2)})
-
-    u_np = u.cpu().numpy()
-    out = {"metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "4K RGB 3840x2160x3 f32, 4% Bernoulli mask shared by the "
-                                  "channels, multilevel ORAS (64x64 blocks, overlap 4, "
-                                  "4 levels: coarsest 1/8), CG local solves",
-                      **prm},
-           "p50_ms": round(float(np.percentile(lat, 50)), 3),
-           "p99_ms": round(float(np.percentile(lat, 99)), 3),
-           "sweeps_per_solve": sorted(set(sweeps_per_solve)),
-           "rel_residual_max": max(rels),
-           "roofline": roofline}
-    if not args.no_cpu:
-        cb, err = cpu_baseline(f_np, c_np, u_np)
-        out["cpu_baseline"] = cb
-        out["max_err_grey"] = round(err, 4)
-    print(json.dumps(out), flush=True)
-    plan.close()
+    run_frame(args, args.workload)
 
 
 if __name__ == "__main__":
