@@ -211,6 +211,14 @@ int ddi_solve(ddi_plan* plan, const float* f, const uint8_t* c, float* u,
 /* Release the plan and its device buffers. NULL is a no-op. */
 int ddi_destroy(ddi_plan* plan);
 
+/* Device memory (bytes) a plan for these sizes and parameters allocates,
+ * without touching the GPU (p == NULL: defaults): what a server admitting
+ * requests by HBM footprint charges for the plan, on top of the caller's
+ * f, c and u. ddi_plan_bytes reports it for an existing plan. */
+int ddi_plan_footprint(int height, int width, int channels,
+                       const ddi_params* p, size_t* bytes);
+int ddi_plan_bytes(const ddi_plan* plan, size_t* bytes);
+
 /* ---- batched solve ------------------------------------------------------
  * Many images of uneven size solved together: every step of the scheme
  * (coarsening, transposed masks, the sweeps of each level, prolongation,

@@ -77,6 +77,39 @@ int level_count(int h, int w, int levels) {
     return L;
 }
 
+size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm) {
+    const int L = level_count(h, w, prm.levels);
+    size_t bytes = 0, part_n = 0;
+    int hl = h, wl = w;
+    for (int l = 0; l < L; ++l) {
+        const size_t n = (size_t)hl * wl, nf = n * C;
+        if (l > 0) bytes += nf * sizeof(float) + n + nf * sizeof(float);  // f, c, u[0]
+        bytes += nf * sizeof(float);                                      // u[1]
+        bytes += (size_t)mask_bit_groups(hl) * wl * sizeof(uint64_t);     // mbits
+        SweepArgs a;
+        if (l == 0) {
+            a = make_sweep(hl, wl, C, prm.block, prm.overlap, prm.robin_alpha, prm.local_iters);
+        } else {
+            const int cb = prm.coarse_block ? prm.coarse_block : prm.block;
+            const int co = prm.coarse_overlap >= 0 ? prm.coarse_overlap : prm.overlap;
+            a = make_sweep(hl, wl, C, cb, co, prm.robin_alpha, 1);
+        }
+        part_n = std::max(part_n, (size_t)sweep_partials(a) * C);
+        part_n = std::max(part_n, (size_t)residual_partials(hl, wl) * C);
+        hl = (hl + 1) / 2;
+        wl = (wl + 1) / 2;
+    }
+    part_n = std::max(part_n, std::max<size_t>((size_t)coarsen_partials(h, w), 1024) * (C + 2));
+    bytes += part_n * sizeof(double);
+    bytes += (3 * (size_t)C + 2) * sizeof(double) + 64;  // red, ctl
+    if (prm.storage == 1) bytes += 3 * (size_t)C * h * w * sizeof(uint16_t);
+    if (prm.timing) {
+        const SweepArgs a0 = make_sweep(h, w, C, prm.block, prm.overlap, prm.robin_alpha, 1);
+        bytes += (size_t)sweep_partials(a0) * C * sizeof(double);
+    }
+    return bytes;
+}
+
 int check_dims(int h, int w, int channels) {
     if (h < 1 || w < 1 || channels < 1 || channels > 4) return DDI_EINVAL;
     if ((int64_t)h * w > (int64_t)1 << 30) return DDI_EINVAL;
@@ -187,7 +220,8 @@ int ddi_destroy(ddi_plan* plan) {
     if (plan->e0) (void)hipEventDestroy(plan->e0);
     if (plan->e1) (void)hipEventDestroy(plan->e1);
     for (hipEvent_t e : plan->sweep_ev) (void)hipEventDestroy(e);
-    if (plan->g_exec) (void)hipGraphExecDestroy(plan->g_exec);
+    for (ddi_plan::Graph& g : plan->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (plan->ev_in) (void)hipEventDestroy(plan->ev_in);
     if (plan->gs) (void)hipStreamDestroy(plan->gs);
     delete plan;
@@ -320,7 +354,28 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
             }
         }
     }
+    P->bytes = plan_device_bytes(height, width, channels, prm);
     *out = P;
+    return DDI_OK;
+}
+
+int ddi_plan_footprint(int height, int width, int channels, const ddi_params* p,
+                       size_t* bytes) {
+    if (!bytes) return DDI_EINVAL;
+    ddi_params prm;
+    if (p)
+        prm = *p;
+    else
+        ddi_default_params(&prm);
+    const int e = ddi_check_params(height, width, channels, &prm);
+    if (e) return e;
+    *bytes = plan_device_bytes(height, width, channels, prm);
+    return DDI_OK;
+}
+
+int ddi_plan_bytes(const ddi_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return DDI_EINVAL;
+    *bytes = plan->bytes;
     return DDI_OK;
 }
 
@@ -577,12 +632,19 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
     if (graph) {
         // one graph per (f, c, u, start buffer, first batch); later solves
         // with the same key replay it
-        const bool same = P->g_exec && P->g_f == f && P->g_c == c && P->g_u == u &&
-                          P->g_start == start0 && P->g_batch == batch;
-        if (!same) {
-            if (P->g_exec) {
-                (void)hipGraphExecDestroy(P->g_exec);
-                P->g_exec = nullptr;
+        ddi_plan::Graph* hit = nullptr;
+        for (ddi_plan::Graph& gr : P->graphs)
+            if (gr.exec && gr.f == f && gr.c == c && gr.u == u && gr.start == start0 &&
+                gr.batch == batch)
+                hit = &gr;
+        if (!hit) {
+            // replace the least recently used entry
+            hit = &P->graphs[0];
+            for (ddi_plan::Graph& gr : P->graphs)
+                if (gr.last_use < hit->last_use) hit = &gr;
+            if (hit->exec) {
+                (void)hipGraphExecDestroy(hit->exec);
+                hit->exec = nullptr;
             }
             hipGraph_t g = nullptr;
             DDI_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -597,19 +659,20 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
                 return e;
             }
             if (he != hipSuccess) return hip_fail(he);
-            he = hipGraphInstantiate(&P->g_exec, g, nullptr, nullptr, 0);
+            he = hipGraphInstantiate(&hit->exec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (he != hipSuccess) {
-                P->g_exec = nullptr;
+                hit->exec = nullptr;
                 return hip_fail(he);
             }
-            P->g_f = f;
-            P->g_c = c;
-            P->g_u = u;
-            P->g_start = start0;
-            P->g_batch = batch;
+            hit->f = f;
+            hit->c = c;
+            hit->u = u;
+            hit->start = start0;
+            hit->batch = batch;
         }
-        DDI_HIP(hipGraphLaunch(P->g_exec, s));
+        hit->last_use = ++P->graph_clock;
+        DDI_HIP(hipGraphLaunch(hit->exec, s));
         enq = batch;
     } else {
         int e = enqueue_front(P, start0, s);

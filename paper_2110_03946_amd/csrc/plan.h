@@ -32,6 +32,8 @@ SweepArgs make_sweep(int h, int w, int channels, int block, int overlap, float a
                      float local_tol = 0.f);
 // DDI_OK when a gfx950 device is current.
 int check_device();
+// Device bytes ddi_create allocates for these sizes and parameters.
+size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm);
 // Levels a plan builds for h x w: `levels`, fewer once a level is 1 x 1.
 int level_count(int h, int w, int levels);
 // DDI_OK for 1 <= h, w; 1 <= channels <= 4; h * w <= 2^30.
@@ -48,6 +50,7 @@ int check_dims(int h, int w, int channels);
 struct ddi_plan {
     int h = 0, w = 0, C = 0;
     ddi_params p;
+    size_t bytes = 0;  // device memory the plan holds
     hipStream_t s = nullptr;
     std::vector<ddi::Level> lv;
     double* part = nullptr;
@@ -64,11 +67,19 @@ struct ddi_plan {
     // solve's first batch with the key it was captured for
     hipStream_t gs = nullptr;
     hipEvent_t ev_in = nullptr;
-    hipGraphExec_t g_exec = nullptr;
-    const void* g_f = nullptr;
-    const void* g_c = nullptr;
-    const void* g_u = nullptr;
-    int g_start = -1, g_batch = -1;
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        const void* f = nullptr;
+        const void* c = nullptr;
+        const void* u = nullptr;
+        int start = -1, batch = -1;
+        long last_use = 0;
+    };
+    // a few instantiated graphs (the start buffer and first batch follow the
+    // sweeps the previous solve needed, so they alternate between values)
+    static constexpr int kGraphs = 4;
+    Graph graphs[kGraphs];
+    long graph_clock = 0;
     // storage = 1: bfloat16 right-hand side and ping-pong corrections of
     // the refinement equation on the finest level
     uint16_t* r16 = nullptr;

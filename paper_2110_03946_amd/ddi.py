@@ -97,6 +97,9 @@ def lib():
             "ddi_prolong": (i, [vp, i, i, vp, vp, i, i, i, vp, vp]),
             "ddi_oras_sweep": (i, [vp, vp, vp, i, i, i, i, i, f, i, vp, vp]),
             "ddi_coarse_solve": (i, [vp, vp, i, i, i, vp, i, d, vp]),
+            "ddi_plan_footprint": (i, [i, i, i, ctypes.POINTER(Params),
+                                       ctypes.POINTER(ctypes.c_size_t)]),
+            "ddi_plan_bytes": (i, [vp, ctypes.POINTER(ctypes.c_size_t)]),
             "ddi_refine_residual": (i, [vp, vp, vp, vp, i, i, i, vp, vp, vp, vp]),
             "ddi_correction_sweep": (i, [vp, vp, vp, vp, i, i, i, i, i, f, i, vp]),
             "ddi_batch_create": (i, [ctypes.POINTER(vp), i, ip, ip, i, ctypes.POINTER(Params),
@@ -136,6 +139,14 @@ def default_params(**overrides) -> Params:
 
 def check_params(h: int, w: int, channels: int, p: Params) -> int:
     return lib().ddi_check_params(h, w, channels, ctypes.byref(p))
+
+
+def plan_footprint(h: int, w: int, channels: int, p: Params | None = None) -> int:
+    """Device bytes a plan for (h, w, channels, p) allocates (no GPU needed)."""
+    n = ctypes.c_size_t()
+    _check(lib().ddi_plan_footprint(h, w, channels, ctypes.byref(p) if p is not None else None,
+                                    ctypes.byref(n)), "ddi_plan_footprint")
+    return n.value
 
 
 def block_count(n: int, block: int, overlap: int) -> int:
@@ -229,6 +240,11 @@ class Plan:
         if rc != DDI_OK and not (allow_noconv and rc == DDI_ENOCONV):
             raise DDIError(rc, "ddi_solve")
         return u, st.as_dict()
+
+    def device_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().ddi_plan_bytes(self._h, ctypes.byref(n)), "ddi_plan_bytes")
+        return n.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -98,3 +98,24 @@ def test_strerror_and_nodev_without_gpu():
     p = ddi.default_params()
     rc = ddi.lib().ddi_create(ctypes.byref(h), 64, 64, 1, ctypes.byref(p), None)
     assert rc == ddi.DDI_ENODEV and not h.value
+
+
+def test_plan_footprint():
+    """Device bytes of a plan: the float32 4K plan holds the second finest
+    iterate (12 B per pixel), on each coarser level f, c and two iterates
+    (37 B per coarse pixel), the transposed masks (1 bit per pixel and
+    level, plus a zero row group) and small partial buffers; bfloat16
+    storage adds three 2-byte planes."""
+    p = ddi.default_params()
+    b = ddi.plan_footprint(2160, 3840, 3, p)
+    n = 2160 * 3840
+    sizes = [(2160, 3840), (1080, 1920), (540, 960), (270, 480)]
+    exp = 12 * n + sum(37 * h * w for h, w in sizes[1:])
+    exp += sum(8 * ((h + 63) // 64 + 1) * w for h, w in sizes)
+    assert exp < b < exp + 2e6
+    p.storage = 1
+    assert ddi.plan_footprint(2160, 3840, 3, p) - b == 3 * 3 * n * 2
+    q = ddi.default_params(levels=1)
+    assert ddi.plan_footprint(64, 64, 1, q) < ddi.plan_footprint(64, 64, 1, ddi.default_params())
+    with pytest.raises(ddi.DDIError):
+        ddi.plan_footprint(0, 10, 1, p)
