@@ -434,6 +434,285 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
     }
 }
 
+// ---------------------------------------------------------------------------
+// One ORAS sweep with two waves per 64 x 64 block
+// ---------------------------------------------------------------------------
+//
+// The same computation as sweep_body for full 64-row blocks, split over a
+// 128-thread workgroup: wave wi holds block rows 32 wi .. 32 wi + 31 in
+// registers (all four CG vectors, no parking in LDS), the two waves of a
+// block run on different SIMDs of the CU, and at about 150 VGPRs three
+// waves share each SIMD instead of two. Per CG step the waves meet three
+// times in LDS: to swap the boundary rows of p (row 31 <-> row 32) for the
+// matvec, and to add their halves of p.q and r.r (wave 0's half first, so
+// both waves hold bitwise equal scalars and take the same branches).
+constexpr int kSplitRows = 32;
+// LDS floats of a split sweep: the 66 x 66 tile, then the exchange area
+// (two p rows, then the per-wave scalars).
+constexpr int kSplitLds = (2 * kSplitRows + 2) * kTileW + 2 * 64 + 8;
+
+template <bool CORR, bool QL>
+__device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
+                                            const uint16_t* __restrict__ rhs,
+                                            const uint64_t* __restrict__ mbits,
+                                            void* __restrict__ uout_v,
+                                            double* __restrict__ partial,
+                                            double* __restrict__ cg_steps,
+                                            const int* __restrict__ ctl, const SweepArgs& a,
+                                            int lb, float* __restrict__ lds) {
+    constexpr int RPW = kSplitRows;
+    constexpr int TW = kTileW;
+    constexpr int CO = 1;
+    if (ctl && ctl[0] != 0) return;  // read by both waves: the same decision
+
+    const int lane = threadIdx.x & 63;
+    const int wi = threadIdx.x >> 6;
+    const BlockGrid g = a.g;
+    const int nblk = g.nby * g.nbx;
+    const int ch = lb / nblk;
+    const int b = lb - ch * nblk;
+    const int by = b / g.nbx;
+    const int bx = b - by * g.nbx;
+    const int y0 = block_origin(by, g.sy, g.h, g.bh);
+    const int x0 = block_origin(bx, g.sx, g.w, g.bw);
+    int oylo, oyhi, oxlo, oxhi;
+    owner_range(by, g.nby, g.sy, g.h, g.bh, &oylo, &oyhi);
+    owner_range(bx, g.nbx, g.sx, g.w, g.bw, &oxlo, &oxhi);
+
+    const float* __restrict__ U = CORR ? nullptr : (const float*)uin_v + ch * a.cpitch;
+    const uint16_t* __restrict__ U16 =
+        CORR && uin_v ? (const uint16_t*)uin_v + ch * a.cpitch : nullptr;
+    const bool on = lane < g.bw;
+    const int x = x0 + lane;
+    const bool has_top = y0 > 0;
+    const bool has_bot = y0 + 2 * RPW < g.h;
+    const bool has_left = x0 > 0;
+    const bool has_right = x0 + g.bw < g.w;
+    float* xrow = lds + (2 * RPW + 2) * TW;  // [2][64] boundary rows of p
+    float* xs = xrow + 2 * 64;               // [2] per-wave scalars (+ 4 for doubles)
+
+    // ---- stage the 66 x 66 tile: wave 0 tile rows 0..32, wave 1 rows
+    // 33..65 (tile row t = image row y0 - 1 + t, clamped: the reflecting
+    // boundary); halo columns: wave 0 rows 0..63, wave 1 rows 64, 65 ----
+    auto stage = [&](auto ld) {
+        const uint32_t xc = on ? x : x0;
+        const uint32_t Wd = g.w;
+        constexpr int NR = RPW + 1;
+        const int t0 = wi * NR;
+        float col[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            const int t = t0 + j;
+            int yy = y0 - 1 + t;
+            if (t == 0) yy = has_top ? yy : y0;
+            if (t == 2 * RPW + 1) yy = has_bot ? yy : y0 + 2 * RPW - 1;
+            col[j] = ld((uint32_t)yy * Wd + xc);
+        }
+        const uint32_t xl = max(x0 - 1, 0), xr = min(x0 + g.bw, g.w - 1);
+        const int th = wi == 0 ? lane : 64 + lane;
+        float hl = 0.f, hr = 0.f;
+        if (th < 2 * RPW + 2) {
+            const uint32_t r1 = (uint32_t)min(max(y0 + th - 1, 0), g.h - 1) * (uint32_t)g.w;
+            hl = ld(r1 + xl);
+            hr = ld(r1 + xr);
+        }
+        if (on) {
+#pragma unroll
+            for (int j = 0; j < NR; ++j) lds[(t0 + j) * TW + lane + CO] = col[j];
+        }
+        if (th < 2 * RPW + 2) {
+            lds[th * TW + CO - 1] = hl;
+            lds[th * TW + CO + g.bw] = hr;
+        }
+    };
+    if constexpr (!CORR) {
+        stage([&](uint32_t i) { return U[i]; });
+    } else {
+        if (U16)
+            stage([&](uint32_t i) { return bf16_to_f(U16[i]); });
+        else
+            stage([](uint32_t) { return 0.f; });
+    }
+    // unknown-pixel bits of this wave's 32 rows of the column
+    uint32_t mw = 0u;
+    if (on) {
+        const int gy = y0 >> 6, sh = y0 & 63;
+        const uint64_t* mb = mbits + (uint32_t)gy * (uint32_t)g.w + (uint32_t)x;
+        uint64_t bits = mb[0] >> sh;
+        if (sh) bits |= mb[g.w] << (64 - sh);
+        mw = (uint32_t)(bits >> (RPW * wi));
+    }
+    __syncthreads();
+
+    // ---- residual of this wave's rows, owned norm ----
+    float r[RPW], w[RPW];
+    float rho_l0 = 0.f, rho_l1 = 0.f, own_l = 0.f;
+    const int ry0 = y0 + RPW * wi;
+    {
+        const int ylo = oylo - ry0, yhi = oyhi - ry0;
+        const float* col = lds + lane + CO + RPW * wi * TW;
+        float uup = col[0];
+        float uy = col[TW];
+        const uint16_t* R16 = nullptr;
+        if constexpr (CORR) R16 = rhs + ch * a.cpitch + (uint32_t)(on ? x : x0);
+#pragma unroll
+        for (int y = 0; y < RPW; ++y) {
+            const float udn = col[(y + 2) * TW];
+            const float ul = col[(y + 1) * TW - 1];
+            const float ur = col[(y + 1) * TW + 1];
+            float lap = ((uup - uy) + (udn - uy)) + ((ul - uy) + (ur - uy));
+            if constexpr (CORR) lap = bf16_to_f(R16[(uint32_t)(ry0 + y) * (uint32_t)g.w]) + lap;
+            const float ry = mask_keep(mw, y, lap);
+            r[y] = ry;
+            w[y] = uy;
+            const float rq = ry * ry;
+            if (y & 1) rho_l1 += rq; else rho_l0 += rq;
+            own_l += (y >= ylo && y < yhi) ? rq : 0.f;
+            uup = uy;
+            uy = udn;
+        }
+    }
+    double* xd = reinterpret_cast<double*>(xs + 4);  // 8-byte aligned: kSplitLds offset is even
+    {
+        const bool own_col = on && x >= oxlo && x < oxhi;
+        const double rsq = wave_sum_d(own_col ? (double)own_l : 0.0);
+        const float rw = wave_sum(rho_l0 + rho_l1);
+        if (lane == 0) {
+            xd[wi] = rsq;
+            xs[wi] = rw;
+        }
+    }
+    __syncthreads();
+    float rho = xs[0] + xs[1];
+    if (wi == 0 && lane == 0) partial[(int64_t)b * a.channels + ch] = xd[0] + xd[1];
+
+    // ---- local CG from v = 0 (same local matrix as sweep_body) ----
+    const float al = a.alpha;
+    const float wl = (lane > 0) ? 1.f : (has_left ? al : 0.f);
+    const float wr = (lane < g.bw - 1) ? 1.f : (has_right ? al : 0.f);
+    const float dmid = 2.f + wl + wr;
+    const float dfirst = wi == 0 ? dmid - 1.f + (has_top ? al : 0.f) : dmid;
+    const float dlast = wi == 1 ? dmid - 1.f + (has_bot ? al : 0.f) : dmid;
+
+    float p[RPW];
+    float q[QL ? 1 : RPW];
+    // QL: q = A p parked in this wave's half of the dead tile (float4 per
+    // lane and 4 rows)
+    float4* qs = reinterpret_cast<float4*>(lds) + wi * (RPW / 4) * 64;
+#pragma unroll
+    for (int y = 0; y < RPW; ++y) p[y] = r[y];
+    const float rho_stop = a.local_tol2 * (float)(g.bh * g.bw);
+    int it = 0;
+    for (; it < a.k; ++it) {
+        if (!(rho > rho_stop)) break;
+        // re-define the mask word each step so that the 32 per-row bit
+        // extracts stay inside the loop instead of holding 32 registers
+        asm volatile("" : "+v"(mw));
+        // swap boundary rows: wave 0 sends row 31, wave 1 row 0
+        xrow[wi * 64 + lane] = wi == 0 ? p[RPW - 1] : p[0];
+        __syncthreads();
+        const float pnb = xrow[(1 - wi) * 64 + lane];
+        float pq0 = 0.f, pq1 = 0.f;
+        float q4[4];
+#pragma unroll
+        for (int y = 0; y < RPW; ++y) {
+            const float up = y > 0 ? p[y - 1] : (wi == 1 ? pnb : 0.f);
+            const float dn = y < RPW - 1 ? p[y + 1] : (wi == 0 ? pnb : 0.f);
+            float s = up + dn;
+            s += from_left(p[y]);
+            s += from_right(p[y]);
+            const float d = y == 0 ? dfirst : (y == RPW - 1 ? dlast : dmid);
+            const float qy = mask_keep(mw, y, d * p[y] - s);
+            if constexpr (QL) {
+                q4[y & 3] = qy;
+                if ((y & 3) == 3) qs[(y >> 2) * 64 + lane] = make_float4(q4[0], q4[1], q4[2], q4[3]);
+            } else {
+                q[y] = qy;
+            }
+            if (y & 1) pq1 += p[y] * qy; else pq0 += p[y] * qy;
+        }
+        const float pqw = wave_sum(pq0 + pq1);
+        if (lane == 0) xs[2 + wi] = pqw;
+        __syncthreads();
+        const float pq = xs[2] + xs[3];
+        if (!(pq > 0.f)) {
+            ++it;
+            break;
+        }
+        const float alpha = rho / pq;
+        float rr0 = 0.f, rr1 = 0.f;
+        float4 qn;
+        if constexpr (QL) qn = qs[lane];
+#pragma unroll
+        for (int y = 0; y < RPW; ++y) {
+            float qy;
+            if constexpr (QL) {
+                if ((y & 3) == 0) {
+                    q4[0] = qn.x; q4[1] = qn.y; q4[2] = qn.z; q4[3] = qn.w;
+                    if (y + 4 < RPW) qn = qs[((y >> 2) + 1) * 64 + lane];
+                }
+                qy = q4[y & 3];
+            } else {
+                qy = q[y];
+            }
+            w[y] += alpha * p[y];
+            r[y] -= alpha * qy;
+            if (y & 1) rr1 += r[y] * r[y]; else rr0 += r[y] * r[y];
+        }
+        const float rrw = wave_sum(rr0 + rr1);
+        if (lane == 0) xs[wi] = rrw;
+        __syncthreads();
+        const float rr = xs[0] + xs[1];
+        const float beta = rr / rho;
+        rho = rr;
+#pragma unroll
+        for (int y = 0; y < RPW; ++y) p[y] = r[y] + beta * p[y];
+    }
+
+    if (cg_steps && wi == 0 && lane == 0) cg_steps[(int64_t)b * a.channels + ch] += (double)it;
+
+    // ---- restricted prolongation on owned pixels (eq. 9) ----
+    if (on && x >= oxlo && x < oxhi) {
+        uint32_t off = (uint32_t)ry0 * (uint32_t)g.w + (uint32_t)x;
+        if constexpr (!CORR) {
+            float* __restrict__ UO = (float*)uout_v + ch * a.cpitch;
+#pragma unroll
+            for (int y = 0; y < RPW; ++y) {
+                const int yy = ry0 + y;
+                if (yy >= oylo && yy < oyhi) UO[off] = w[y];
+                off += (uint32_t)g.w;
+            }
+        } else {
+            uint16_t* __restrict__ UO = (uint16_t*)uout_v + ch * a.cpitch;
+#pragma unroll
+            for (int y = 0; y < RPW; ++y) {
+                const int yy = ry0 + y;
+                if (yy >= oylo && yy < oyhi) UO[off] = f_to_bf16(w[y]);
+                off += (uint32_t)g.w;
+            }
+        }
+    }
+}
+
+#ifndef DDI_SPLIT_QL
+#define DDI_SPLIT_QL 1
+#endif
+#ifndef DDI_SPLIT_WAVES
+#define DDI_SPLIT_WAVES 4
+#endif
+template <bool CORR>
+__global__ __launch_bounds__(128, DDI_SPLIT_WAVES) void k_sweep2(const void* __restrict__ uin,
+                                                const uint16_t* __restrict__ rhs,
+                                                const uint64_t* __restrict__ mbits,
+                                                void* __restrict__ uout,
+                                                double* __restrict__ partial,
+                                                double* __restrict__ cg_steps,
+                                                const int* __restrict__ ctl, SweepArgs a) {
+    __shared__ __attribute__((aligned(16))) float lds[kSplitLds];
+    sweep2_body<CORR, DDI_SPLIT_QL>(uin, rhs, mbits, uout, partial, cg_steps, ctl, a,
+                                    xcd_remap(blockIdx.x, gridDim.x), lds);
+}
+
 // Zero fill (a kernel rather than hipMemsetAsync, so that the solve can be
 // captured into a graph).
 __global__ void k_clear(double* __restrict__ p, int n) {
@@ -491,6 +770,16 @@ __global__ __launch_bounds__(64) void k_sweep_batch(const SweepJob* __restrict__
     const SweepJob& J = jobs[find_job(jobs, njobs, lb)];
     sweep_body<RPW, RAGGED, QLDS, MBITS>(J.uin, nullptr, J.mbits, J.uout, J.partial, J.cg_steps,
                                          J.ctl, J.a, lb - J.wg0, lds);
+}
+
+// Split-sweep variant of k_sweep_batch (every job has full 64-row blocks).
+__global__ __launch_bounds__(128, DDI_SPLIT_WAVES) void k_sweep2_batch(const SweepJob* __restrict__ jobs,
+                                                      int njobs) {
+    __shared__ __attribute__((aligned(16))) float lds[kSplitLds];
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const SweepJob& J = jobs[find_job(jobs, njobs, lb)];
+    sweep2_body<false, DDI_SPLIT_QL>(J.uin, nullptr, J.mbits, J.uout, J.partial, J.cg_steps,
+                                     J.ctl, J.a, lb - J.wg0, lds);
 }
 
 // Column-transposed unknown-pixel bits of a mask: word (g, x) holds bit j
@@ -1254,11 +1543,22 @@ __global__ __launch_bounds__(kCgTpb) void k_coarse_cg64_batch(const CoarseJob* _
 // launchers
 // ---------------------------------------------------------------------------
 
+// Full 64-row blocks take the two-wave split sweep.
+#ifndef DDI_SPLIT
+#define DDI_SPLIT 1
+#endif
+static bool use_split(const SweepArgs& a) { return DDI_SPLIT && a.g.bh == 2 * kSplitRows; }
+
 template <int RPW, bool QLDS, bool MBITS>
 static hipError_t sweep_rpw(const float* uin, const uint64_t* mbits, float* uout,
                             double* partial, double* cg_steps, const int* ctl,
                             const SweepArgs& a, hipStream_t s) {
     const int grid = a.g.nby * a.g.nbx * a.channels;
+    if (use_split(a)) {
+        hipLaunchKernelGGL((k_sweep2<false>), dim3(grid), dim3(128), 0, s, uin, nullptr, mbits,
+                           uout, partial, cg_steps, ctl, a);
+        return hipGetLastError();
+    }
     if (a.g.bh == RPW)
         hipLaunchKernelGGL((k_sweep<RPW, false, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
                            uin, mbits, uout, partial, cg_steps, ctl, a);
@@ -1274,6 +1574,11 @@ static hipError_t sweep_corr_rpw(const uint16_t* din, const uint16_t* rhs,
                                  double* cg_steps, const int* ctl, const SweepArgs& a,
                                  hipStream_t s) {
     const int grid = a.g.nby * a.g.nbx * a.channels;
+    if (use_split(a)) {
+        hipLaunchKernelGGL((k_sweep2<true>), dim3(grid), dim3(128), 0, s, din, rhs, mbits, dout,
+                           partial, cg_steps, ctl, a);
+        return hipGetLastError();
+    }
     if (a.g.bh == RPW)
         hipLaunchKernelGGL((k_sweep_corr<RPW, false, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
                            din, rhs, mbits, dout, partial, cg_steps, ctl, a);
@@ -1487,9 +1792,15 @@ void sweep_instance(int bh, int* rpw, bool* ragged) {
     *ragged = bh != *rpw;
 }
 
+bool sweep_split(int bh) { return DDI_SPLIT && bh == 2 * kSplitRows; }
+
 hipError_t launch_sweep_batch(const SweepJob* jobs, int njobs, int total_wg, int rpw,
                               bool ragged, hipStream_t s) {
     if (total_wg <= 0 || njobs <= 0) return hipSuccess;
+    if (rpw == 64 && !ragged && DDI_SPLIT) {
+        hipLaunchKernelGGL(k_sweep2_batch, dim3(total_wg), dim3(128), 0, s, jobs, njobs);
+        return hipGetLastError();
+    }
 #define DDI_SB(R, G, Q, M)                                                                   \
     hipLaunchKernelGGL((k_sweep_batch<R, G, Q, M>), dim3(total_wg), dim3(64), 0, s, jobs, njobs)
     switch (rpw) {
