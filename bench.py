@@ -34,7 +34,11 @@ Prints one JSON line. Besides the driver's fields it carries
                 of the images, scaled to frames of the batch's mix);
   max_err_grey  max |u - u_oracle| on the 0-255 scale (batch: over the
                 sample);
-  p50_ms/p99_ms latency of the timed solves.
+  p50_ms/p99_ms latency of one frame solved on its own (wall clock of a
+                synchronous solve, after the timed region); the timed
+                region keeps two frames in flight on two plans
+                (ddi_solve_async / ddi_solve_wait) so that the GPU does not
+                idle while the host reads a stop test back.
 
 Usage: python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu]
                        [--workload 4k|batch|precision|serve]
@@ -213,26 +217,54 @@ def run_frame(args, workload: str):
     c = torch.from_numpy(c_np).cuda()
     u = torch.empty_like(f)
     prm = precision_params() if precision else solver_params()
-    plan = ddi.Plan(H, W, C, timing=1, **prm)
+    # two plans with a frame each in flight (float32 path): while the host
+    # waits for one plan's stop test, the other's solve is already queued,
+    # so the GPU does not idle between frames
+    nplans = 1 if precision else 2
+    plans = [ddi.Plan(H, W, C, timing=1, **prm) for _ in range(nplans)]
+    us = [u] + [torch.empty_like(f) for _ in range(nplans - 1)]
+    plan = plans[0]
 
     for _ in range(args.warmup):
-        plan.solve(f, c, u)
+        for p, uu in zip(plans, us):
+            p.solve(f, c, uu)
     torch.cuda.synchronize()
-    lat, sweep_ms, nsweeps, sweeps_per_solve, rels, steps, refs = [], 0.0, 0, [], [], 0.0, 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        _, st = plan.solve(f, c, u)
-        lat.append((time.perf_counter() - ts) * 1e3)
+    sweep_ms, nsweeps, sweeps_per_solve, rels, steps, refs = 0.0, 0, [], [], 0.0, 0
+
+    def account(st):
+        nonlocal sweep_ms, nsweeps, steps, refs
         sweep_ms += st["sweep_ms"]
         nsweeps += st["sweeps"]
         steps += st["cg_steps"]
         refs += st["refinements"]
         sweeps_per_solve.append(st["sweeps"])
         rels.append(st["rel_residual"])
+
+    t0 = time.perf_counter()
+    if nplans == 1:
+        for _ in range(args.steps):
+            _, st = plan.solve(f, c, u)
+            account(st)
+    else:
+        plans[0].solve_async(f, c, us[0])
+        for i in range(args.steps):
+            if i + 1 < args.steps:
+                plans[(i + 1) % 2].solve_async(f, c, us[(i + 1) % 2])
+            _, st = plans[i % 2].wait()
+            account(st)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     fps = args.steps / elapsed
+    # latency of one frame on its own (no other frame queued): wall clock
+    # of a synchronous solve
+    lat = []
+    for _ in range(max(10, min(args.steps, 50))):
+        ts = time.perf_counter()
+        plan.solve(f, c, u)
+        lat.append((time.perf_counter() - ts) * 1e3)
+    sync_fps = 1e3 / float(np.mean(lat))
+    for p in plans[1:]:
+        p.close()
 
     flops, bytes_ = sweep_work(prm, nsweeps, steps)
     if precision:
@@ -264,6 +296,8 @@ def run_frame(args, workload: str):
            "config": {"workload": desc, **prm},
            "p50_ms": round(float(np.percentile(lat, 50)), 3),
            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "frames_in_flight": nplans,
+           "single_frame_sync_fps": round(sync_fps, 2),
            "sweeps_per_solve": sorted(set(sweeps_per_solve)),
            "rel_residual_max": max(rels),
            "roofline": roofline}

@@ -208,6 +208,22 @@ int ddi_create(ddi_plan** out, int height, int width, int channels,
 int ddi_solve(ddi_plan* plan, const float* f, const uint8_t* c, float* u,
               ddi_stats* st);
 
+/*
+ * ddi_solve in two halves, so that one host thread can keep the GPU busy
+ * with several plans (e.g. consecutive frames on two plans sharing a
+ * stream): ddi_solve_async enqueues the solve up to its first host check
+ * (the pyramid, the coarse levels and as many finest-level sweeps as the
+ * plan's previous solve needed, with their device stop tests) and returns;
+ * ddi_solve_wait waits for that plan's work only (HIP events), enqueues
+ * more sweeps if the stop test has not passed, finishes and fills *st.
+ * Each plan holds at most one pending solve; f, c, u must stay valid until
+ * the wait returns. st->ms then spans the plan's own enqueue-to-finish
+ * interval on the stream, which includes work of other plans queued in
+ * between. storage = 1 plans: use ddi_solve (DDI_EINVAL here).
+ */
+int ddi_solve_async(ddi_plan* plan, const float* f, const uint8_t* c, float* u);
+int ddi_solve_wait(ddi_plan* plan, ddi_stats* st);
+
 /* Release the plan and its device buffers. NULL is a no-op. */
 int ddi_destroy(ddi_plan* plan);
 

@@ -219,6 +219,7 @@ int ddi_destroy(ddi_plan* plan) {
     if (plan->host) (void)hipHostFree(plan->host);
     if (plan->e0) (void)hipEventDestroy(plan->e0);
     if (plan->e1) (void)hipEventDestroy(plan->e1);
+    if (plan->ev_ctl) (void)hipEventDestroy(plan->ev_ctl);
     for (hipEvent_t e : plan->sweep_ev) (void)hipEventDestroy(e);
     for (ddi_plan::Graph& g : plan->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -312,7 +313,8 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
         (err = hipMalloc(&P->ctl, 64)) != hipSuccess ||
         (err = hipHostMalloc(&P->hctl, 64, hipHostMallocDefault)) != hipSuccess ||
         (err = hipEventCreate(&P->e0)) != hipSuccess ||
-        (err = hipEventCreate(&P->e1)) != hipSuccess) {
+        (err = hipEventCreate(&P->e1)) != hipSuccess ||
+        (err = hipEventCreate(&P->ev_ctl)) != hipSuccess) {
         ddi_destroy(P);
         return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
     }
@@ -583,27 +585,31 @@ static int solve_refine(ddi_plan* P, const float* f, const uint8_t* c, float* u,
     return converged ? DDI_OK : DDI_ENOCONV;
 }
 
-int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats* st) {
-    if (!P || !f || !c || !u) return DDI_EINVAL;
-    if (P->p.storage == 1) {
-        Level& L0 = P->lv[0];
-        L0.f = f;
-        L0.c = c;
-        L0.u[0] = u;
-        if (st) std::memset(st, 0, sizeof(*st));
-        return solve_refine(P, f, c, u, st);
-    }
-    const int C = P->C;
+static int enqueue_check(ddi_plan* P);
+
+// Enqueues a solve up to the first host check: pyramid, coarse levels, the
+// first batch of finest-level sweeps with their device stop tests, then the
+// read-back of the control word (and, with timing, of the CG step counts),
+// recorded by ev_ctl. The finest level ping-pongs between u (index 0) and
+// the plan's buffer (index 1). It starts in the buffer that makes the
+// expected final iterate -- as many sweeps as the previous solve needed --
+// land in u, so that usually no copy is needed at the end. Once a stop test
+// passes, the sweeps still enqueued exit at once.
+static int begin_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u) {
     const ddi_params& prm = P->p;
     Level& L0 = P->lv[0];
     L0.f = f;
     L0.c = c;
     L0.u[0] = u;
-    if (st) std::memset(st, 0, sizeof(*st));
-
-    const bool timing = !P->sweep_ev.empty();
+    ddi_plan::Pending& q = P->pend;
+    q = ddi_plan::Pending();
+    q.f = f;
+    q.c = c;
+    q.u = u;
+    q.timing = !P->sweep_ev.empty();
     const bool graph = P->gs != nullptr;
     hipStream_t s = graph ? P->gs : P->s;
+    q.s = s;
     if (graph) {
         // order the plan's stream after work the caller queued before
         DDI_HIP(hipEventRecord(P->ev_in, P->s));
@@ -611,30 +617,22 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
     }
     DDI_HIP(hipEventRecord(P->e0, s));
 
-    // The finest level ping-pongs between u (index 0) and the plan's buffer
-    // (index 1). It starts in the buffer that makes the expected final
-    // iterate -- as many sweeps as the previous solve needed -- land in u,
-    // so that usually no copy is needed at the end. Sweeps are enqueued
-    // ahead in batches; after each sweep where the stop test applies,
-    // k_decide runs it on the device, and once it passes the sweeps still
-    // enqueued exit at once. The host waits once per batch; the first batch
-    // is as long as the previous solve needed.
     const int expect = P->last_sweeps >= 0 ? P->last_sweeps : std::max(prm.min_sweeps, 1);
-    const int start0 = std::min(expect, prm.max_sweeps) & 1;
+    q.start0 = std::min(expect, prm.max_sweeps) & 1;
     int batch = std::min(prm.max_sweeps, std::max(expect, prm.min_sweeps));
     if (batch > 0) {
         int upto = std::max(1, batch);
         while (upto < prm.max_sweeps && !is_check(prm, upto)) ++upto;
         batch = std::min(upto, prm.max_sweeps);
     }
+    if (q.timing) DDI_HIP(launch_clear(P->cgcnt, sweep_partials(L0.sw) * P->C, s));
 
-    int enq = 0;
     if (graph) {
         // one graph per (f, c, u, start buffer, first batch); later solves
         // with the same key replay it
         ddi_plan::Graph* hit = nullptr;
         for (ddi_plan::Graph& gr : P->graphs)
-            if (gr.exec && gr.f == f && gr.c == c && gr.u == u && gr.start == start0 &&
+            if (gr.exec && gr.f == f && gr.c == c && gr.u == u && gr.start == q.start0 &&
                 gr.batch == batch)
                 hit = &gr;
         if (!hit) {
@@ -648,10 +646,10 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
             }
             hipGraph_t g = nullptr;
             DDI_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            int e = enqueue_front(P, start0, s);
+            int e = enqueue_front(P, q.start0, s);
             if (!e) {
                 hipError_t he = launch_clear_int(P->ctl, 4, s);
-                e = he != hipSuccess ? hip_fail(he) : enqueue_sweeps(P, 0, batch, start0, false, s);
+                e = he != hipSuccess ? hip_fail(he) : enqueue_sweeps(P, 0, batch, q.start0, false, s);
             }
             hipError_t he = hipStreamEndCapture(s, &g);
             if (e) {
@@ -668,49 +666,72 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
             hit->f = f;
             hit->c = c;
             hit->u = u;
-            hit->start = start0;
+            hit->start = q.start0;
             hit->batch = batch;
         }
         hit->last_use = ++P->graph_clock;
         DDI_HIP(hipGraphLaunch(hit->exec, s));
-        enq = batch;
+        q.done_upto = batch;
     } else {
-        int e = enqueue_front(P, start0, s);
+        int e = enqueue_front(P, q.start0, s);
         if (e) return e;
         DDI_HIP(launch_clear_int(P->ctl, 4, s));
+        e = enqueue_sweeps(P, 0, batch, q.start0, q.timing, s);
+        if (e) return e;
+        q.done_upto = batch;
     }
+    q.active = true;
+    return enqueue_check(P);
+}
 
-    // ---- finest level: wait for each batch, then enqueue more if needed ----
+// Read-back of the control word (and of the CG step counts with timing),
+// recorded by ev_ctl.
+static int enqueue_check(ddi_plan* P) {
+    const int C = P->C;
+    hipStream_t s = P->pend.s;
+    if (P->pend.timing) {
+        DDI_HIP(launch_reduce(P->cgcnt, sweep_partials(P->lv[0].sw), C, C, P->red + 2 * C + 2, s));
+        DDI_HIP(hipMemcpyAsync(P->host + 2 * C + 2, P->red + 2 * C + 2, C * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    }
+    DDI_HIP(hipMemcpyAsync(P->hctl, P->ctl, 4 * sizeof(int) + sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    DDI_HIP(hipEventRecord(P->ev_ctl, s));
+    return DDI_OK;
+}
+
+// Waits for the enqueued sweeps, enqueues more batches while the stop test
+// has not passed, then finishes: the optional final residual, the move of
+// the result into u, and the statistics. Only this plan's work is waited for
+// (events), so solves of other plans queued behind it keep the GPU busy.
+static int finish_solve(ddi_plan* P, ddi_stats* st) {
+    ddi_plan::Pending& q = P->pend;
+    if (!q.active) return DDI_EINVAL;
+    q.active = false;
+    const int C = P->C;
+    const ddi_params& prm = P->p;
+    Level& L0 = P->lv[0];
+    hipStream_t s = q.s;
+    const float* f = q.f;
+    const uint8_t* c = q.c;
+    float* u = q.u;
+    if (st) std::memset(st, 0, sizeof(*st));
+
     bool validated = false, converged = false;
     double rel = INFINITY;
-    auto validate = [&]() -> int {
-        validated = true;
-        if (P->host[C + 1] > 0.0) return DDI_EINVAL;
-        if (P->host[C] <= 0.0) return DDI_ESINGULAR;
-        return DDI_OK;
-    };
     int sweeps = 0;
-    int done_upto = enq;  // sweeps enqueued so far
-    bool first = true;
-    while (done_upto < prm.max_sweeps || (first && done_upto > 0)) {
-        if (!first || !graph) {
-            int upto = std::min(prm.max_sweeps, std::max(done_upto + 1, first ? batch : done_upto + 2));
-            while (upto < prm.max_sweeps && !is_check(prm, upto)) ++upto;
-            int e = enqueue_sweeps(P, done_upto, upto, start0, timing, s);
-            if (e) return e;
-            done_upto = upto;
-        }
-        first = false;
-        DDI_HIP(hipMemcpyAsync(P->hctl, P->ctl, 4 * sizeof(int) + sizeof(double),
-                               hipMemcpyDeviceToHost, s));
-        DDI_HIP(hipStreamSynchronize(s));
+    int done_upto = q.done_upto;
+    for (;;) {
+        DDI_HIP(hipEventSynchronize(P->ev_ctl));
         const int* hc = reinterpret_cast<const int*>(P->hctl);
-        validated = true;
+        validated = done_upto > 0;
         if (hc[2] == 1) return DDI_EINVAL;
         if (hc[2] == 2) return DDI_ESINGULAR;
-        double rel2;
-        std::memcpy(&rel2, hc + 4, sizeof(rel2));
-        rel = std::sqrt(rel2);
+        if (done_upto > 0) {
+            double rel2;
+            std::memcpy(&rel2, hc + 4, sizeof(rel2));
+            rel = std::sqrt(rel2);
+        }
         if (hc[0] != 0) {
             sweeps = hc[1];
             converged = true;
@@ -718,11 +739,18 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
         }
         sweeps = done_upto;
         if (done_upto >= prm.max_sweeps) break;
+        int upto = std::min(prm.max_sweeps, done_upto + 2);
+        while (upto < prm.max_sweeps && !is_check(prm, upto)) ++upto;
+        int e = enqueue_sweeps(P, done_upto, upto, q.start0, q.timing, s);
+        if (e) return e;
+        done_upto = upto;
+        if ((e = enqueue_check(P))) return e;
     }
-    int cur = start0 ^ (sweeps & 1);
+    int cur = q.start0 ^ (sweeps & 1);
     P->last_sweeps = sweeps;
 
     // ---- final residual of the returned iterate; move it into u ----
+    hipEvent_t end = P->ev_ctl;
     if (prm.final_residual || !validated) {
         int rwg = 0;
         DDI_HIP(launch_residual(f, c, L0.u[cur], P->h, P->w, C, nullptr,
@@ -730,9 +758,12 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
         DDI_HIP(launch_reduce(P->part, rwg, C, C, P->red + C + 2, s));
         DDI_HIP(hipMemcpyAsync(P->host, P->red, (2 * C + 2) * sizeof(double),
                                hipMemcpyDeviceToHost, s));
-        DDI_HIP(hipStreamSynchronize(s));
-        int e;
-        if (!validated && (e = validate())) return e;
+        DDI_HIP(hipEventRecord(P->e1, s));
+        DDI_HIP(hipEventSynchronize(P->e1));
+        end = P->e1;
+        validated = true;
+        if (P->host[C + 1] > 0.0) return DDI_EINVAL;
+        if (P->host[C] <= 0.0) return DDI_ESINGULAR;
         if (prm.final_residual) {
             rel = rel_from_host(P, P->host + C + 2);
             converged = rel <= prm.rel_tol || converged;
@@ -740,22 +771,16 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
     } else if (cur == 1) {
         DDI_HIP(hipMemcpyAsync(u, L0.u[1], (size_t)C * P->h * P->w * sizeof(float),
                                hipMemcpyDeviceToDevice, s));
+        DDI_HIP(hipEventRecord(P->e1, s));
+        DDI_HIP(hipEventSynchronize(P->e1));
+        end = P->e1;
     }
-    const int nb = sweep_partials(L0.sw);
-    if (timing) {
-        // the counters are cleared as they are read, ready for the next solve
-        DDI_HIP(launch_reduce(P->cgcnt, nb, C, C, P->red + 2 * C + 2, s, true));
-        DDI_HIP(hipMemcpyAsync(P->host + 2 * C + 2, P->red + 2 * C + 2, C * sizeof(double),
-                               hipMemcpyDeviceToHost, s));
-    }
-    DDI_HIP(hipEventRecord(P->e1, s));
-    DDI_HIP(hipEventSynchronize(P->e1));
     double nsteps = 0.0;
-    for (int k = 0; timing && k < C; ++k) nsteps += P->host[2 * C + 2 + k];
+    for (int k = 0; q.timing && k < C; ++k) nsteps += P->host[2 * C + 2 + k];
     float ms = 0.f;
-    DDI_HIP(hipEventElapsedTime(&ms, P->e0, P->e1));
+    DDI_HIP(hipEventElapsedTime(&ms, P->e0, end));
     double sweep_ms = 0.0;
-    for (int i = 0; timing && i < sweeps; ++i) {
+    for (int i = 0; q.timing && i < sweeps; ++i) {
         float t = 0.f;
         DDI_HIP(hipEventElapsedTime(&t, P->sweep_ev[2 * i], P->sweep_ev[2 * i + 1]));
         sweep_ms += t;
@@ -769,6 +794,38 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
         st->cg_steps = nsteps;
     }
     return converged ? DDI_OK : DDI_ENOCONV;
+}
+
+int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats* st) {
+    if (!P || !f || !c || !u) return DDI_EINVAL;
+    if (P->pend.active) return DDI_EINVAL;
+    if (P->p.storage == 1) {
+        Level& L0 = P->lv[0];
+        L0.f = f;
+        L0.c = c;
+        L0.u[0] = u;
+        if (st) std::memset(st, 0, sizeof(*st));
+        return solve_refine(P, f, c, u, st);
+    }
+    int e = begin_solve(P, f, c, u);
+    if (e) {
+        P->pend.active = false;
+        return e;
+    }
+    return finish_solve(P, st);
+}
+
+int ddi_solve_async(ddi_plan* P, const float* f, const uint8_t* c, float* u) {
+    if (!P || !f || !c || !u) return DDI_EINVAL;
+    if (P->pend.active || P->p.storage != 0) return DDI_EINVAL;
+    int e = begin_solve(P, f, c, u);
+    if (e) P->pend.active = false;
+    return e;
+}
+
+int ddi_solve_wait(ddi_plan* P, ddi_stats* st) {
+    if (!P || !P->pend.active) return DDI_EINVAL;
+    return finish_solve(P, st);
 }
 
 const char* ddi_strerror(int code) {

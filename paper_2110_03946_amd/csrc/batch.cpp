@@ -330,7 +330,7 @@ void build_front(ddi_batch* B, const std::vector<int>& start0, Arena& A, Front& 
             const Level& lev = P->lv[l];
             Level& fine = P->lv[l - 1];
             const int dst = l == 1 ? start0[i] : 0;
-            if (!prolong4_ok(fine.f, fine.c, fine.u[dst], fine.w)) {
+            if (!prolong4_ok(lev.u[cur[i]], fine.f, fine.c, fine.u[dst], fine.w)) {
                 Front::Step st;
                 st.kind = Front::Step::ProlongOne;
                 st.img = i;

@@ -222,7 +222,7 @@ hipError_t launch_reduce_batch(const ReduceJob* jobs, int njobs, int ncols, hipS
 // Whether the width-4 coarsening / prolongation applies (w % 4 == 0 and
 // vector-aligned buffers); launch_coarsen / launch_prolong take it then.
 bool coarsen4_ok(const float* f, const uint8_t* c, const float* fc, const uint8_t* cc, int w);
-bool prolong4_ok(const float* f, const uint8_t* c, const float* u, int w);
+bool prolong4_ok(const float* uc, const float* f, const uint8_t* c, const float* u, int w);
 // Statistics rows launch_coarsen / launch_stats write for these arguments.
 int coarsen_rows(const float* f, const uint8_t* c, const float* fc, const uint8_t* cc, int h,
                  int w);

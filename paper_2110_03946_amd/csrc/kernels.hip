@@ -74,6 +74,17 @@ constexpr int kXcds = 8;
 #endif
 constexpr int kXcdChunk = DDI_XCD_CHUNK;
 
+// Workgroup b of n -> logical index: XCD j (= b mod 8) takes one
+// contiguous band of the logical order, so that row-streaming kernels whose
+// neighbouring rows share reads (prolongation: four fine rows read each
+// coarse row) fetch them into one L2 only. A tail shorter than 8 keeps its
+// order.
+__device__ __forceinline__ int xcd_band(int b, int n) {
+    const int full = n - n % kXcds;
+    if (b >= full) return b;
+    return (b % kXcds) * (full / kXcds) + b / kXcds;
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int n) {
     const int full = n - n % (kXcds * kXcdChunk);
     if (b >= full) return b;
@@ -451,110 +462,131 @@ constexpr int kSplitRows = 32;
 // (two p rows, then the per-wave scalars).
 constexpr int kSplitLds = (2 * kSplitRows + 2) * kTileW + 2 * 64 + 8;
 
-template <bool CORR, bool QL>
-__device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
-                                            const uint16_t* __restrict__ rhs,
-                                            const uint64_t* __restrict__ mbits,
-                                            void* __restrict__ uout_v,
-                                            double* __restrict__ partial,
-                                            double* __restrict__ cg_steps,
-                                            const int* __restrict__ ctl, const SweepArgs& a,
-                                            int lb, float* __restrict__ lds) {
+// Geometry of one block of the grid (logical index lb, channel-major).
+struct Blk {
+    int ch, b, y0, x0, oylo, oyhi, oxlo, oxhi;
+    bool has_top, has_bot, has_left, has_right;
+};
+
+__device__ __forceinline__ Blk blk_geo(const SweepArgs& a, int lb) {
+    const BlockGrid& g = a.g;
+    Blk k;
+    const int nblk = g.nby * g.nbx;
+    k.ch = lb / nblk;
+    k.b = lb - k.ch * nblk;
+    const int by = k.b / g.nbx;
+    const int bx = k.b - by * g.nbx;
+    k.y0 = block_origin(by, g.sy, g.h, g.bh);
+    k.x0 = block_origin(bx, g.sx, g.w, g.bw);
+    owner_range(by, g.nby, g.sy, g.h, g.bh, &k.oylo, &k.oyhi);
+    owner_range(bx, g.nbx, g.sx, g.w, g.bw, &k.oxlo, &k.oxhi);
+    k.has_top = k.y0 > 0;
+    k.has_bot = k.y0 + g.bh < g.h;
+    k.has_left = k.x0 > 0;
+    k.has_right = k.x0 + g.bw < g.w;
+    return k;
+}
+
+// This wave's share of a split block's tile, held in registers between the
+// loads and the LDS stores: tile rows 33 wi .. 33 wi + 32 of its column
+// (tile row t = image row y0 - 1 + t, clamped: the reflecting boundary),
+// one row of each halo column, and the block's 64 unknown-pixel bits.
+struct Tile2 {
+    float col[kSplitRows + 1];
+    float hl, hr;
+    uint32_t mlo, mhi;
+};
+
+// Loads (no waits): ld(ch, i) returns the widened value at element offset
+// i of channel plane ch.
+template <class LD>
+__device__ __forceinline__ void tile2_load(Tile2& T, const Blk& k, const SweepArgs& a,
+                                           const uint64_t* __restrict__ mbits, LD ld) {
+    constexpr int RPW = kSplitRows;
+    const BlockGrid& g = a.g;
+    const int lane = threadIdx.x & 63;
+    const int wi = threadIdx.x >> 6;
+    const bool on = lane < g.bw;
+    const int x = k.x0 + lane;
+    const uint32_t xc = on ? x : k.x0;
+    const uint32_t Wd = g.w;
+    const int t0 = wi * (RPW + 1);
+#pragma unroll
+    for (int j = 0; j < RPW + 1; ++j) {
+        const int t = t0 + j;
+        int yy = k.y0 - 1 + t;
+        if (t == 0) yy = k.has_top ? yy : k.y0;
+        if (t == 2 * RPW + 1) yy = k.has_bot ? yy : k.y0 + 2 * RPW - 1;
+        T.col[j] = ld(k.ch, (uint32_t)yy * Wd + xc);
+    }
+    const uint32_t xl = max(k.x0 - 1, 0), xr = min(k.x0 + g.bw, g.w - 1);
+    const int th = wi == 0 ? lane : 64 + lane;
+    const uint32_t r1 = (uint32_t)min(max(k.y0 + min(th, 2 * RPW + 1) - 1, 0), g.h - 1) * Wd;
+    T.hl = ld(k.ch, r1 + xl);
+    T.hr = ld(k.ch, r1 + xr);
+    uint64_t bits = 0;
+    if (on) {
+        const int gy = k.y0 >> 6, sh = k.y0 & 63;
+        const uint64_t* mb = mbits + (uint32_t)gy * Wd + (uint32_t)x;
+        bits = mb[0] >> sh;
+        if (sh) bits |= mb[g.w] << (64 - sh);
+    }
+    T.mlo = (uint32_t)bits;
+    T.mhi = (uint32_t)(bits >> 32);
+}
+
+__device__ __forceinline__ void tile2_store(const Tile2& T, const SweepArgs& a,
+                                            float* __restrict__ lds) {
     constexpr int RPW = kSplitRows;
     constexpr int TW = kTileW;
     constexpr int CO = 1;
-    if (ctl && ctl[0] != 0) return;  // read by both waves: the same decision
-
     const int lane = threadIdx.x & 63;
     const int wi = threadIdx.x >> 6;
-    const BlockGrid g = a.g;
-    const int nblk = g.nby * g.nbx;
-    const int ch = lb / nblk;
-    const int b = lb - ch * nblk;
-    const int by = b / g.nbx;
-    const int bx = b - by * g.nbx;
-    const int y0 = block_origin(by, g.sy, g.h, g.bh);
-    const int x0 = block_origin(bx, g.sx, g.w, g.bw);
-    int oylo, oyhi, oxlo, oxhi;
-    owner_range(by, g.nby, g.sy, g.h, g.bh, &oylo, &oyhi);
-    owner_range(bx, g.nbx, g.sx, g.w, g.bw, &oxlo, &oxhi);
+    const int t0 = wi * (RPW + 1);
+    if (lane < a.g.bw) {
+#pragma unroll
+        for (int j = 0; j < RPW + 1; ++j) lds[(t0 + j) * TW + lane + CO] = T.col[j];
+    }
+    const int th = wi == 0 ? lane : 64 + lane;
+    if (th < 2 * RPW + 2) {
+        lds[th * TW + CO - 1] = T.hl;
+        lds[th * TW + CO + a.g.bw] = T.hr;
+    }
+}
 
-    const float* __restrict__ U = CORR ? nullptr : (const float*)uin_v + ch * a.cpitch;
-    const uint16_t* __restrict__ U16 =
-        CORR && uin_v ? (const uint16_t*)uin_v + ch * a.cpitch : nullptr;
+// Residual, local CG and owned write-back of one split block whose tile is
+// in LDS (staged and followed by a barrier). QL: q parked in the wave's half
+// of the tile.
+template <bool CORR, bool QL>
+__device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
+                                               const uint16_t* __restrict__ rhs,
+                                               void* __restrict__ uout_v,
+                                               double* __restrict__ partial,
+                                               double* __restrict__ cg_steps,
+                                               const SweepArgs& a, float* __restrict__ lds) {
+    constexpr int RPW = kSplitRows;
+    constexpr int TW = kTileW;
+    constexpr int CO = 1;
+    const BlockGrid& g = a.g;
+    const int lane = threadIdx.x & 63;
+    const int wi = threadIdx.x >> 6;
     const bool on = lane < g.bw;
-    const int x = x0 + lane;
-    const bool has_top = y0 > 0;
-    const bool has_bot = y0 + 2 * RPW < g.h;
-    const bool has_left = x0 > 0;
-    const bool has_right = x0 + g.bw < g.w;
+    const int x = k.x0 + lane;
     float* xrow = lds + (2 * RPW + 2) * TW;  // [2][64] boundary rows of p
-    float* xs = xrow + 2 * 64;               // [2] per-wave scalars (+ 4 for doubles)
-
-    // ---- stage the 66 x 66 tile: wave 0 tile rows 0..32, wave 1 rows
-    // 33..65 (tile row t = image row y0 - 1 + t, clamped: the reflecting
-    // boundary); halo columns: wave 0 rows 0..63, wave 1 rows 64, 65 ----
-    auto stage = [&](auto ld) {
-        const uint32_t xc = on ? x : x0;
-        const uint32_t Wd = g.w;
-        constexpr int NR = RPW + 1;
-        const int t0 = wi * NR;
-        float col[NR];
-#pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            const int t = t0 + j;
-            int yy = y0 - 1 + t;
-            if (t == 0) yy = has_top ? yy : y0;
-            if (t == 2 * RPW + 1) yy = has_bot ? yy : y0 + 2 * RPW - 1;
-            col[j] = ld((uint32_t)yy * Wd + xc);
-        }
-        const uint32_t xl = max(x0 - 1, 0), xr = min(x0 + g.bw, g.w - 1);
-        const int th = wi == 0 ? lane : 64 + lane;
-        float hl = 0.f, hr = 0.f;
-        if (th < 2 * RPW + 2) {
-            const uint32_t r1 = (uint32_t)min(max(y0 + th - 1, 0), g.h - 1) * (uint32_t)g.w;
-            hl = ld(r1 + xl);
-            hr = ld(r1 + xr);
-        }
-        if (on) {
-#pragma unroll
-            for (int j = 0; j < NR; ++j) lds[(t0 + j) * TW + lane + CO] = col[j];
-        }
-        if (th < 2 * RPW + 2) {
-            lds[th * TW + CO - 1] = hl;
-            lds[th * TW + CO + g.bw] = hr;
-        }
-    };
-    if constexpr (!CORR) {
-        stage([&](uint32_t i) { return U[i]; });
-    } else {
-        if (U16)
-            stage([&](uint32_t i) { return bf16_to_f(U16[i]); });
-        else
-            stage([](uint32_t) { return 0.f; });
-    }
-    // unknown-pixel bits of this wave's 32 rows of the column
-    uint32_t mw = 0u;
-    if (on) {
-        const int gy = y0 >> 6, sh = y0 & 63;
-        const uint64_t* mb = mbits + (uint32_t)gy * (uint32_t)g.w + (uint32_t)x;
-        uint64_t bits = mb[0] >> sh;
-        if (sh) bits |= mb[g.w] << (64 - sh);
-        mw = (uint32_t)(bits >> (RPW * wi));
-    }
-    __syncthreads();
+    float* xs = xrow + 2 * 64;               // [4] per-wave scalars, then 2 doubles
+    double* xd = reinterpret_cast<double*>(xs + 4);
 
     // ---- residual of this wave's rows, owned norm ----
     float r[RPW], w[RPW];
     float rho_l0 = 0.f, rho_l1 = 0.f, own_l = 0.f;
-    const int ry0 = y0 + RPW * wi;
+    const int ry0 = k.y0 + RPW * wi;
     {
-        const int ylo = oylo - ry0, yhi = oyhi - ry0;
+        const int ylo = k.oylo - ry0, yhi = k.oyhi - ry0;
         const float* col = lds + lane + CO + RPW * wi * TW;
         float uup = col[0];
         float uy = col[TW];
         const uint16_t* R16 = nullptr;
-        if constexpr (CORR) R16 = rhs + ch * a.cpitch + (uint32_t)(on ? x : x0);
+        if constexpr (CORR) R16 = rhs + k.ch * a.cpitch + (uint32_t)(on ? x : k.x0);
 #pragma unroll
         for (int y = 0; y < RPW; ++y) {
             const float udn = col[(y + 2) * TW];
@@ -572,9 +604,8 @@ __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
             uy = udn;
         }
     }
-    double* xd = reinterpret_cast<double*>(xs + 4);  // 8-byte aligned: kSplitLds offset is even
     {
-        const bool own_col = on && x >= oxlo && x < oxhi;
+        const bool own_col = on && x >= k.oxlo && x < k.oxhi;
         const double rsq = wave_sum_d(own_col ? (double)own_l : 0.0);
         const float rw = wave_sum(rho_l0 + rho_l1);
         if (lane == 0) {
@@ -584,20 +615,18 @@ __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
     }
     __syncthreads();
     float rho = xs[0] + xs[1];
-    if (wi == 0 && lane == 0) partial[(int64_t)b * a.channels + ch] = xd[0] + xd[1];
+    if (wi == 0 && lane == 0) partial[(int64_t)k.b * a.channels + k.ch] = xd[0] + xd[1];
 
     // ---- local CG from v = 0 (same local matrix as sweep_body) ----
     const float al = a.alpha;
-    const float wl = (lane > 0) ? 1.f : (has_left ? al : 0.f);
-    const float wr = (lane < g.bw - 1) ? 1.f : (has_right ? al : 0.f);
+    const float wl = (lane > 0) ? 1.f : (k.has_left ? al : 0.f);
+    const float wr = (lane < g.bw - 1) ? 1.f : (k.has_right ? al : 0.f);
     const float dmid = 2.f + wl + wr;
-    const float dfirst = wi == 0 ? dmid - 1.f + (has_top ? al : 0.f) : dmid;
-    const float dlast = wi == 1 ? dmid - 1.f + (has_bot ? al : 0.f) : dmid;
+    const float dfirst = wi == 0 ? dmid - 1.f + (k.has_top ? al : 0.f) : dmid;
+    const float dlast = wi == 1 ? dmid - 1.f + (k.has_bot ? al : 0.f) : dmid;
 
     float p[RPW];
     float q[QL ? 1 : RPW];
-    // QL: q = A p parked in this wave's half of the dead tile (float4 per
-    // lane and 4 rows)
     float4* qs = reinterpret_cast<float4*>(lds) + wi * (RPW / 4) * 64;
 #pragma unroll
     for (int y = 0; y < RPW; ++y) p[y] = r[y];
@@ -669,29 +698,59 @@ __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
         for (int y = 0; y < RPW; ++y) p[y] = r[y] + beta * p[y];
     }
 
-    if (cg_steps && wi == 0 && lane == 0) cg_steps[(int64_t)b * a.channels + ch] += (double)it;
+    if (cg_steps && wi == 0 && lane == 0) cg_steps[(int64_t)k.b * a.channels + k.ch] += (double)it;
 
     // ---- restricted prolongation on owned pixels (eq. 9) ----
-    if (on && x >= oxlo && x < oxhi) {
+    if (on && x >= k.oxlo && x < k.oxhi) {
         uint32_t off = (uint32_t)ry0 * (uint32_t)g.w + (uint32_t)x;
         if constexpr (!CORR) {
-            float* __restrict__ UO = (float*)uout_v + ch * a.cpitch;
+            float* __restrict__ UO = (float*)uout_v + k.ch * a.cpitch;
 #pragma unroll
             for (int y = 0; y < RPW; ++y) {
                 const int yy = ry0 + y;
-                if (yy >= oylo && yy < oyhi) UO[off] = w[y];
+                if (yy >= k.oylo && yy < k.oyhi) UO[off] = w[y];
                 off += (uint32_t)g.w;
             }
         } else {
-            uint16_t* __restrict__ UO = (uint16_t*)uout_v + ch * a.cpitch;
+            uint16_t* __restrict__ UO = (uint16_t*)uout_v + k.ch * a.cpitch;
 #pragma unroll
             for (int y = 0; y < RPW; ++y) {
                 const int yy = ry0 + y;
-                if (yy >= oylo && yy < oyhi) UO[off] = f_to_bf16(w[y]);
+                if (yy >= k.oylo && yy < k.oyhi) UO[off] = f_to_bf16(w[y]);
                 off += (uint32_t)g.w;
             }
         }
     }
+}
+
+// One split block (tile loaded, stored, computed).
+template <bool CORR, bool QL>
+__device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
+                                            const uint16_t* __restrict__ rhs,
+                                            const uint64_t* __restrict__ mbits,
+                                            void* __restrict__ uout_v,
+                                            double* __restrict__ partial,
+                                            double* __restrict__ cg_steps,
+                                            const int* __restrict__ ctl, const SweepArgs& a,
+                                            int lb, float* __restrict__ lds) {
+    if (ctl && ctl[0] != 0) return;  // read by both waves: the same decision
+    const Blk k = blk_geo(a, lb);
+    Tile2 T;
+    if constexpr (!CORR) {
+        const float* U = (const float*)uin_v;
+        tile2_load(T, k, a, mbits, [&](int ch, uint32_t i) { return U[ch * a.cpitch + i]; });
+    } else {
+        const uint16_t* U16 = (const uint16_t*)uin_v;
+        if (U16)
+            tile2_load(T, k, a, mbits,
+                       [&](int ch, uint32_t i) { return bf16_to_f(U16[ch * a.cpitch + i]); });
+        else
+            tile2_load(T, k, a, mbits, [](int, uint32_t) { return 0.f; });
+    }
+    tile2_store(T, a, lds);
+    const uint32_t mw = (threadIdx.x >> 6) ? T.mhi : T.mlo;
+    __syncthreads();
+    sweep2_compute<CORR, QL>(k, mw, rhs, uout_v, partial, cg_steps, a, lds);
 }
 
 #ifndef DDI_SPLIT_QL
@@ -712,6 +771,7 @@ __global__ __launch_bounds__(128, DDI_SPLIT_WAVES) void k_sweep2(const void* __r
     sweep2_body<CORR, DDI_SPLIT_QL>(uin, rhs, mbits, uout, partial, cg_steps, ctl, a,
                                     xcd_remap(blockIdx.x, gridDim.x), lds);
 }
+
 
 // Zero fill (a kernel rather than hipMemsetAsync, so that the solve can be
 // captured into a graph).
@@ -1000,8 +1060,10 @@ __global__ __launch_bounds__(kTpb) void k_coarsen4_batch(const LevelJob* __restr
 // (y, 4t .. 4t+3) of all channels with one u32 mask load, float4 loads of f
 // where the mask is set, and float4 stores. Fine x = 2J sits at coarse
 // column J - 1/4 and x = 2J + 1 at J + 1/4, so the four pixels read coarse
-// columns 2t - 1 .. 2t + 2 (clamped) of two coarse rows. Same float64
-// bilinear expression as k_prolong.
+// columns 2t - 1 .. 2t + 2 (clamped) of two coarse rows: one float2 (2t,
+// 2t + 1: in range and 8-byte aligned since the coarse width is even) and
+// two scalars per row and channel. Every load is issued before the first
+// result is computed. Same float64 bilinear expression as k_prolong.
 template <int NC>
 __device__ __forceinline__ void prolong4_body(const float* __restrict__ uc, int hc, int wc,
                                               const float* __restrict__ f,
@@ -1022,12 +1084,32 @@ __device__ __forceinline__ void prolong4_body(const float* __restrict__ uc, int 
     } else {
         r0 = I; r1 = min(I + 1, hc - 1); ay = I + 1 < hc ? 0.25 : 0.0;
     }
-    // coarse columns 2t-1 .. 2t+2 clamped
-    int cj[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) cj[q] = min(max(2 * t - 1 + q, 0), wc - 1);
-    // per fine pixel b: first coarse column index (into cj) and weight of the second
     const int J0 = 2 * t;
+    const int jl = max(J0 - 1, 0), jr = min(J0 + 2, wc - 1);
+    // ---- all loads: the coarse values first (unconditional), then f
+    // where the mask is set; 32-bit element offsets inside a plane ----
+    float2 m0[NC], m1[NC];
+    float l0[NC], l1[NC], e0[NC], e1[NC];
+    const uint32_t o0 = (uint32_t)r0 * (uint32_t)wc, o1 = (uint32_t)r1 * (uint32_t)wc;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const float* C = uc + k * ncs;
+        m0[k] = *reinterpret_cast<const float2*>(C + (o0 + J0));
+        m1[k] = *reinterpret_cast<const float2*>(C + (o1 + J0));
+        l0[k] = C[o0 + jl];
+        l1[k] = C[o1 + jl];
+        e0[k] = C[o0 + jr];
+        e1[k] = C[o1 + jr];
+    }
+    float4 fk[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) fk[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (m) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) fk[k] = *reinterpret_cast<const float4*>(f + k * n + i);
+    }
+    // per fine pixel b: first coarse column (index into q0/q1) and weight of
+    // the second
     double ax[4];
     int c0[4];
     // x = 4t   -> coarse J0 - 1/4: (J0 - 1, J0), weight 0.75 (0 if J0 == 0)
@@ -1041,28 +1123,27 @@ __device__ __forceinline__ void prolong4_body(const float* __restrict__ uc, int 
     if (J0 == 0) c0[0] = 1;  // clamped: coordinate 0 -> column J0 only
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-        const float* C = uc + k * ncs;
-        double q0[4], q1[4];
+        // interpolate the four coarse columns in y first, then in x. With
+        // weights in {0, 1/4, 3/4, 1}, float64 holds these sums of float32
+        // values exactly unless their magnitudes differ by more than about
+        // 2^26, so the order does not matter for grey-level data; the
+        // result is rounded to float32 once
+        const double q0[4] = {l0[k], m0[k].x, m0[k].y, e0[k]};
+        const double q1[4] = {l1[k], m1[k].x, m1[k].y, e1[k]};
+        double yv[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            q0[q] = C[(int64_t)r0 * wc + cj[q]];
-            q1[q] = C[(int64_t)r1 * wc + cj[q]];
-        }
-        const float4 fk = m ? *reinterpret_cast<const float4*>(f + k * n + i)
-                            : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int j = 0; j < 4; ++j) yv[j] = (1.0 - ay) * q0[j] + ay * q1[j];
         float o[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int a0 = c0[b], a1 = min(c0[b] + 1, 3);
-            const double v = (1.0 - ay) * ((1.0 - ax[b]) * q0[a0] + ax[b] * q0[a1]) +
-                             ay * ((1.0 - ax[b]) * q1[a0] + ax[b] * q1[a1]);
-            o[b] = (float)v;
+            o[b] = (float)((1.0 - ax[b]) * yv[a0] + ax[b] * yv[a1]);
         }
         float4 out;
-        out.x = (m & 0xffu) ? fk.x : o[0];
-        out.y = (m & 0xff00u) ? fk.y : o[1];
-        out.z = (m & 0xff0000u) ? fk.z : o[2];
-        out.w = (m & 0xff000000u) ? fk.w : o[3];
+        out.x = (m & 0xffu) ? fk[k].x : o[0];
+        out.y = (m & 0xff00u) ? fk[k].y : o[1];
+        out.z = (m & 0xff0000u) ? fk[k].z : o[2];
+        out.w = (m & 0xff000000u) ? fk[k].w : o[3];
         *reinterpret_cast<float4*>(u + k * n + i) = out;
     }
 }
@@ -1072,13 +1153,15 @@ __global__ __launch_bounds__(kTpb) void k_prolong4(const float* __restrict__ uc,
                                                    const float* __restrict__ f,
                                                    const uint8_t* __restrict__ c, int h, int w,
                                                    float* __restrict__ u) {
-    prolong4_body<NC>(uc, hc, wc, f, c, h, w, u, blockIdx.x, blockIdx.y);
+    const int gx = (w / 4 + kTpb - 1) / kTpb;
+    const int L = xcd_band(blockIdx.x, gridDim.x);
+    prolong4_body<NC>(uc, hc, wc, f, c, h, w, u, L % gx, L / gx);
 }
 
 template <int NC>
 __global__ __launch_bounds__(kTpb) void k_prolong4_batch(const LevelJob* __restrict__ jobs,
                                                          int njobs) {
-    const int lb = blockIdx.x;
+    const int lb = xcd_band(blockIdx.x, gridDim.x);
     const LevelJob& J = jobs[find_job(jobs, njobs, lb)];
     const int local = lb - J.wg0;
     prolong4_body<NC>(J.uc, J.hc, J.wc, J.f, J.c, J.h, J.w, J.u, local % J.gx, local / J.gx);
@@ -1549,6 +1632,7 @@ __global__ __launch_bounds__(kCgTpb) void k_coarse_cg64_batch(const CoarseJob* _
 #endif
 static bool use_split(const SweepArgs& a) { return DDI_SPLIT && a.g.bh == 2 * kSplitRows; }
 
+
 template <int RPW, bool QLDS, bool MBITS>
 static hipError_t sweep_rpw(const float* uin, const uint64_t* mbits, float* uout,
                             double* partial, double* cg_steps, const int* ctl,
@@ -1744,8 +1828,8 @@ hipError_t launch_init(const float* f, const uint8_t* c, int h, int w, int chann
 
 hipError_t launch_prolong(const float* uc, int hc, int wc, const float* f, const uint8_t* c,
                           int h, int w, int channels, float* u, hipStream_t s) {
-    if (prolong4_ok(f, c, u, w)) {
-        dim3 grid((w / 4 + kTpb - 1) / kTpb, h);
+    if (prolong4_ok(uc, f, c, u, w)) {
+        dim3 grid(((w / 4 + kTpb - 1) / kTpb) * h);
         switch (channels) {
 #define DDI_CASE(NC)                                                                          \
     case NC:                                                                                  \
@@ -1818,8 +1902,8 @@ bool coarsen4_ok(const float* f, const uint8_t* c, const float* fc, const uint8_
     return w % 4 == 0 && aligned(f, 16) && aligned(c, 4) && aligned(fc, 8) && aligned(cc, 2);
 }
 
-bool prolong4_ok(const float* f, const uint8_t* c, const float* u, int w) {
-    return w % 4 == 0 && aligned(f, 16) && aligned(c, 4) && aligned(u, 16);
+bool prolong4_ok(const float* uc, const float* f, const uint8_t* c, const float* u, int w) {
+    return w % 4 == 0 && aligned(uc, 8) && aligned(f, 16) && aligned(c, 4) && aligned(u, 16);
 }
 
 int coarsen_rows(const float* f, const uint8_t* c, const float* fc, const uint8_t* cc, int h,

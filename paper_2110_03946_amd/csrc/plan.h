@@ -61,6 +61,17 @@ struct ddi_plan {
     int* ctl = nullptr;      // device stop test: done, sweeps, error, -, rel (double)
     void* hctl = nullptr;    // pinned mirror of ctl
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t ev_ctl = nullptr;  // after the control-word read-back of a batch
+    // a solve enqueued by ddi_solve_async and not yet waited for
+    struct Pending {
+        bool active = false, timing = false;
+        const float* f = nullptr;
+        const uint8_t* c = nullptr;
+        float* u = nullptr;
+        hipStream_t s = nullptr;
+        int start0 = 0, done_upto = 0;
+    };
+    Pending pend;
     std::vector<hipEvent_t> sweep_ev;  // 2 per finest-level sweep (timing)
     int last_sweeps = -1;              // finest-level sweeps of the previous solve
     // graph mode: a plan-owned stream, and the instantiated graph of the

@@ -88,6 +88,8 @@ def lib():
             "ddi_create": (i, [ctypes.POINTER(vp), i, i, i, ctypes.POINTER(Params), vp]),
             "ddi_solve": (i, [vp, vp, vp, vp, ctypes.POINTER(Stats)]),
             "ddi_destroy": (i, [vp]),
+            "ddi_solve_async": (i, [vp, vp, vp, vp]),
+            "ddi_solve_wait": (i, [vp, ctypes.POINTER(Stats)]),
             "ddi_strerror": (ctypes.c_char_p, [i]),
             "ddi_last_hip_error": (i, []),
             "ddi_block_count": (i, [i, i, i]),
@@ -239,6 +241,26 @@ class Plan:
         rc = lib().ddi_solve(self._h, _ptr(f), _ptr(c), _ptr(u), ctypes.byref(st))
         if rc != DDI_OK and not (allow_noconv and rc == DDI_ENOCONV):
             raise DDIError(rc, "ddi_solve")
+        return u, st.as_dict()
+
+    def solve_async(self, f, c, u):
+        """Enqueue a solve (ddi_solve_async); f, c, u must stay alive until wait()."""
+        hw = (self.height, self.width)
+        f = _img(f, "f", self.channels, hw)
+        c = _mask(c, hw)
+        u = _img(u, "u", self.channels, hw)
+        self._pending = (f, c, u)
+        _check(lib().ddi_solve_async(self._h, _ptr(f), _ptr(c), _ptr(u)), "ddi_solve_async")
+        return u
+
+    def wait(self, allow_noconv: bool = False):
+        """Finish the pending solve (ddi_solve_wait); returns (u, stats)."""
+        st = Stats()
+        rc = lib().ddi_solve_wait(self._h, ctypes.byref(st))
+        u = self._pending[2] if getattr(self, "_pending", None) else None
+        self._pending = None
+        if rc != DDI_OK and not (allow_noconv and rc == DDI_ENOCONV):
+            raise DDIError(rc, "ddi_solve_wait")
         return u, st.as_dict()
 
     def device_bytes(self) -> int:
