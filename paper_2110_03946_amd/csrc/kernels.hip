@@ -109,6 +109,15 @@ __device__ __forceinline__ uint16_t f_to_bf16(float x) {
     return (uint16_t)(u >> 16);
 }
 
+// The same selection with the bit field extract written out: the compiler
+// otherwise turns a one-bit v_bfe_i32 into and + compare + select (three
+// instructions for two).
+__device__ __forceinline__ float mask_bfe(uint32_t bits, int bit, float q) {
+    int sel;
+    asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(sel) : "v"(bits), "s"(bit));
+    return __int_as_float(__float_as_int(q) & sel);
+}
+
 // Mask of one block column, built from the bits of the unknown pixels.
 // Float storage (1 = unknown) for short columns; the bits themselves for
 // 64-row columns, where registers are scarce.
@@ -497,33 +506,73 @@ struct Tile2 {
     uint32_t mlo, mhi;
 };
 
-// Loads (no waits): ld(ch, i) returns the widened value at element offset
-// i of channel plane ch.
+// Element i of a plane through a 32-bit byte offset: a uniform base plus an
+// unsigned 32-bit offset maps onto one global load with a scalar base
+// (element offsets are below 2^30, so the byte offset fits).
+template <class T>
+__device__ __forceinline__ T at32(const T* base, uint32_t i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void put32(T* base, uint32_t i, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
+}
+
+// Tile loaders: ld(i) reads element i of the plane, ld.bytes(b) the element
+// at byte offset b of a float32 plane (b / 2 for bfloat16).
+struct LoadF32 {
+    const float* p;
+    __device__ __forceinline__ float operator()(uint32_t i) const { return at32(p, i); }
+    __device__ __forceinline__ float bytes(uint32_t b) const {
+        return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(p) + b);
+    }
+};
+struct LoadBf16 {
+    const uint16_t* p;
+    __device__ __forceinline__ float operator()(uint32_t i) const { return bf16_to_f(at32(p, i)); }
+    __device__ __forceinline__ float bytes(uint32_t b) const {
+        return bf16_to_f(*reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(p) + (b >> 1)));
+    }
+};
+struct LoadZero {
+    __device__ __forceinline__ float operator()(uint32_t) const { return 0.f; }
+    __device__ __forceinline__ float bytes(uint32_t) const { return 0.f; }
+};
+
+// Loads (no waits): ld(i) returns the widened value at element offset i of
+// the block's channel plane (the plane base is uniform, the offsets 32-bit,
+// so every load is one scalar base plus a vector offset).
 template <class LD>
 __device__ __forceinline__ void tile2_load(Tile2& T, const Blk& k, const SweepArgs& a,
                                            const uint64_t* __restrict__ mbits, LD ld) {
     constexpr int RPW = kSplitRows;
     const BlockGrid& g = a.g;
     const int lane = threadIdx.x & 63;
-    const int wi = threadIdx.x >> 6;
+    const int wi = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool on = lane < g.bw;
     const int x = k.x0 + lane;
     const uint32_t xc = on ? x : k.x0;
     const uint32_t Wd = g.w;
+    // tile row t0 + j = image row y0 - 1 + t0 + j; only tile rows 0 and 65
+    // (first of wave 0, last of wave 1) can lie outside the image
     const int t0 = wi * (RPW + 1);
+    const int yfirst = (wi == 0 && !k.has_top) ? k.y0 : k.y0 - 1 + t0;
+    const int ylast = (wi == 1 && !k.has_bot) ? k.y0 + 2 * RPW - 1 : k.y0 - 1 + t0 + RPW;
+    T.col[0] = ld((uint32_t)yfirst * Wd + xc);
+    // byte offsets: one add per row
+    const uint32_t bstride = Wd * 4u;
+    uint32_t boff = ((uint32_t)(k.y0 + t0) * Wd + xc) * 4u;
 #pragma unroll
-    for (int j = 0; j < RPW + 1; ++j) {
-        const int t = t0 + j;
-        int yy = k.y0 - 1 + t;
-        if (t == 0) yy = k.has_top ? yy : k.y0;
-        if (t == 2 * RPW + 1) yy = k.has_bot ? yy : k.y0 + 2 * RPW - 1;
-        T.col[j] = ld(k.ch, (uint32_t)yy * Wd + xc);
+    for (int j = 1; j < RPW; ++j) {
+        T.col[j] = ld.bytes(boff);
+        boff += bstride;
     }
+    T.col[RPW] = ld((uint32_t)ylast * Wd + xc);
     const uint32_t xl = max(k.x0 - 1, 0), xr = min(k.x0 + g.bw, g.w - 1);
     const int th = wi == 0 ? lane : 64 + lane;
     const uint32_t r1 = (uint32_t)min(max(k.y0 + min(th, 2 * RPW + 1) - 1, 0), g.h - 1) * Wd;
-    T.hl = ld(k.ch, r1 + xl);
-    T.hr = ld(k.ch, r1 + xr);
+    T.hl = ld(r1 + xl);
+    T.hr = ld(r1 + xr);
     uint64_t bits = 0;
     if (on) {
         const int gy = k.y0 >> 6, sh = k.y0 & 63;
@@ -541,7 +590,7 @@ __device__ __forceinline__ void tile2_store(const Tile2& T, const SweepArgs& a,
     constexpr int TW = kTileW;
     constexpr int CO = 1;
     const int lane = threadIdx.x & 63;
-    const int wi = threadIdx.x >> 6;
+    const int wi = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t0 = wi * (RPW + 1);
     if (lane < a.g.bw) {
 #pragma unroll
@@ -569,7 +618,7 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
     constexpr int CO = 1;
     const BlockGrid& g = a.g;
     const int lane = threadIdx.x & 63;
-    const int wi = threadIdx.x >> 6;
+    const int wi = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool on = lane < g.bw;
     const int x = k.x0 + lane;
     float* xrow = lds + (2 * RPW + 2) * TW;  // [2][64] boundary rows of p
@@ -586,20 +635,24 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
         float uup = col[0];
         float uy = col[TW];
         const uint16_t* R16 = nullptr;
-        if constexpr (CORR) R16 = rhs + k.ch * a.cpitch + (uint32_t)(on ? x : k.x0);
+        if constexpr (CORR) R16 = rhs + k.ch * a.cpitch;
+        uint32_t roff = (uint32_t)ry0 * (uint32_t)g.w + (uint32_t)(on ? x : k.x0);
 #pragma unroll
         for (int y = 0; y < RPW; ++y) {
             const float udn = col[(y + 2) * TW];
             const float ul = col[(y + 1) * TW - 1];
             const float ur = col[(y + 1) * TW + 1];
             float lap = ((uup - uy) + (udn - uy)) + ((ul - uy) + (ur - uy));
-            if constexpr (CORR) lap = bf16_to_f(R16[(uint32_t)(ry0 + y) * (uint32_t)g.w]) + lap;
-            const float ry = mask_keep(mw, y, lap);
+            if constexpr (CORR) {
+                lap = bf16_to_f(at32(R16, roff)) + lap;
+                roff += (uint32_t)g.w;
+            }
+            const float ry = mask_bfe(mw, y, lap);
             r[y] = ry;
             w[y] = uy;
             const float rq = ry * ry;
             if (y & 1) rho_l1 += rq; else rho_l0 += rq;
-            own_l += (y >= ylo && y < yhi) ? rq : 0.f;
+            if (y >= ylo && y < yhi) own_l += rq;  // wave-uniform test
             uup = uy;
             uy = udn;
         }
@@ -651,7 +704,7 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
             s += from_left(p[y]);
             s += from_right(p[y]);
             const float d = y == 0 ? dfirst : (y == RPW - 1 ? dlast : dmid);
-            const float qy = mask_keep(mw, y, d * p[y] - s);
+            const float qy = mask_bfe(mw, y, d * p[y] - s);
             if constexpr (QL) {
                 q4[y & 3] = qy;
                 if ((y & 3) == 3) qs[(y >> 2) * 64 + lane] = make_float4(q4[0], q4[1], q4[2], q4[3]);
@@ -700,23 +753,23 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
 
     if (cg_steps && wi == 0 && lane == 0) cg_steps[(int64_t)k.b * a.channels + k.ch] += (double)it;
 
-    // ---- restricted prolongation on owned pixels (eq. 9) ----
+    // ---- restricted prolongation on owned pixels (eq. 9): the row test is
+    // wave-uniform, the column test per lane ----
     if (on && x >= k.oxlo && x < k.oxhi) {
+        const int ylo = k.oylo - ry0, yhi = k.oyhi - ry0;
         uint32_t off = (uint32_t)ry0 * (uint32_t)g.w + (uint32_t)x;
         if constexpr (!CORR) {
             float* __restrict__ UO = (float*)uout_v + k.ch * a.cpitch;
 #pragma unroll
             for (int y = 0; y < RPW; ++y) {
-                const int yy = ry0 + y;
-                if (yy >= k.oylo && yy < k.oyhi) UO[off] = w[y];
+                if (y >= ylo && y < yhi) put32(UO, off, w[y]);
                 off += (uint32_t)g.w;
             }
         } else {
             uint16_t* __restrict__ UO = (uint16_t*)uout_v + k.ch * a.cpitch;
 #pragma unroll
             for (int y = 0; y < RPW; ++y) {
-                const int yy = ry0 + y;
-                if (yy >= k.oylo && yy < k.oyhi) UO[off] = f_to_bf16(w[y]);
+                if (y >= ylo && y < yhi) put32(UO, off, f_to_bf16(w[y]));
                 off += (uint32_t)g.w;
             }
         }
@@ -737,18 +790,16 @@ __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
     const Blk k = blk_geo(a, lb);
     Tile2 T;
     if constexpr (!CORR) {
-        const float* U = (const float*)uin_v;
-        tile2_load(T, k, a, mbits, [&](int ch, uint32_t i) { return U[ch * a.cpitch + i]; });
+        tile2_load(T, k, a, mbits, LoadF32{(const float*)uin_v + k.ch * a.cpitch});
     } else {
         const uint16_t* U16 = (const uint16_t*)uin_v;
         if (U16)
-            tile2_load(T, k, a, mbits,
-                       [&](int ch, uint32_t i) { return bf16_to_f(U16[ch * a.cpitch + i]); });
+            tile2_load(T, k, a, mbits, LoadBf16{U16 + k.ch * a.cpitch});
         else
-            tile2_load(T, k, a, mbits, [](int, uint32_t) { return 0.f; });
+            tile2_load(T, k, a, mbits, LoadZero{});
     }
     tile2_store(T, a, lds);
-    const uint32_t mw = (threadIdx.x >> 6) ? T.mhi : T.mlo;
+    const uint32_t mw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) ? T.mhi : T.mlo;
     __syncthreads();
     sweep2_compute<CORR, QL>(k, mw, rhs, uout_v, partial, cg_steps, a, lds);
 }
