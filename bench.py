@@ -25,6 +25,8 @@ memory.
 (alpha = 1), and their single-level forms, each to the same stop tolerance.
 --workload psnr: PSNR of the 4K inpainting against the whole synthetic image
 as the stop tolerance tightens.
+--workload scaling: 960x540 to 3840x2160, multilevel ORAS against the
+multilevel-CG comparator at the same stop tolerance.
 
 Inputs are synthetic (paper_2110_03946_amd.synth) and already resident in
 HBM when the timed region starts.
@@ -46,7 +48,7 @@ Prints one JSON line. Besides the driver's fields it carries
                 idle while the host reads a stop test back.
 
 Usage: python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu]
-                       [--workload 4k|batch|precision|serve|ablation|psnr]
+                       [--workload 4k|batch|precision|serve|ablation|psnr|scaling]
 """
 from __future__ import annotations
 
@@ -414,6 +416,56 @@ def run_psnr(args):
     print(json.dumps(out), flush=True)
 
 
+SCALING_SIZES = ((540, 960), (1080, 1920), (2160, 3840))
+
+
+def run_scaling(args):
+    """Resolution sweep of multilevel ORAS against the multilevel-CG
+    comparator (method = 1) on the same frames and stop tolerance: solve
+    time, time per megapixel, and each result's deviation from a tight solve
+    of the solver itself."""
+    import torch
+    from paper_2110_03946_amd import ddi, synth
+    base = solver_params()
+    rows = []
+    for h, w in SCALING_SIZES:
+        f_np, c_np = synth.make_workload(h, w, C, DENSITY, "bernoulli", workload=1)
+        f = torch.from_numpy(f_np).cuda()
+        c = torch.from_numpy(c_np).cuda()
+        u = torch.empty_like(f)
+        p_ref = dict(base, local_tol=0.0, rel_tol=1e-6, max_sweeps=400, min_sweeps=1,
+                     final_residual=1)
+        with ddi.Plan(h, w, C, **p_ref) as plan:
+            ref, _ = plan.solve(f, c, allow_noconv=True)
+        row = {"size": f"{w}x{h}", "megapixels": round(h * w / 1e6, 3)}
+        # ML-CG at the same stop tolerance, and at a 10x tighter one (its
+        # error at equal residual is larger: CG leaves smooth error that
+        # the residual norm weighs little)
+        for name, prm in [("oras", dict(base)),
+                          ("mlcg", dict(base, method=1, max_sweeps=5000)),
+                          ("mlcg_tight", dict(base, method=1, max_sweeps=5000,
+                                              rel_tol=base["rel_tol"] / 10))]:
+            with ddi.Plan(h, w, C, **prm) as plan:
+                ms, st = timed_solves(plan, f, c, u, 5)
+            row[name] = {"ms": round(ms, 3), "ms_per_mpx": round(ms / (h * w / 1e6), 4),
+                         "finest_iterations": st["sweeps"],
+                         "max_dev_from_tight_solve_grey": round(float((u - ref).abs().max()), 4)}
+            if name != "oras":
+                row[name]["cg_steps_all_levels"] = st["cg_steps"]
+        row["mlcg_over_oras"] = round(row["mlcg"]["ms"] / row["oras"]["ms"], 2)
+        row["mlcg_tight_over_oras"] = round(row["mlcg_tight"]["ms"] / row["oras"]["ms"], 2)
+        rows.append(row)
+        print(f"[bench] {row}", file=sys.stderr, flush=True)
+    out = {"metric": "solve time vs resolution: multilevel ORAS against multilevel CG",
+           "value": rows[-1]["mlcg_over_oras"], "unit": "x (ML-CG time / ORAS time at 4K)",
+           "higher_is_better": True, "n_gpus": 1, "data": "synthetic", "dtype": "f32",
+           "config": {"workload": "RGB frames 960x540, 1920x1080, 3840x2160, 4% Bernoulli; both "
+                                  "methods stop at rel_tol 5e-4 on the finest level (ML-CG on "
+                                  "every level)"},
+           "rows": rows, "roofline": None}
+    print(json.dumps(out), flush=True)
+
+
 def run_serve(args):
     """Poisson stream of mixed-resolution requests through the serving loop
     (slot pools under an HBM budget, graph replays, results copied back to
@@ -565,8 +617,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--workload", choices=["4k", "batch", "precision", "serve", "ablation", "psnr"],
-                    default="4k")
+    ap.add_argument("--workload", choices=["4k", "batch", "precision", "serve", "ablation", "psnr",
+                                           "scaling"], default="4k")
     ap.add_argument("--serve-seconds", type=float, default=SERVE_SECONDS)
     ap.add_argument("--serve-budget-gb", type=int, default=16)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -610,6 +662,9 @@ def main():
         return
     if args.workload == "psnr":
         run_psnr(args)
+        return
+    if args.workload == "scaling":
+        run_scaling(args)
         return
 
     run_frame(args, args.workload)

@@ -119,6 +119,13 @@ extern "C" {
  *                  is the iterate whose residual was tested. Single-image
  *                  plans only.
  *   inner_sweeps   correction sweeps per refinement step (storage = 1), >= 1.
+ *   method         0: multilevel ORAS (the method). 1: multilevel conjugate
+ *                  gradients, the comparator of Sec. 5: the same pyramid and
+ *                  coarse-to-fine start, every level solved by global CG on
+ *                  its unknown pixels (float32 vectors, float64 dot products)
+ *                  to rel_tol; max_sweeps then caps the CG steps per level
+ *                  and stats.sweeps counts the finest level's steps. Single-
+ *                  image float32 plans only.
  */
 typedef struct ddi_params {
     int block;
@@ -144,6 +151,7 @@ typedef struct ddi_params {
     double coarse_cg_tol;
     int storage;
     int inner_sweeps;
+    int method;
 } ddi_params;
 
 /*
@@ -179,7 +187,7 @@ typedef struct ddi_plan ddi_plan;
  * min_sweeps = 2, max_sweeps = 50, check_every = 1, final_residual = 1,
  * timing = 0, coarse_block = 0, coarse_overlap = -1, coarse_local_iters = 0,
  * local_tol = 0, use_graph = 0, coarse_solver = 0, coarse_cg_iters = 500,
- * coarse_cg_tol = 1e-10, storage = 0, inner_sweeps = 2. */
+ * coarse_cg_tol = 1e-10, storage = 0, inner_sweeps = 2, method = 0. */
 int ddi_default_params(ddi_params* p);
 
 /* Check *p for one image size without touching the GPU (this includes the

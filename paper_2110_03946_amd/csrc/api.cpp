@@ -103,6 +103,9 @@ size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm) {
     bytes += part_n * sizeof(double);
     bytes += (3 * (size_t)C + 2) * sizeof(double) + 64;  // red, ctl
     if (prm.storage == 1) bytes += 3 * (size_t)C * h * w * sizeof(uint16_t);
+    if (prm.method == 1)
+        bytes += 4 * (size_t)C * h * w * sizeof(float) + (3 * (size_t)C + L * ((size_t)C + 2)) *
+                                                             sizeof(double);
     if (prm.timing) {
         const SweepArgs a0 = make_sweep(h, w, C, prm.block, prm.overlap, prm.robin_alpha, 1);
         bytes += (size_t)sweep_partials(a0) * C * sizeof(double);
@@ -160,6 +163,7 @@ int ddi_default_params(ddi_params* p) {
     p->coarse_cg_tol = 1e-10;
     p->storage = 0;
     p->inner_sweeps = 2;
+    p->method = 0;
     return DDI_OK;
 }
 
@@ -188,6 +192,8 @@ int ddi_check_params(int height, int width, int channels, const ddi_params* p) {
     if (p->coarse_cg_iters < 1 || !(p->coarse_cg_tol >= 0.0)) return DDI_EINVAL;
     if (p->storage != 0 && p->storage != 1) return DDI_EINVAL;
     if (p->inner_sweeps < 1) return DDI_EINVAL;
+    if (p->method != 0 && p->method != 1) return DDI_EINVAL;
+    if (p->method == 1 && p->storage != 0) return DDI_EINVAL;
     if (p->coarse_solver == 1) {
         int hl = height, wl = width;
         for (int l = 1; l < level_count(height, width, p->levels); ++l) {
@@ -209,6 +215,8 @@ int ddi_destroy(ddi_plan* plan) {
             if (l.u[i] && (i == 1 || l.own_u0)) (void)hipFree(l.u[i]);
     }
     if (plan->r16) (void)hipFree(plan->r16);
+    if (plan->cg_vec) (void)hipFree(plan->cg_vec);
+    if (plan->cg_sc) (void)hipFree(plan->cg_sc);
     for (uint16_t* d : plan->d16)
         if (d) (void)hipFree(d);
     if (plan->part) (void)hipFree(plan->part);
@@ -327,7 +335,17 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
             return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
         }
     }
-    if (prm.use_graph && !prm.timing && prm.storage == 0) {
+    if (prm.method == 1) {
+        const size_t nv = (size_t)channels * height * width * sizeof(float);
+        if ((err = hipMalloc(&P->cg_vec, 4 * nv)) != hipSuccess ||
+            (err = hipMalloc(&P->cg_sc, (size_t)(3 * channels + L * (channels + 2)) *
+                                            sizeof(double))) != hipSuccess) {
+            ddi_destroy(P);
+            return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
+        }
+        P->last_iters.assign(L, -1);
+    }
+    if (prm.use_graph && !prm.timing && prm.storage == 0 && prm.method == 0) {
         // a stream of our own (default priority): the caller's may be the
         // legacy default stream, which cannot be captured
         if ((err = hipStreamCreate(&P->gs)) != hipSuccess ||
@@ -799,13 +817,13 @@ static int finish_solve(ddi_plan* P, ddi_stats* st) {
 int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats* st) {
     if (!P || !f || !c || !u) return DDI_EINVAL;
     if (P->pend.active) return DDI_EINVAL;
-    if (P->p.storage == 1) {
+    if (P->p.storage == 1 || P->p.method == 1) {
         Level& L0 = P->lv[0];
         L0.f = f;
         L0.c = c;
         L0.u[0] = u;
         if (st) std::memset(st, 0, sizeof(*st));
-        return solve_refine(P, f, c, u, st);
+        return P->p.method == 1 ? solve_mlcg(P, st) : solve_refine(P, f, c, u, st);
     }
     int e = begin_solve(P, f, c, u);
     if (e) {
@@ -817,7 +835,7 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
 
 int ddi_solve_async(ddi_plan* P, const float* f, const uint8_t* c, float* u) {
     if (!P || !f || !c || !u) return DDI_EINVAL;
-    if (P->pend.active || P->p.storage != 0) return DDI_EINVAL;
+    if (P->pend.active || P->p.storage != 0 || P->p.method != 0) return DDI_EINVAL;
     int e = begin_solve(P, f, c, u);
     if (e) P->pend.active = false;
     return e;

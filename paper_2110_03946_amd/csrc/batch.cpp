@@ -526,7 +526,8 @@ int ddi_batch_create(ddi_batch** out, int n, const int* heights, const int* widt
         prm[i].use_graph = 0;
         int e = ddi_check_params(heights[i], widths[i], channels, &prm[i]);
         if (e) return e;
-        if (prm[i].storage != 0) return DDI_EINVAL;  // batches iterate in float32
+        // batches run float32 ORAS
+        if (prm[i].storage != 0 || prm[i].method != 0) return DDI_EINVAL;
         if (prm[i].min_sweeps != prm[0].min_sweeps || prm[i].max_sweeps != prm[0].max_sweeps ||
             prm[i].check_every != prm[0].check_every || prm[i].timing != prm[0].timing)
             return DDI_EINVAL;

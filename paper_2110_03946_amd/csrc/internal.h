@@ -257,6 +257,23 @@ hipError_t launch_coarse_cg(const float* f, const uint8_t* c, int h, int w, int 
                             float* u, int max_iter, double tol, hipStream_t s);
 hipError_t launch_coarse_cg_batch(const CoarseJob* jobs, int njobs, int channels, hipStream_t s);
 
+// ---- global conjugate gradients (multilevel-CG comparator) ----
+// Partial rows of these kernels: residual_partials(h, w). All skip their
+// work once ctl[0] != 0.
+hipError_t launch_cg_dir_matvec(const float* r, const float* pin, float* pout, float* q,
+                                const uint8_t* c, int h, int w, int channels,
+                                const double* beta, bool first, double* partial, const int* ctl,
+                                int* nwg, hipStream_t s);
+hipError_t launch_cg_update(float* x, float* r, const float* p, const float* q, int h, int w,
+                            int channels, const double* alpha, double* partial, const int* ctl,
+                            hipStream_t s);
+// stage 0: alpha = rho / p.q; 1: beta = r.r / rho, rho = r.r, stop test
+// (tol < 0: never passes); 2: rho = r.r and the stop test. sc = [rho,
+// alpha, beta] x channels.
+hipError_t launch_cg_scalars(const double* partial, int nb, int channels, double* sc,
+                             const double* b2, int* ctl, double tol, int stage, int n,
+                             hipStream_t s);
+
 // Partials per channel written by one sweep: one per block.
 inline int sweep_partials(const SweepArgs& a) {
     return a.g.nby * a.g.nbx;

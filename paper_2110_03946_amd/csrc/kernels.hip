@@ -1531,6 +1531,149 @@ __global__ void k_clear_int(int* __restrict__ p, int n) {
 }
 
 // ---------------------------------------------------------------------------
+// Global conjugate gradients on one level (the multilevel-CG comparator of
+// Sec. 5): float32 vectors of all channels, float64 dot products per
+// channel, scalars kept on the device. The vectors vanish on the mask (r,
+// p, q) and x = f there, so the masked 5-point operator needs no branches
+// beyond the in-image tests.
+// ---------------------------------------------------------------------------
+
+// p_out = r + beta p_in (beta per channel; first: p_out = r), q = A p_out on
+// unknown pixels, partial[wg][ch] = sum p_out q. p_out is computed at the
+// pixel and its four neighbours from r and p_in (no write-read hazard).
+__global__ __launch_bounds__(64 * kResRows) void k_cg_dir_matvec(
+    const float* __restrict__ r, const float* __restrict__ pin, float* __restrict__ pout,
+    float* __restrict__ q, const uint8_t* __restrict__ c, int h, int w, int channels,
+    const double* __restrict__ beta, int first, double* __restrict__ partial,
+    const int* __restrict__ ctl) {
+    if (ctl[0] != 0) return;
+    const int lane = threadIdx.x & 63;
+    const int x = blockIdx.x * 64 + lane;
+    const int y = blockIdx.y * kResRows + (threadIdx.x >> 6);
+    const int ch = blockIdx.z;
+    const int64_t n = (int64_t)h * w;
+    const float* __restrict__ R = r + ch * n;
+    const float* __restrict__ P = pin + ch * n;
+    const float b = first ? 0.f : (float)beta[ch];
+    double acc = 0.0;
+    if (x < w && y < h) {
+        const uint32_t W = w;
+        const uint32_t i = (uint32_t)y * W + x;
+        auto pn = [&](uint32_t j) { return first ? R[j] : R[j] + b * P[j]; };
+        const float pc = pn(i);
+        float qv = 0.f;
+        if (c[i] == 0) {
+            float s = 0.f, deg = 0.f;
+            if (y > 0) { s += pn(i - W); deg += 1.f; }
+            if (y + 1 < h) { s += pn(i + W); deg += 1.f; }
+            if (x > 0) { s += pn(i - 1); deg += 1.f; }
+            if (x + 1 < w) { s += pn(i + 1); deg += 1.f; }
+            qv = deg * pc - s;
+        }
+        pout[ch * n + i] = pc;
+        q[ch * n + i] = qv;
+        acc = (double)pc * (double)qv;
+    }
+    acc = wave_sum_d(acc);
+    __shared__ double sm[kResRows];
+    if (lane == 0) sm[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < kResRows; ++j) t += sm[j];
+        partial[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * channels + ch] = t;
+    }
+}
+
+// x += alpha p, r -= alpha q (alpha per channel), partial[wg][ch] = sum r^2.
+__global__ __launch_bounds__(64 * kResRows) void k_cg_update(
+    float* __restrict__ xv, float* __restrict__ r, const float* __restrict__ p,
+    const float* __restrict__ q, int h, int w, int channels, const double* __restrict__ alpha,
+    double* __restrict__ partial, const int* __restrict__ ctl) {
+    if (ctl[0] != 0) return;
+    const int lane = threadIdx.x & 63;
+    const int x = blockIdx.x * 64 + lane;
+    const int y = blockIdx.y * kResRows + (threadIdx.x >> 6);
+    const int ch = blockIdx.z;
+    const int64_t n = (int64_t)h * w;
+    const float a = (float)alpha[ch];
+    double acc = 0.0;
+    if (x < w && y < h) {
+        const int64_t i = ch * n + (int64_t)y * w + x;
+        xv[i] += a * p[i];
+        const float rv = r[i] - a * q[i];
+        r[i] = rv;
+        acc = (double)rv * (double)rv;
+    }
+    acc = wave_sum_d(acc);
+    __shared__ double sm[kResRows];
+    if (lane == 0) sm[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < kResRows; ++j) t += sm[j];
+        partial[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * channels + ch] = t;
+    }
+}
+
+// The CG scalars of one step from the partials of the last dot product,
+// in one workgroup (fixed-order sums). stage 0 (after the matvec): alpha =
+// rho / (p.q). stage 1 (after the update): rr = r.r, beta = rr / rho, rho =
+// rr, and the stop test max_k rr_k / b2_k <= tol2 (sets ctl[0], ctl[1] =
+// n). stage 2 (initial residual): rho = r.r and the same test. sc holds
+// [rho, alpha, beta] x channels; b2 = ||C f||^2 per channel.
+template <int NC>
+__global__ __launch_bounds__(kDecideTpb) void k_cg_scalars(const double* __restrict__ partial,
+                                                           int nb, double* __restrict__ sc,
+                                                           const double* __restrict__ b2,
+                                                           int* __restrict__ ctl, double tol2,
+                                                           int stage, int n) {
+    if (ctl[0] != 0) return;
+    __shared__ double sm[kDecideTpb / 64][NC];
+    double v[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) v[k] = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kDecideTpb) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) v[k] += partial[(int64_t)i * NC + k];
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) v[k] = wave_sum_d(v[k]);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) sm[threadIdx.x >> 6][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double worst = 0.0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        double t = 0.0;
+        for (int j = 0; j < kDecideTpb / 64; ++j) t += sm[j][k];
+        double* rho = sc + k;
+        double* alpha = sc + NC + k;
+        double* beta = sc + 2 * NC + k;
+        if (stage == 0) {
+            *alpha = t > 0.0 ? *rho / t : 0.0;
+        } else {
+            if (stage == 1) *beta = *rho > 0.0 ? t / *rho : 0.0;
+            *rho = t;
+            const double q = b2[k] > 0.0 ? t / b2[k] : (t > 0.0 ? INFINITY : 0.0);
+            worst = fmax(worst, q);
+        }
+    }
+    if (stage != 0) {
+        reinterpret_cast<double*>(ctl + 4)[0] = worst;
+        if (worst <= tol2) {
+            ctl[1] = n;
+            ctl[0] = 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Float64 solve of the coarsest level (Sec. 2 system, eq. 6, on the coarse
 // grid): conjugate gradients on the unknown pixels, known pixels fixed at
 // their value, in one workgroup per channel. Thread t owns pixels t,
@@ -2058,6 +2201,43 @@ hipError_t launch_refine_residual(const float* f, const uint8_t* c, const float*
     if (nwg) *nwg = (int)(grid.x * grid.y);
     hipLaunchKernelGGL(k_refine_residual, grid, dim3(64 * kResRows), 0, s, f, c, u, d, h, w,
                        channels, unext, rhs, partial, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_dir_matvec(const float* r, const float* pin, float* pout, float* q,
+                                const uint8_t* c, int h, int w, int channels,
+                                const double* beta, bool first, double* partial, const int* ctl,
+                                int* nwg, hipStream_t s) {
+    dim3 grid((w + 63) / 64, (h + kResRows - 1) / kResRows, channels);
+    if (nwg) *nwg = (int)(grid.x * grid.y);
+    hipLaunchKernelGGL(k_cg_dir_matvec, grid, dim3(64 * kResRows), 0, s, r, pin, pout, q, c, h, w,
+                       channels, beta, first ? 1 : 0, partial, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(float* x, float* r, const float* p, const float* q, int h, int w,
+                            int channels, const double* alpha, double* partial, const int* ctl,
+                            hipStream_t s) {
+    dim3 grid((w + 63) / 64, (h + kResRows - 1) / kResRows, channels);
+    hipLaunchKernelGGL(k_cg_update, grid, dim3(64 * kResRows), 0, s, x, r, p, q, h, w, channels,
+                       alpha, partial, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_scalars(const double* partial, int nb, int channels, double* sc,
+                             const double* b2, int* ctl, double tol, int stage, int n,
+                             hipStream_t s) {
+    const double tol2 = tol < 0.0 ? -1.0 : tol * tol;
+    switch (channels) {
+#define DDI_CASE(NC)                                                                          \
+    case NC:                                                                                  \
+        hipLaunchKernelGGL(k_cg_scalars<NC>, dim3(1), dim3(kDecideTpb), 0, s, partial, nb, sc, \
+                           b2, ctl, tol2, stage, n);                                          \
+        break;
+        DDI_CASE(1) DDI_CASE(2) DDI_CASE(3) DDI_CASE(4)
+#undef DDI_CASE
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

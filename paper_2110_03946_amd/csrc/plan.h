@@ -95,4 +95,13 @@ struct ddi_plan {
     // the refinement equation on the finest level
     uint16_t* r16 = nullptr;
     uint16_t* d16[2] = {nullptr, nullptr};
+    // method = 1 (multilevel CG): r, p[2], q planes sized for the finest
+    // level, the CG scalars [rho, alpha, beta] x C, per-level statistics
+    // [L][C + 2], and the CG steps each level needed last time
+    float* cg_vec = nullptr;
+    double* cg_sc = nullptr;
+    std::vector<int> last_iters;
 };
+
+// Multilevel CG solve (mlcg.cpp); the level-0 pointers are set.
+int solve_mlcg(ddi_plan* P, ddi_stats* st);

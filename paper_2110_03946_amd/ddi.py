@@ -42,7 +42,7 @@ class Params(ctypes.Structure):
                 ("local_tol", ctypes.c_float), ("use_graph", ctypes.c_int),
                 ("coarse_solver", ctypes.c_int), ("coarse_cg_iters", ctypes.c_int),
                 ("coarse_cg_tol", ctypes.c_double), ("storage", ctypes.c_int),
-                ("inner_sweeps", ctypes.c_int)]
+                ("inner_sweeps", ctypes.c_int), ("method", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
