@@ -10,8 +10,8 @@
 //   k_stats     ||C f||^2 per channel, known-pixel count, bad mask bytes.
 //   k_init      u = c ? f : 0 on the coarsest level.
 //   k_prolong   u = c ? f : bilinear(coarse u) (Sec. 4 coarse-to-fine start).
-//   k_residual  r = b - A u (eq. 7), float64 partial norms; column-walking
-//               waves keep the vertical stencil in registers.
+//   k_residual_walk  r = b - A u (eq. 7), float64 partial norms; column-
+//               walking waves keep the vertical stencil in registers.
 //   k_reduce    fixed-order float64 sums of per-workgroup partials.
 //
 // All reductions run in a fixed order, so results are bitwise reproducible.
@@ -1341,93 +1341,132 @@ __global__ __launch_bounds__(kTpb) void k_prolong(const float* __restrict__ uc, 
     }
 }
 
-// Residual r = b - A u: one thread per pixel of a 64 x kResRows tile (the
-// vertical neighbours of a row are the rows the neighbouring waves of the
-// tile load, so they come from cache). Offsets are 32-bit indices into one
-// channel plane.
-constexpr int kResRows = 4;
+// ---------------------------------------------------------------------------
+// Column-walking stencil kernels. A workgroup is kWalkWaves waves side by
+// side, each covering 64 consecutive columns of a band of kWalkRows rows;
+// every lane walks down its column and keeps the rows above and below in
+// registers, so each value is loaded once. Horizontal neighbours come from
+// the neighbouring lanes (DPP); the columns just left and right of a wave
+// come from one extra load per row in lanes 0 and 63. A missing neighbour
+// at the image border takes the pixel's own value, so its difference is
+// 0: the reflecting boundary. One float64 partial per workgroup and
+// channel, in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kWalkRows = 16;
+constexpr int kWalkWaves = 4;
 
-__global__ __launch_bounds__(64 * kResRows) void k_residual(
-    const float* __restrict__ f, const uint8_t* __restrict__ c, const float* __restrict__ u,
-    int h, int w, int channels, float* __restrict__ r, float* __restrict__ ucopy,
-    double* __restrict__ partial) {
-    const int lane = threadIdx.x & 63;
-    const int x = blockIdx.x * 64 + lane;
-    const int y = blockIdx.y * kResRows + (threadIdx.x >> 6);
-    const int ch = blockIdx.z;
-    const int64_t n = (int64_t)h * w;
-    const float* __restrict__ U = u + ch * n;
-    double acc = 0.0;
-    if (x < w && y < h) {
-        const uint32_t W = w;
-        const uint32_t i = (uint32_t)y * W + x;
-        const float uc = U[i];
-        const float uu = y > 0 ? U[i - W] : uc;
-        const float ud = y + 1 < h ? U[i + W] : uc;
-        const float ul = x > 0 ? U[i - 1] : uc;
-        const float ur = x + 1 < w ? U[i + 1] : uc;
-        const bool known = c[i] != 0;
-        const float fv = known ? f[ch * n + i] : 0.f;
-        const float ry = known ? fv - uc : ((uu - uc) + (ud - uc)) + ((ul - uc) + (ur - uc));
-        acc = (double)ry * (double)ry;
-        if (r) r[ch * n + i] = ry;
-        if (ucopy) ucopy[ch * n + i] = uc;
+struct Walk {
+    int lane, x, y0, y1;
+    uint32_t xc, xe;  // clamped column, and the edge column lanes 0 / 63 read
+    bool inb, edge;
+};
+
+__device__ __forceinline__ Walk walk_geom(int h, int w) {
+    Walk k;
+    k.lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    k.x = (blockIdx.x * kWalkWaves + wv) * 64 + k.lane;
+    k.inb = k.x < w;
+    k.xc = k.inb ? k.x : w - 1;
+    k.edge = k.lane == 0 || k.lane == 63;
+    k.xe = k.lane == 0 ? (uint32_t)max(k.x - 1, 0) : (uint32_t)min(k.x + 1, w - 1);
+    k.y0 = blockIdx.y * kWalkRows;
+    k.y1 = min(k.y0 + kWalkRows, h);
+    return k;
+}
+
+// Horizontal neighbours of value v of row y (val(j) reads element j).
+template <class V>
+__device__ __forceinline__ void walk_lr(const Walk& k, int w, uint32_t row, float v, V val,
+                                        float* lft, float* rgt) {
+    float l = from_left(v), r = from_right(v);
+    if (k.edge) {
+        const float e = val(row + k.xe);
+        if (k.lane == 0) l = e; else r = e;
     }
+    if (k.x == 0) l = v;
+    if (k.x + 1 >= w) r = v;
+    *lft = l;
+    *rgt = r;
+}
+
+// Sum of acc over the workgroup into partial[wg][ch] (fixed order).
+__device__ __forceinline__ void walk_partial(double acc, double* __restrict__ partial,
+                                             int channels) {
     acc = wave_sum_d(acc);
-    __shared__ double sm[kResRows];
-    if (lane == 0) sm[threadIdx.x >> 6] = acc;
+    __shared__ double sm[kWalkWaves];
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double s = 0.0;
+        double t = 0.0;
 #pragma unroll
-        for (int j = 0; j < kResRows; ++j) s += sm[j];
-        partial[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * channels + ch] = s;
+        for (int j = 0; j < kWalkWaves; ++j) t += sm[j];
+        partial[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * channels + blockIdx.z] = t;
     }
 }
 
-// Refinement step on the float32 iterate: u_next = u + d (d in bfloat16;
-// d == nullptr: u_next = u, not written), rhs = b - A u_next rounded to
-// bfloat16, and float64 partial norms of b - A u_next (float32 values) laid
-// out as k_residual's. Skipped once ctl[0] is set.
-__global__ __launch_bounds__(64 * kResRows) void k_refine_residual(
+// Residual r = b - A v of eq. 7 with v = u (d == nullptr) or v = u + d (d in
+// bfloat16: the refinement update). Outputs, each optional: r (float32),
+// rhs (bfloat16 of r), vout (v; with ucopy semantics for d == nullptr),
+// and the float64 partials of ||r||^2. Skipped once ctl[0] is set.
+template <bool REF>
+__global__ __launch_bounds__(64 * kWalkWaves) void k_residual_walk(
     const float* __restrict__ f, const uint8_t* __restrict__ c, const float* __restrict__ u,
-    const uint16_t* __restrict__ d, int h, int w, int channels, float* __restrict__ unext,
-    uint16_t* __restrict__ rhs, double* __restrict__ partial, const int* __restrict__ ctl) {
+    const uint16_t* __restrict__ d, int h, int w, int channels, float* __restrict__ r,
+    uint16_t* __restrict__ rhs, float* __restrict__ vout, double* __restrict__ partial,
+    const int* __restrict__ ctl) {
+    constexpr int R = kWalkRows;
     if (ctl && ctl[0] != 0) return;
-    const int lane = threadIdx.x & 63;
-    const int x = blockIdx.x * 64 + lane;
-    const int y = blockIdx.y * kResRows + (threadIdx.x >> 6);
+    const Walk k = walk_geom(h, w);
     const int ch = blockIdx.z;
     const int64_t n = (int64_t)h * w;
+    const uint32_t W = w;
     const float* __restrict__ U = u + ch * n;
-    const uint16_t* __restrict__ D = d ? d + ch * n : nullptr;
-    double acc = 0.0;
-    if (x < w && y < h) {
-        const uint32_t W = w;
-        const uint32_t i = (uint32_t)y * W + x;
-        auto val = [&](uint32_t j) { return D ? U[j] + bf16_to_f(D[j]) : U[j]; };
-        const float uc = val(i);
-        const float uu = y > 0 ? val(i - W) : uc;
-        const float ud = y + 1 < h ? val(i + W) : uc;
-        const float ul = x > 0 ? val(i - 1) : uc;
-        const float ur = x + 1 < w ? val(i + 1) : uc;
-        const bool known = c[i] != 0;
-        const float fv = known ? f[ch * n + i] : 0.f;
-        const float ry = known ? fv - uc : ((uu - uc) + (ud - uc)) + ((ul - uc) + (ur - uc));
-        acc = (double)ry * (double)ry;
-        rhs[ch * n + i] = f_to_bf16(ry);
-        if (D) unext[ch * n + i] = uc;
-    }
-    acc = wave_sum_d(acc);
-    __shared__ double sm[kResRows];
-    if (lane == 0) sm[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
+    const uint16_t* __restrict__ D = REF ? d + ch * n : nullptr;
+    const float* __restrict__ F = f + ch * n;
+    auto val = [&](uint32_t j) -> float {
+        if constexpr (REF) return at32(U, j) + bf16_to_f(at32(D, j));
+        else return at32(U, j);
+    };
+    // every load of the band first: rows y0 - 1 .. y0 + R (clamped to the
+    // image: the clamped rows are the reflecting boundary), mask bytes,
+    // edge columns, then f where the mask is set
+    float v[R + 2], e[R];
+    uint32_t cm[R];
 #pragma unroll
-        for (int j = 0; j < kResRows; ++j) s += sm[j];
-        partial[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * channels + ch] = s;
+    for (int t = 0; t < R + 2; ++t)
+        v[t] = val((uint32_t)min(max(k.y0 - 1 + t, 0), h - 1) * W + k.xc);
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const uint32_t row = (uint32_t)min(k.y0 + t, h - 1) * W;
+        cm[t] = at32(c, row + k.xc);
+        e[t] = k.edge ? val(row + k.xe) : 0.f;
     }
+    float fv[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t)
+        fv[t] = cm[t] ? at32(F, (uint32_t)min(k.y0 + t, h - 1) * W + k.xc) : 0.f;
+    const int nr = k.y1 - k.y0;
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const float cur = v[t + 1];
+        float lft = from_left(cur), rgt = from_right(cur);
+        if (k.lane == 0) lft = e[t];
+        if (k.lane == 63) rgt = e[t];
+        if (k.x == 0) lft = cur;
+        if (k.x + 1 >= w) rgt = cur;
+        const float ry = cm[t] ? fv[t] - cur
+                               : ((v[t] - cur) + (v[t + 2] - cur)) + ((lft - cur) + (rgt - cur));
+        if (k.inb && t < nr) {
+            const uint32_t i = (uint32_t)(k.y0 + t) * W + k.xc;
+            acc += (double)ry * (double)ry;
+            if (r) put32(r + ch * n, i, ry);
+            if (rhs) put32(rhs + ch * n, i, f_to_bf16(ry));
+            if (vout) put32(vout + ch * n, i, cur);
+        }
+    }
+    walk_partial(acc, partial, channels);
 }
 
 __global__ __launch_bounds__(kTpb) void k_reduce(double* __restrict__ partial, int nrows,
@@ -1539,83 +1578,100 @@ __global__ void k_clear_int(int* __restrict__ p, int n) {
 // ---------------------------------------------------------------------------
 
 // p_out = r + beta p_in (beta per channel; first: p_out = r), q = A p_out on
-// unknown pixels, partial[wg][ch] = sum p_out q. p_out is computed at the
-// pixel and its four neighbours from r and p_in (no write-read hazard).
-__global__ __launch_bounds__(64 * kResRows) void k_cg_dir_matvec(
+// unknown pixels (0 on the mask), partial[wg][ch] = sum p_out q. Column
+// walk: p_out is formed once per pixel from r and p_in and shared with the
+// neighbours through registers and DPP.
+__global__ __launch_bounds__(64 * kWalkWaves) void k_cg_dir_matvec(
     const float* __restrict__ r, const float* __restrict__ pin, float* __restrict__ pout,
     float* __restrict__ q, const uint8_t* __restrict__ c, int h, int w, int channels,
     const double* __restrict__ beta, int first, double* __restrict__ partial,
     const int* __restrict__ ctl) {
+    constexpr int R = kWalkRows;
     if (ctl[0] != 0) return;
-    const int lane = threadIdx.x & 63;
-    const int x = blockIdx.x * 64 + lane;
-    const int y = blockIdx.y * kResRows + (threadIdx.x >> 6);
+    const Walk k = walk_geom(h, w);
     const int ch = blockIdx.z;
     const int64_t n = (int64_t)h * w;
-    const float* __restrict__ R = r + ch * n;
+    const uint32_t W = w;
+    const float* __restrict__ RR = r + ch * n;
     const float* __restrict__ P = pin + ch * n;
     const float b = first ? 0.f : (float)beta[ch];
-    double acc = 0.0;
-    if (x < w && y < h) {
-        const uint32_t W = w;
-        const uint32_t i = (uint32_t)y * W + x;
-        auto pn = [&](uint32_t j) { return first ? R[j] : R[j] + b * P[j]; };
-        const float pc = pn(i);
-        float qv = 0.f;
-        if (c[i] == 0) {
-            float s = 0.f, deg = 0.f;
-            if (y > 0) { s += pn(i - W); deg += 1.f; }
-            if (y + 1 < h) { s += pn(i + W); deg += 1.f; }
-            if (x > 0) { s += pn(i - 1); deg += 1.f; }
-            if (x + 1 < w) { s += pn(i + 1); deg += 1.f; }
-            qv = deg * pc - s;
-        }
-        pout[ch * n + i] = pc;
-        q[ch * n + i] = qv;
-        acc = (double)pc * (double)qv;
-    }
-    acc = wave_sum_d(acc);
-    __shared__ double sm[kResRows];
-    if (lane == 0) sm[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
+    auto pn = [&](uint32_t j) -> float {
+        return first ? at32(RR, j) : at32(RR, j) + b * at32(P, j);
+    };
+    float v[R + 2], e[R];
+    uint32_t cm[R];
 #pragma unroll
-        for (int j = 0; j < kResRows; ++j) t += sm[j];
-        partial[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * channels + ch] = t;
+    for (int t = 0; t < R + 2; ++t)
+        v[t] = pn((uint32_t)min(max(k.y0 - 1 + t, 0), h - 1) * W + k.xc);
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const uint32_t row = (uint32_t)min(k.y0 + t, h - 1) * W;
+        cm[t] = at32(c, row + k.xc);
+        e[t] = k.edge ? pn(row + k.xe) : 0.f;
     }
+    const int nr = k.y1 - k.y0;
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const float cur = v[t + 1];
+        float lft = from_left(cur), rgt = from_right(cur);
+        if (k.lane == 0) lft = e[t];
+        if (k.lane == 63) rgt = e[t];
+        if (k.x == 0) lft = cur;
+        if (k.x + 1 >= w) rgt = cur;
+        const float qv =
+            cm[t] == 0 ? ((cur - v[t]) + (cur - v[t + 2])) + ((cur - lft) + (cur - rgt)) : 0.f;
+        if (k.inb && t < nr) {
+            const uint32_t i = (uint32_t)(k.y0 + t) * W + k.xc;
+            put32(pout + ch * n, i, cur);
+            put32(q + ch * n, i, qv);
+            acc += (double)cur * (double)qv;
+        }
+    }
+    walk_partial(acc, partial, channels);
 }
 
-// x += alpha p, r -= alpha q (alpha per channel), partial[wg][ch] = sum r^2.
-__global__ __launch_bounds__(64 * kResRows) void k_cg_update(
+// x += alpha p, r -= alpha q (alpha per channel), partial[wg][ch] = sum r^2,
+// over the column-walk layout (same partial rows as the other CG kernels).
+__global__ __launch_bounds__(64 * kWalkWaves) void k_cg_update(
     float* __restrict__ xv, float* __restrict__ r, const float* __restrict__ p,
     const float* __restrict__ q, int h, int w, int channels, const double* __restrict__ alpha,
     double* __restrict__ partial, const int* __restrict__ ctl) {
+    constexpr int R = kWalkRows;
     if (ctl[0] != 0) return;
-    const int lane = threadIdx.x & 63;
-    const int x = blockIdx.x * 64 + lane;
-    const int y = blockIdx.y * kResRows + (threadIdx.x >> 6);
+    const Walk k = walk_geom(h, w);
     const int ch = blockIdx.z;
     const int64_t n = (int64_t)h * w;
+    const uint32_t W = w;
     const float a = (float)alpha[ch];
+    float* __restrict__ X = xv + ch * n;
+    float* __restrict__ RR = r + ch * n;
+    const float* __restrict__ P = p + ch * n;
+    const float* __restrict__ Q = q + ch * n;
+    const int nr = k.y1 - k.y0;
     double acc = 0.0;
-    if (x < w && y < h) {
-        const int64_t i = ch * n + (int64_t)y * w + x;
-        xv[i] += a * p[i];
-        const float rv = r[i] - a * q[i];
-        r[i] = rv;
-        acc = (double)rv * (double)rv;
-    }
-    acc = wave_sum_d(acc);
-    __shared__ double sm[kResRows];
-    if (lane == 0) sm[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
+    if (k.inb) {
+        float xs[R], rs[R], ps[R], qs[R];
 #pragma unroll
-        for (int j = 0; j < kResRows; ++j) t += sm[j];
-        partial[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * channels + ch] = t;
+        for (int t = 0; t < R; ++t) {
+            const uint32_t i = (uint32_t)min(k.y0 + t, h - 1) * W + k.xc;
+            xs[t] = at32(X, i);
+            rs[t] = at32(RR, i);
+            ps[t] = at32(P, i);
+            qs[t] = at32(Q, i);
+        }
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            if (t < nr) {
+                const uint32_t i = (uint32_t)(k.y0 + t) * W + k.xc;
+                put32(X, i, xs[t] + a * ps[t]);
+                const float rv = rs[t] - a * qs[t];
+                put32(RR, i, rv);
+                acc += (double)rv * (double)rv;
+            }
+        }
     }
+    walk_partial(acc, partial, channels);
 }
 
 // The CG scalars of one step from the partials of the last dot product,
@@ -2040,17 +2096,23 @@ hipError_t launch_prolong(const float* uc, int hc, int wc, const float* f, const
     return hipGetLastError();
 }
 
+static dim3 walk_grid(int h, int w, int channels) {
+    return dim3((w + 64 * kWalkWaves - 1) / (64 * kWalkWaves), (h + kWalkRows - 1) / kWalkRows,
+                channels);
+}
+
 int residual_partials(int h, int w) {
-    return ((w + 63) / 64) * ((h + kResRows - 1) / kResRows);
+    const dim3 g = walk_grid(h, w, 1);
+    return (int)(g.x * g.y);
 }
 
 hipError_t launch_residual(const float* f, const uint8_t* c, const float* u, int h, int w,
                            int channels, float* r, float* ucopy, double* partial, int* nwg,
                            hipStream_t s) {
-    dim3 grid((w + 63) / 64, (h + kResRows - 1) / kResRows, channels);
+    const dim3 grid = walk_grid(h, w, channels);
     if (nwg) *nwg = (int)(grid.x * grid.y);
-    hipLaunchKernelGGL(k_residual, grid, dim3(64 * kResRows), 0, s, f, c, u, h, w, channels, r,
-                       ucopy, partial);
+    hipLaunchKernelGGL(k_residual_walk<false>, grid, dim3(64 * kWalkWaves), 0, s, f, c, u,
+                       nullptr, h, w, channels, r, nullptr, ucopy, partial, nullptr);
     return hipGetLastError();
 }
 
@@ -2197,10 +2259,14 @@ hipError_t launch_refine_residual(const float* f, const uint8_t* c, const float*
                                   const uint16_t* d, int h, int w, int channels, float* unext,
                                   uint16_t* rhs, double* partial, const int* ctl, int* nwg,
                                   hipStream_t s) {
-    dim3 grid((w + 63) / 64, (h + kResRows - 1) / kResRows, channels);
+    const dim3 grid = walk_grid(h, w, channels);
     if (nwg) *nwg = (int)(grid.x * grid.y);
-    hipLaunchKernelGGL(k_refine_residual, grid, dim3(64 * kResRows), 0, s, f, c, u, d, h, w,
-                       channels, unext, rhs, partial, ctl);
+    if (d)
+        hipLaunchKernelGGL(k_residual_walk<true>, grid, dim3(64 * kWalkWaves), 0, s, f, c, u, d,
+                           h, w, channels, nullptr, rhs, unext, partial, ctl);
+    else
+        hipLaunchKernelGGL(k_residual_walk<false>, grid, dim3(64 * kWalkWaves), 0, s, f, c, u,
+                           nullptr, h, w, channels, nullptr, rhs, nullptr, partial, ctl);
     return hipGetLastError();
 }
 
@@ -2208,18 +2274,18 @@ hipError_t launch_cg_dir_matvec(const float* r, const float* pin, float* pout, f
                                 const uint8_t* c, int h, int w, int channels,
                                 const double* beta, bool first, double* partial, const int* ctl,
                                 int* nwg, hipStream_t s) {
-    dim3 grid((w + 63) / 64, (h + kResRows - 1) / kResRows, channels);
+    const dim3 grid = walk_grid(h, w, channels);
     if (nwg) *nwg = (int)(grid.x * grid.y);
-    hipLaunchKernelGGL(k_cg_dir_matvec, grid, dim3(64 * kResRows), 0, s, r, pin, pout, q, c, h, w,
-                       channels, beta, first ? 1 : 0, partial, ctl);
+    hipLaunchKernelGGL(k_cg_dir_matvec, grid, dim3(64 * kWalkWaves), 0, s, r, pin, pout, q, c, h,
+                       w, channels, beta, first ? 1 : 0, partial, ctl);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_update(float* x, float* r, const float* p, const float* q, int h, int w,
                             int channels, const double* alpha, double* partial, const int* ctl,
                             hipStream_t s) {
-    dim3 grid((w + 63) / 64, (h + kResRows - 1) / kResRows, channels);
-    hipLaunchKernelGGL(k_cg_update, grid, dim3(64 * kResRows), 0, s, x, r, p, q, h, w, channels,
+    const dim3 grid = walk_grid(h, w, channels);
+    hipLaunchKernelGGL(k_cg_update, grid, dim3(64 * kWalkWaves), 0, s, x, r, p, q, h, w, channels,
                        alpha, partial, ctl);
     return hipGetLastError();
 }
