@@ -142,7 +142,7 @@ def measured_traffic():
     """HBM bytes per finest-level sweep launch from the committed rocprofv3
     counter summary, or None when the kernels changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_sweep_4k_rgb_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_sweep2_4k_rgb_traffic.json")
     src = os.path.join(ROOT, "paper_2110_03946_amd", "csrc", "kernels.hip")
     try:
         d = json.load(open(path))
@@ -278,8 +278,8 @@ def run_frame(args, workload: str):
         bytes_ = correction_bytes(prm["inner_sweeps"], refs)
     roofline = roofline_of(flops, bytes_, sweep_ms, nsweeps)
     roofline.update({"traffic": None if precision else measured_traffic(),
-                     "kernel": ("k_sweep_corr<64> (finest-level correction sweep, bf16)"
-                                if precision else "k_sweep<64> (finest-level ORAS sweep)"),
+                     "kernel": ("k_sweep2<true> (finest-level correction sweep, bf16)"
+                                if precision else "k_sweep2<false> (finest-level ORAS sweep)"),
                      "cg_steps_per_block_sweep": round(
                          steps / max(nsweeps, 1) /
                          (ddi.block_count(H, prm["block"], prm["overlap"]) *
@@ -566,7 +566,7 @@ def run_batch(args):
 
     roofline = roofline_of(flops, bytes_, sweep_ms, launches)
     roofline.update({"traffic": None,
-                     "kernel": "k_sweep_batch<64> (finest-level ORAS sweep, all images)"})
+                     "kernel": "k_sweep2_batch (finest-level ORAS sweep, all images)"})
     npix = sum(h * w for h, w in sizes)
     out = {"metric": METRIC_BATCH, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,
