@@ -126,6 +126,16 @@ extern "C" {
  *                  to rel_tol; max_sweeps then caps the CG steps per level
  *                  and stats.sweeps counts the finest level's steps. Single-
  *                  image float32 plans only.
+ *   fuse_prolong   1: the first ORAS sweep on a level after the coarse-to-
+ *                  fine prolongation builds its tiles from the coarser
+ *                  level's iterate and f (the prolongation is computed in
+ *                  the sweep's tile load and never stored); levels whose
+ *                  blocks are not 64 rows high, the finest level of
+ *                  storage = 1 and max_sweeps = 0 keep the separate
+ *                  prolongation. 0: always the separate prolongation. Both
+ *                  give the same iterates whenever the interpolation sums
+ *                  are exact in float64 (neighbouring coarse values within
+ *                  a factor 2^26 of each other).
  */
 typedef struct ddi_params {
     int block;
@@ -152,6 +162,7 @@ typedef struct ddi_params {
     int storage;
     int inner_sweeps;
     int method;
+    int fuse_prolong;
 } ddi_params;
 
 /*
@@ -169,6 +180,11 @@ typedef struct ddi_params {
  *                 x local_iters when local_tol stops blocks early).
  *   refinements   storage = 1: refinement steps taken (the finest-level
  *                 sweeps are then refinements x inner_sweeps); 0 otherwise.
+ *   first_sweep_ms, first_cg_steps
+ *                 with timing = 1 and storage = 0: the part of sweep_ms and
+ *                 cg_steps that falls on the first finest-level sweep (the
+ *                 one that also computes the prolongation when
+ *                 fuse_prolong applies); 0 otherwise.
  */
 typedef struct ddi_stats {
     int sweeps;
@@ -178,6 +194,8 @@ typedef struct ddi_stats {
     double sweep_ms;
     double cg_steps;
     int refinements;
+    double first_sweep_ms;
+    double first_cg_steps;
 } ddi_stats;
 
 typedef struct ddi_plan ddi_plan;
@@ -187,7 +205,8 @@ typedef struct ddi_plan ddi_plan;
  * min_sweeps = 2, max_sweeps = 50, check_every = 1, final_residual = 1,
  * timing = 0, coarse_block = 0, coarse_overlap = -1, coarse_local_iters = 0,
  * local_tol = 0, use_graph = 0, coarse_solver = 0, coarse_cg_iters = 500,
- * coarse_cg_tol = 1e-10, storage = 0, inner_sweeps = 2, method = 0. */
+ * coarse_cg_tol = 1e-10, storage = 0, inner_sweeps = 2, method = 0,
+ * fuse_prolong = 1. */
 int ddi_default_params(ddi_params* p);
 
 /* Check *p for one image size without touching the GPU (this includes the

@@ -101,7 +101,7 @@ size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm) {
     }
     part_n = std::max(part_n, std::max<size_t>((size_t)coarsen_partials(h, w), 1024) * (C + 2));
     bytes += part_n * sizeof(double);
-    bytes += (3 * (size_t)C + 2) * sizeof(double) + 64;  // red, ctl
+    bytes += (4 * (size_t)C + 2) * sizeof(double) + 64;  // red, ctl
     if (prm.storage == 1) bytes += 3 * (size_t)C * h * w * sizeof(uint16_t);
     if (prm.method == 1)
         bytes += 4 * (size_t)C * h * w * sizeof(float) + (3 * (size_t)C + L * ((size_t)C + 2)) *
@@ -164,6 +164,7 @@ int ddi_default_params(ddi_params* p) {
     p->storage = 0;
     p->inner_sweeps = 2;
     p->method = 0;
+    p->fuse_prolong = 1;
     return DDI_OK;
 }
 
@@ -194,6 +195,7 @@ int ddi_check_params(int height, int width, int channels, const ddi_params* p) {
     if (p->inner_sweeps < 1) return DDI_EINVAL;
     if (p->method != 0 && p->method != 1) return DDI_EINVAL;
     if (p->method == 1 && p->storage != 0) return DDI_EINVAL;
+    if (p->fuse_prolong != 0 && p->fuse_prolong != 1) return DDI_EINVAL;
     if (p->coarse_solver == 1) {
         int hl = height, wl = width;
         for (int l = 1; l < level_count(height, width, p->levels); ++l) {
@@ -314,7 +316,7 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
         ddi_destroy(P);
         return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
     }
-    const size_t nred = 3 * channels + 2;
+    const size_t nred = 4 * channels + 2;
     if ((err = hipMalloc(&P->red, nred * sizeof(double))) != hipSuccess ||
         (err = hipHostMalloc(&P->host, nred * sizeof(double), hipHostMallocDefault)) !=
             hipSuccess ||
@@ -416,8 +418,11 @@ static double rel_from_host(const ddi_plan* P, const double* rsq) {
 
 // Pyramid, input statistics, transposed masks, coarsest level and the
 // coarse-to-fine passes down to the start of the finest level, enqueued on
-// `s`. The finest level starts in buffer `start0` (0 = u).
-static int enqueue_front(ddi_plan* P, int start0, hipStream_t s) {
+// `s`. The finest level starts in buffer `start0` (0 = u). With
+// fuse_prolong, the first sweep on each coarser level reads the level
+// above it directly; fuse_l0 extends that to the finest level, whose
+// prolongation is then left to enqueue_sweeps (P->pro0).
+static int enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0) {
     const int C = P->C;
     const int L = (int)P->lv.size();
     const ddi_params& prm = P->p;
@@ -454,19 +459,40 @@ static int enqueue_front(ddi_plan* P, int start0, hipStream_t s) {
     else
         DDI_HIP(launch_init(P->lv[top].f, P->lv[top].c, P->lv[top].h, P->lv[top].w, C,
                             P->lv[top].u[cur], s));
+    P->pro0_on = false;
+    // set: this level's first sweep prolongs from it (only when the level
+    // has coarse_sweeps > 0 sweeps to fuse into)
+    const ProSrc* from = nullptr;
+    ProSrc src;
     for (int l = top; l >= 1; --l) {
         Level& lev = P->lv[l];
         const int n = (l == top) ? (prm.coarse_solver == 1 ? 0 : prm.coarsest_sweeps)
                                  : prm.coarse_sweeps;
         for (int i = 0; i < n; ++i) {
-            DDI_HIP(launch_sweep(lev.u[cur], lev.mbits, lev.u[1 - cur], P->part, nullptr, nullptr,
-                                 lev.sw, s));
+            if (i == 0 && from)
+                DDI_HIP(launch_sweep_prolong(*from, lev.mbits, lev.u[1 - cur], P->part, nullptr,
+                                             nullptr, lev.sw, s));
+            else
+                DDI_HIP(launch_sweep(lev.u[cur], lev.mbits, lev.u[1 - cur], P->part, nullptr,
+                                     nullptr, lev.sw, s));
             cur ^= 1;
         }
+        from = nullptr;
         Level& fine = P->lv[l - 1];
         const int dst = (l == 1) ? start0 : 0;
-        DDI_HIP(launch_prolong(lev.u[cur], lev.h, lev.w, fine.f, fine.c, fine.h, fine.w, C,
-                               fine.u[dst], s));
+        const bool fuse = prm.fuse_prolong == 1 && sweep_prolong_ok(fine.sw) &&
+                          (l == 1 ? fuse_l0 : prm.coarse_sweeps > 0);
+        if (fuse) {
+            src = ProSrc{lev.u[cur], lev.h, lev.w, fine.f, fine.c};
+            from = &src;
+            if (l == 1) {
+                P->pro0 = src;
+                P->pro0_on = true;
+            }
+        } else {
+            DDI_HIP(launch_prolong(lev.u[cur], lev.h, lev.w, fine.f, fine.c, fine.h, fine.w, C,
+                                   fine.u[dst], s));
+        }
         cur = dst;
     }
     return DDI_OK;
@@ -488,9 +514,15 @@ static int enqueue_sweeps(ddi_plan* P, int from, int to, int start0, bool timing
     for (int i = from; i < to; ++i) {
         const int c0 = start0 ^ (i & 1);
         if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * i], s));
-        DDI_HIP(launch_sweep(L0.u[c0], L0.mbits, L0.u[c0 ^ 1], P->part, timing ? P->cgcnt : nullptr,
-                             ctl, L0.sw, s));
+        if (i == 0 && P->pro0_on)
+            DDI_HIP(launch_sweep_prolong(P->pro0, L0.mbits, L0.u[c0 ^ 1], P->part,
+                                         timing ? P->cgcnt : nullptr, ctl, L0.sw, s));
+        else
+            DDI_HIP(launch_sweep(L0.u[c0], L0.mbits, L0.u[c0 ^ 1], P->part,
+                                 timing ? P->cgcnt : nullptr, ctl, L0.sw, s));
         if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * i + 1], s));
+        if (timing && i == 0)  // the first sweep's CG steps on their own
+            DDI_HIP(launch_reduce(P->cgcnt, nb, P->C, P->C, P->red + 3 * P->C + 2, s));
         if (is_check(prm, i + 1) || i + 1 == prm.max_sweeps)
             DDI_HIP(launch_decide(P->part, nb, P->C, P->red, ctl, drel,
                                   is_check(prm, i + 1) ? prm.rel_tol : -1.0, i + 1, s));
@@ -515,7 +547,7 @@ static int solve_refine(ddi_plan* P, const float* f, const uint8_t* c, float* u,
     DDI_HIP(hipEventRecord(P->e0, s));
     const int expect = P->last_sweeps >= 0 ? P->last_sweeps : std::max(prm.min_sweeps, 1);
     const int start0 = std::min(expect, kmax) & 1;
-    int e = enqueue_front(P, start0, s);
+    int e = enqueue_front(P, start0, s, false);
     if (e) return e;
     DDI_HIP(launch_clear_int(P->ctl, 4, s));
     int* ctl = P->ctl;
@@ -664,7 +696,7 @@ static int begin_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u) 
             }
             hipGraph_t g = nullptr;
             DDI_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            int e = enqueue_front(P, q.start0, s);
+            int e = enqueue_front(P, q.start0, s, batch > 0);
             if (!e) {
                 hipError_t he = launch_clear_int(P->ctl, 4, s);
                 e = he != hipSuccess ? hip_fail(he) : enqueue_sweeps(P, 0, batch, q.start0, false, s);
@@ -691,7 +723,7 @@ static int begin_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u) 
         DDI_HIP(hipGraphLaunch(hit->exec, s));
         q.done_upto = batch;
     } else {
-        int e = enqueue_front(P, q.start0, s);
+        int e = enqueue_front(P, q.start0, s, batch > 0);
         if (e) return e;
         DDI_HIP(launch_clear_int(P->ctl, 4, s));
         e = enqueue_sweeps(P, 0, batch, q.start0, q.timing, s);
@@ -709,7 +741,7 @@ static int enqueue_check(ddi_plan* P) {
     hipStream_t s = P->pend.s;
     if (P->pend.timing) {
         DDI_HIP(launch_reduce(P->cgcnt, sweep_partials(P->lv[0].sw), C, C, P->red + 2 * C + 2, s));
-        DDI_HIP(hipMemcpyAsync(P->host + 2 * C + 2, P->red + 2 * C + 2, C * sizeof(double),
+        DDI_HIP(hipMemcpyAsync(P->host + 2 * C + 2, P->red + 2 * C + 2, 2 * C * sizeof(double),
                                hipMemcpyDeviceToHost, s));
     }
     DDI_HIP(hipMemcpyAsync(P->hctl, P->ctl, 4 * sizeof(int) + sizeof(double),
@@ -793,15 +825,19 @@ static int finish_solve(ddi_plan* P, ddi_stats* st) {
         DDI_HIP(hipEventSynchronize(P->e1));
         end = P->e1;
     }
-    double nsteps = 0.0;
-    for (int k = 0; q.timing && k < C; ++k) nsteps += P->host[2 * C + 2 + k];
+    double nsteps = 0.0, steps0 = 0.0;
+    for (int k = 0; q.timing && k < C; ++k) {
+        nsteps += P->host[2 * C + 2 + k];
+        steps0 += P->host[3 * C + 2 + k];
+    }
     float ms = 0.f;
     DDI_HIP(hipEventElapsedTime(&ms, P->e0, end));
-    double sweep_ms = 0.0;
+    double sweep_ms = 0.0, first_ms = 0.0;
     for (int i = 0; q.timing && i < sweeps; ++i) {
         float t = 0.f;
         DDI_HIP(hipEventElapsedTime(&t, P->sweep_ev[2 * i], P->sweep_ev[2 * i + 1]));
         sweep_ms += t;
+        if (i == 0) first_ms = t;
     }
     if (st) {
         st->sweeps = sweeps;
@@ -810,6 +846,8 @@ static int finish_solve(ddi_plan* P, ddi_stats* st) {
         st->ms = ms;
         st->sweep_ms = sweep_ms;
         st->cg_steps = nsteps;
+        st->first_sweep_ms = first_ms;
+        st->first_cg_steps = steps0;
     }
     return converged ? DDI_OK : DDI_ENOCONV;
 }

@@ -27,6 +27,16 @@ struct SweepArgs {
     float local_tol2; // stop CG once r.r <= local_tol2 * block pixels (0: k steps)
 };
 
+// The coarse level a first sweep prolongs from (the bilinear prolongation
+// of Sec. 4 fused into the tile load): the coarse iterate (hc x wc per
+// channel) and the fine level's data and mask, the known pixels taking f.
+struct ProSrc {
+    const float* uc;
+    int hc, wc;
+    const float* f;
+    const uint8_t* c;
+};
+
 __host__ __device__ inline int block_origin(int k, int stride, int n, int size) {
     int o = k * stride;
     return o < n - size ? o : n - size;
@@ -131,6 +141,19 @@ constexpr int kMaxBlock = 64;
 hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
                         double* partial, double* cg_steps, const int* ctl, const SweepArgs& a,
                         hipStream_t s);
+
+// True when the sweep of `a` can take its input from a coarser level
+// (launch_sweep_prolong): full 64-row blocks.
+bool sweep_prolong_ok(const SweepArgs& a);
+
+// One ORAS sweep whose input iterate is the bilinear prolongation of
+// src.uc (known pixels: src.f), computed while the tiles are loaded, so the
+// prolonged iterate is never stored; otherwise as launch_sweep. Bit for bit
+// the sweep of launch_prolong's output whenever the interpolation sums are
+// exact in float64 (coarse values within a factor 2^26 of their neighbours).
+hipError_t launch_sweep_prolong(const ProSrc& src, const uint64_t* mbits, float* uout,
+                                double* partial, double* cg_steps, const int* ctl,
+                                const SweepArgs& a, hipStream_t s);
 
 // Device stop test after finest-level sweep n (see k_decide): reduces the
 // sweep's partials, stores max_k ||r_k||^2/||b_k||^2 in rel[0] and, when

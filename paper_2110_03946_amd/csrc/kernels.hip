@@ -584,6 +584,129 @@ __device__ __forceinline__ void tile2_load(Tile2& T, const Blk& k, const SweepAr
     T.mhi = (uint32_t)(bits >> 32);
 }
 
+// Bilinear prolongation (Sec. 4, cell-centred) of one fine pixel from the
+// coarse plane: fine row y lies between coarse rows (y - 1) >> 1 and the
+// next, weight 3/4 on the second for even y, 1/4 for odd y (likewise in x);
+// indices clamped to the coarse grid, where both weights then fall on the
+// same value, which float64 sums back exactly. Each coarse row is
+// interpolated in x first, then the two rows in y, in float64, and rounded
+// to float32 once.
+__device__ __forceinline__ double pro_lerp(double a, double b, double t) {
+    return (1.0 - t) * a + t * b;
+}
+__device__ __forceinline__ float pro_pixel(const ProSrc& S, const float* __restrict__ Uc,
+                                           int y, int x) {
+    const int r0 = min(max((y - 1) >> 1, 0), S.hc - 1), r1 = min(max(((y - 1) >> 1) + 1, 0), S.hc - 1);
+    const int c0 = min(max((x - 1) >> 1, 0), S.wc - 1), c1 = min(max(((x - 1) >> 1) + 1, 0), S.wc - 1);
+    const double ay = (y & 1) ? 0.25 : 0.75, ax = (x & 1) ? 0.25 : 0.75;
+    const uint32_t o0 = (uint32_t)r0 * (uint32_t)S.wc, o1 = (uint32_t)r1 * (uint32_t)S.wc;
+    const double h0 = pro_lerp(at32(Uc, o0 + c0), at32(Uc, o0 + c1), ax);
+    const double h1 = pro_lerp(at32(Uc, o1 + c0), at32(Uc, o1 + c1), ax);
+    return (float)pro_lerp(h0, h1, ay);
+}
+
+// tile2_load for a first sweep: the tile of the prolonged iterate, built
+// from the coarse plane and f. The wave's 33 rows ybase .. ybase + 32 need
+// coarse rows F0 .. F0 + 17 (F0 = (ybase - 1) >> 1); fine row ybase + j
+// uses rows F0 + ((j + Q) >> 1) and the next, Q = (ybase - 1) & 1, so the
+// 18 x-interpolated coarse rows are shared by the fine rows. Image rows
+// outside the image (tile rows 0 and 65 at the border) are computed
+// clamped and then replaced by their reflection.
+template <int Q>
+__device__ __forceinline__ void tile2_prolong_rows(Tile2& T, const ProSrc& S,
+                                                   const float* __restrict__ Uc,
+                                                   const float* __restrict__ F, int ybase,
+                                                   int hmax, uint32_t xc, uint32_t Wd,
+                                                   const bool* known) {
+    constexpr int RPW = kSplitRows;
+    constexpr int NQ = RPW / 2 + 2;
+    const int F0 = (ybase - 1) >> 1;
+    const int X = (int)xc;
+    const uint32_t c0 = min(max((X - 1) >> 1, 0), S.wc - 1);
+    const uint32_t c1 = min(max(((X - 1) >> 1) + 1, 0), S.wc - 1);
+    const double ax = (X & 1) ? 0.25 : 0.75;
+    // all loads first: f where known, then the coarse pairs
+    float fv[RPW + 1];
+#pragma unroll
+    for (int j = 0; j < RPW + 1; ++j) {
+        const uint32_t y = (uint32_t)min(max(ybase + j, 0), hmax);
+        fv[j] = known[j] ? at32(F, y * Wd + xc) : 0.f;
+    }
+    float q0[NQ], q1[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const uint32_t o = (uint32_t)min(max(F0 + i, 0), S.hc - 1) * (uint32_t)S.wc;
+        q0[i] = at32(Uc, o + c0);
+        q1[i] = at32(Uc, o + c1);
+    }
+    double hq[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) hq[i] = pro_lerp(q0[i], q1[i], ax);
+#pragma unroll
+    for (int j = 0; j < RPW + 1; ++j) {
+        const int m = (j + Q) >> 1;
+        const double ay = ((j + Q) & 1) ? 0.75 : 0.25;
+        const float v = (float)pro_lerp(hq[m], hq[m + 1], ay);
+        T.col[j] = known[j] ? fv[j] : v;
+    }
+}
+
+__device__ __forceinline__ void tile2_load_prolong(Tile2& T, const Blk& k, const SweepArgs& a,
+                                                   const uint64_t* __restrict__ mbits,
+                                                   const ProSrc& S) {
+    constexpr int RPW = kSplitRows;
+    const BlockGrid& g = a.g;
+    const int lane = threadIdx.x & 63;
+    const int wi = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool on = lane < g.bw;
+    const int x = k.x0 + lane;
+    const uint32_t xc = on ? x : k.x0;
+    const uint32_t Wd = g.w;
+    const float* __restrict__ Uc = S.uc + (int64_t)k.ch * S.hc * S.wc;
+    const float* __restrict__ F = S.f + k.ch * a.cpitch;
+    uint64_t bits = 0;
+    if (on) {
+        const int gy = k.y0 >> 6, sh = k.y0 & 63;
+        const uint64_t* mb = mbits + (uint32_t)gy * Wd + (uint32_t)x;
+        bits = mb[0] >> sh;
+        if (sh) bits |= mb[g.w] << (64 - sh);
+    }
+    T.mlo = (uint32_t)bits;
+    T.mhi = (uint32_t)(bits >> 32);
+    // known pixels of this wave's 33 rows: the block's bits, and the mask
+    // byte for the halo row (above the block for wave 0, below for wave 1)
+    const int ybase = k.y0 - 1 + wi * (RPW + 1);
+    const int yh = wi == 0 ? k.y0 - 1 : k.y0 + 2 * RPW;
+    const bool hin = wi == 0 ? k.has_top : k.has_bot;
+    const bool hknown = hin && at32(S.c, (uint32_t)min(max(yh, 0), g.h - 1) * Wd + xc) != 0;
+    bool known[RPW + 1];
+#pragma unroll
+    for (int j = 0; j < RPW + 1; ++j) {
+        if (wi == 0)
+            known[j] = j == 0 ? hknown : ((T.mlo >> (j - 1)) & 1u) == 0;
+        else
+            known[j] = j == RPW ? hknown : ((T.mhi >> j) & 1u) == 0;
+    }
+    if ((ybase - 1) & 1)
+        tile2_prolong_rows<1>(T, S, Uc, F, ybase, g.h - 1, xc, Wd, known);
+    else
+        tile2_prolong_rows<0>(T, S, Uc, F, ybase, g.h - 1, xc, Wd, known);
+    // reflecting border: the clamped tile row repeats its neighbour
+    if (wi == 0 && !k.has_top) T.col[0] = T.col[1];
+    if (wi == 1 && !k.has_bot) T.col[RPW] = T.col[RPW - 1];
+    // halo columns: one pixel each per lane th (tile row th)
+    const int xl = max(k.x0 - 1, 0), xr = min(k.x0 + g.bw, g.w - 1);
+    const int th = wi == 0 ? lane : 64 + lane;
+    const int r1 = min(max(k.y0 + min(th, 2 * RPW + 1) - 1, 0), g.h - 1);
+    const uint32_t ro = (uint32_t)r1 * Wd;
+    const bool kl = at32(S.c, ro + xl) != 0, kr = at32(S.c, ro + xr) != 0;
+    const float fl = kl ? at32(F, ro + xl) : 0.f;
+    const float fr = kr ? at32(F, ro + xr) : 0.f;
+    const float pl = pro_pixel(S, Uc, r1, xl), pr = pro_pixel(S, Uc, r1, xr);
+    T.hl = kl ? fl : pl;
+    T.hr = kr ? fr : pr;
+}
+
 __device__ __forceinline__ void tile2_store(const Tile2& T, const SweepArgs& a,
                                             float* __restrict__ lds) {
     constexpr int RPW = kSplitRows;
@@ -776,8 +899,9 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
     }
 }
 
-// One split block (tile loaded, stored, computed).
-template <bool CORR, bool QL>
+// One split block (tile loaded, stored, computed). PRO: the input iterate
+// is the prolongation of pro (uin_v unused).
+template <bool CORR, bool QL, bool PRO = false>
 __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
                                             const uint16_t* __restrict__ rhs,
                                             const uint64_t* __restrict__ mbits,
@@ -785,11 +909,14 @@ __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
                                             double* __restrict__ partial,
                                             double* __restrict__ cg_steps,
                                             const int* __restrict__ ctl, const SweepArgs& a,
-                                            int lb, float* __restrict__ lds) {
+                                            int lb, float* __restrict__ lds,
+                                            const ProSrc* pro = nullptr) {
     if (ctl && ctl[0] != 0) return;  // read by both waves: the same decision
     const Blk k = blk_geo(a, lb);
     Tile2 T;
-    if constexpr (!CORR) {
+    if constexpr (PRO) {
+        tile2_load_prolong(T, k, a, mbits, *pro);
+    } else if constexpr (!CORR) {
         tile2_load(T, k, a, mbits, LoadF32{(const float*)uin_v + k.ch * a.cpitch});
     } else {
         const uint16_t* U16 = (const uint16_t*)uin_v;
@@ -821,6 +948,19 @@ __global__ __launch_bounds__(128, DDI_SPLIT_WAVES) void k_sweep2(const void* __r
     __shared__ __attribute__((aligned(16))) float lds[kSplitLds];
     sweep2_body<CORR, DDI_SPLIT_QL>(uin, rhs, mbits, uout, partial, cg_steps, ctl, a,
                                     xcd_remap(blockIdx.x, gridDim.x), lds);
+}
+
+// k_sweep2 whose input iterate is the bilinear prolongation of a coarser
+// level, computed in the tile load.
+__global__ __launch_bounds__(128, DDI_SPLIT_WAVES) void k_sweep2_pro(ProSrc pro,
+                                                    const uint64_t* __restrict__ mbits,
+                                                    float* __restrict__ uout,
+                                                    double* __restrict__ partial,
+                                                    double* __restrict__ cg_steps,
+                                                    const int* __restrict__ ctl, SweepArgs a) {
+    __shared__ __attribute__((aligned(16))) float lds[kSplitLds];
+    sweep2_body<false, DDI_SPLIT_QL, true>(nullptr, nullptr, mbits, uout, partial, cg_steps, ctl,
+                                           a, xcd_remap(blockIdx.x, gridDim.x), lds, &pro);
 }
 
 
@@ -1947,6 +2087,20 @@ hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
     if (bh > 16) return sweep_rpw<32, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
     if (bh > 8) return sweep_rpw<16, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
     return sweep_rpw<8, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
+}
+
+bool sweep_prolong_ok(const SweepArgs& a) { return use_split(a); }
+
+hipError_t launch_sweep_prolong(const ProSrc& src, const uint64_t* mbits, float* uout,
+                                double* partial, double* cg_steps, const int* ctl,
+                                const SweepArgs& a, hipStream_t s) {
+    if (!use_split(a) || a.g.bw < 1 || a.g.bw > kMaxBlock || !src.uc || !src.f || !src.c ||
+        src.hc != (a.g.h + 1) / 2 || src.wc != (a.g.w + 1) / 2)
+        return hipErrorInvalidValue;
+    const int grid = a.g.nby * a.g.nbx * a.channels;
+    hipLaunchKernelGGL(k_sweep2_pro, dim3(grid), dim3(128), 0, s, src, mbits, uout, partial,
+                       cg_steps, ctl, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_decide(const double* partial, int nb, int channels, const double* stats,

@@ -101,6 +101,10 @@ struct ddi_plan {
     float* cg_vec = nullptr;
     double* cg_sc = nullptr;
     std::vector<int> last_iters;
+    // the finest level's first sweep of the solve being enqueued prolongs
+    // from this source (fuse_prolong)
+    ddi::ProSrc pro0{};
+    bool pro0_on = false;
 };
 
 // Multilevel CG solve (mlcg.cpp); the level-0 pointers are set.

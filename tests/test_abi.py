@@ -30,7 +30,8 @@ def test_default_params_valid():
 @pytest.mark.parametrize("field,value", [
     ("block", 1), ("block", 65), ("overlap", -1), ("overlap", 64), ("levels", 0),
     ("local_iters", 0), ("robin_alpha", 0.0), ("robin_alpha", 1.5),
-    ("coarse_sweeps", -1), ("rel_tol", -1.0), ("check_every", 0), ("max_sweeps", 1)])
+    ("coarse_sweeps", -1), ("rel_tol", -1.0), ("check_every", 0), ("max_sweeps", 1),
+    ("fuse_prolong", 2), ("fuse_prolong", -1)])
 def test_bad_params_rejected(field, value):
     p = ddi.default_params()
     setattr(p, field, value)

@@ -1,0 +1,120 @@
+"""Prolongation fused into the first sweep of a level (fuse_prolong = 1)
+against the separate prolongation kernel (fuse_prolong = 0).
+
+The fused tile load evaluates the same bilinear formula in float64 and
+rounds once, so for grey-level data (every interpolation sum exact in
+float64) both paths give the same iterates: the solves must agree bit for
+bit, in the returned image and in the statistics. The separate path is
+itself pinned to the oracle's prolongation and sweep; the full solves are
+also checked against the oracle's exact solution.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_03946_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ddi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2110_03946_amd import ddi as mod
+    mod.lib()
+    return mod
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+BENCH = dict(block=64, overlap=4, levels=4, local_iters=16, robin_alpha=0.25, coarse_sweeps=1,
+             coarsest_sweeps=1, coarse_local_iters=4, local_tol=0.002, rel_tol=5e-4,
+             min_sweeps=2, max_sweeps=30, final_residual=0)
+
+CASES = [
+    # the benchmark workload: every level fused
+    (3, 2160, 3840, 0.04, "bernoulli", BENCH),
+    # odd sizes: the last block row and column start at odd pixels, the
+    # coarse grids have a half-covered last row and column
+    (3, 1081, 1923, 0.03, "clustered", dict(levels=4, rel_tol=1e-4, max_sweeps=60)),
+    (1, 200, 300, 0.05, "bernoulli", dict(levels=3, coarse_sweeps=2, rel_tol=1e-5,
+                                          max_sweeps=80)),
+    # narrow levels: level 1 is 65 x 39 (blocks narrower than 64 columns)
+    (2, 130, 77, 0.1, "bernoulli", dict(levels=2, rel_tol=1e-5, max_sweeps=80)),
+    # level 1 has 50 rows: its blocks are not 64 high, only the finest
+    # level fuses
+    (1, 100, 500, 0.05, "clustered", dict(levels=3, rel_tol=1e-5, max_sweeps=120)),
+    # coarse_sweeps = 0: the coarser levels keep the separate prolongation
+    (3, 540, 960, 0.04, "bernoulli", dict(levels=4, coarse_sweeps=0, rel_tol=1e-4,
+                                          max_sweeps=80)),
+    # float64 coarsest level, 5 levels
+    (3, 1080, 1920, 0.03, "bernoulli", dict(levels=5, coarse_solver=1, rel_tol=1e-4,
+                                            max_sweeps=60)),
+    # min_sweeps = 1: the stop test right after the fused sweep
+    (3, 270, 480, 0.1, "bernoulli", dict(levels=3, min_sweeps=1, rel_tol=2e-3,
+                                         max_sweeps=40)),
+]
+
+
+@pytest.mark.parametrize("C,H,W,d,kind,prm", CASES)
+def test_fused_prolongation_matches_separate(ddi, C, H, W, d, kind, prm):
+    f, c = synth.make_workload(H, W, C, d, kind, workload=70, index=H + W)
+    say("fuse vs separate", C, H, W, d, kind, prm)
+    out = {}
+    for fuse in (0, 1):
+        with ddi.Plan(H, W, C, fuse_prolong=fuse, **prm) as plan:
+            u_t, st = plan.solve(dev(f), dev(c), allow_noconv=True)
+            u2_t, st2 = plan.solve(dev(f), dev(c), allow_noconv=True)  # other start buffer
+        out[fuse] = (host(u_t), st, host(u2_t), st2)
+        say("  fuse", fuse, "sweeps", st["sweeps"], "rel", st["rel_residual"])
+    u0, s0, v0, t0 = out[0]
+    u1, s1, v1, t1 = out[1]
+    assert s1["sweeps"] == s0["sweeps"] and s1["rel_residual"] == s0["rel_residual"]
+    assert t1["sweeps"] == t0["sweeps"] and t1["rel_residual"] == t0["rel_residual"]
+    np.testing.assert_array_equal(u1, u0)
+    np.testing.assert_array_equal(v1, v0)
+    np.testing.assert_array_equal(u1[:, c == 1], f[:, c == 1])
+    if H * W <= 600_000 and s1["converged"]:
+        ex = oracle.solve_exact(f.astype(np.float64), c)
+        err = float(np.abs(u1 - ex).max())
+        say("  max err vs exact", err)
+        assert err <= 0.5
+
+
+def test_fused_prolongation_graph_and_timing(ddi):
+    """The fused first sweep inside a captured graph and under timing gives
+    the separate path's result."""
+    C, H, W = 3, 540, 960
+    f, c = synth.make_workload(H, W, C, 0.04, "bernoulli", workload=71)
+    say("fuse graph / timing")
+    ref = None
+    for fuse, extra in [(0, {}), (1, dict(use_graph=1)), (1, dict(timing=1))]:
+        with ddi.Plan(H, W, C, fuse_prolong=fuse, **dict(BENCH, **extra)) as plan:
+            for _ in range(3):
+                u_t, st = plan.solve(dev(f), dev(c))
+        u = host(u_t)
+        if ref is None:
+            ref = (u, st["sweeps"])
+        else:
+            assert st["sweeps"] == ref[1]
+            np.testing.assert_array_equal(u, ref[0])
+        if extra.get("timing"):
+            # the first sweep's share of the timing statistics
+            assert 0 < st["first_sweep_ms"] < st["sweep_ms"]
+            assert 0 < st["first_cg_steps"] < st["cg_steps"]
+        else:
+            assert st["first_sweep_ms"] == 0 and st["first_cg_steps"] == 0
+
