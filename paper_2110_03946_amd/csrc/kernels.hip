@@ -1509,25 +1509,12 @@ __device__ __forceinline__ Walk walk_geom(int h, int w) {
     k.inb = k.x < w;
     k.xc = k.inb ? k.x : w - 1;
     k.edge = k.lane == 0 || k.lane == 63;
-    k.xe = k.lane == 0 ? (uint32_t)max(k.x - 1, 0) : (uint32_t)min(k.x + 1, w - 1);
+    // from the clamped column, so that lane 0 of a wave lying wholly right of
+    // the image still reads inside the row (its values are not used)
+    k.xe = k.lane == 0 ? (uint32_t)max((int)k.xc - 1, 0) : (uint32_t)min(k.x + 1, w - 1);
     k.y0 = blockIdx.y * kWalkRows;
     k.y1 = min(k.y0 + kWalkRows, h);
     return k;
-}
-
-// Horizontal neighbours of value v of row y (val(j) reads element j).
-template <class V>
-__device__ __forceinline__ void walk_lr(const Walk& k, int w, uint32_t row, float v, V val,
-                                        float* lft, float* rgt) {
-    float l = from_left(v), r = from_right(v);
-    if (k.edge) {
-        const float e = val(row + k.xe);
-        if (k.lane == 0) l = e; else r = e;
-    }
-    if (k.x == 0) l = v;
-    if (k.x + 1 >= w) r = v;
-    *lft = l;
-    *rgt = r;
 }
 
 // Sum of acc over the workgroup into partial[wg][ch] (fixed order).
