@@ -94,6 +94,7 @@ void put_sweeps(Arena& A, const std::vector<SweepJob>& jobs, std::vector<SweepLa
         int wg = 0;
         for (const SweepJob& j : jobs) {
             if (instance_index(j.a.g.bh) != inst) continue;
+            // fused jobs are built only for split blocks (k_sweep2_batch)
             SweepJob k = j;
             k.wg0 = wg;
             wg += sweep_partials(j.a) * j.a.channels;
@@ -292,6 +293,10 @@ void build_front(ddi_batch* B, const std::vector<int>& start0, Arena& A, Front& 
     }
 
     // coarse levels, coarsest first: sweeps, then prolongation one level down
+    // (fused into the first sweep of the finer level where it has one: the
+    // image's pending source `from`)
+    std::vector<ProSrc> from(n, ProSrc{});
+    for (ddi_plan* P : B->plans) P->pro0_on = false;
     for (int l = Lmax - 1; l >= 1; --l) {
         int nmax = 0;
         for (ddi_plan* P : B->plans) {
@@ -314,6 +319,10 @@ void build_front(ddi_batch* B, const std::vector<int>& start0, Arena& A, Front& 
                 j.uout = lev.u[cur[i] ^ 1];
                 j.partial = P->part;
                 j.a = lev.sw;
+                if (k == 0 && from[i].uc) {
+                    j.uin = nullptr;
+                    j.pro = from[i];
+                }
                 jobs.push_back(j);
                 cur[i] ^= 1;
             }
@@ -330,7 +339,16 @@ void build_front(ddi_batch* B, const std::vector<int>& start0, Arena& A, Front& 
             const Level& lev = P->lv[l];
             Level& fine = P->lv[l - 1];
             const int dst = l == 1 ? start0[i] : 0;
-            if (!prolong4_ok(lev.u[cur[i]], fine.f, fine.c, fine.u[dst], fine.w)) {
+            from[i] = ProSrc{};
+            const bool fuse = P->p.fuse_prolong == 1 && sweep_prolong_ok(fine.sw) &&
+                              (l == 1 ? B->max_sweeps > 0 : coarse_sweeps_at(P, l - 1) > 0);
+            if (fuse) {
+                from[i] = ProSrc{lev.u[cur[i]], lev.h, lev.w, fine.f, fine.c};
+                if (l == 1) {
+                    P->pro0 = from[i];
+                    P->pro0_on = true;
+                }
+            } else if (!prolong4_ok(lev.u[cur[i]], fine.f, fine.c, fine.u[dst], fine.w)) {
                 Front::Step st;
                 st.kind = Front::Step::ProlongOne;
                 st.img = i;
@@ -424,12 +442,37 @@ int enqueue_front(ddi_batch* B, const Front& F) {
 // the last allowed sweep when that is not a check point).
 struct FineTables {
     std::vector<SweepLaunch> sweep[2];
+    std::vector<SweepLaunch> first;  // sweep 0 with fused prolongations (empty: sweep[0])
     const DecideJob* decide[2] = {nullptr, nullptr};
     int ndecide = 0;
 };
 
 void build_fine(ddi_batch* B, const std::vector<int>& act, const std::vector<int>& start0,
-                Arena& A, FineTables& T) {
+                Arena& A, FineTables& T, bool with_first) {
+    T.first.clear();
+    if (with_first) {
+        std::vector<SweepJob> jobs;
+        bool any = false;
+        for (int i : act) {
+            ddi_plan* P = B->plans[i];
+            Level& L0 = P->lv[0];
+            SweepJob j{};
+            j.uin = L0.u[start0[i]];
+            j.mbits = L0.mbits;
+            j.uout = L0.u[start0[i] ^ 1];
+            j.partial = P->part;
+            j.cg_steps = B->timing ? P->cgcnt : nullptr;
+            j.ctl = B->ctl + (size_t)i * kCtlInts;
+            j.a = L0.sw;
+            if (P->pro0_on) {
+                j.uin = nullptr;
+                j.pro = P->pro0;
+                any = true;
+            }
+            jobs.push_back(j);
+        }
+        if (any) put_sweeps(A, jobs, T.first);
+    }
     for (int q = 0; q < 2; ++q) {
         std::vector<SweepJob> jobs;
         for (int i : act) {
@@ -470,7 +513,7 @@ int enqueue_fine(ddi_batch* B, const FineTables& T, int from, int to) {
     hipStream_t s = B->s;
     for (int i = from; i < to; ++i) {
         if (B->timing) DDI_HIP(hipEventRecord(B->sweep_ev[2 * i], s));
-        DDI_HIP(run_sweeps(T.sweep[i & 1], s));
+        DDI_HIP(run_sweeps(i == 0 && !T.first.empty() ? T.first : T.sweep[i & 1], s));
         if (B->timing) DDI_HIP(hipEventRecord(B->sweep_ev[2 * i + 1], s));
         const bool chk = is_check(B, i + 1);
         if (chk || i + 1 == B->max_sweeps)
@@ -582,7 +625,7 @@ int ddi_batch_create(ddi_batch** out, int n, const int* heights, const int* widt
         }
         build_front(B, start0, A, F);
         FineTables T;
-        build_fine(B, act, start0, A, T);
+        build_fine(B, act, start0, A, T, true);
         for (int i = 0; i < n; ++i) {
             Level& L0 = B->plans[i]->lv[0];
             L0.f = nullptr;
@@ -634,7 +677,7 @@ int ddi_batch_solve(ddi_batch* B, const float* const* f, const uint8_t* const* c
     Front F;
     build_front(B, start0, A, F);
     FineTables T;
-    build_fine(B, act, start0, A, T);
+    build_fine(B, act, start0, A, T, true);
     int e = upload(B, A);
     if (e) return e;
     if ((e = enqueue_front(B, F))) return e;
@@ -650,7 +693,7 @@ int ddi_batch_solve(ddi_batch* B, const float* const* f, const uint8_t* const* c
             R.h = B->hjob;
             R.d = B->djob;
             R.cap = B->jcap;
-            build_fine(B, act, start0, R, T);
+            build_fine(B, act, start0, R, T, false);
             if ((e = upload(B, R))) return e;
         }
         first_batch = false;

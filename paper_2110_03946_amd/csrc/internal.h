@@ -80,6 +80,8 @@ struct SweepJob {
     const int* ctl;
     SweepArgs a;
     int wg0;
+    ProSrc pro;  // pro.uc set: the input is the prolongation of pro (uin unused;
+                 // only for jobs with sweep_prolong_ok)
 };
 
 // One image at one level for the batched level kernels (coarsening,

@@ -1029,8 +1029,12 @@ __global__ __launch_bounds__(128, DDI_SPLIT_WAVES) void k_sweep2_batch(const Swe
     __shared__ __attribute__((aligned(16))) float lds[kSplitLds];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const SweepJob& J = jobs[find_job(jobs, njobs, lb)];
-    sweep2_body<false, DDI_SPLIT_QL>(J.uin, nullptr, J.mbits, J.uout, J.partial, J.cg_steps,
-                                     J.ctl, J.a, lb - J.wg0, lds);
+    if (J.pro.uc)  // uniform per workgroup
+        sweep2_body<false, DDI_SPLIT_QL, true>(nullptr, nullptr, J.mbits, J.uout, J.partial,
+                                               J.cg_steps, J.ctl, J.a, lb - J.wg0, lds, &J.pro);
+    else
+        sweep2_body<false, DDI_SPLIT_QL>(J.uin, nullptr, J.mbits, J.uout, J.partial, J.cg_steps,
+                                         J.ctl, J.a, lb - J.wg0, lds);
 }
 
 // Column-transposed unknown-pixel bits of a mask: word (g, x) holds bit j

@@ -118,3 +118,34 @@ def test_fused_prolongation_graph_and_timing(ddi):
         else:
             assert st["first_sweep_ms"] == 0 and st["first_cg_steps"] == 0
 
+
+
+def test_fused_prolongation_in_batches(ddi):
+    """Batched solves with per-image fuse_prolong settings (fused and
+    separate images in the same launches, images whose finest blocks are
+    not 64 rows high, one-level images) equal the separate path bit for
+    bit."""
+    C = 3
+    specs = [(540, 960, 0.04, "bernoulli", 4, 1), (257, 333, 0.05, "clustered", 3, 1),
+             (48, 200, 0.1, "bernoulli", 2, 1), (300, 300, 0.03, "bernoulli", 4, 0),
+             (130, 77, 0.1, "clustered", 1, 1), (1080, 1920, 0.03, "bernoulli", 5, 1)]
+    data = [synth.make_workload(h, w, C, d, k, workload=72, index=i)
+            for i, (h, w, d, k, _, _) in enumerate(specs)]
+    base = dict(rel_tol=1e-4, max_sweeps=60, final_residual=0)
+    say("batch fuse mix")
+    res = {}
+    for fuse_on in (0, 1):
+        prms = [ddi.default_params(levels=L, fuse_prolong=fz if fuse_on else 0, **base)
+                for *_, L, fz in specs]
+        with ddi.Batch([c.shape for _, c in data], C, params=prms) as b:
+            for rep in range(2):  # the second solve starts in the other buffer
+                us, st, codes = b.solve([dev(f) for f, _ in data], [dev(c) for _, c in data])
+                assert codes == [0] * len(specs)
+                res[(fuse_on, rep)] = ([host(u) for u in us], [s["sweeps"] for s in st])
+        say("  fuse", fuse_on, "sweeps", res[(fuse_on, 0)][1])
+    for rep in range(2):
+        u0, s0 = res[(0, rep)]
+        u1, s1 = res[(1, rep)]
+        assert s1 == s0
+        for a, b_ in zip(u1, u0):
+            np.testing.assert_array_equal(a, b_)
