@@ -35,6 +35,14 @@ Contents
                    solves: the same local solves and partition of unity
                    applied to a general right-hand side.
   ml_oras          coarse-to-fine multilevel ORAS (Sec. 4).
+  apply_matrix     A z for the matrix of eq. 6.
+  fgmres_oras, krylov_oras
+                   ORAS as a preconditioner of a Krylov method (not in the
+                   paper): flexible GMRES(m) (Saad's flexible inner-outer
+                   GMRES, 1993) on A u = b, each basis vector preconditioned
+                   by one ORAS iteration on the correction equation
+                   (correction_step from d = 0), after the coarse-to-fine
+                   start of ml_oras.
   inverse_inf_norm ||K_UU^{-1}||_inf, which turns a residual bound into a
                    guaranteed bound on the error of an inpainting.
 
@@ -487,7 +495,13 @@ def correction_step(d, rhs, c, size: int, overlap: int, alpha: float, k: int | N
     for by, bx in blocks:
         y0, x0 = oy[by], ox[bx]
         M = local_matrix(c, y0, x0, bh, bw, alpha)
-        v = local_cg(M, r[y0:y0 + bh, x0:x0 + bw].reshape(-1), k).reshape(bh, bw)
+        rhs_i = r[y0:y0 + bh, x0:x0 + bw].reshape(-1)
+        if k is None:  # exact local solve, as in oras_step
+            import scipy.sparse.linalg as spl
+            v = spl.spsolve(M.tocsc(), rhs_i)
+        else:
+            v = local_cg(M, rhs_i, k)
+        v = v.reshape(bh, bw)
         ys, ye, xs, xe = ly[by], hy[by], lx[bx], hx[bx]
         out[ys:ye, xs:xe] += v[ys - y0:ye - y0, xs - x0:xe - x0]
     return out
@@ -516,3 +530,77 @@ def ml_oras(f, c, levels: int, size: int, overlap: int, alpha: float,
         for _ in range(sweeps[lev]):
             u, _ = oras_step(u, fl, cl, size, overlap, alpha, k)
     return u
+
+
+def apply_matrix(z, c):
+    """A z for the matrix of eq. 6: z_p on the mask, the sum over in-image
+    4-neighbours q of (z_p - z_q) elsewhere. Since residual(f, c, u) is
+    b - A u, A z = -residual(0, c, z)."""
+    z = np.asarray(z, dtype=np.float64)
+    return -residual(np.zeros_like(z), c, z)
+
+
+def fgmres_oras(f, c, u0, size: int, overlap: int, alpha: float, k: int | None,
+                m: int, tol: float, max_iter: int):
+    """Flexible GMRES(m) on A u = b (eq. 6) for one channel, from u0 (with
+    u0 = f on the mask), right-preconditioned by one ORAS iteration on the
+    correction equation: z_j = correction_step(0, v_j). Local CG with a fixed
+    step count is not a linear map of its right-hand side, so the
+    preconditioned vectors z_j are kept (flexible variant): the update is
+    u = u0 + Z y with y minimising ||beta e_1 - H y||.
+
+    Orthogonalisation by modified Gram-Schmidt; restart after m steps.
+    Stops once ||b - A u|| <= tol ||b|| (the least-squares residual within a
+    cycle, recomputed from u at each restart) or after max_iter steps.
+    Returns (u, history): history[0] is the relative residual of u0, then
+    one entry per step.
+    """
+    f = np.asarray(f, dtype=np.float64)
+    c = np.asarray(c)
+    u = np.asarray(u0, dtype=np.float64).copy()
+    bnorm = float(np.linalg.norm(np.where(c == 1, f, 0.0)))
+    history = []
+    steps = 0
+    while True:
+        r = residual(f, c, u)
+        beta = float(np.linalg.norm(r))
+        history.append(beta / bnorm if bnorm > 0 else 0.0)
+        if beta <= tol * bnorm or steps >= max_iter or beta == 0.0:
+            return u, history
+        V = [r / beta]
+        Z = []
+        H = np.zeros((m + 1, m))
+        y = np.zeros(0)
+        for j in range(m):
+            z = correction_step(np.zeros_like(u), V[j], c, size, overlap, alpha, k)
+            wv = apply_matrix(z, c)
+            for i in range(j + 1):
+                H[i, j] = float(np.sum(wv * V[i]))
+                wv = wv - H[i, j] * V[i]
+            H[j + 1, j] = float(np.linalg.norm(wv))
+            Z.append(z)
+            steps += 1
+            g = np.zeros(j + 2)
+            g[0] = beta
+            y, *_ = np.linalg.lstsq(H[:j + 2, :j + 1], g, rcond=None)
+            res = float(np.linalg.norm(g - H[:j + 2, :j + 1] @ y))
+            history.append(res / bnorm)
+            if res <= tol * bnorm or steps >= max_iter or H[j + 1, j] == 0.0:
+                break
+            V.append(wv / H[j + 1, j])
+        for j, z in enumerate(Z):
+            u = u + y[j] * z
+        if history[-1] <= tol or steps >= max_iter:
+            r = residual(f, c, u)
+            history[-1] = float(np.linalg.norm(r)) / bnorm
+            return u, history
+
+
+def krylov_oras(f, c, levels: int, size: int, overlap: int, alpha: float,
+                k: int | None, coarse_sweeps, m: int, tol: float, max_iter: int):
+    """Krylov-accelerated multilevel ORAS for one channel: the coarse-to-fine
+    start of ml_oras (coarse_sweeps[l] ORAS iterations on level l >= 1, none
+    on the finest), then fgmres_oras on the finest level."""
+    sweeps = [0] + list(coarse_sweeps)
+    u0 = ml_oras(f, c, levels, size, overlap, alpha, k, sweeps)
+    return fgmres_oras(f, c, u0, size, overlap, alpha, k, m, tol, max_iter)

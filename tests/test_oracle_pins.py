@@ -487,3 +487,65 @@ def test_correction_step_fixed_point_and_convergence():
     for _ in range(60):
         d = oracle.correction_step(d, r, c, 16, 4, 0.3, 8)
     np.testing.assert_allclose(u + d, ex, atol=1e-6)
+
+
+# ---- Krylov-accelerated ORAS (flexible GMRES with an ORAS preconditioner) ----
+
+def _kry_case(seed=0, h=36, w=44, d=0.06, kind="bernoulli"):
+    f, c = synth.make_workload(h, w, 1, d, kind, workload=81, index=seed)
+    return f[0].astype(np.float64), c
+
+
+def test_apply_matrix_equals_literal_dense_matrix():
+    """A z from the residual routine equals the literal dense A of eq. 6."""
+    f, c = _kry_case(0, 9, 11, 0.2)
+    A, _ = oracle.dense_matrix(f, c)
+    z = np.random.default_rng(3).normal(0, 1, c.shape)
+    np.testing.assert_allclose(oracle.apply_matrix(z, c).reshape(-1), A @ z.reshape(-1),
+                               atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("seed,kind,levels", [(0, "bernoulli", 2), (1, "clustered", 3),
+                                              (2, "bernoulli", 1)])
+def test_fgmres_oras_converges_to_exact(seed, kind, levels):
+    f, c = _kry_case(seed, kind=kind)
+    ex = oracle.solve_exact(f, c)
+    u, hist = oracle.krylov_oras(f, c, levels, 16, 4, 0.3, 6, [1] * (levels - 1), 6, 1e-11, 80)
+    assert hist[-1] <= 1e-11
+    np.testing.assert_allclose(u, ex, atol=1e-6, rtol=0)
+    np.testing.assert_array_equal(u[c == 1], f[c == 1])
+
+
+def test_fgmres_first_step_no_worse_than_one_oras_step():
+    """Local CG from zero is homogeneous of degree one in its right-hand
+    side, so one stationary ORAS step from u0 is u0 + beta z_1, a point of
+    the space the first FGMRES step minimises the residual over."""
+    for seed in range(3):
+        f, c = _kry_case(seed)
+        u0 = np.where(c == 1, f, 0.0)
+        _, hist = oracle.fgmres_oras(f, c, u0, 16, 4, 0.3, 5, 4, 0.0, 1)
+        u1, _ = oracle.oras_step(u0, f, c, 16, 4, 0.3, 5)
+        assert hist[1] <= oracle.rel_residual(f, c, u1) * (1 + 1e-12)
+        assert hist[1] <= hist[0]
+
+
+def test_fgmres_with_exact_preconditioner_takes_one_step():
+    """One block over the whole image with an exact local solve makes the
+    preconditioner A^-1 on the unknowns: one step solves the system."""
+    f, c = _kry_case(4, 20, 24)
+    u0 = np.where(c == 1, f, 0.0)
+    u, hist = oracle.fgmres_oras(f, c, u0, 24, 0, 1.0, None, 4, 1e-12, 1)
+    assert hist[1] < 1e-12
+    np.testing.assert_allclose(u, oracle.solve_exact(f, c), atol=1e-9, rtol=0)
+
+
+def test_fgmres_residuals_do_not_increase_within_a_cycle():
+    f, c = _kry_case(5, kind="clustered")
+    u0 = np.where(c == 1, f, 0.0)
+    u, hist = oracle.fgmres_oras(f, c, u0, 16, 4, 1.0, 4, 8, 0.0, 8)
+    # u0, the least-squares residuals of steps 1..7, and in place of step
+    # 8's the residual of the returned u recomputed from scratch
+    assert len(hist) == 9
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(hist[:8], hist[1:8]))
+    assert hist[8] == oracle.rel_residual(f, c, u)
+    assert hist[8] <= hist[7] * (1 + 1e-9)
