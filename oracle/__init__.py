@@ -553,7 +553,9 @@ def fgmres_oras(f, c, u0, size: int, overlap: int, alpha: float, k: int | None,
     Stops once ||b - A u|| <= tol ||b|| (the least-squares residual within a
     cycle, recomputed from u at each restart) or after max_iter steps.
     Returns (u, history): history[0] is the relative residual of u0, then
-    one entry per step.
+    one entry per step -- the least-squares residual, except that the last
+    step of a cycle carries the residual of the updated u recomputed from
+    scratch -- so len(history) - 1 is the number of steps.
     """
     f = np.asarray(f, dtype=np.float64)
     c = np.asarray(c)
@@ -564,7 +566,11 @@ def fgmres_oras(f, c, u0, size: int, overlap: int, alpha: float, k: int | None,
     while True:
         r = residual(f, c, u)
         beta = float(np.linalg.norm(r))
-        history.append(beta / bnorm if bnorm > 0 else 0.0)
+        rel0 = beta / bnorm if bnorm > 0 else 0.0
+        if history:
+            history[-1] = rel0  # the cycle's last step, recomputed from u
+        else:
+            history.append(rel0)
         if beta <= tol * bnorm or steps >= max_iter or beta == 0.0:
             return u, history
         V = [r / beta]
@@ -590,10 +596,6 @@ def fgmres_oras(f, c, u0, size: int, overlap: int, alpha: float, k: int | None,
             V.append(wv / H[j + 1, j])
         for j, z in enumerate(Z):
             u = u + y[j] * z
-        if history[-1] <= tol or steps >= max_iter:
-            r = residual(f, c, u)
-            history[-1] = float(np.linalg.norm(r)) / bnorm
-            return u, history
 
 
 def krylov_oras(f, c, levels: int, size: int, overlap: int, alpha: float,
