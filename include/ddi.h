@@ -126,6 +126,19 @@ extern "C" {
  *                  to rel_tol; max_sweeps then caps the CG steps per level
  *                  and stats.sweeps counts the finest level's steps. Single-
  *                  image float32 plans only.
+ *                  2: Krylov-accelerated ORAS (not in the paper): the same
+ *                  coarse-to-fine start, then flexible GMRES(krylov_restart)
+ *                  on the finest level per channel, each basis vector
+ *                  preconditioned by one ORAS sweep (block, overlap,
+ *                  robin_alpha, local_iters, local_tol) on the correction
+ *                  equation A d = v from d = 0; it stops once max_k
+ *                  ||b - A u||/||b|| <= rel_tol (signalled by the
+ *                  least-squares estimate, confirmed on the recomputed
+ *                  residual). max_sweeps caps the Krylov steps (one
+ *                  preconditioner sweep each), stats.sweeps counts them.
+ *                  Single-image float32 plans only.
+ *   krylov_restart restart length m of method = 2, 1 <= m <= 16 (the plan
+ *                  holds 2m + 1 finest-level vectors).
  *   fuse_prolong   1: the first ORAS sweep on a level after the coarse-to-
  *                  fine prolongation builds its tiles from the coarser
  *                  level's iterate and f (the prolongation is computed in
@@ -163,6 +176,7 @@ typedef struct ddi_params {
     int inner_sweeps;
     int method;
     int fuse_prolong;
+    int krylov_restart;
 } ddi_params;
 
 /*
@@ -206,7 +220,7 @@ typedef struct ddi_plan ddi_plan;
  * timing = 0, coarse_block = 0, coarse_overlap = -1, coarse_local_iters = 0,
  * local_tol = 0, use_graph = 0, coarse_solver = 0, coarse_cg_iters = 500,
  * coarse_cg_tol = 1e-10, storage = 0, inner_sweeps = 2, method = 0,
- * fuse_prolong = 1. */
+ * fuse_prolong = 1, krylov_restart = 8. */
 int ddi_default_params(ddi_params* p);
 
 /* Check *p for one image size without touching the GPU (this includes the

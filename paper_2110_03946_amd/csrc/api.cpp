@@ -106,6 +106,12 @@ size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm) {
     if (prm.method == 1)
         bytes += 4 * (size_t)C * h * w * sizeof(float) + (3 * (size_t)C + L * ((size_t)C + 2)) *
                                                              sizeof(double);
+    if (prm.method == 2) {
+        const size_t m = prm.krylov_restart;
+        bytes += (2 * m + 1) * (size_t)C * h * w * sizeof(float) + (size_t)C * sizeof(KryState) +
+                 ((m + 1) * C + 2 * (size_t)C) * sizeof(double) +
+                 (size_t)residual_partials(h, w) * (m + 1) * C * sizeof(double);
+    }
     if (prm.timing) {
         const SweepArgs a0 = make_sweep(h, w, C, prm.block, prm.overlap, prm.robin_alpha, 1);
         bytes += (size_t)sweep_partials(a0) * C * sizeof(double);
@@ -165,6 +171,7 @@ int ddi_default_params(ddi_params* p) {
     p->inner_sweeps = 2;
     p->method = 0;
     p->fuse_prolong = 1;
+    p->krylov_restart = 8;
     return DDI_OK;
 }
 
@@ -193,8 +200,9 @@ int ddi_check_params(int height, int width, int channels, const ddi_params* p) {
     if (p->coarse_cg_iters < 1 || !(p->coarse_cg_tol >= 0.0)) return DDI_EINVAL;
     if (p->storage != 0 && p->storage != 1) return DDI_EINVAL;
     if (p->inner_sweeps < 1) return DDI_EINVAL;
-    if (p->method != 0 && p->method != 1) return DDI_EINVAL;
-    if (p->method == 1 && p->storage != 0) return DDI_EINVAL;
+    if (p->method < 0 || p->method > 2) return DDI_EINVAL;
+    if (p->method != 0 && p->storage != 0) return DDI_EINVAL;
+    if (p->krylov_restart < 1 || p->krylov_restart > kKryMaxM) return DDI_EINVAL;
     if (p->fuse_prolong != 0 && p->fuse_prolong != 1) return DDI_EINVAL;
     if (p->coarse_solver == 1) {
         int hl = height, wl = width;
@@ -219,6 +227,10 @@ int ddi_destroy(ddi_plan* plan) {
     if (plan->r16) (void)hipFree(plan->r16);
     if (plan->cg_vec) (void)hipFree(plan->cg_vec);
     if (plan->cg_sc) (void)hipFree(plan->cg_sc);
+    if (plan->kry_vec) (void)hipFree(plan->kry_vec);
+    if (plan->kry_state) (void)hipFree(plan->kry_state);
+    if (plan->kry_sc) (void)hipFree(plan->kry_sc);
+    if (plan->kry_part) (void)hipFree(plan->kry_part);
     for (uint16_t* d : plan->d16)
         if (d) (void)hipFree(d);
     if (plan->part) (void)hipFree(plan->part);
@@ -347,6 +359,20 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
         }
         P->last_iters.assign(L, -1);
     }
+    if (prm.method == 2) {
+        const size_t m = prm.krylov_restart;
+        const size_t nv = (size_t)channels * height * width * sizeof(float);
+        if ((err = hipMalloc(&P->kry_vec, (2 * m + 1) * nv)) != hipSuccess ||
+            (err = hipMalloc(&P->kry_state, (size_t)channels * sizeof(KryState))) !=
+                hipSuccess ||
+            (err = hipMalloc(&P->kry_sc, ((m + 1) * channels + 2 * (size_t)channels) *
+                                             sizeof(double))) != hipSuccess ||
+            (err = hipMalloc(&P->kry_part, (size_t)residual_partials(height, width) * (m + 1) *
+                                               channels * sizeof(double))) != hipSuccess) {
+            ddi_destroy(P);
+            return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
+        }
+    }
     if (prm.use_graph && !prm.timing && prm.storage == 0 && prm.method == 0) {
         // a stream of our own (default priority): the caller's may be the
         // legacy default stream, which cannot be captured
@@ -423,6 +449,12 @@ static double rel_from_host(const ddi_plan* P, const double* rsq) {
 // above it directly; fuse_l0 extends that to the finest level, whose
 // prolongation is then left to enqueue_sweeps (P->pro0).
 static int enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0) {
+    return plan_enqueue_front(P, start0, s, fuse_l0);
+}
+
+}  // extern "C"
+
+int plan_enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0) {
     const int C = P->C;
     const int L = (int)P->lv.size();
     const ddi_params& prm = P->p;
@@ -497,6 +529,8 @@ static int enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0) {
     }
     return DDI_OK;
 }
+
+extern "C" {
 
 static bool is_check(const ddi_params& prm, int n) {
     return n >= prm.min_sweeps && (n - prm.min_sweeps) % prm.check_every == 0;
@@ -855,13 +889,15 @@ static int finish_solve(ddi_plan* P, ddi_stats* st) {
 int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats* st) {
     if (!P || !f || !c || !u) return DDI_EINVAL;
     if (P->pend.active) return DDI_EINVAL;
-    if (P->p.storage == 1 || P->p.method == 1) {
+    if (P->p.storage == 1 || P->p.method != 0) {
         Level& L0 = P->lv[0];
         L0.f = f;
         L0.c = c;
         L0.u[0] = u;
         if (st) std::memset(st, 0, sizeof(*st));
-        return P->p.method == 1 ? solve_mlcg(P, st) : solve_refine(P, f, c, u, st);
+        if (P->p.method == 1) return solve_mlcg(P, st);
+        if (P->p.method == 2) return solve_krylov(P, st);
+        return solve_refine(P, f, c, u, st);
     }
     int e = begin_solve(P, f, c, u);
     if (e) {

@@ -30,6 +30,22 @@ struct SweepArgs {
 // The coarse level a first sweep prolongs from (the bilinear prolongation
 // of Sec. 4 fused into the tile load): the coarse iterate (hc x wc per
 // channel) and the fine level's data and mask, the known pixels taking f.
+// Largest restart length of the Krylov method (method = 2).
+constexpr int kKryMaxM = 16;
+
+// Per-channel state of a Krylov cycle (device memory): the rotated
+// Hessenberg matrix R (column j at R[j * (kKryMaxM + 1)]), the Givens
+// rotations, the right-hand side g of the least-squares problem and its
+// solution y, ||b||^2, and the steps taken in the cycle.
+struct KryState {
+    double R[kKryMaxM * (kKryMaxM + 1)];
+    double cs[kKryMaxM], sn[kKryMaxM];
+    double g[kKryMaxM + 1];
+    double y[kKryMaxM];
+    double bnorm2;
+    int steps, pad;
+};
+
 struct ProSrc {
     const float* uc;
     int hc, wc;
@@ -259,6 +275,34 @@ int init_grid(int h, int w);
 int mask_bits_grid(int h, int w, int* gx);
 
 // ---- bfloat16 storage with float32 iterative refinement ----
+
+// ---- Krylov-accelerated ORAS (method = 2) ----
+// w = A z and (w, v_i) for i < nv (v_i = V + i * vstride): partials
+// [wg][i][C] over residual_partials(h, w) workgroups.
+hipError_t launch_kry_matvec_dots(const float* z, const uint8_t* c, int h, int w, int channels,
+                                  float* wout, const float* V, int64_t vstride, int nv,
+                                  double* partial, const int* ctl, hipStream_t s);
+// w -= sum_i hcol[i * C + ch] v_i; partials [wg][C] of ||w||^2.
+hipError_t launch_kry_orth(float* wv, const float* V, int64_t vstride, int nv,
+                           const double* hcol, int h, int w, int channels, double* partial,
+                           const int* ctl, hipStream_t s);
+// dst = src / sqrt(norm2[ch]) (skipped after convergence unless force).
+hipError_t launch_kry_scale(const float* src, float* dst, const double* norm2, int64_t n,
+                            int channels, const int* ctl, bool force, hipStream_t s);
+hipError_t launch_kry_start(KryState* st, const double* beta2, const double* b2, int channels,
+                            int* ctl, double tol2, int total, hipStream_t s);
+hipError_t launch_kry_givens(KryState* st, const double* hcol, const double* hn2, int j,
+                             int channels, int* ctl, double tol2, int total, hipStream_t s);
+hipError_t launch_kry_backsolve(KryState* st, int channels, hipStream_t s);
+hipError_t launch_kry_combine(float* u, const float* Z, int64_t zstride, const KryState* st,
+                              int64_t n, int channels, hipStream_t s);
+
+// One ORAS sweep of the correction equation A d = rhs with d and rhs in
+// float32 (din == nullptr: d = 0; d = 0 on the mask): the preconditioner of
+// the Krylov method. Otherwise as launch_sweep.
+hipError_t launch_sweep_c32(const float* din, const float* rhs, const uint64_t* mbits,
+                            float* dout, double* partial, double* cg_steps, const int* ctl,
+                            const SweepArgs& a, hipStream_t s);
 
 // One ORAS sweep of the refinement equation A d = rhs (d = 0 on the mask):
 // din, rhs, dout bfloat16 planes like u (din == nullptr: d = 0); float32

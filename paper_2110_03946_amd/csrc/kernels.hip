@@ -181,9 +181,11 @@ constexpr int kTileW = kMaxBlock + 2;
 // stored in bfloat16); the block residual is rhs - A d = rhs + L d on
 // unknown pixels. uin == nullptr stands for d = 0. Arithmetic is float32 in
 // both cases; only the loads widen and the stores narrow.
-template <int RPW, bool RAGGED, bool QLDS, bool MBITS, bool CORR = false>
+// CORR and F32: the same correction equation with d and rhs in float32 (the
+// preconditioner of the Krylov method).
+template <int RPW, bool RAGGED, bool QLDS, bool MBITS, bool CORR = false, bool F32 = false>
 __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
-                                           const uint16_t* __restrict__ rhs,
+                                           const void* __restrict__ rhs,
                                            const uint64_t* __restrict__ mbits,
                                            void* __restrict__ uout_v,
                                            double* __restrict__ partial,
@@ -211,7 +213,9 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
 
     const float* __restrict__ U = CORR ? nullptr : (const float*)uin_v + ch * a.cpitch;
     const uint16_t* __restrict__ U16 =
-        CORR && uin_v ? (const uint16_t*)uin_v + ch * a.cpitch : nullptr;
+        CORR && !F32 && uin_v ? (const uint16_t*)uin_v + ch * a.cpitch : nullptr;
+    const float* __restrict__ UF = CORR && F32 && uin_v ? (const float*)uin_v + ch * a.cpitch
+                                                        : nullptr;
     const bool on = lane < g.bw;
     const int x = x0 + lane;
     const int nrows = RAGGED ? g.bh : RPW;
@@ -275,6 +279,11 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
     };
     if constexpr (!CORR) {
         stage([&](uint32_t i) { return U[i]; });
+    } else if constexpr (F32) {
+        if (UF)
+            stage([&](uint32_t i) { return UF[i]; });
+        else
+            stage([](uint32_t) { return 0.f; });
     } else {
         if (U16)
             stage([&](uint32_t i) { return bf16_to_f(U16[i]); });
@@ -307,7 +316,11 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
         float uup = col[0];
         float uy = col[TW];
         const uint16_t* R16 = nullptr;
-        if constexpr (CORR) R16 = rhs + ch * a.cpitch + (uint32_t)(on ? x : x0);
+        const float* RF = nullptr;
+        if constexpr (CORR && !F32)
+            R16 = (const uint16_t*)rhs + ch * a.cpitch + (uint32_t)(on ? x : x0);
+        if constexpr (CORR && F32)
+            RF = (const float*)rhs + ch * a.cpitch + (uint32_t)(on ? x : x0);
 #pragma unroll
         for (int y = 0; y < RPW; ++y) {
             const float udn = col[(y + 2) * TW];
@@ -316,7 +329,10 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
             float lap = ((uup - uy) + (udn - uy)) + ((ul - uy) + (ur - uy));
             if constexpr (CORR) {
                 const uint32_t yy = RAGGED ? min(y0 + y, g.h - 1) : y0 + y;
-                lap = bf16_to_f(R16[yy * (uint32_t)g.w]) + lap;
+                if constexpr (F32)
+                    lap = RF[yy * (uint32_t)g.w] + lap;
+                else
+                    lap = bf16_to_f(R16[yy * (uint32_t)g.w]) + lap;
             }
             const float ry = mask_keep(y < 32 ? mlo : mhi, y & 31, lap);
             r[y] = ry;
@@ -434,7 +450,7 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
     // ---- restricted prolongation: u_out = u_in + v on owned pixels (eq. 9)
     if (on && x >= oxlo && x < oxhi) {
         uint32_t off = (uint32_t)y0 * (uint32_t)g.w + (uint32_t)x;
-        if constexpr (!CORR) {
+        if constexpr (!CORR || F32) {
             float* __restrict__ UO = (float*)uout_v + ch * a.cpitch;
 #pragma unroll
             for (int y = 0; y < RPW; ++y) {
@@ -729,9 +745,9 @@ __device__ __forceinline__ void tile2_store(const Tile2& T, const SweepArgs& a,
 // Residual, local CG and owned write-back of one split block whose tile is
 // in LDS (staged and followed by a barrier). QL: q parked in the wave's half
 // of the tile.
-template <bool CORR, bool QL>
+template <bool CORR, bool QL, bool F32 = false>
 __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
-                                               const uint16_t* __restrict__ rhs,
+                                               const void* __restrict__ rhs,
                                                void* __restrict__ uout_v,
                                                double* __restrict__ partial,
                                                double* __restrict__ cg_steps,
@@ -758,7 +774,9 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
         float uup = col[0];
         float uy = col[TW];
         const uint16_t* R16 = nullptr;
-        if constexpr (CORR) R16 = rhs + k.ch * a.cpitch;
+        const float* RF = nullptr;
+        if constexpr (CORR && !F32) R16 = (const uint16_t*)rhs + k.ch * a.cpitch;
+        if constexpr (CORR && F32) RF = (const float*)rhs + k.ch * a.cpitch;
         uint32_t roff = (uint32_t)ry0 * (uint32_t)g.w + (uint32_t)(on ? x : k.x0);
 #pragma unroll
         for (int y = 0; y < RPW; ++y) {
@@ -767,7 +785,10 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
             const float ur = col[(y + 1) * TW + 1];
             float lap = ((uup - uy) + (udn - uy)) + ((ul - uy) + (ur - uy));
             if constexpr (CORR) {
-                lap = bf16_to_f(at32(R16, roff)) + lap;
+                if constexpr (F32)
+                    lap = at32(RF, roff) + lap;
+                else
+                    lap = bf16_to_f(at32(R16, roff)) + lap;
                 roff += (uint32_t)g.w;
             }
             const float ry = mask_bfe(mw, y, lap);
@@ -881,7 +902,7 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
     if (on && x >= k.oxlo && x < k.oxhi) {
         const int ylo = k.oylo - ry0, yhi = k.oyhi - ry0;
         uint32_t off = (uint32_t)ry0 * (uint32_t)g.w + (uint32_t)x;
-        if constexpr (!CORR) {
+        if constexpr (!CORR || F32) {
             float* __restrict__ UO = (float*)uout_v + k.ch * a.cpitch;
 #pragma unroll
             for (int y = 0; y < RPW; ++y) {
@@ -901,9 +922,9 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
 
 // One split block (tile loaded, stored, computed). PRO: the input iterate
 // is the prolongation of pro (uin_v unused).
-template <bool CORR, bool QL, bool PRO = false>
+template <bool CORR, bool QL, bool PRO = false, bool F32 = false>
 __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
-                                            const uint16_t* __restrict__ rhs,
+                                            const void* __restrict__ rhs,
                                             const uint64_t* __restrict__ mbits,
                                             void* __restrict__ uout_v,
                                             double* __restrict__ partial,
@@ -918,6 +939,12 @@ __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
         tile2_load_prolong(T, k, a, mbits, *pro);
     } else if constexpr (!CORR) {
         tile2_load(T, k, a, mbits, LoadF32{(const float*)uin_v + k.ch * a.cpitch});
+    } else if constexpr (F32) {
+        const float* UF = (const float*)uin_v;
+        if (UF)
+            tile2_load(T, k, a, mbits, LoadF32{UF + k.ch * a.cpitch});
+        else
+            tile2_load(T, k, a, mbits, LoadZero{});
     } else {
         const uint16_t* U16 = (const uint16_t*)uin_v;
         if (U16)
@@ -928,7 +955,7 @@ __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
     tile2_store(T, a, lds);
     const uint32_t mw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) ? T.mhi : T.mlo;
     __syncthreads();
-    sweep2_compute<CORR, QL>(k, mw, rhs, uout_v, partial, cg_steps, a, lds);
+    sweep2_compute<CORR, QL, F32>(k, mw, rhs, uout_v, partial, cg_steps, a, lds);
 }
 
 #ifndef DDI_SPLIT_QL
@@ -996,6 +1023,32 @@ __global__ __launch_bounds__(64) void k_sweep_corr(const uint16_t* __restrict__ 
     __shared__ __attribute__((aligned(16))) float lds[(RPW + 2) * kTileW];
     sweep_body<RPW, RAGGED, QLDS, MBITS, true>(din, rhs, mbits, dout, partial, cg_steps, ctl, a,
                                                xcd_remap(blockIdx.x, gridDim.x), lds);
+}
+
+// One sweep of the correction equation A d = rhs with d and rhs in float32
+// (din == nullptr: d = 0): the ORAS preconditioner of the Krylov method.
+template <int RPW, bool RAGGED, bool QLDS, bool MBITS>
+__global__ __launch_bounds__(64) void k_sweep_c32(const float* __restrict__ din,
+                                                  const float* __restrict__ rhs,
+                                                  const uint64_t* __restrict__ mbits,
+                                                  float* __restrict__ dout,
+                                                  double* __restrict__ partial,
+                                                  double* __restrict__ cg_steps,
+                                                  const int* __restrict__ ctl, SweepArgs a) {
+    __shared__ __attribute__((aligned(16))) float lds[(RPW + 2) * kTileW];
+    sweep_body<RPW, RAGGED, QLDS, MBITS, true, true>(din, rhs, mbits, dout, partial, cg_steps,
+                                                     ctl, a, xcd_remap(blockIdx.x, gridDim.x),
+                                                     lds);
+}
+
+// Split (two-wave) variant for full 64-row blocks.
+__global__ __launch_bounds__(128, DDI_SPLIT_WAVES) void k_sweep2_c32(
+    const float* __restrict__ din, const float* __restrict__ rhs,
+    const uint64_t* __restrict__ mbits, float* __restrict__ dout, double* __restrict__ partial,
+    double* __restrict__ cg_steps, const int* __restrict__ ctl, SweepArgs a) {
+    __shared__ __attribute__((aligned(16))) float lds[kSplitLds];
+    sweep2_body<true, DDI_SPLIT_QL, false, true>(din, rhs, mbits, dout, partial, cg_steps, ctl,
+                                                 a, xcd_remap(blockIdx.x, gridDim.x), lds);
 }
 
 // Index of the job whose workgroup range holds logical workgroup lb (jobs
@@ -1861,6 +1914,239 @@ __global__ __launch_bounds__(kDecideTpb) void k_cg_scalars(const double* __restr
 }
 
 // ---------------------------------------------------------------------------
+// Krylov-accelerated ORAS: flexible GMRES(m) on A u = b per channel, each
+// basis vector v_j preconditioned by one ORAS sweep on the correction
+// equation (z_j = k_sweep*_c32 from d = 0), classical Gram-Schmidt, the
+// Hessenberg least-squares problem updated by Givens rotations on the device.
+// ---------------------------------------------------------------------------
+
+// Workgroup sum of acc into *dst (fixed order), column-walk workgroups.
+__device__ __forceinline__ void walk_sum_to(double acc, double* __restrict__ dst) {
+    acc = wave_sum_d(acc);
+    __shared__ double sm[kWalkWaves];
+    __syncthreads();  // an earlier call's readers are done
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < kWalkWaves; ++j) t += sm[j];
+        *dst = t;
+    }
+}
+
+// w = A z (eq. 6; 0 on the mask, where z vanishes) and the dot products
+// (w, v_i) for i < nv: partial[(wg * nv + i) * C + ch], wg = workgroup of
+// the column walk.
+__global__ __launch_bounds__(64 * kWalkWaves) void k_kry_matvec_dots(
+    const float* __restrict__ z, const uint8_t* __restrict__ c, int h, int w, int channels,
+    float* __restrict__ wout, const float* __restrict__ V, int64_t vstride, int nv,
+    double* __restrict__ partial, const int* __restrict__ ctl) {
+    constexpr int R = kWalkRows;
+    if (ctl[0] != 0) return;
+    const Walk k = walk_geom(h, w);
+    const int ch = blockIdx.z;
+    const int64_t n = (int64_t)h * w;
+    const uint32_t W = w;
+    const float* __restrict__ Z = z + ch * n;
+    float v[R + 2], e[R];
+    uint32_t cm[R];
+#pragma unroll
+    for (int t = 0; t < R + 2; ++t)
+        v[t] = at32(Z, (uint32_t)min(max(k.y0 - 1 + t, 0), h - 1) * W + k.xc);
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const uint32_t row = (uint32_t)min(k.y0 + t, h - 1) * W;
+        cm[t] = at32(c, row + k.xc);
+        e[t] = k.edge ? at32(Z, row + k.xe) : 0.f;
+    }
+    const int nr = k.y1 - k.y0;
+    float wv[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const float cur = v[t + 1];
+        float lft = from_left(cur), rgt = from_right(cur);
+        if (k.lane == 0) lft = e[t];
+        if (k.lane == 63) rgt = e[t];
+        if (k.x == 0) lft = cur;
+        if (k.x + 1 >= w) rgt = cur;
+        const float q =
+            cm[t] == 0 ? ((cur - v[t]) + (cur - v[t + 2])) + ((cur - lft) + (cur - rgt)) : 0.f;
+        wv[t] = q;
+        if (k.inb && t < nr) put32(wout + ch * n, (uint32_t)(k.y0 + t) * W + k.xc, q);
+    }
+    const int64_t wg = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    for (int i = 0; i < nv; ++i) {
+        const float* __restrict__ Vi = V + i * vstride + ch * n;
+        double acc = 0.0;
+        if (k.inb) {
+#pragma unroll
+            for (int t = 0; t < R; ++t)
+                if (t < nr) acc += (double)wv[t] * (double)at32(Vi, (uint32_t)(k.y0 + t) * W + k.xc);
+        }
+        walk_sum_to(acc, partial + (wg * nv + i) * channels + ch);
+    }
+}
+
+// w -= sum_{i < nv} h_i v_i with h_i = hcol[i * C + ch] (rounded to float32),
+// partial[wg * C + ch] = ||w||^2.
+__global__ __launch_bounds__(64 * kWalkWaves) void k_kry_orth(
+    float* __restrict__ wv, const float* __restrict__ V, int64_t vstride, int nv,
+    const double* __restrict__ hcol, int h, int w, int channels, double* __restrict__ partial,
+    const int* __restrict__ ctl) {
+    constexpr int R = kWalkRows;
+    if (ctl[0] != 0) return;
+    const Walk k = walk_geom(h, w);
+    const int ch = blockIdx.z;
+    const int64_t n = (int64_t)h * w;
+    const uint32_t W = w;
+    float* __restrict__ Wp = wv + ch * n;
+    const int nr = k.y1 - k.y0;
+    double acc = 0.0;
+    if (k.inb) {
+        float x[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) x[t] = at32(Wp, (uint32_t)min(k.y0 + t, h - 1) * W + k.xc);
+        for (int i = 0; i < nv; ++i) {
+            const float hi = (float)hcol[i * channels + ch];
+            const float* __restrict__ Vi = V + i * vstride + ch * n;
+#pragma unroll
+            for (int t = 0; t < R; ++t)
+                x[t] -= hi * at32(Vi, (uint32_t)min(k.y0 + t, h - 1) * W + k.xc);
+        }
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            if (t < nr) {
+                put32(Wp, (uint32_t)(k.y0 + t) * W + k.xc, x[t]);
+                acc += (double)x[t] * (double)x[t];
+            }
+        }
+    }
+    walk_partial(acc, partial, channels);
+}
+
+// dst = src / sqrt(norm2[ch]) per channel (0 where the norm is 0); skipped
+// once the solve has converged unless force.
+__global__ __launch_bounds__(256) void k_kry_scale(const float* __restrict__ src,
+                                                   float* __restrict__ dst,
+                                                   const double* __restrict__ norm2, int64_t n,
+                                                   const int* __restrict__ ctl, int force) {
+    if (!force && ctl[0] != 0) return;
+    const int ch = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double s2 = norm2[ch];
+    const float inv = s2 > 0.0 ? (float)(1.0 / sqrt(s2)) : 0.f;
+    dst[ch * n + i] = src[ch * n + i] * inv;
+}
+
+// Cycle start: beta = ||r|| per channel (beta2 = ||r||^2), g = beta e_1;
+// the stop test on the residual of the current u.
+template <int NC>
+__global__ __launch_bounds__(64) void k_kry_start(KryState* __restrict__ st,
+                                                  const double* __restrict__ beta2,
+                                                  const double* __restrict__ b2,
+                                                  int* __restrict__ ctl, double tol2, int total) {
+    if (ctl[0] != 0) return;
+    __shared__ double q[NC];
+    const int ch = threadIdx.x;
+    if (ch < NC) {
+        KryState& S = st[ch];
+        S.bnorm2 = b2[ch];
+        S.steps = 0;
+        for (int i = 0; i <= kKryMaxM; ++i) S.g[i] = 0.0;
+        S.g[0] = sqrt(fmax(beta2[ch], 0.0));
+        q[ch] = b2[ch] > 0.0 ? beta2[ch] / b2[ch] : (beta2[ch] > 0.0 ? INFINITY : 0.0);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double worst = 0.0;
+        for (int k = 0; k < NC; ++k) worst = fmax(worst, q[k]);
+        reinterpret_cast<double*>(ctl + 4)[0] = worst;
+        if (worst <= tol2) {
+            ctl[1] = total;
+            ctl[0] = 1;
+        }
+    }
+}
+
+// Step j of the cycle: the new Hessenberg column (dots hcol[i * C + ch],
+// i <= j, and sqrt(hn2[ch]) below the diagonal), the earlier rotations
+// applied to it, a new rotation that zeroes the subdiagonal, and the
+// least-squares residual |g_{j+1}|; the stop test (sets ctl[0] with ctl[1]
+// = total + j + 1 once max_k g_{j+1}^2 / ||b_k||^2 <= tol2).
+template <int NC>
+__global__ __launch_bounds__(64) void k_kry_givens(KryState* __restrict__ st,
+                                                   const double* __restrict__ hcol,
+                                                   const double* __restrict__ hn2, int j,
+                                                   int* __restrict__ ctl, double tol2,
+                                                   int total) {
+    if (ctl[0] != 0) return;
+    __shared__ double q[NC];
+    const int ch = threadIdx.x;
+    if (ch < NC) {
+        KryState& S = st[ch];
+        double* col = S.R + j * (kKryMaxM + 1);
+        for (int i = 0; i <= j; ++i) col[i] = hcol[i * NC + ch];
+        double sub = sqrt(fmax(hn2[ch], 0.0));
+        for (int i = 0; i < j; ++i) {
+            const double a = col[i], b = col[i + 1];
+            col[i] = S.cs[i] * a + S.sn[i] * b;
+            col[i + 1] = -S.sn[i] * a + S.cs[i] * b;
+        }
+        const double r = sqrt(col[j] * col[j] + sub * sub);
+        const double cs = r > 0.0 ? col[j] / r : 1.0, sn = r > 0.0 ? sub / r : 0.0;
+        S.cs[j] = cs;
+        S.sn[j] = sn;
+        col[j] = r > 0.0 ? r : col[j];
+        S.g[j + 1] = -sn * S.g[j];
+        S.g[j] = cs * S.g[j];
+        S.steps = j + 1;
+        const double res2 = S.g[j + 1] * S.g[j + 1];
+        q[ch] = S.bnorm2 > 0.0 ? res2 / S.bnorm2 : (res2 > 0.0 ? INFINITY : 0.0);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double worst = 0.0;
+        for (int k = 0; k < NC; ++k) worst = fmax(worst, q[k]);
+        reinterpret_cast<double*>(ctl + 4)[0] = worst;
+        if (worst <= tol2) {
+            ctl[1] = total + j + 1;
+            ctl[0] = 1;
+        }
+    }
+}
+
+// y = R^-1 g over the cycle's steps (back substitution; a zero pivot gives
+// y_i = 0), one thread per channel.
+template <int NC>
+__global__ __launch_bounds__(64) void k_kry_backsolve(KryState* __restrict__ st) {
+    const int ch = threadIdx.x;
+    if (ch >= NC) return;
+    KryState& S = st[ch];
+    for (int i = S.steps - 1; i >= 0; --i) {
+        double t = S.g[i];
+        for (int l = i + 1; l < S.steps; ++l) t -= S.R[l * (kKryMaxM + 1) + i] * S.y[l];
+        const double d = S.R[i * (kKryMaxM + 1) + i];
+        S.y[i] = d != 0.0 ? t / d : 0.0;
+    }
+}
+
+// u += sum_{i < steps} y_i z_i per channel (z_i vanish on the mask, so u = f
+// there is kept exactly).
+__global__ __launch_bounds__(256) void k_kry_combine(float* __restrict__ u,
+                                                     const float* __restrict__ Z, int64_t zstride,
+                                                     const KryState* __restrict__ st, int64_t n) {
+    const int ch = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const KryState& S = st[ch];
+    float x = u[ch * n + i];
+    for (int l = 0; l < S.steps; ++l) x += (float)S.y[l] * Z[l * zstride + ch * n + i];
+    u[ch * n + i] = x;
+}
+
+// ---------------------------------------------------------------------------
 // Float64 solve of the coarsest level (Sec. 2 system, eq. 6, on the coarse
 // grid): conjugate gradients on the unknown pixels, known pixels fixed at
 // their value, in one workgroup per channel. Thread t owns pixels t,
@@ -2050,6 +2336,104 @@ static hipError_t sweep_corr_rpw(const uint16_t* din, const uint16_t* rhs,
     else
         hipLaunchKernelGGL((k_sweep_corr<RPW, true, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
                            din, rhs, mbits, dout, partial, cg_steps, ctl, a);
+    return hipGetLastError();
+}
+
+template <int RPW, bool QLDS, bool MBITS>
+static hipError_t sweep_c32_rpw(const float* din, const float* rhs, const uint64_t* mbits,
+                                float* dout, double* partial, double* cg_steps, const int* ctl,
+                                const SweepArgs& a, hipStream_t s) {
+    const int grid = a.g.nby * a.g.nbx * a.channels;
+    if (use_split(a)) {
+        hipLaunchKernelGGL(k_sweep2_c32, dim3(grid), dim3(128), 0, s, din, rhs, mbits, dout,
+                           partial, cg_steps, ctl, a);
+        return hipGetLastError();
+    }
+    if (a.g.bh == RPW)
+        hipLaunchKernelGGL((k_sweep_c32<RPW, false, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
+                           din, rhs, mbits, dout, partial, cg_steps, ctl, a);
+    else
+        hipLaunchKernelGGL((k_sweep_c32<RPW, true, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
+                           din, rhs, mbits, dout, partial, cg_steps, ctl, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_c32(const float* din, const float* rhs, const uint64_t* mbits,
+                            float* dout, double* partial, double* cg_steps, const int* ctl,
+                            const SweepArgs& a, hipStream_t s) {
+    const int bh = a.g.bh;
+    if (a.g.bw < 1 || a.g.bw > kMaxBlock || bh < 1 || bh > kMaxBlock) return hipErrorInvalidValue;
+    if (bh > 32)
+        return sweep_c32_rpw<64, true, true>(din, rhs, mbits, dout, partial, cg_steps, ctl, a, s);
+    if (bh > 16)
+        return sweep_c32_rpw<32, false, false>(din, rhs, mbits, dout, partial, cg_steps, ctl, a,
+                                               s);
+    if (bh > 8)
+        return sweep_c32_rpw<16, false, false>(din, rhs, mbits, dout, partial, cg_steps, ctl, a,
+                                               s);
+    return sweep_c32_rpw<8, false, false>(din, rhs, mbits, dout, partial, cg_steps, ctl, a, s);
+}
+
+static dim3 walk_grid(int h, int w, int channels);
+
+hipError_t launch_kry_matvec_dots(const float* z, const uint8_t* c, int h, int w, int channels,
+                                  float* wout, const float* V, int64_t vstride, int nv,
+                                  double* partial, const int* ctl, hipStream_t s) {
+    if (nv < 1 || nv > kKryMaxM + 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_kry_matvec_dots, walk_grid(h, w, channels), dim3(64 * kWalkWaves), 0, s,
+                       z, c, h, w, channels, wout, V, vstride, nv, partial, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_kry_orth(float* wv, const float* V, int64_t vstride, int nv,
+                           const double* hcol, int h, int w, int channels, double* partial,
+                           const int* ctl, hipStream_t s) {
+    if (nv < 1 || nv > kKryMaxM + 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_kry_orth, walk_grid(h, w, channels), dim3(64 * kWalkWaves), 0, s, wv, V,
+                       vstride, nv, hcol, h, w, channels, partial, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_kry_scale(const float* src, float* dst, const double* norm2, int64_t n,
+                            int channels, const int* ctl, bool force, hipStream_t s) {
+    dim3 grid((unsigned)((n + 255) / 256), channels);
+    hipLaunchKernelGGL(k_kry_scale, grid, dim3(256), 0, s, src, dst, norm2, n, ctl,
+                       force ? 1 : 0);
+    return hipGetLastError();
+}
+
+#define DDI_KRY_NC(KERNEL, ...)                                                              \
+    switch (channels) {                                                                      \
+        case 1: hipLaunchKernelGGL(KERNEL<1>, dim3(1), dim3(64), 0, s, __VA_ARGS__); break; \
+        case 2: hipLaunchKernelGGL(KERNEL<2>, dim3(1), dim3(64), 0, s, __VA_ARGS__); break; \
+        case 3: hipLaunchKernelGGL(KERNEL<3>, dim3(1), dim3(64), 0, s, __VA_ARGS__); break; \
+        case 4: hipLaunchKernelGGL(KERNEL<4>, dim3(1), dim3(64), 0, s, __VA_ARGS__); break; \
+        default: return hipErrorInvalidValue;                                                \
+    }
+
+hipError_t launch_kry_start(KryState* st, const double* beta2, const double* b2, int channels,
+                            int* ctl, double tol2, int total, hipStream_t s) {
+    DDI_KRY_NC(k_kry_start, st, beta2, b2, ctl, tol2, total)
+    return hipGetLastError();
+}
+
+hipError_t launch_kry_givens(KryState* st, const double* hcol, const double* hn2, int j,
+                             int channels, int* ctl, double tol2, int total, hipStream_t s) {
+    if (j < 0 || j >= kKryMaxM) return hipErrorInvalidValue;
+    DDI_KRY_NC(k_kry_givens, st, hcol, hn2, j, ctl, tol2, total)
+    return hipGetLastError();
+}
+
+hipError_t launch_kry_backsolve(KryState* st, int channels, hipStream_t s) {
+    DDI_KRY_NC(k_kry_backsolve, st)
+    return hipGetLastError();
+}
+#undef DDI_KRY_NC
+
+hipError_t launch_kry_combine(float* u, const float* Z, int64_t zstride, const KryState* st,
+                              int64_t n, int channels, hipStream_t s) {
+    dim3 grid((unsigned)((n + 255) / 256), channels);
+    hipLaunchKernelGGL(k_kry_combine, grid, dim3(256), 0, s, u, Z, zstride, st, n);
     return hipGetLastError();
 }
 

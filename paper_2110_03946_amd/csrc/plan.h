@@ -101,6 +101,14 @@ struct ddi_plan {
     float* cg_vec = nullptr;
     double* cg_sc = nullptr;
     std::vector<int> last_iters;
+    // method = 2 (Krylov-accelerated ORAS): the basis V_0..V_m and the
+    // preconditioned vectors Z_0..Z_{m-1} (finest-level planes), the
+    // per-channel cycle state, scalars [hcol (m+1) x C][hn2 C][beta2 C], and
+    // the dot-product partials [wg][m+1][C]
+    float* kry_vec = nullptr;
+    ddi::KryState* kry_state = nullptr;
+    double* kry_sc = nullptr;
+    double* kry_part = nullptr;
     // the finest level's first sweep of the solve being enqueued prolongs
     // from this source (fuse_prolong)
     ddi::ProSrc pro0{};
@@ -109,3 +117,8 @@ struct ddi_plan {
 
 // Multilevel CG solve (mlcg.cpp); the level-0 pointers are set.
 int solve_mlcg(ddi_plan* P, ddi_stats* st);
+// Krylov-accelerated ORAS solve (krylov.cpp); the level-0 pointers are set.
+int solve_krylov(ddi_plan* P, ddi_stats* st);
+// Pyramid, statistics, transposed masks, coarsest level and coarse-to-fine
+// passes down to the finest level's start in buffer start0 (api.cpp).
+int plan_enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0);

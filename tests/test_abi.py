@@ -31,7 +31,8 @@ def test_default_params_valid():
     ("block", 1), ("block", 65), ("overlap", -1), ("overlap", 64), ("levels", 0),
     ("local_iters", 0), ("robin_alpha", 0.0), ("robin_alpha", 1.5),
     ("coarse_sweeps", -1), ("rel_tol", -1.0), ("check_every", 0), ("max_sweeps", 1),
-    ("fuse_prolong", 2), ("fuse_prolong", -1)])
+    ("fuse_prolong", 2), ("fuse_prolong", -1), ("method", 3), ("krylov_restart", 0),
+    ("krylov_restart", 17)])
 def test_bad_params_rejected(field, value):
     p = ddi.default_params()
     setattr(p, field, value)
@@ -120,3 +121,11 @@ def test_plan_footprint():
     assert ddi.plan_footprint(64, 64, 1, q) < ddi.plan_footprint(64, 64, 1, ddi.default_params())
     with pytest.raises(ddi.DDIError):
         ddi.plan_footprint(0, 10, 1, p)
+
+
+def test_krylov_method_needs_float32_storage():
+    assert ddi.check_params(64, 64, 1, ddi.default_params(method=2)) == ddi.DDI_OK
+    assert ddi.check_params(64, 64, 1, ddi.default_params(method=2, storage=1)) == ddi.DDI_EINVAL
+    a = ddi.plan_footprint(540, 960, 3, ddi.default_params(levels=3))
+    b = ddi.plan_footprint(540, 960, 3, ddi.default_params(levels=3, method=2, krylov_restart=4))
+    assert b - a >= 9 * 3 * 540 * 960 * 4  # 2m + 1 = 9 finest-level vectors
