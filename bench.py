@@ -386,7 +386,15 @@ def run_ablation(args):
     for name, over in [("multilevel ORAS (alpha 0.25, 4 levels)", {}),
                        ("multilevel RAS (alpha 1)", dict(robin_alpha=1.0)),
                        ("single-level ORAS (alpha 0.25)", dict(levels=1)),
-                       ("single-level RAS (alpha 1)", dict(levels=1, robin_alpha=1.0))]:
+                       ("single-level RAS (alpha 1)", dict(levels=1, robin_alpha=1.0)),
+                       # Krylov acceleration (not in the paper): flexible GMRES(8) over
+                       # one ORAS sweep per step, after the same multilevel start
+                       ("Krylov-accelerated multilevel ORAS (FGMRES(8))",
+                        dict(method=2, krylov_restart=8)),
+                       ("Krylov-accelerated multilevel ORAS (FGMRES(8)), rel_tol 5e-5",
+                        dict(method=2, krylov_restart=8, rel_tol=5e-5)),
+                       ("Krylov-accelerated single-level ORAS (FGMRES(8))",
+                        dict(method=2, krylov_restart=8, levels=1))]:
         prm = dict(base, **over, max_sweeps=400, final_residual=1)
         with ddi.Plan(H, W, C, **prm) as plan:
             ms, st = timed_solves(plan, f, c, u, max(3, args.steps // 10))
@@ -395,7 +403,8 @@ def run_ablation(args):
                      "converged": st["converged"], "rel_residual": st["rel_residual"],
                      "max_dev_from_tight_solve_grey": round(err, 4)})
         print(f"[bench] {name}: {ms:.3f} ms, {st['sweeps']} sweeps", file=sys.stderr, flush=True)
-    out = {"metric": "4K RGB solve time to rel_tol 5e-4: ORAS vs RAS, multilevel vs single level",
+    out = {"metric": "4K RGB solve time to rel_tol 5e-4: ORAS vs RAS, multilevel vs single "
+                     "level, stationary vs Krylov-accelerated",
            "value": rows[0]["ms"], "unit": "ms", "higher_is_better": False, "n_gpus": 1,
            "data": "synthetic", "dtype": "f32",
            "config": {"workload": "4K RGB 3840x2160x3, 4% Bernoulli; each variant stops at the "
@@ -469,16 +478,24 @@ def run_scaling(args):
         for name, prm in [("oras", dict(base)),
                           ("mlcg", dict(base, method=1, max_sweeps=5000)),
                           ("mlcg_tight", dict(base, method=1, max_sweeps=5000,
-                                              rel_tol=base["rel_tol"] / 10))]:
+                                              rel_tol=base["rel_tol"] / 10)),
+                          ("krylov_oras", dict(base, method=2, krylov_restart=8,
+                                               max_sweeps=200)),
+                          ("krylov_oras_tight", dict(base, method=2, krylov_restart=8,
+                                                     max_sweeps=200,
+                                                     rel_tol=base["rel_tol"] / 10))]:
             with ddi.Plan(h, w, C, **prm) as plan:
                 ms, st = timed_solves(plan, f, c, u, 5)
             row[name] = {"ms": round(ms, 3), "ms_per_mpx": round(ms / (h * w / 1e6), 4),
                          "finest_iterations": st["sweeps"],
                          "max_dev_from_tight_solve_grey": round(float((u - ref).abs().max()), 4)}
-            if name != "oras":
+            if name.startswith("mlcg"):
                 row[name]["cg_steps_all_levels"] = st["cg_steps"]
         row["mlcg_over_oras"] = round(row["mlcg"]["ms"] / row["oras"]["ms"], 2)
         row["mlcg_tight_over_oras"] = round(row["mlcg_tight"]["ms"] / row["oras"]["ms"], 2)
+        row["krylov_over_oras"] = round(row["krylov_oras"]["ms"] / row["oras"]["ms"], 2)
+        row["krylov_tight_over_oras"] = round(row["krylov_oras_tight"]["ms"] / row["oras"]["ms"],
+                                              2)
         rows.append(row)
         print(f"[bench] {row}", file=sys.stderr, flush=True)
     out = {"metric": "solve time vs resolution: multilevel ORAS against multilevel CG",

@@ -130,8 +130,10 @@ extern "C" {
  *                  coarse-to-fine start, then flexible GMRES(krylov_restart)
  *                  on the finest level per channel, each basis vector
  *                  preconditioned by one ORAS sweep (block, overlap,
- *                  robin_alpha, local_iters, local_tol) on the correction
- *                  equation A d = v from d = 0; it stops once max_k
+ *                  robin_alpha, local_iters; local_tol, an absolute
+ *                  threshold, does not apply to the unit basis vectors) on
+ *                  the correction equation A d = v from d = 0; it stops once
+ *                  max_k
  *                  ||b - A u||/||b|| <= rel_tol (signalled by the
  *                  least-squares estimate, confirmed on the recomputed
  *                  residual). max_sweeps caps the Krylov steps (one

@@ -41,6 +41,11 @@ int solve_krylov(ddi_plan* P, ddi_stats* st) {
     int* ctl = P->ctl;
     const double tol2 = prm.rel_tol * prm.rel_tol;
     const int nres = residual_partials(h, w);
+    // the preconditioner's local CG runs its local_iters steps: the local
+    // stop is an absolute threshold on the block residual, which the unit
+    // basis vectors (entries ~ 1/sqrt(pixels)) would meet before any step
+    SweepArgs pre = L0.sw;
+    pre.local_tol2 = 0.f;
 
     DDI_HIP(hipEventRecord(P->e0, s));
     int e = plan_enqueue_front(P, 0, s, false);  // u = the coarse-to-fine start
@@ -62,7 +67,7 @@ int solve_krylov(ddi_plan* P, ddi_stats* st) {
             float* vj = V + j * vstride;
             float* zj = Z + j * vstride;
             float* vn = V + (j + 1) * vstride;
-            DDI_HIP(launch_sweep_c32(nullptr, vj, L0.mbits, zj, P->part, nullptr, ctl, L0.sw, s));
+            DDI_HIP(launch_sweep_c32(nullptr, vj, L0.mbits, zj, P->part, nullptr, ctl, pre, s));
             DDI_HIP(launch_kry_matvec_dots(zj, L0.c, h, w, C, vn, V, vstride, j + 1, P->kry_part,
                                            ctl, s));
             DDI_HIP(launch_reduce(P->kry_part, nres, (j + 1) * C, (j + 1) * C, hcol, s));

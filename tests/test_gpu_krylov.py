@@ -95,6 +95,9 @@ def test_krylov_step_count_matches_oracle(ddi, C, H, W, d, kind, S, o, alpha, k,
     (3, 300, 400, 0.04, "clustered", dict(levels=3, krylov_restart=2)),
     (1, 257, 333, 0.05, "bernoulli", dict(levels=3, block=32, krylov_restart=16)),
     (2, 61, 90, 0.1, "bernoulli", dict(levels=1, block=16, krylov_restart=3)),
+    # the benchmark's absolute local stop must not silence the preconditioner
+    # (its basis vectors have unit norm)
+    (3, 540, 960, 0.04, "bernoulli", dict(levels=4, local_tol=0.002)),
 ])
 def test_krylov_solve_matches_exact(ddi, C, H, W, d, kind, prm):
     f, c = synth.make_workload(H, W, C, d, kind, workload=92, index=H)
