@@ -66,6 +66,7 @@ sys.path.insert(0, ROOT)
 
 H, W, C = 2160, 3840, 3
 DENSITY = 0.04
+FRAMES_IN_FLIGHT = 4
 METRIC = "4K RGB frames/s at ≤0.5 grey-level err vs FP64; HBM GB/s frac; p99 ms"
 
 # MI355X (gfx950) figures used for the roofline.
@@ -212,6 +213,39 @@ def correction_bytes(m: int, refinements: int, h: int = H, w: int = W, ch: int =
     return refinements * per_step
 
 
+def concurrent_streams(n: int, candidates: int = 24) -> list:
+    """n torch streams (default priority) whose kernels run concurrently.
+
+    HIP maps streams onto a few hardware queues (GPU_MAX_HW_QUEUES, 4 by
+    default), and two streams on one queue execute one after the other;
+    which streams share a queue is not exposed. Candidates are probed: a
+    short single-thread spin kernel on the candidate and on every stream
+    already chosen takes one spin's time only if none of them share a
+    queue. Returns fewer than n streams if the candidates run out."""
+    import torch
+    spin = int(0.5e-3 * CLOCK_HZ)
+
+    def run(streams):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for st in streams:
+            with torch.cuda.stream(st):
+                torch.cuda._sleep(spin)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    pool = [torch.cuda.Stream() for _ in range(candidates)]
+    run(pool[:1])
+    one = min(run(pool[:1]) for _ in range(3))
+    chosen = [pool[0]]
+    for cand in pool[1:]:
+        if len(chosen) == n:
+            break
+        if min(run(chosen + [cand]) for _ in range(2)) < 1.5 * one:
+            chosen.append(cand)
+    return chosen
+
+
 def run_frame(args, workload: str):
     """One 4K RGB frame per step: the float32 path (4k) or the mixed-precision
     path (precision)."""
@@ -224,11 +258,17 @@ def run_frame(args, workload: str):
     c = torch.from_numpy(c_np).cuda()
     u = torch.empty_like(f)
     prm = precision_params() if precision else solver_params()
-    # two plans with a frame each in flight (float32 path): while the host
-    # waits for one plan's stop test, the other's solve is already queued,
-    # so the GPU does not idle between frames
-    nplans = 1 if precision else 2
-    plans = [ddi.Plan(H, W, C, timing=1, **prm) for _ in range(nplans)]
+    # several plans, each with a frame in flight on a stream of its own
+    # (float32 path): one frame's latency-bound kernels (coarse levels,
+    # stop tests, reductions) and the load phases of its sweeps run beside
+    # the other frames' sweeps, and the host's wait for one plan's stop test
+    # never leaves the GPU idle
+    nplans = 1 if precision else args.frames_in_flight
+    streams = concurrent_streams(nplans) if nplans > 1 else [None]
+    if len(streams) < nplans:
+        print(f"[bench] only {len(streams)} concurrent streams found", file=sys.stderr)
+        streams = [streams[i % len(streams)] for i in range(nplans)]
+    plans = [ddi.Plan(H, W, C, timing=1, stream=s, **prm) for s in streams]
     us = [u] + [torch.empty_like(f) for _ in range(nplans - 1)]
     plan = plans[0]
 
@@ -236,49 +276,59 @@ def run_frame(args, workload: str):
         for p, uu in zip(plans, us):
             p.solve(f, c, uu)
     torch.cuda.synchronize()
-    sweep_ms, nsweeps, sweeps_per_solve, rels, steps, refs = 0.0, 0, [], [], 0.0, 0
-    first_ms, first_steps, nfirst = 0.0, 0.0, 0
+    sweeps_per_solve, rels = [], []
+    acc = {"timed": dict.fromkeys(["sweep_ms", "nsweeps", "steps", "refs", "first_ms",
+                                   "first_steps", "nfirst"], 0.0)}
+    acc["isolated"] = dict(acc["timed"])
 
-    def account(st):
+    def account(st, a):
         # float32 storage: the first finest-level sweep of each solve is a
         # different kernel (it also computes the prolongation), accounted
         # on its own; the rest are the steady-state sweep kernel
-        nonlocal sweep_ms, nsweeps, steps, refs, first_ms, first_steps, nfirst
-        sweep_ms += st["sweep_ms"] - st["first_sweep_ms"]
-        steps += st["cg_steps"] - st["first_cg_steps"]
-        nsweeps += st["sweeps"] - (0 if precision else 1)
-        first_ms += st["first_sweep_ms"]
-        first_steps += st["first_cg_steps"]
-        nfirst += 0 if precision else 1
-        refs += st["refinements"]
-        sweeps_per_solve.append(st["sweeps"])
-        rels.append(st["rel_residual"])
+        a["sweep_ms"] += st["sweep_ms"] - st["first_sweep_ms"]
+        a["steps"] += st["cg_steps"] - st["first_cg_steps"]
+        a["nsweeps"] += st["sweeps"] - (0 if precision else 1)
+        a["first_ms"] += st["first_sweep_ms"]
+        a["first_steps"] += st["first_cg_steps"]
+        a["nfirst"] += 0 if precision else 1
+        a["refs"] += st["refinements"]
 
     t0 = time.perf_counter()
     if nplans == 1:
         for _ in range(args.steps):
             _, st = plan.solve(f, c, u)
-            account(st)
+            account(st, acc["timed"])
+            sweeps_per_solve.append(st["sweeps"])
+            rels.append(st["rel_residual"])
     else:
-        plans[0].solve_async(f, c, us[0])
+        for i in range(min(nplans, args.steps)):
+            plans[i].solve_async(f, c, us[i])
         for i in range(args.steps):
-            if i + 1 < args.steps:
-                plans[(i + 1) % 2].solve_async(f, c, us[(i + 1) % 2])
-            _, st = plans[i % 2].wait()
-            account(st)
+            k = i % nplans
+            _, st = plans[k].wait()
+            account(st, acc["timed"])
+            sweeps_per_solve.append(st["sweeps"])
+            rels.append(st["rel_residual"])
+            if i + nplans < args.steps:
+                plans[k].solve_async(f, c, us[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     fps = args.steps / elapsed
     # latency of one frame on its own (no other frame queued): wall clock
-    # of a synchronous solve
+    # of a synchronous solve; its sweeps also give the kernels' launch
+    # durations with the GPU to themselves
     lat = []
     for _ in range(max(10, min(args.steps, 50))):
         ts = time.perf_counter()
-        plan.solve(f, c, u)
+        _, st = plan.solve(f, c, u)
         lat.append((time.perf_counter() - ts) * 1e3)
+        account(st, acc["isolated"])
     sync_fps = 1e3 / float(np.mean(lat))
     for p in plans[1:]:
         p.close()
+    a = acc["timed"]
+    sweep_ms, nsweeps, steps, refs = a["sweep_ms"], int(a["nsweeps"]), a["steps"], int(a["refs"])
+    first_ms, first_steps, nfirst = a["first_ms"], a["first_steps"], int(a["nfirst"])
 
     flops, bytes_ = sweep_work(prm, nsweeps, steps)
     if precision:
@@ -309,6 +359,26 @@ def run_frame(args, workload: str):
                 first_steps / nfirst / (ddi.block_count(H, prm["block"], prm["overlap"]) *
                                         ddi.block_count(W, prm["block"], prm["overlap"]) * C),
                 2)}
+    # launches in the timed region share the GPU with the other frames in
+    # flight; the synchronous latency solves give the same kernels alone
+    roofline["frames_sharing_gpu"] = nplans
+    if not precision and nfirst:
+        # the finest sweeps' algorithmic bytes over the timed region's wall
+        # clock: what the overlapping launches of all frames sustain together
+        agg = (bytes_ + fb1) / elapsed / 1e9
+        roofline["finest_sweeps_wall_gbs"] = round(agg, 1)
+        roofline["finest_sweeps_wall_frac"] = round(agg / HBM_PEAK_GBS, 4)
+    b = acc["isolated"]
+    if b["nsweeps"]:
+        fi, bi = sweep_work(prm, int(b["nsweeps"]), b["steps"])
+        if precision:
+            bi = correction_bytes(prm["inner_sweeps"], int(b["refs"]))
+        ri = roofline_of(fi, bi, b["sweep_ms"], int(b["nsweeps"]))
+        roofline["isolated"] = {k: ri[k] for k in ("avg_launch_us", "hbm_gbs", "hbm_frac",
+                                                    "valu_tflops", "valu_frac")}
+        if b["nfirst"]:
+            roofline["isolated"]["first_sweep_avg_launch_us"] = round(
+                b["first_ms"] / b["nfirst"] * 1e3, 2)
 
     u_np = u.cpu().numpy()
     if precision:
@@ -656,9 +726,11 @@ def run_batch(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--frames-in-flight", type=int, default=FRAMES_IN_FLIGHT,
+                    help="4K workload: plans (one stream each) with a frame in flight")
     ap.add_argument("--workload", choices=["4k", "batch", "precision", "serve", "ablation", "psnr",
                                            "scaling"], default="4k")
     ap.add_argument("--serve-seconds", type=float, default=SERVE_SECONDS)

@@ -334,7 +334,8 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
             hipSuccess ||
         (err = hipMalloc(&P->ctl, 64)) != hipSuccess ||
         (err = hipHostMalloc(&P->hctl, 64, hipHostMallocDefault)) != hipSuccess ||
-        (err = hipEventCreate(&P->e0)) != hipSuccess ||
+        // e0 only starts the solve's timer: no system-scope fence
+        (err = hipEventCreateWithFlags(&P->e0, hipEventDisableSystemFence)) != hipSuccess ||
         (err = hipEventCreate(&P->e1)) != hipSuccess ||
         (err = hipEventCreate(&P->ev_ctl)) != hipSuccess) {
         ddi_destroy(P);
@@ -395,8 +396,11 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
         }
         const int per = prm.storage == 1 ? prm.inner_sweeps : 1;
         P->sweep_ev.assign(2 * (size_t)std::max(prm.max_sweeps, 1) * per, nullptr);
+        // timing-only events: no system-scope fence (no L2 writeback and
+        // invalidate between sweeps); the host reads their times only after
+        // synchronizing on a later default event of the same stream
         for (hipEvent_t& ev : P->sweep_ev) {
-            if ((err = hipEventCreate(&ev)) != hipSuccess) {
+            if ((err = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence)) != hipSuccess) {
                 ddi_destroy(P);
                 return hip_fail(err);
             }

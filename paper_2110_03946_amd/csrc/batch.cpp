@@ -602,12 +602,16 @@ int ddi_batch_create(ddi_batch** out, int n, const int* heights, const int* widt
     if ((err = hipMalloc(&B->ctl, ctl_bytes)) != hipSuccess) return fail(err);
     if ((err = hipHostMalloc(&B->hctl, ctl_bytes, hipHostMallocDefault)) != hipSuccess)
         return fail(err);
-    if ((err = hipEventCreate(&B->e0)) != hipSuccess) return fail(err);
+    // e0 only starts the solve's timer: no system-scope fence
+    if ((err = hipEventCreateWithFlags(&B->e0, hipEventDisableSystemFence)) != hipSuccess)
+        return fail(err);
     if ((err = hipEventCreate(&B->e1)) != hipSuccess) return fail(err);
     if (B->timing) {
         B->sweep_ev.assign(2 * (size_t)B->max_sweeps, nullptr);
+        // timing only: no system-scope fence between sweeps
         for (hipEvent_t& ev : B->sweep_ev)
-            if ((err = hipEventCreate(&ev)) != hipSuccess) return fail(err);
+            if ((err = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence)) != hipSuccess)
+                return fail(err);
     }
     // size the job arena: the front plus the finest-level tables of all
     // images (a dry run of the builders; pointers do not matter here, but
