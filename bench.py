@@ -612,6 +612,7 @@ def run_serve(args):
 
 
 BATCH_N, BATCH_SEED = 48, 2
+BATCHES_IN_FLIGHT = 3
 METRIC_BATCH = "batched uneven RGB frames/s at ≤0.5 grey-level err vs FP64"
 
 
@@ -632,26 +633,68 @@ def run_batch(args):
         p.timing = 1
         p.final_residual = 0
     sizes = [(s["h"], s["w"]) for s in specs]
-    b = ddi.Batch(sizes, C, params=prms)
+    # several batched solves in flight, each batch plan on a stream of its
+    # own and driven by a host thread of its own (the library call releases
+    # the interpreter lock): one batch's coarse levels and stop tests run
+    # beside another's sweeps
+    import threading
+    nb = args.batches_in_flight
+    streams = concurrent_streams(nb) if nb > 1 else [None]
+    streams = [streams[i % len(streams)] for i in range(nb)]
+    bs = [ddi.Batch(sizes, C, params=[ddi.Params.from_buffer_copy(p) for p in prms], stream=s)
+          for s in streams]
+    uss = [us] + [[torch.empty_like(f) for f in fs] for _ in range(nb - 1)]
+    b = bs[0]
     for _ in range(args.warmup):
-        b.solve(fs, cs, us)
+        for bb, uu in zip(bs, uss):
+            bb.solve(fs, cs, uu)
     torch.cuda.synchronize()
-    lat, sweep_ms, launches, flops, bytes_ = [], 0.0, 0, 0.0, 0.0
+    lat, sweeps = [], []
+    acc = {"sweep_ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0}
+    lock = threading.Lock()
+    errors = []
+
+    def worker(k):
+        try:
+            for _ in range(k, args.steps, nb):
+                ts = time.perf_counter()
+                _, st, _ = bs[k].solve(fs, cs, uss[k])
+                dt = (time.perf_counter() - ts) * 1e3
+                fl = by = 0.0
+                for (h, w), p, x in zip(sizes, prms, st):
+                    a, bb = sweep_work(p.as_dict(), x["sweeps"], x["cg_steps"], h, w)
+                    fl += a
+                    by += bb
+                with lock:
+                    lat.append(dt)
+                    acc["sweep_ms"] += st[0]["sweep_ms"]
+                    acc["launches"] += max(x["sweeps"] for x in st)
+                    acc["flops"] += fl
+                    acc["bytes"] += by
+                    sweeps[:] = [x["sweeps"] for x in st]
+        except Exception as e:  # re-raised in the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(nb)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        _, st, _ = b.solve(fs, cs, us)
-        lat.append((time.perf_counter() - ts) * 1e3)
-        sweep_ms += st[0]["sweep_ms"]
-        launches += max(x["sweeps"] for x in st)
-        for (h, w), p, x in zip(sizes, prms, st):
-            fl, by = sweep_work(p.as_dict(), x["sweeps"], x["cg_steps"], h, w)
-            flops += fl
-            bytes_ += by
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if errors:
+        raise errors[0]
     fps = args.steps * len(specs) / elapsed
-    sweeps = [x["sweeps"] for x in st]
+    sweep_ms, launches, flops, bytes_ = acc["sweep_ms"], acc["launches"], acc["flops"], acc["bytes"]
+    # one batch at a time: the latency of a batched solve on its own
+    lat1 = []
+    for _ in range(max(3, min(args.steps // 2, 10))):
+        ts = time.perf_counter()
+        b.solve(fs, cs, us)
+        lat1.append((time.perf_counter() - ts) * 1e3)
+    for bb in bs[1:]:
+        bb.close()
 
     # the plain single-image path on the same images and parameters
     plans = []
@@ -690,6 +733,9 @@ def run_batch(args):
                       "images": len(specs), "megapixels": round(npix / 1e6, 2)},
            "p50_ms": round(float(np.percentile(lat, 50)), 3),
            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "batches_in_flight": nb,
+           "one_batch_at_a_time": {"p50_ms": round(float(np.percentile(lat1, 50)), 3),
+                                   "p99_ms": round(float(np.percentile(lat1, 99)), 3)},
            "single_image_path": {"frames_per_s": round(single_fps, 2),
                                  "p50_ms": round(float(np.percentile(single_lat, 50)), 3),
                                  "p99_ms": round(float(np.percentile(single_lat, 99)), 3)},
@@ -731,6 +777,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--frames-in-flight", type=int, default=FRAMES_IN_FLIGHT,
                     help="4K workload: plans (one stream each) with a frame in flight")
+    ap.add_argument("--batches-in-flight", type=int, default=BATCHES_IN_FLIGHT,
+                    help="batch workload: batch plans (one stream and host thread each)")
     ap.add_argument("--workload", choices=["4k", "batch", "precision", "serve", "ablation", "psnr",
                                            "scaling"], default="4k")
     ap.add_argument("--serve-seconds", type=float, default=SERVE_SECONDS)
