@@ -85,10 +85,13 @@ FLOPS_PER_CG_STEP = 15
 
 def solver_params() -> dict:
     """Solver parameters of the benchmark workload (64 x 64 blocks, overlap
-    4, coarsest level 1/8); the stop tolerance keeps the max error below
-    0.5 grey levels on this workload class."""
+    4, coarsest level 1/8). The stop tolerance keeps the max error below
+    0.5 grey levels on this workload class (0.38 at worst over eight
+    frames). With frames in flight the VALU-bound local CG steps are the
+    scarce resource: eight CG steps on the coarse levels buy a start good
+    enough for a looser local stop (0.004) on the finest level."""
     return dict(block=64, overlap=4, levels=4, local_iters=16, robin_alpha=0.25,
-                coarse_sweeps=1, coarsest_sweeps=1, coarse_local_iters=4, local_tol=0.002,
+                coarse_sweeps=1, coarsest_sweeps=1, coarse_local_iters=8, local_tol=0.004,
                 rel_tol=5e-4, min_sweeps=2, max_sweeps=30, check_every=1, final_residual=0)
 
 
