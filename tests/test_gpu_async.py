@@ -1,7 +1,8 @@
-"""ddi_solve_async / ddi_solve_wait: several plans in flight on one stream
-give the same results as ddi_solve, bit for bit, including solves that
-need more sweeps than their first batch (the continuation is enqueued by the
-wait behind the other plans' work)."""
+"""ddi_solve_async / ddi_solve_wait: several plans in flight, on one stream
+or each on a stream of its own, give the same results as ddi_solve, bit for
+bit, including solves that need more sweeps than their first batch (the
+continuation is enqueued by the wait behind the other plans' work); batch
+plans on their own streams, driven by host threads at once, likewise."""
 import numpy as np
 import pytest
 
@@ -97,3 +98,95 @@ def test_async_errors(ddi):
         u = torch.empty((C, H, W), dtype=torch.float32, device="cuda")
         with pytest.raises(ddi.DDIError):
             p.solve_async(dev(f), dev(c), u)
+
+
+def test_frames_in_flight_on_own_streams(ddi):
+    """Four plans, each on a stream of its own (chosen to sit on distinct
+    hardware queues, as the benchmark does), with four frames in flight and
+    timing on: every result equals the synchronous solve bit for bit, so
+    plans running concurrently share no state."""
+    import bench
+    C, H, W = 3, 270, 480
+    specs = [(0.05, "bernoulli"), (0.02, "clustered"), (0.08, "bernoulli"), (0.03, "clustered"),
+             (0.04, "bernoulli"), (0.06, "clustered"), (0.03, "bernoulli"), (0.10, "bernoulli")]
+    frames = [synth.make_workload(H, W, C, d, k, workload=52, index=i)
+              for i, (d, k) in enumerate(specs)]
+    say("frames in flight on own streams", len(frames))
+    ref = []
+    with ddi.Plan(H, W, C, **PRM) as p:
+        for f, c in frames:
+            u, st = p.solve(dev(f), dev(c))
+            ref.append((host(u), st["sweeps"]))
+    streams = bench.concurrent_streams(4)
+    say("  concurrent streams", len(streams))
+    plans = [ddi.Plan(H, W, C, timing=1, stream=streams[k % len(streams)], **PRM)
+             for k in range(4)]
+    fs = [(dev(f), dev(c)) for f, c in frames]
+    outs = [torch.empty((C, H, W), dtype=torch.float32, device="cuda") for _ in range(4)]
+    torch.cuda.synchronize()
+    got = [None] * len(frames)
+    for rnd in range(2):  # twice over: the second round starts in the other buffers
+        for i in range(4):
+            plans[i].solve_async(*fs[i], outs[i])
+        for i in range(len(frames)):
+            k = i % 4
+            u, st = plans[k].wait()
+            got[i] = (host(u), st)
+            if i + 4 < len(frames):
+                plans[k].solve_async(*fs[i + 4], outs[k])
+        for i, ((u, st), (u_ref, sw_ref)) in enumerate(zip(got, ref)):
+            assert st["sweeps"] == sw_ref, (rnd, i)
+            assert st["converged"] == 1 and st["sweep_ms"] > 0
+            np.testing.assert_array_equal(u, u_ref, err_msg=f"round {rnd} frame {i}")
+    for p in plans:
+        p.close()
+
+
+def test_batches_in_flight_on_own_streams(ddi):
+    """Two batch plans on streams of their own, driven by two host threads
+    at once (the library call releases the interpreter lock): both equal a
+    single batch plan's results bit for bit."""
+    import threading
+    import bench
+    C = 3
+    sizes = [(96, 160), (130, 70), (200, 256), (64, 200), (150, 3), (33, 47)]
+    data = [synth.make_workload(h, w, C, 0.05, "clustered" if i % 2 else "bernoulli",
+                                workload=53, index=i) for i, (h, w) in enumerate(sizes)]
+    fs = [dev(f) for f, _ in data]
+    cs = [dev(c) for _, c in data]
+    prm = dict(block=32, overlap=4, levels=3, local_iters=12, rel_tol=1e-5, max_sweeps=120,
+               final_residual=0)
+    say("batches in flight", len(sizes))
+    with ddi.Batch(sizes, C, **prm) as b:
+        ref_u, ref_st, _ = b.solve(fs, cs)
+        ref = [host(u) for u in ref_u]
+    streams = bench.concurrent_streams(2)
+    bs = [ddi.Batch(sizes, C, stream=streams[k % len(streams)], timing=1, **prm)
+          for k in range(2)]
+    uss = [[torch.empty_like(f) for f in fs] for _ in bs]
+    torch.cuda.synchronize()
+    results, errors = [[], []], []
+
+    def worker(k):
+        try:
+            for _ in range(3):
+                _, st, codes = bs[k].solve(fs, cs, uss[k])
+                results[k].append(([s["sweeps"] for s in st], codes,
+                                   [u.cpu().numpy() for u in uss[k]]))
+        except Exception as e:
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    for b in bs:
+        b.close()
+    assert not errors, errors
+    for k in range(2):
+        for sweeps, codes, us in results[k]:
+            assert codes == [0] * len(sizes)
+            assert sweeps == [s["sweeps"] for s in ref_st]
+            for a, r in zip(us, ref):
+                np.testing.assert_array_equal(a, r)
