@@ -41,19 +41,22 @@ from . import ddi, synth
 # sweeps of all images in lock step, so the stop schedule is common
 SCHEDULE = dict(min_sweeps=2, max_sweeps=60, check_every=1)
 
-# starting points of the search: a light one (fast where the mask is easy)
-# and a robust one (large holes: more levels and coarse work, longer local
-# solves, a tighter local stop)
+# starting points of the search: a light one (fast where the mask is easy),
+# one with more coarse CG work and a looser finest-level local stop, and a
+# robust one (large holes: more levels and coarse work, longer local solves,
+# a tighter local stop)
 STARTS = [
     dict(block=64, overlap=4, levels=4, local_iters=16, robin_alpha=0.25,
          coarse_sweeps=1, coarsest_sweeps=1, coarse_local_iters=4, local_tol=0.002),
+    dict(block=64, overlap=4, levels=4, local_iters=16, robin_alpha=0.25,
+         coarse_sweeps=1, coarsest_sweeps=1, coarse_local_iters=8, local_tol=0.004),
     dict(block=64, overlap=4, levels=5, local_iters=24, robin_alpha=0.25,
          coarse_sweeps=2, coarsest_sweeps=4, coarse_local_iters=16, local_tol=0.0005),
 ]
 
 SPACE = [
     ("local_iters", [12, 16, 24, 32]),
-    ("local_tol", [0.0, 0.0005, 0.001, 0.002]),
+    ("local_tol", [0.0, 0.0005, 0.001, 0.002, 0.003, 0.004, 0.006]),
     ("levels", [3, 4, 5, 6]),
     ("coarse_local_iters", [4, 8, 16]),
     ("coarse_sweeps", [1, 2, 3]),
