@@ -266,7 +266,7 @@ def run_frame(args, workload: str):
     # stop tests, reductions) and the load phases of its sweeps run beside
     # the other frames' sweeps, and the host's wait for one plan's stop test
     # never leaves the GPU idle
-    nplans = 1 if precision else args.frames_in_flight
+    nplans = args.frames_in_flight
     streams = concurrent_streams(nplans) if nplans > 1 else [None]
     if len(streams) < nplans:
         print(f"[bench] only {len(streams)} concurrent streams found", file=sys.stderr)
@@ -303,6 +303,32 @@ def run_frame(args, workload: str):
             account(st, acc["timed"])
             sweeps_per_solve.append(st["sweeps"])
             rels.append(st["rel_residual"])
+    elif precision:
+        # the refinement loop has no asynchronous entry point: one host
+        # thread per plan drives synchronous solves (the library call
+        # releases the interpreter lock)
+        import threading
+        lock = threading.Lock()
+        errors = []
+
+        def worker(k):
+            try:
+                for _ in range(k, args.steps, nplans):
+                    _, st = plans[k].solve(f, c, us[k])
+                    with lock:
+                        account(st, acc["timed"])
+                        sweeps_per_solve.append(st["sweeps"])
+                        rels.append(st["rel_residual"])
+            except Exception as e:  # re-raised in the main thread
+                errors.append(e)
+
+        threads = [threading.Thread(target=worker, args=(k,)) for k in range(nplans)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        if errors:
+            raise errors[0]
     else:
         for i in range(min(nplans, args.steps)):
             plans[i].solve_async(f, c, us[i])
@@ -317,18 +343,24 @@ def run_frame(args, workload: str):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     fps = args.steps / elapsed
-    # latency of one frame on its own (no other frame queued): wall clock
-    # of a synchronous solve; its sweeps also give the kernels' launch
-    # durations with the GPU to themselves
-    lat = []
-    for _ in range(max(10, min(args.steps, 50))):
-        ts = time.perf_counter()
+    # the kernels' launch durations with the GPU to themselves: synchronous
+    # solves, one frame at a time, on a timed plan
+    for _ in range(20):
         _, st = plan.solve(f, c, u)
-        lat.append((time.perf_counter() - ts) * 1e3)
         account(st, acc["isolated"])
-    sync_fps = 1e3 / float(np.mean(lat))
     for p in plans[1:]:
         p.close()
+    # latency of one frame on its own (no other frame queued): wall clock
+    # of a synchronous solve on a plan without timing events
+    lat = []
+    with ddi.Plan(H, W, C, **prm) as lat_plan:
+        for _ in range(3):
+            lat_plan.solve(f, c, u)
+        for _ in range(max(10, min(args.steps, 100))):
+            ts = time.perf_counter()
+            lat_plan.solve(f, c, u)
+            lat.append((time.perf_counter() - ts) * 1e3)
+    sync_fps = 1e3 / float(np.mean(lat))
     a = acc["timed"]
     sweep_ms, nsweeps, steps, refs = a["sweep_ms"], int(a["nsweeps"]), a["steps"], int(a["refs"])
     first_ms, first_steps, nfirst = a["first_ms"], a["first_steps"], int(a["nfirst"])
@@ -363,7 +395,7 @@ def run_frame(args, workload: str):
                                         ddi.block_count(W, prm["block"], prm["overlap"]) * C),
                 2)}
     # launches in the timed region share the GPU with the other frames in
-    # flight; the synchronous latency solves give the same kernels alone
+    # flight; synchronous solves one frame at a time give the same kernels alone
     roofline["frames_sharing_gpu"] = nplans
     if not precision and nfirst:
         # the finest sweeps' algorithmic bytes over the timed region's wall
@@ -779,7 +811,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--frames-in-flight", type=int, default=FRAMES_IN_FLIGHT,
-                    help="4K workload: plans (one stream each) with a frame in flight")
+                    help="4k and precision workloads: plans (one stream each) with a frame in flight")
     ap.add_argument("--batches-in-flight", type=int, default=BATCHES_IN_FLIGHT,
                     help="batch workload: batch plans (one stream and host thread each)")
     ap.add_argument("--workload", choices=["4k", "batch", "precision", "serve", "ablation", "psnr",
