@@ -226,6 +226,11 @@ def concurrent_streams(n: int, candidates: int = 24) -> list:
     already chosen takes one spin's time only if none of them share a
     queue. Returns fewer than n streams if the candidates run out."""
     import torch
+    if not hasattr(torch.cuda, "_sleep"):
+        # no spin kernel to probe with: plain pool streams (consecutive pool
+        # streams usually, but not always, sit on distinct queues)
+        print("[bench] torch.cuda._sleep missing: streams not probed", file=sys.stderr)
+        return [torch.cuda.Stream() for _ in range(n)]
     spin = int(0.5e-3 * CLOCK_HZ)
 
     def run(streams):
