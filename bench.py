@@ -31,24 +31,31 @@ multilevel-CG comparator at the same stop tolerance.
 Inputs are synthetic (paper_2110_03946_amd.synth) and already resident in
 HBM when the timed region starts.
 
+The timed region keeps several frames in flight (4k and precision: four
+plans, batch: three batch plans), each on a stream of its own picked so that
+no two share a hardware queue: one frame's latency-bound kernels run beside
+another's sweeps, and the host's wait for a stop test never idles the GPU.
+
 Prints one JSON line. Besides the driver's fields it carries
   roofline      the finest-level ORAS sweep (the dominant kernel): its
                 average duration from HIP events bracketing every such
-                launch on the solver's stream during the timed region, the
+                launch on its plan's stream during the timed region (so
+                while it shares the GPU with the other frames), the
                 algorithmic float32 work per launch, and the peak it is
-                held against;
+                held against; `isolated` gives the same kernels timed in
+                synchronous solves one frame at a time;
   cpu_baseline  the float64 CPU oracle (4k: the same frame; batch: a sample
                 of the images, scaled to frames of the batch's mix);
   max_err_grey  max |u - u_oracle| on the 0-255 scale (batch: over the
                 sample);
-  p50_ms/p99_ms latency of one frame solved on its own (wall clock of a
-                synchronous solve, after the timed region); the timed
-                region keeps two frames in flight on two plans
-                (ddi_solve_async / ddi_solve_wait) so that the GPU does not
-                idle while the host reads a stop test back.
+  p50_ms/p99_ms 4k and precision: latency of one frame solved on its own
+                (wall clock of a synchronous solve on a plan without timing
+                events, after the timed region); batch: of a batched solve
+                in flight.
 
-Usage: python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 5] [--no-cpu]
                        [--workload 4k|batch|precision|serve|ablation|psnr|scaling]
+                       [--frames-in-flight 4] [--batches-in-flight 3]
 """
 from __future__ import annotations
 

@@ -1,0 +1,41 @@
+"""bench.py host logic that runs without a GPU: the one-GPU contract and the
+rocprofv3 trace summary."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_summarize_trace(tmp_path):
+    """Per (kernel, grid) rows: the grid in workgroups tells the levels of
+    the same kernel apart; averages in microseconds."""
+    rows = [("ddi::k_sweep2<false>(args)", 6912 * 128, 128, 1000, 61000),
+            ("ddi::k_sweep2<false>(args)", 6912 * 128, 128, 2000, 61000),
+            ("ddi::k_sweep2<false>(args)", 120 * 128, 128, 500, 12500),
+            ("ddi::k_decide<3>(args)", 64, 64, 0, 4000)]
+    p = tmp_path / "trace.csv"
+    with open(p, "w") as fh:
+        fh.write("Kernel_Name,Grid_Size_X,Grid_Size_Y,Grid_Size_Z,Workgroup_Size_X,"
+                 "Workgroup_Size_Y,Workgroup_Size_Z,Start_Timestamp,End_Timestamp\n")
+        for name, gx, wx, t0, t1 in rows:
+            fh.write(f'"{name}",{gx},1,1,{wx},1,1,{t0},{t1}\n')
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--summarize-trace",
+                        str(p)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("| ddi::")]
+    cells = {(ln.split("|")[1].strip(), int(ln.split("|")[2])): ln.split("|") for ln in lines}
+    big = cells[("ddi::k_sweep2<false>", 6912)]
+    assert int(big[3]) == 2 and float(big[4]) == 59.5  # calls, average us
+    assert float(big[5]) == 59.0 and float(big[6]) == 60.0  # min, max
+    assert int(cells[("ddi::k_sweep2<false>", 120)][3]) == 1
+    assert ("ddi::k_decide<3>", 1) in cells
