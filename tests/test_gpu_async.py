@@ -190,3 +190,40 @@ def test_batches_in_flight_on_own_streams(ddi):
             assert sweeps == [s["sweeps"] for s in ref_st]
             for a, r in zip(us, ref):
                 np.testing.assert_array_equal(a, r)
+
+
+def test_benchmark_launch_configuration_4k(ddi):
+    """The 4K benchmark frame in the benchmark's own launch configuration:
+    four plans with timing on, each on a stream of its own, four frames in
+    flight through ddi_solve_async / ddi_solve_wait. Every result is the
+    same bit for bit and within the 0.5 grey-level bar of the exact float64
+    solution."""
+    import bench
+    C, H, W = 3, 2160, 3840
+    f, c = synth.make_workload(H, W, C, bench.DENSITY, "bernoulli", workload=1)
+    say("4K benchmark launch configuration")
+    fd, cd = dev(f), dev(c)
+    streams = bench.concurrent_streams(4)
+    plans = [ddi.Plan(H, W, C, timing=1, stream=streams[k % len(streams)],
+                      **bench.solver_params()) for k in range(4)]
+    outs = [torch.empty_like(fd) for _ in range(4)]
+    torch.cuda.synchronize()
+    got = []
+    for k in range(4):
+        plans[k].solve_async(fd, cd, outs[k])
+    for i in range(8):
+        k = i % 4
+        u, st = plans[k].wait()
+        assert st["converged"] == 1
+        got.append(host(u))
+        if i + 4 < 8:
+            plans[k].solve_async(fd, cd, outs[k])
+    for p in plans:
+        p.close()
+    for u in got[1:]:
+        np.testing.assert_array_equal(u, got[0])
+    ex = oracle.solve_exact(f.astype(np.float64), c)
+    err = float(np.abs(got[0] - ex).max())
+    say("  max err vs exact", err)
+    assert err <= 0.5
+    np.testing.assert_array_equal(got[0][:, c == 1], f[:, c == 1])
