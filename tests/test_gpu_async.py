@@ -227,3 +227,48 @@ def test_benchmark_launch_configuration_4k(ddi):
     say("  max err vs exact", err)
     assert err <= 0.5
     np.testing.assert_array_equal(got[0][:, c == 1], f[:, c == 1])
+
+
+def test_precision_plans_in_flight_from_threads(ddi):
+    """Mixed-precision plans (storage = 1: synchronous refinement loop) on
+    streams of their own, driven by host threads at once, as the precision
+    benchmark does: every result equals the single plan's bit for bit."""
+    import threading
+    import bench
+    C, H, W = 3, 270, 480
+    prm = dict(bench.precision_params(), levels=4)
+    frames = [synth.make_workload(H, W, C, 0.03, "bernoulli", workload=54, index=i)
+              for i in range(2)]
+    say("precision plans in flight")
+    ref = []
+    with ddi.Plan(H, W, C, **prm) as p:
+        for f, c in frames:
+            u, st = p.solve(dev(f), dev(c))
+            ref.append((host(u), st["sweeps"]))
+    streams = bench.concurrent_streams(2)
+    plans = [ddi.Plan(H, W, C, timing=1, stream=streams[k % len(streams)], **prm)
+             for k in range(2)]
+    data = [(dev(f), dev(c)) for f, c in frames]
+    torch.cuda.synchronize()
+    res, errors = [[], []], []
+
+    def worker(k):
+        try:
+            for _ in range(3):
+                u, st = plans[k].solve(*data[k])
+                res[k].append((u.cpu().numpy(), st["sweeps"]))
+        except Exception as e:
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    for p in plans:
+        p.close()
+    assert not errors, errors
+    for k in range(2):
+        for u, sw in res[k]:
+            assert sw == ref[k][1]
+            np.testing.assert_array_equal(u, ref[k][0])
