@@ -175,6 +175,52 @@ def test_sweep_sampled_blocks_at_4k(ddi):
         assert err <= 2e-3, (by, bx, err)
 
 
+def test_large_image_sampled_blocks_and_solve(ddi):
+    """8192 x 8192 x 2 (channel planes of 2^26 pixels, so 32-bit offsets
+    reach 2^27 across both planes of a buffer): one full-size ORAS sweep
+    against the oracle on sampled blocks (the four corners, where the
+    last blocks are clamped, and two inside), then a multilevel solve that
+    must converge, keep u = f on the mask bit for bit and stay within the
+    range of the known values (discrete maximum principle, to the stop
+    tolerance)."""
+    C, H, W = 2, 8192, 8192
+    rng = np.random.default_rng(12)
+    yy = np.arange(H, dtype=np.float32)[:, None]
+    xx = np.arange(W, dtype=np.float32)[None, :]
+    f = np.stack([128.0 + 100.0 * np.sin(xx / (400.0 + 90 * k)) * np.cos(yy / (650.0 - 70 * k))
+                  for k in range(C)]).astype(np.float32)
+    c = (rng.random((H, W)) < 0.04).astype(np.uint8)
+    say("large image", C, H, W)
+    fd, cd = dev(f), dev(c)
+    u0 = np.where(c == 1, f, np.float32(128.0)).astype(np.float32)
+    out = host(ddi.oras_sweep(dev(u0), cd, 64, 4, 0.25, 16)[0])
+    oy, bh = oracle.block_origins(H, 64, 4)
+    ox, bw = oracle.block_origins(W, 64, 4)
+    ly, hy = oracle.owner_bounds(oy, bh, H)
+    lx, hx = oracle.owner_bounds(ox, bw, W)
+    nby, nbx = len(oy), len(ox)
+    picks = [(0, 0), (nby - 1, nbx - 1), (0, nbx - 1), (nby - 1, 0)]
+    picks += [(int(rng.integers(nby)), int(rng.integers(nbx))) for _ in range(2)]
+    for i, (by, bx) in enumerate(picks):
+        ch = i % C
+        ref, _ = oracle.oras_step(u0[ch].astype(np.float64), f[ch].astype(np.float64), c,
+                                  64, 4, 0.25, 16, blocks=[(by, bx)])
+        sl = (slice(ly[by], hy[by]), slice(lx[bx], hx[bx]))
+        err = float(np.abs(out[ch][sl] - ref[sl]).max())
+        say("  block", by, bx, "ch", ch, "dev", err)
+        assert err <= 2e-3, (by, bx, err)
+    del out
+    with ddi.Plan(H, W, C, levels=5, rel_tol=1e-4, max_sweeps=60) as plan:
+        u_t, st = plan.solve(fd, cd)
+    u = host(u_t)
+    say("  solve sweeps", st["sweeps"], "rel", st["rel_residual"])
+    assert st["converged"] == 1
+    np.testing.assert_array_equal(u[:, c == 1], f[:, c == 1])
+    for ch in range(C):
+        known = f[ch][c == 1]
+        assert u[ch].min() >= known.min() - 0.5 and u[ch].max() <= known.max() + 0.5
+
+
 # ---------------------------------------------------------------------------
 # full multilevel solve vs the exact solution (Sec. 2-4)
 # ---------------------------------------------------------------------------
