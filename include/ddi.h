@@ -32,6 +32,7 @@
  *     turns it into text. On DDI_EHIP, ddi_last_hip_error gives the HIP
  *     error code of the failing runtime call.
  *   - Nothing here is thread-safe for one plan; use one plan per stream.
+ *     Different plans may be driven from different host threads at once.
  */
 #ifndef DDI_H
 #define DDI_H
@@ -321,7 +322,8 @@ int ddi_batch_destroy(ddi_batch* b);
 /* Text for an error code (static storage). */
 const char* ddi_strerror(int code);
 
-/* HIP error code of the last DDI_EHIP in this process (0 if none). */
+/* HIP error code of the last DDI_EHIP returned to the calling host thread
+ * (0 if none). */
 int ddi_last_hip_error(void);
 
 /* Geometry of the block grid the solver uses on an n-pixel axis: number of

@@ -16,7 +16,8 @@ using namespace ddi;
 static_assert(DDI_COARSE_MAX_PIXELS == kCoarseMaxPixels, "coarse solve size limit");
 
 namespace {
-int g_last_hip = 0;
+// per host thread: plans may be driven from several threads at once
+thread_local int g_last_hip = 0;
 }  // namespace
 
 int ddi::hip_fail(hipError_t e) {
