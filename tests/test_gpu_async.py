@@ -272,3 +272,49 @@ def test_precision_plans_in_flight_from_threads(ddi):
         for u, sw in res[k]:
             assert sw == ref[k][1]
             np.testing.assert_array_equal(u, ref[k][0])
+
+
+@pytest.mark.parametrize("method", [1, 2])
+def test_comparator_plans_in_flight_from_threads(ddi, method):
+    """Multilevel CG (method 1) and Krylov-accelerated ORAS (method 2)
+    plans, whose solves wait on the host inside the call, driven from two
+    host threads on streams of their own: results equal the single plan's
+    bit for bit."""
+    import threading
+    import bench
+    C, H, W = 3, 200, 320
+    prm = dict(method=method, levels=3, rel_tol=1e-5, max_sweeps=200, final_residual=1)
+    frames = [synth.make_workload(H, W, C, d, k, workload=55, index=i)
+              for i, (d, k) in enumerate([(0.04, "bernoulli"), (0.03, "clustered")])]
+    say("comparator plans in flight", method)
+    ref = []
+    with ddi.Plan(H, W, C, **prm) as p:
+        for f, c in frames:
+            u, st = p.solve(dev(f), dev(c))
+            ref.append((host(u), st["sweeps"]))
+    streams = bench.concurrent_streams(2)
+    plans = [ddi.Plan(H, W, C, stream=streams[k % len(streams)], **prm) for k in range(2)]
+    data = [(dev(f), dev(c)) for f, c in frames]
+    torch.cuda.synchronize()
+    res, errors = [[], []], []
+
+    def worker(k):
+        try:
+            for _ in range(3):
+                u, st = plans[k].solve(*data[k])
+                res[k].append((u.cpu().numpy(), st["sweeps"]))
+        except Exception as e:
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    for p in plans:
+        p.close()
+    assert not errors, errors
+    for k in range(2):
+        for u, sw in res[k]:
+            assert sw == ref[k][1]
+            np.testing.assert_array_equal(u, ref[k][0])
