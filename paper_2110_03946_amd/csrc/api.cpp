@@ -486,7 +486,8 @@ int plan_enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0) {
             hs[l] = P->lv[l].h;
             ws[l] = P->lv[l].w;
         }
-        DDI_HIP(launch_mask_bits_levels(L, cs, hs, ws, mbs, s));
+        // the same launch clears the stop-test control word of this solve
+        DDI_HIP(launch_mask_bits_levels(L, cs, hs, ws, mbs, s, P->ctl, 4));
     }
     const int top = L - 1;
     int cur = (top == 0) ? start0 : 0;
@@ -586,9 +587,8 @@ static int solve_refine(ddi_plan* P, const float* f, const uint8_t* c, float* u,
     DDI_HIP(hipEventRecord(P->e0, s));
     const int expect = P->last_sweeps >= 0 ? P->last_sweeps : std::max(prm.min_sweeps, 1);
     const int start0 = std::min(expect, kmax) & 1;
-    int e = enqueue_front(P, start0, s, false);
+    int e = enqueue_front(P, start0, s, false);  // also clears the control word
     if (e) return e;
-    DDI_HIP(launch_clear_int(P->ctl, 4, s));
     int* ctl = P->ctl;
     double* drel = reinterpret_cast<double*>(ctl + 4);
     const int nres = residual_partials(P->h, P->w);
@@ -735,11 +735,8 @@ static int begin_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u) 
             }
             hipGraph_t g = nullptr;
             DDI_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            int e = enqueue_front(P, q.start0, s, batch > 0);
-            if (!e) {
-                hipError_t he = launch_clear_int(P->ctl, 4, s);
-                e = he != hipSuccess ? hip_fail(he) : enqueue_sweeps(P, 0, batch, q.start0, false, s);
-            }
+            int e = enqueue_front(P, q.start0, s, batch > 0);  // clears the control word
+            if (!e) e = enqueue_sweeps(P, 0, batch, q.start0, false, s);
             hipError_t he = hipStreamEndCapture(s, &g);
             if (e) {
                 if (g) (void)hipGraphDestroy(g);
@@ -762,9 +759,8 @@ static int begin_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u) 
         DDI_HIP(hipGraphLaunch(hit->exec, s));
         q.done_upto = batch;
     } else {
-        int e = enqueue_front(P, q.start0, s, batch > 0);
+        int e = enqueue_front(P, q.start0, s, batch > 0);  // clears the control word
         if (e) return e;
-        DDI_HIP(launch_clear_int(P->ctl, 4, s));
         e = enqueue_sweeps(P, 0, batch, q.start0, q.timing, s);
         if (e) return e;
         q.done_upto = batch;

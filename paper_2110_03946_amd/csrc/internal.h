@@ -192,9 +192,11 @@ hipError_t launch_mask_bits(const uint8_t* c, int h, int w, uint64_t* mbits, hip
 // Largest number of levels a plan holds.
 constexpr int kMaxLevels = 16;
 
-// The transposed masks of n levels in one launch.
+// The transposed masks of n levels in one launch; optionally also zeroes
+// clear[0 .. nclear) (nclear <= 256), e.g. a solve's control word.
 hipError_t launch_mask_bits_levels(int n, const uint8_t* const* c, const int* h, const int* w,
-                                   uint64_t* const* mbits, hipStream_t s);
+                                   uint64_t* const* mbits, hipStream_t s,
+                                   int* clear = nullptr, int nclear = 0);
 
 // p[0..n) = 0.
 hipError_t launch_clear(double* p, int n, hipStream_t s);

@@ -1455,9 +1455,14 @@ struct MaskBitsLevels {
     const uint8_t* c[kMaxLevels];
     uint64_t* mbits[kMaxLevels];
     int h[kMaxLevels], w[kMaxLevels];
+    int* clear;  // optional: nclear ints zeroed by the first workgroup
+    int nclear;
 };
 
 __global__ __launch_bounds__(256) void k_mask_bits_levels(MaskBitsLevels L) {
+    if (L.clear && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 &&
+        (int)threadIdx.x < L.nclear)
+        L.clear[threadIdx.x] = 0;
     const int lv = blockIdx.z;
     const int h = L.h[lv], w = L.w[lv];
     const int x = blockIdx.x * 256 + threadIdx.x;
@@ -2505,9 +2510,12 @@ hipError_t launch_clear(double* p, int n, hipStream_t s) {
 }
 
 hipError_t launch_mask_bits_levels(int n, const uint8_t* const* c, const int* h, const int* w,
-                                  uint64_t* const* mbits, hipStream_t s) {
-    if (n < 1 || n > kMaxLevels) return hipErrorInvalidValue;
+                                  uint64_t* const* mbits, hipStream_t s, int* clear,
+                                  int nclear) {
+    if (n < 1 || n > kMaxLevels || nclear < 0 || nclear > 256) return hipErrorInvalidValue;
     MaskBitsLevels L;
+    L.clear = nclear > 0 ? clear : nullptr;
+    L.nclear = nclear;
     int gx = 1, gy = 1;
     for (int i = 0; i < n; ++i) {
         L.c[i] = c[i];

@@ -48,9 +48,9 @@ int solve_krylov(ddi_plan* P, ddi_stats* st) {
     pre.local_tol2 = 0.f;
 
     DDI_HIP(hipEventRecord(P->e0, s));
-    int e = plan_enqueue_front(P, 0, s, false);  // u = the coarse-to-fine start
+    // u = the coarse-to-fine start; the front also clears the control word
+    int e = plan_enqueue_front(P, 0, s, false);
     if (e) return e;
-    DDI_HIP(launch_clear_int(ctl, 4, s));
 
     int total = 0;
     bool converged = false, checked = false;

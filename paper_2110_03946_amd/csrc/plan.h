@@ -120,5 +120,6 @@ int solve_mlcg(ddi_plan* P, ddi_stats* st);
 // Krylov-accelerated ORAS solve (krylov.cpp); the level-0 pointers are set.
 int solve_krylov(ddi_plan* P, ddi_stats* st);
 // Pyramid, statistics, transposed masks, coarsest level and coarse-to-fine
-// passes down to the finest level's start in buffer start0 (api.cpp).
+// passes down to the finest level's start in buffer start0 (api.cpp); it
+// also zeroes the stop-test control word ctl[0..4).
 int plan_enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0);
