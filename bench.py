@@ -114,20 +114,26 @@ def batch_params(specs):
                                                      s["density"])) for s in specs]
 
 
-def sweep_work(p: dict, sweeps: int, cg_steps: float, h: int = H, w: int = W, ch: int = C):
+def sweep_work(p: dict, sweeps: int, cg_steps: float, h: int = H, w: int = W, ch: int = C,
+               skipped: float = 0.0, unwritten: float = 0.0):
     """Algorithmic flops and HBM bytes of the finest-level sweeps of a solve
     of an h x w x ch image (`sweeps` launches, `cg_steps` block CG steps
-    actually run)."""
+    actually run; `skipped` blocks skipped whole and `unwritten` blocks that
+    skipped their write-back, summed over channels and launches)."""
     from paper_2110_03946_amd import ddi
     nby = ddi.block_count(h, p["block"], p["overlap"])
     nbx = ddi.block_count(w, p["block"], p["overlap"])
     bh, bw = min(p["block"], h), min(p["block"], w)
     blocks = nby * nbx * ch
-    flops = bh * bw * (blocks * sweeps * FLOPS_RESIDUAL + cg_steps * FLOPS_PER_CG_STEP)
-    # per launch: the iterate is read once and written once (float32), plus
-    # the transposed mask (one bit per pixel); re-reads of the tile overlap
-    # are not algorithmic (the L2 serves them)
-    bytes_ = sweeps * (ch * h * w * 8 + h * w // 8)
+    run = blocks * sweeps - skipped
+    flops = bh * bw * (run * FLOPS_RESIDUAL + cg_steps * FLOPS_PER_CG_STEP)
+    # per block that runs: its owned pixels of the iterate read once and
+    # written once (float32; the write is skipped where the output already
+    # holds the values), plus the transposed mask (one bit per pixel);
+    # re-reads of the tile overlap are not algorithmic (the L2 serves them).
+    # A block's owned pixels are taken as the mean, h * w / (nby * nbx).
+    own = h * w / (nby * nbx)
+    bytes_ = own * 4 * (2 * run - unwritten) + (run / ch) * own / 8
     return flops, bytes_
 
 
@@ -296,7 +302,7 @@ def run_frame(args, workload: str):
     torch.cuda.synchronize()
     sweeps_per_solve, rels = [], []
     acc = {"timed": dict.fromkeys(["sweep_ms", "nsweeps", "steps", "refs", "first_ms",
-                                   "first_steps", "nfirst"], 0.0)}
+                                   "first_steps", "nfirst", "skipped", "unwritten"], 0.0)}
     acc["isolated"] = dict(acc["timed"])
 
     def account(st, a):
@@ -310,6 +316,8 @@ def run_frame(args, workload: str):
         a["first_steps"] += st["first_cg_steps"]
         a["nfirst"] += 0 if precision else 1
         a["refs"] += st["refinements"]
+        a["skipped"] += st["skipped_blocks"]
+        a["unwritten"] += st["unwritten_blocks"]
 
     t0 = time.perf_counter()
     if nplans == 1:
@@ -380,7 +388,8 @@ def run_frame(args, workload: str):
     sweep_ms, nsweeps, steps, refs = a["sweep_ms"], int(a["nsweeps"]), a["steps"], int(a["refs"])
     first_ms, first_steps, nfirst = a["first_ms"], a["first_steps"], int(a["nfirst"])
 
-    flops, bytes_ = sweep_work(prm, nsweeps, steps)
+    flops, bytes_ = sweep_work(prm, nsweeps, steps, skipped=a["skipped"],
+                               unwritten=a["unwritten"])
     if precision:
         bytes_ = correction_bytes(prm["inner_sweeps"], refs)
     roofline = roofline_of(flops, bytes_, sweep_ms, nsweeps)
@@ -390,7 +399,17 @@ def run_frame(args, workload: str):
                      "cg_steps_per_block_sweep": round(
                          steps / max(nsweeps, 1) /
                          (ddi.block_count(H, prm["block"], prm["overlap"]) *
-                          ddi.block_count(W, prm["block"], prm["overlap"]) * C), 2)})
+                          ddi.block_count(W, prm["block"], prm["overlap"]) * C), 2),
+                     # blocks of the steady sweeps skipped whole / without
+                     # their write-back (the previous sweep left them unchanged)
+                     "skipped_block_frac": round(
+                         a["skipped"] / max(nsweeps, 1) /
+                         (ddi.block_count(H, prm["block"], prm["overlap"]) *
+                          ddi.block_count(W, prm["block"], prm["overlap"]) * C), 4),
+                     "unwritten_block_frac": round(
+                         a["unwritten"] / max(nsweeps, 1) /
+                         (ddi.block_count(H, prm["block"], prm["overlap"]) *
+                          ddi.block_count(W, prm["block"], prm["overlap"]) * C), 4)})
     if not precision and nfirst:
         # the first sweep of a solve: prolongation fused into the tile load
         # (algorithmic bytes: the level-1 iterate and f on the known pixels
@@ -420,7 +439,8 @@ def run_frame(args, workload: str):
         roofline["finest_sweeps_wall_frac"] = round(agg / HBM_PEAK_GBS, 4)
     b = acc["isolated"]
     if b["nsweeps"]:
-        fi, bi = sweep_work(prm, int(b["nsweeps"]), b["steps"])
+        fi, bi = sweep_work(prm, int(b["nsweeps"]), b["steps"], skipped=b["skipped"],
+                            unwritten=b["unwritten"])
         if precision:
             bi = correction_bytes(prm["inner_sweeps"], int(b["refs"]))
         ri = roofline_of(fi, bi, b["sweep_ms"], int(b["nsweeps"]))

@@ -152,6 +152,21 @@ extern "C" {
  *                  give the same iterates whenever the interpolation sums
  *                  are exact in float64 (neighbouring coarse values within
  *                  a factor 2^26 of each other).
+ *   skip_unchanged 1: finest-level ORAS sweeps after the second one skip
+ *                  work the previous sweep made redundant. A block that the
+ *                  previous sweep left unchanged (no local CG step) and
+ *                  that runs no CG step again skips its write-back: the
+ *                  output buffer, the previous sweep's input, already holds
+ *                  these values on its owned pixels. A block whose 3 x 3
+ *                  neighbourhood of blocks the previous sweep left unchanged
+ *                  has the same input tile as then, hence the same residual
+ *                  and again no CG step: it is skipped whole. The iterates
+ *                  are bit for bit those of skip_unchanged = 0. Applies to
+ *                  float32 single-image ORAS plans (storage = 0, method =
+ *                  0) whose finest level has 64-row blocks and a grid where
+ *                  every block's tile lies in its 3 x 3 neighbourhood
+ *                  (overlap small against the block size); ignored
+ *                  otherwise. 0: every sweep does all its work.
  */
 typedef struct ddi_params {
     int block;
@@ -180,6 +195,7 @@ typedef struct ddi_params {
     int method;
     int fuse_prolong;
     int krylov_restart;
+    int skip_unchanged;
 } ddi_params;
 
 /*
@@ -202,6 +218,11 @@ typedef struct ddi_params {
  *                 cg_steps that falls on the first finest-level sweep (the
  *                 one that also computes the prolongation when
  *                 fuse_prolong applies); 0 otherwise.
+ *   skipped_blocks, unwritten_blocks
+ *                 with timing = 1 and skip_unchanged in effect: blocks (over
+ *                 channels and finest-level sweeps) skipped whole, and
+ *                 blocks that ran but skipped their write-back; 0
+ *                 otherwise.
  */
 typedef struct ddi_stats {
     int sweeps;
@@ -213,6 +234,8 @@ typedef struct ddi_stats {
     int refinements;
     double first_sweep_ms;
     double first_cg_steps;
+    double skipped_blocks;
+    double unwritten_blocks;
 } ddi_stats;
 
 typedef struct ddi_plan ddi_plan;
@@ -223,7 +246,7 @@ typedef struct ddi_plan ddi_plan;
  * timing = 0, coarse_block = 0, coarse_overlap = -1, coarse_local_iters = 0,
  * local_tol = 0, use_graph = 0, coarse_solver = 0, coarse_cg_iters = 500,
  * coarse_cg_tol = 1e-10, storage = 0, inner_sweeps = 2, method = 0,
- * fuse_prolong = 1, krylov_restart = 8. */
+ * fuse_prolong = 1, krylov_restart = 8, skip_unchanged = 1. */
 int ddi_default_params(ddi_params* p);
 
 /* Check *p for one image size without touching the GPU (this includes the

@@ -78,6 +78,10 @@ int level_count(int h, int w, int levels) {
     return L;
 }
 
+bool use_skip(const ddi_params& prm, const SweepArgs& a0) {
+    return prm.skip_unchanged == 1 && prm.storage == 0 && prm.method == 0 && sweep_skip_ok(a0);
+}
+
 size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm) {
     const int L = level_count(h, w, prm.levels);
     size_t bytes = 0, part_n = 0;
@@ -102,7 +106,11 @@ size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm) {
     }
     part_n = std::max(part_n, std::max<size_t>((size_t)coarsen_partials(h, w), 1024) * (C + 2));
     bytes += part_n * sizeof(double);
-    bytes += (4 * (size_t)C + 2) * sizeof(double) + 64;  // red, ctl
+    bytes += (6 * (size_t)C + 2) * sizeof(double) + 64;  // red, ctl
+    {
+        const SweepArgs a0 = make_sweep(h, w, C, prm.block, prm.overlap, prm.robin_alpha, 1);
+        if (use_skip(prm, a0)) bytes += 2 * (size_t)sweep_partials(a0) * C * sizeof(int);
+    }
     if (prm.storage == 1) bytes += 3 * (size_t)C * h * w * sizeof(uint16_t);
     if (prm.method == 1)
         bytes += 4 * (size_t)C * h * w * sizeof(float) + (3 * (size_t)C + L * ((size_t)C + 2)) *
@@ -115,7 +123,7 @@ size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm) {
     }
     if (prm.timing) {
         const SweepArgs a0 = make_sweep(h, w, C, prm.block, prm.overlap, prm.robin_alpha, 1);
-        bytes += (size_t)sweep_partials(a0) * C * sizeof(double);
+        bytes += 3 * (size_t)sweep_partials(a0) * C * sizeof(double);
     }
     return bytes;
 }
@@ -173,6 +181,7 @@ int ddi_default_params(ddi_params* p) {
     p->method = 0;
     p->fuse_prolong = 1;
     p->krylov_restart = 8;
+    p->skip_unchanged = 1;
     return DDI_OK;
 }
 
@@ -205,6 +214,7 @@ int ddi_check_params(int height, int width, int channels, const ddi_params* p) {
     if (p->method != 0 && p->storage != 0) return DDI_EINVAL;
     if (p->krylov_restart < 1 || p->krylov_restart > kKryMaxM) return DDI_EINVAL;
     if (p->fuse_prolong != 0 && p->fuse_prolong != 1) return DDI_EINVAL;
+    if (p->skip_unchanged != 0 && p->skip_unchanged != 1) return DDI_EINVAL;
     if (p->coarse_solver == 1) {
         int hl = height, wl = width;
         for (int l = 1; l < level_count(height, width, p->levels); ++l) {
@@ -237,6 +247,7 @@ int ddi_destroy(ddi_plan* plan) {
     if (plan->part) (void)hipFree(plan->part);
     if (plan->red) (void)hipFree(plan->red);
     if (plan->cgcnt) (void)hipFree(plan->cgcnt);
+    if (plan->flg) (void)hipFree(plan->flg);
     if (plan->ctl) (void)hipFree(plan->ctl);
     if (plan->hctl) (void)hipHostFree(plan->hctl);
     if (plan->host) (void)hipHostFree(plan->host);
@@ -329,7 +340,7 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
         ddi_destroy(P);
         return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
     }
-    const size_t nred = 4 * channels + 2;
+    const size_t nred = 6 * channels + 2;
     if ((err = hipMalloc(&P->red, nred * sizeof(double))) != hipSuccess ||
         (err = hipHostMalloc(&P->host, nred * sizeof(double), hipHostMallocDefault)) !=
             hipSuccess ||
@@ -384,8 +395,15 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
             return hip_fail(err);
         }
     }
+    if (use_skip(prm, P->lv[0].sw)) {
+        const size_t nfl = 2 * (size_t)sweep_partials(P->lv[0].sw) * channels;
+        if ((err = hipMalloc(&P->flg, nfl * sizeof(int))) != hipSuccess) {
+            ddi_destroy(P);
+            return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
+        }
+    }
     if (prm.timing) {
-        const size_t nc = (size_t)sweep_partials(P->lv[0].sw) * channels;
+        const size_t nc = 3 * (size_t)sweep_partials(P->lv[0].sw) * channels;
         if ((err = hipMalloc(&P->cgcnt, nc * sizeof(double))) != hipSuccess) {
             ddi_destroy(P);
             return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
@@ -557,9 +575,19 @@ static int enqueue_sweeps(ddi_plan* P, int from, int to, int start0, bool timing
         if (i == 0 && P->pro0_on)
             DDI_HIP(launch_sweep_prolong(P->pro0, L0.mbits, L0.u[c0 ^ 1], P->part,
                                          timing ? P->cgcnt : nullptr, ctl, L0.sw, s));
-        else
+        else if (P->flg) {
+            // sweep i writes the flags of parity i & 1 and reads those of the
+            // sweep before (from the third sweep on: the first sweep's
+            // output buffer is the only one the solve has written yet)
+            const int nfl = nb * P->C;
+            DDI_HIP(launch_sweep(L0.u[c0], L0.mbits, L0.u[c0 ^ 1], P->part,
+                                 timing ? P->cgcnt : nullptr, ctl, L0.sw, s,
+                                 i >= 2 ? P->flg + ((i - 1) & 1) * nfl : nullptr,
+                                 P->flg + (i & 1) * nfl));
+        } else {
             DDI_HIP(launch_sweep(L0.u[c0], L0.mbits, L0.u[c0 ^ 1], P->part,
                                  timing ? P->cgcnt : nullptr, ctl, L0.sw, s));
+        }
         if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * i + 1], s));
         if (timing && i == 0)  // the first sweep's CG steps on their own
             DDI_HIP(launch_reduce(P->cgcnt, nb, P->C, P->C, P->red + 3 * P->C + 2, s));
@@ -714,7 +742,7 @@ static int begin_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u) 
         while (upto < prm.max_sweeps && !is_check(prm, upto)) ++upto;
         batch = std::min(upto, prm.max_sweeps);
     }
-    if (q.timing) DDI_HIP(launch_clear(P->cgcnt, sweep_partials(L0.sw) * P->C, s));
+    if (q.timing) DDI_HIP(launch_clear(P->cgcnt, 3 * sweep_partials(L0.sw) * P->C, s));
 
     if (graph) {
         // one graph per (f, c, u, start buffer, first batch); later solves
@@ -775,8 +803,11 @@ static int enqueue_check(ddi_plan* P) {
     const int C = P->C;
     hipStream_t s = P->pend.s;
     if (P->pend.timing) {
-        DDI_HIP(launch_reduce(P->cgcnt, sweep_partials(P->lv[0].sw), C, C, P->red + 2 * C + 2, s));
-        DDI_HIP(hipMemcpyAsync(P->host + 2 * C + 2, P->red + 2 * C + 2, 2 * C * sizeof(double),
+        const int nb = sweep_partials(P->lv[0].sw);
+        DDI_HIP(launch_reduce(P->cgcnt, nb, C, C, P->red + 2 * C + 2, s));
+        DDI_HIP(launch_reduce(P->cgcnt + (size_t)nb * C, nb, C, C, P->red + 4 * C + 2, s));
+        DDI_HIP(launch_reduce(P->cgcnt + 2 * (size_t)nb * C, nb, C, C, P->red + 5 * C + 2, s));
+        DDI_HIP(hipMemcpyAsync(P->host + 2 * C + 2, P->red + 2 * C + 2, 4 * C * sizeof(double),
                                hipMemcpyDeviceToHost, s));
     }
     DDI_HIP(hipMemcpyAsync(P->hctl, P->ctl, 4 * sizeof(int) + sizeof(double),
@@ -860,10 +891,12 @@ static int finish_solve(ddi_plan* P, ddi_stats* st) {
         DDI_HIP(hipEventSynchronize(P->e1));
         end = P->e1;
     }
-    double nsteps = 0.0, steps0 = 0.0;
+    double nsteps = 0.0, steps0 = 0.0, nskip = 0.0, nunwr = 0.0;
     for (int k = 0; q.timing && k < C; ++k) {
         nsteps += P->host[2 * C + 2 + k];
         steps0 += P->host[3 * C + 2 + k];
+        nskip += P->host[4 * C + 2 + k];
+        nunwr += P->host[5 * C + 2 + k];
     }
     float ms = 0.f;
     DDI_HIP(hipEventElapsedTime(&ms, P->e0, end));
@@ -883,6 +916,8 @@ static int finish_solve(ddi_plan* P, ddi_stats* st) {
         st->cg_steps = nsteps;
         st->first_sweep_ms = first_ms;
         st->first_cg_steps = steps0;
+        st->skipped_blocks = nskip;
+        st->unwritten_blocks = nunwr;
     }
     return converged ? DDI_OK : DDI_ENOCONV;
 }

@@ -156,9 +156,26 @@ constexpr int kMaxBlock = 64;
 // launch_mask_bits for the same level. When cg_steps is non-null, block b
 // of channel ch adds the number of CG steps it ran to cg_steps[b * C + ch].
 // When ctl is non-null and ctl[0] != 0 the sweep does nothing.
+// Unchanged-block flags (only where sweep_skip_ok): fout (may be null)
+// receives per block (index ch * blocks + b) 1 if the sweep left the block's
+// owned pixels unchanged (no CG step), else 0. fin (may be null) holds the
+// flags of the previous sweep on the same level, whose input was u_out and
+// whose output is u_in: a block that this sweep would leave unchanged and
+// that the previous sweep left unchanged skips its write-back (u_out holds
+// the values already), and a block whose 3 x 3 neighbourhood the previous
+// sweep left unchanged is skipped whole (its partial keeps the previous
+// value, which is its residual norm again). The result is bit for bit that
+// of the sweep without flags. With cg_steps, planes 1 and 2 of cg_steps
+// (offsets blocks * C and 2 * blocks * C) count the blocks skipped whole and
+// those whose write-back was skipped.
 hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
                         double* partial, double* cg_steps, const int* ctl, const SweepArgs& a,
-                        hipStream_t s);
+                        hipStream_t s, const int* fin = nullptr, int* fout = nullptr);
+
+// True when a sweep of `a` can use unchanged-block flags: full 64-row
+// blocks, each tile inside the owned pixels of its block and its 8
+// neighbours.
+bool sweep_skip_ok(const SweepArgs& a);
 
 // True when the sweep of `a` can take its input from a coarser level
 // (launch_sweep_prolong): full 64-row blocks.

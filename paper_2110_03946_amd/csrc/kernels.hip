@@ -118,6 +118,36 @@ __device__ __forceinline__ float mask_bfe(uint32_t bits, int bit, float q) {
     return __int_as_float(__float_as_int(q) & sel);
 }
 
+// Byte masks: byte k of a word is 0xff where row 4 j + k of the column is
+// unknown (bit 4 j + k of the 32-bit mask word), 0 elsewhere.
+__device__ __forceinline__ uint32_t mask_bytes(uint32_t bits, int j) {
+    const uint32_t nib = (bits >> (4 * j)) & 0xfu;
+    return ((nib * 0x00204081u) & 0x01010101u) * 0xffu;
+}
+
+// q where byte K of the byte mask m is 0xff, +0 where it is 0: one AND whose
+// first operand is that byte sign-extended to 32 bits (an SDWA operand
+// select), so a masked row costs one instruction instead of an extract and
+// an AND.
+template <int K>
+__device__ __forceinline__ float mask_byte(uint32_t m, float q) {
+    uint32_t out;
+    asm("v_and_b32_sdwa %0, sext(%1), %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_%3 src1_sel:DWORD"
+        : "=v"(out)
+        : "v"(m), "v"(__float_as_uint(q)), "i"(K));
+    return __uint_as_float(out);
+}
+// The same with the byte index as an argument; in unrolled loops it is a
+// constant and the switch folds away.
+__device__ __forceinline__ float mask_byte(uint32_t m, int k, float q) {
+    switch (k & 3) {
+        case 0: return mask_byte<0>(m, q);
+        case 1: return mask_byte<1>(m, q);
+        case 2: return mask_byte<2>(m, q);
+        default: return mask_byte<3>(m, q);
+    }
+}
+
 // Mask of one block column, built from the bits of the unknown pixels.
 // Float storage (1 = unknown) for short columns; the bits themselves for
 // 64-row columns, where registers are scarce.
@@ -745,13 +775,19 @@ __device__ __forceinline__ void tile2_store(const Tile2& T, const SweepArgs& a,
 // Residual, local CG and owned write-back of one split block whose tile is
 // in LDS (staged and followed by a barrier). QL: q parked in the wave's half
 // of the tile.
+// keep: the previous sweep left this block's owned pixels unchanged, so the
+// output buffer already holds the input's values there; a block that then
+// runs no CG step skips its write-back. fout (may be null) receives 1 for a
+// block whose output equals its input on its owned pixels (no CG step).
 template <bool CORR, bool QL, bool F32 = false>
 __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
                                                const void* __restrict__ rhs,
                                                void* __restrict__ uout_v,
                                                double* __restrict__ partial,
                                                double* __restrict__ cg_steps,
-                                               const SweepArgs& a, float* __restrict__ lds) {
+                                               const SweepArgs& a, float* __restrict__ lds,
+                                               int* __restrict__ fout = nullptr, int lb = 0,
+                                               bool keep = false) {
     constexpr int RPW = kSplitRows;
     constexpr int TW = kTileW;
     constexpr int CO = 1;
@@ -828,12 +864,12 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
 #pragma unroll
     for (int y = 0; y < RPW; ++y) p[y] = r[y];
     const float rho_stop = a.local_tol2 * (float)(g.bh * g.bw);
+    uint32_t mb[RPW / 4];
+#pragma unroll
+    for (int j = 0; j < RPW / 4; ++j) mb[j] = mask_bytes(mw, j);
     int it = 0;
     for (; it < a.k; ++it) {
         if (!(rho > rho_stop)) break;
-        // re-define the mask word each step so that the 32 per-row bit
-        // extracts stay inside the loop instead of holding 32 registers
-        asm volatile("" : "+v"(mw));
         // swap boundary rows: wave 0 sends row 31, wave 1 row 0
         xrow[wi * 64 + lane] = wi == 0 ? p[RPW - 1] : p[0];
         __syncthreads();
@@ -848,7 +884,7 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
             s += from_left(p[y]);
             s += from_right(p[y]);
             const float d = y == 0 ? dfirst : (y == RPW - 1 ? dlast : dmid);
-            const float qy = mask_bfe(mw, y, d * p[y] - s);
+            const float qy = mask_byte(mb[y >> 2], y, d * p[y] - s);
             if constexpr (QL) {
                 q4[y & 3] = qy;
                 if ((y & 3) == 3) qs[(y >> 2) * 64 + lane] = make_float4(q4[0], q4[1], q4[2], q4[3]);
@@ -896,6 +932,14 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
     }
 
     if (cg_steps && wi == 0 && lane == 0) cg_steps[(int64_t)k.b * a.channels + k.ch] += (double)it;
+    if (fout && wi == 0 && lane == 0) fout[lb] = it == 0 ? 1 : 0;
+    if (keep && it == 0) {  // output already equals the input here
+        // timing counters: plane 2 counts blocks whose write-back was skipped
+        if (cg_steps && wi == 0 && lane == 0)
+            cg_steps[2 * (int64_t)a.g.nby * a.g.nbx * a.channels + (int64_t)k.b * a.channels +
+                     k.ch] += 1.0;
+        return;
+    }
 
     // ---- restricted prolongation on owned pixels (eq. 9): the row test is
     // wave-uniform, the column test per lane ----
@@ -922,6 +966,13 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
 
 // One split block (tile loaded, stored, computed). PRO: the input iterate
 // is the prolongation of pro (uin_v unused).
+// fin (may be null): the previous sweep's flags (1 = block left unchanged,
+// see sweep2_compute), fout those of this sweep. A block whose tile lies in
+// blocks that the previous sweep all left unchanged has the same input as
+// then, so the same residual and again no CG step: it keeps its partial and
+// its output (which already holds these values) and exits. Each tile lies
+// in the owned pixels of its own block and its 8 neighbours (the host
+// passes fin only for grids where this holds).
 template <bool CORR, bool QL, bool PRO = false, bool F32 = false>
 __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
                                             const void* __restrict__ rhs,
@@ -931,9 +982,37 @@ __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
                                             double* __restrict__ cg_steps,
                                             const int* __restrict__ ctl, const SweepArgs& a,
                                             int lb, float* __restrict__ lds,
-                                            const ProSrc* pro = nullptr) {
-    if (ctl && ctl[0] != 0) return;  // read by both waves: the same decision
+                                            const ProSrc* pro = nullptr,
+                                            const int* __restrict__ fin = nullptr,
+                                            int* __restrict__ fout = nullptr) {
     const Blk k = blk_geo(a, lb);
+    // the control word and the flags are loaded together (uniform loads):
+    // read by both waves, so both take the same decisions
+    const int stop = ctl ? ctl[0] : 0;
+    bool keep = false, same = false;
+    if (fin) {
+        const int nbx = a.g.nbx, nby = a.g.nby;
+        const int by = k.b / nbx, bx = k.b - by * nbx;
+        const int* F = fin + (int64_t)k.ch * nby * nbx;
+        const int r0 = max(by - 1, 0) * nbx, r1 = by * nbx, r2 = min(by + 1, nby - 1) * nbx;
+        const int c0 = max(bx - 1, 0), c2 = min(bx + 1, nbx - 1);
+        const int own = F[r1 + bx];
+        const int nb = (F[r0 + c0] & F[r0 + bx] & F[r0 + c2]) & (F[r1 + c0] & F[r1 + c2]) &
+                       (F[r2 + c0] & F[r2 + bx] & F[r2 + c2]);
+        keep = own != 0;
+        same = (own & nb) != 0;
+    }
+    if (stop != 0) return;
+    if (same) {
+        if (threadIdx.x == 0) {
+            if (fout) fout[lb] = 1;
+            // timing counters: plane 1 counts blocks skipped whole
+            if (cg_steps)
+                cg_steps[(int64_t)a.g.nby * a.g.nbx * a.channels + (int64_t)k.b * a.channels +
+                         k.ch] += 1.0;
+        }
+        return;
+    }
     Tile2 T;
     if constexpr (PRO) {
         tile2_load_prolong(T, k, a, mbits, *pro);
@@ -955,7 +1034,7 @@ __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
     tile2_store(T, a, lds);
     const uint32_t mw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) ? T.mhi : T.mlo;
     __syncthreads();
-    sweep2_compute<CORR, QL, F32>(k, mw, rhs, uout_v, partial, cg_steps, a, lds);
+    sweep2_compute<CORR, QL, F32>(k, mw, rhs, uout_v, partial, cg_steps, a, lds, fout, lb, keep);
 }
 
 #ifndef DDI_SPLIT_QL
@@ -971,10 +1050,12 @@ __global__ __launch_bounds__(128, DDI_SPLIT_WAVES) void k_sweep2(const void* __r
                                                 void* __restrict__ uout,
                                                 double* __restrict__ partial,
                                                 double* __restrict__ cg_steps,
-                                                const int* __restrict__ ctl, SweepArgs a) {
+                                                const int* __restrict__ ctl, SweepArgs a,
+                                                const int* __restrict__ fin,
+                                                int* __restrict__ fout) {
     __shared__ __attribute__((aligned(16))) float lds[kSplitLds];
     sweep2_body<CORR, DDI_SPLIT_QL>(uin, rhs, mbits, uout, partial, cg_steps, ctl, a,
-                                    xcd_remap(blockIdx.x, gridDim.x), lds);
+                                    xcd_remap(blockIdx.x, gridDim.x), lds, nullptr, fin, fout);
 }
 
 // k_sweep2 whose input iterate is the bilinear prolongation of a coarser
@@ -2304,15 +2385,35 @@ __global__ __launch_bounds__(kCgTpb) void k_coarse_cg64_batch(const CoarseJob* _
 #endif
 static bool use_split(const SweepArgs& a) { return DDI_SPLIT && a.g.bh == 2 * kSplitRows; }
 
+// Along one axis, does every block's tile (the block and its one-pixel
+// halo, clamped to the level) lie in the pixels owned by the block and its
+// two neighbours? Then a sweep may skip blocks whose 3 x 3 neighbourhood the
+// previous sweep left unchanged.
+static bool skip_axis_ok(int n, int nb, int stride, int size) {
+    for (int k = 0; k < nb; ++k) {
+        const int o = block_origin(k, stride, n, size);
+        const int lo = std::max(o - 1, 0), hi = std::min(o + size, n - 1);
+        int l0, h0, l2, h2;
+        owner_range(std::max(k - 1, 0), nb, stride, n, size, &l0, &h0);
+        owner_range(std::min(k + 1, nb - 1), nb, stride, n, size, &l2, &h2);
+        if (lo < l0 || hi >= h2) return false;
+    }
+    return true;
+}
+static bool skip_grid_ok(const BlockGrid& g) {
+    return skip_axis_ok(g.h, g.nby, g.sy, g.bh) && skip_axis_ok(g.w, g.nbx, g.sx, g.bw);
+}
+
 
 template <int RPW, bool QLDS, bool MBITS>
 static hipError_t sweep_rpw(const float* uin, const uint64_t* mbits, float* uout,
                             double* partial, double* cg_steps, const int* ctl,
-                            const SweepArgs& a, hipStream_t s) {
+                            const SweepArgs& a, hipStream_t s, const int* fin = nullptr,
+                            int* fout = nullptr) {
     const int grid = a.g.nby * a.g.nbx * a.channels;
     if (use_split(a)) {
         hipLaunchKernelGGL((k_sweep2<false>), dim3(grid), dim3(128), 0, s, uin, nullptr, mbits,
-                           uout, partial, cg_steps, ctl, a);
+                           uout, partial, cg_steps, ctl, a, fin, fout);
         return hipGetLastError();
     }
     if (a.g.bh == RPW)
@@ -2332,7 +2433,7 @@ static hipError_t sweep_corr_rpw(const uint16_t* din, const uint16_t* rhs,
     const int grid = a.g.nby * a.g.nbx * a.channels;
     if (use_split(a)) {
         hipLaunchKernelGGL((k_sweep2<true>), dim3(grid), dim3(128), 0, s, din, rhs, mbits, dout,
-                           partial, cg_steps, ctl, a);
+                           partial, cg_steps, ctl, a, (const int*)nullptr, (int*)nullptr);
         return hipGetLastError();
     }
     if (a.g.bh == RPW)
@@ -2460,16 +2561,21 @@ hipError_t launch_sweep_corr(const uint16_t* din, const uint16_t* rhs, const uin
 
 hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
                         double* partial, double* cg_steps, const int* ctl, const SweepArgs& a,
-                        hipStream_t s) {
+                        hipStream_t s, const int* fin, int* fout) {
     const int bh = a.g.bh;
     if (a.g.bw < 1 || a.g.bw > kMaxBlock || bh < 1 || bh > kMaxBlock) return hipErrorInvalidValue;
-    if (bh > 32) return sweep_rpw<64, true, true>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
+    if ((fin || fout) && !(use_split(a) && skip_grid_ok(a.g))) return hipErrorInvalidValue;
+    if (bh > 32)
+        return sweep_rpw<64, true, true>(uin, mbits, uout, partial, cg_steps, ctl, a, s, fin,
+                                         fout);
     if (bh > 16) return sweep_rpw<32, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
     if (bh > 8) return sweep_rpw<16, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
     return sweep_rpw<8, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
 }
 
 bool sweep_prolong_ok(const SweepArgs& a) { return use_split(a); }
+
+bool sweep_skip_ok(const SweepArgs& a) { return use_split(a) && skip_grid_ok(a.g); }
 
 hipError_t launch_sweep_prolong(const ProSrc& src, const uint64_t* mbits, float* uout,
                                 double* partial, double* cg_steps, const int* ctl,

@@ -34,6 +34,9 @@ SweepArgs make_sweep(int h, int w, int channels, int block, int overlap, float a
 int check_device();
 // Device bytes ddi_create allocates for these sizes and parameters.
 size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm);
+// Finest-level sweeps of this plan use unchanged-block flags
+// (skip_unchanged, float32 ORAS, a grid where launch_sweep accepts them).
+bool use_skip(const ddi_params& prm, const SweepArgs& a0);
 // Levels a plan builds for h x w: `levels`, fewer once a level is 1 x 1.
 int level_count(int h, int w, int levels);
 // DDI_OK for 1 <= h, w; 1 <= channels <= 4; h * w <= 2^30.
@@ -55,9 +58,13 @@ struct ddi_plan {
     std::vector<ddi::Level> lv;
     double* part = nullptr;
     size_t part_n = 0;
-    double* red = nullptr;   // [C + 2] stats, [C] norms, [C] CG step totals
+    double* red = nullptr;   // [C + 2] stats, [C] norms, [C] CG step totals,
+                             // [C] first-sweep CG steps, [2C] skip totals
     double* host = nullptr;  // pinned mirror of red
-    double* cgcnt = nullptr; // timing: CG steps per finest-level block
+    double* cgcnt = nullptr; // timing: per finest-level block, CG steps, whole
+                             // skips and skipped write-backs (three planes)
+    int* flg = nullptr;      // unchanged-block flags of the finest level, two
+                             // arrays (sweep parity); null: no skipping
     int* ctl = nullptr;      // device stop test: done, sweeps, error, -, rel (double)
     void* hctl = nullptr;    // pinned mirror of ctl
     hipEvent_t e0 = nullptr, e1 = nullptr;

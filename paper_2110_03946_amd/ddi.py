@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
                 ("coarse_solver", ctypes.c_int), ("coarse_cg_iters", ctypes.c_int),
                 ("coarse_cg_tol", ctypes.c_double), ("storage", ctypes.c_int),
                 ("inner_sweeps", ctypes.c_int), ("method", ctypes.c_int),
-                ("fuse_prolong", ctypes.c_int), ("krylov_restart", ctypes.c_int)]
+                ("fuse_prolong", ctypes.c_int), ("krylov_restart", ctypes.c_int),
+                ("skip_unchanged", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -54,7 +55,8 @@ class Stats(ctypes.Structure):
                 ("rel_residual", ctypes.c_double), ("ms", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double), ("cg_steps", ctypes.c_double),
                 ("refinements", ctypes.c_int), ("first_sweep_ms", ctypes.c_double),
-                ("first_cg_steps", ctypes.c_double)]
+                ("first_cg_steps", ctypes.c_double), ("skipped_blocks", ctypes.c_double),
+                ("unwritten_blocks", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -32,7 +32,7 @@ def test_default_params_valid():
     ("local_iters", 0), ("robin_alpha", 0.0), ("robin_alpha", 1.5),
     ("coarse_sweeps", -1), ("rel_tol", -1.0), ("check_every", 0), ("max_sweeps", 1),
     ("fuse_prolong", 2), ("fuse_prolong", -1), ("method", 3), ("krylov_restart", 0),
-    ("krylov_restart", 17)])
+    ("krylov_restart", 17), ("skip_unchanged", 2), ("skip_unchanged", -1)])
 def test_bad_params_rejected(field, value):
     p = ddi.default_params()
     setattr(p, field, value)
@@ -107,7 +107,9 @@ def test_plan_footprint():
     iterate (12 B per pixel), on each coarser level f, c and two iterates
     (37 B per coarse pixel), the transposed masks (1 bit per pixel and
     level, plus a zero row group) and small partial buffers; bfloat16
-    storage adds three 2-byte planes."""
+    storage adds three 2-byte planes. The unchanged-block flags of the
+    finest level (skip_unchanged) are two int arrays per block and
+    channel."""
     p = ddi.default_params()
     b = ddi.plan_footprint(2160, 3840, 3, p)
     n = 2160 * 3840
@@ -115,8 +117,15 @@ def test_plan_footprint():
     exp = 12 * n + sum(37 * h * w for h, w in sizes[1:])
     exp += sum(8 * ((h + 63) // 64 + 1) * w for h, w in sizes)
     assert exp < b < exp + 2e6
+    nblk = ddi.block_count(2160, 64, 4) * ddi.block_count(3840, 64, 4)
+    p.skip_unchanged = 0
+    b0 = ddi.plan_footprint(2160, 3840, 3, p)
+    assert b - b0 == 2 * nblk * 3 * 4
     p.storage = 1
-    assert ddi.plan_footprint(2160, 3840, 3, p) - b == 3 * 3 * n * 2
+    assert ddi.plan_footprint(2160, 3840, 3, p) - b0 == 3 * 3 * n * 2
+    p.skip_unchanged = 1  # ignored with bfloat16 storage
+    assert ddi.plan_footprint(2160, 3840, 3, p) - b0 == 3 * 3 * n * 2
+    p.storage = 0
     q = ddi.default_params(levels=1)
     assert ddi.plan_footprint(64, 64, 1, q) < ddi.plan_footprint(64, 64, 1, ddi.default_params())
     with pytest.raises(ddi.DDIError):
