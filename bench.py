@@ -734,7 +734,9 @@ def run_batch(args):
                 dt = (time.perf_counter() - ts) * 1e3
                 fl = by = 0.0
                 for (h, w), p, x in zip(sizes, prms, st):
-                    a, bb = sweep_work(p.as_dict(), x["sweeps"], x["cg_steps"], h, w)
+                    a, bb = sweep_work(p.as_dict(), x["sweeps"], x["cg_steps"], h, w,
+                                       skipped=x["skipped_blocks"],
+                                       unwritten=x["unwritten_blocks"])
                     fl += a
                     by += bb
                 with lock:

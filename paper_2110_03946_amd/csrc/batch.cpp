@@ -441,8 +441,9 @@ int enqueue_front(ddi_batch* B, const Front& F) {
 // parities and the decide tables (stop test, and the non-passing test after
 // the last allowed sweep when that is not a check point).
 struct FineTables {
-    std::vector<SweepLaunch> sweep[2];
-    std::vector<SweepLaunch> first;  // sweep 0 with fused prolongations (empty: sweep[0])
+    std::vector<SweepLaunch> sweep[2];  // sweeps 2, 3, ... by parity
+    std::vector<SweepLaunch> early[2];  // sweeps 0 and 1: no unchanged-block flags to read
+    std::vector<SweepLaunch> first;  // sweep 0 with fused prolongations (empty: early[0])
     const DecideJob* decide[2] = {nullptr, nullptr};
     int ndecide = 0;
 };
@@ -473,23 +474,33 @@ void build_fine(ddi_batch* B, const std::vector<int>& act, const std::vector<int
         }
         if (any) put_sweeps(A, jobs, T.first);
     }
-    for (int q = 0; q < 2; ++q) {
-        std::vector<SweepJob> jobs;
-        for (int i : act) {
-            ddi_plan* P = B->plans[i];
-            Level& L0 = P->lv[0];
-            const int c0 = start0[i] ^ q;
-            SweepJob j{};
-            j.uin = L0.u[c0];
-            j.mbits = L0.mbits;
-            j.uout = L0.u[c0 ^ 1];
-            j.partial = P->part;
-            j.cg_steps = B->timing ? P->cgcnt : nullptr;
-            j.ctl = B->ctl + (size_t)i * kCtlInts;
-            j.a = L0.sw;
-            jobs.push_back(j);
+    // sweep k of parity q = k & 1 writes the image's unchanged-block flags
+    // q and, from the third sweep on, reads those of the sweep before
+    // (launch_sweep); images whose plan keeps no flags run every block
+    for (int late = 0; late < 2; ++late) {
+        for (int q = 0; q < 2; ++q) {
+            std::vector<SweepJob> jobs;
+            for (int i : act) {
+                ddi_plan* P = B->plans[i];
+                Level& L0 = P->lv[0];
+                const int c0 = start0[i] ^ q;
+                SweepJob j{};
+                j.uin = L0.u[c0];
+                j.mbits = L0.mbits;
+                j.uout = L0.u[c0 ^ 1];
+                j.partial = P->part;
+                j.cg_steps = B->timing ? P->cgcnt : nullptr;
+                j.ctl = B->ctl + (size_t)i * kCtlInts;
+                j.a = L0.sw;
+                if (P->flg) {
+                    const size_t nfl = (size_t)sweep_partials(L0.sw) * P->C;
+                    j.fout = P->flg + q * nfl;
+                    j.fin = late ? P->flg + (q ^ 1) * nfl : nullptr;
+                }
+                jobs.push_back(j);
+            }
+            put_sweeps(A, jobs, late ? T.sweep[q] : T.early[q]);
         }
-        put_sweeps(A, jobs, T.sweep[q]);
     }
     for (int t = 0; t < 2; ++t) {
         std::vector<DecideJob> jobs;
@@ -513,7 +524,10 @@ int enqueue_fine(ddi_batch* B, const FineTables& T, int from, int to) {
     hipStream_t s = B->s;
     for (int i = from; i < to; ++i) {
         if (B->timing) DDI_HIP(hipEventRecord(B->sweep_ev[2 * i], s));
-        DDI_HIP(run_sweeps(i == 0 && !T.first.empty() ? T.first : T.sweep[i & 1], s));
+        DDI_HIP(run_sweeps(i == 0 && !T.first.empty() ? T.first
+                           : i < 2                      ? T.early[i]
+                                                        : T.sweep[i & 1],
+                           s));
         if (B->timing) DDI_HIP(hipEventRecord(B->sweep_ev[2 * i + 1], s));
         const bool chk = is_check(B, i + 1);
         if (chk || i + 1 == B->max_sweeps)
@@ -749,9 +763,14 @@ int ddi_batch_solve(ddi_batch* B, const float* const* f, const uint8_t* const* c
                                    hipMemcpyDeviceToDevice, s));
         }
         if (B->timing) {
+            // CG steps, whole skips and skipped write-backs (three planes)
             const int nb = sweep_partials(L0.sw);
             DDI_HIP(launch_reduce(P->cgcnt, nb, C, C, P->red + 2 * C + 2, s, true));
-            DDI_HIP(hipMemcpyAsync(P->host + 2 * C + 2, P->red + 2 * C + 2, C * sizeof(double),
+            DDI_HIP(launch_reduce(P->cgcnt + (size_t)nb * C, nb, C, C, P->red + 4 * C + 2, s,
+                                  true));
+            DDI_HIP(launch_reduce(P->cgcnt + 2 * (size_t)nb * C, nb, C, C, P->red + 5 * C + 2,
+                                  s, true));
+            DDI_HIP(hipMemcpyAsync(P->host + 2 * C + 2, P->red + 2 * C + 2, 4 * C * sizeof(double),
                                    hipMemcpyDeviceToHost, s));
         }
     }
@@ -794,9 +813,15 @@ int ddi_batch_solve(ddi_batch* B, const float* const* f, const uint8_t* const* c
             st[i].rel_residual = rel[i];
             st[i].ms = ms;
             st[i].sweep_ms = sweep_ms;
-            double steps = 0.0;
-            for (int k = 0; B->timing && !code[i] && k < C; ++k) steps += P->host[2 * C + 2 + k];
+            double steps = 0.0, skipped = 0.0, unwritten = 0.0;
+            for (int k = 0; B->timing && !code[i] && k < C; ++k) {
+                steps += P->host[2 * C + 2 + k];
+                skipped += P->host[4 * C + 2 + k];
+                unwritten += P->host[5 * C + 2 + k];
+            }
             st[i].cg_steps = steps;
+            st[i].skipped_blocks = skipped;
+            st[i].unwritten_blocks = unwritten;
         }
         if (ret == DDI_OK && code[i] != DDI_OK) ret = code[i];
     }

@@ -98,6 +98,8 @@ struct SweepJob {
     int wg0;
     ProSrc pro;  // pro.uc set: the input is the prolongation of pro (uin unused;
                  // only for jobs with sweep_prolong_ok)
+    const int* fin;  // unchanged-block flags of the previous sweep (or null)
+    int* fout;       // this sweep's flags (or null); as in launch_sweep
 };
 
 // One image at one level for the batched level kernels (coarsening,

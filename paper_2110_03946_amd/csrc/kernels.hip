@@ -1168,7 +1168,7 @@ __global__ __launch_bounds__(128, DDI_SPLIT_WAVES) void k_sweep2_batch(const Swe
                                                J.cg_steps, J.ctl, J.a, lb - J.wg0, lds, &J.pro);
     else
         sweep2_body<false, DDI_SPLIT_QL>(J.uin, nullptr, J.mbits, J.uout, J.partial, J.cg_steps,
-                                         J.ctl, J.a, lb - J.wg0, lds);
+                                         J.ctl, J.a, lb - J.wg0, lds, nullptr, J.fin, J.fout);
 }
 
 // Column-transposed unknown-pixel bits of a mask: word (g, x) holds bit j

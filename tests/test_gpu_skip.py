@@ -153,3 +153,44 @@ def test_skip_ignored_where_it_does_not_apply(ddi):
                 res.append((host(u_t), st["sweeps"]))
         assert res[0][1] == res[1][1]
         np.testing.assert_array_equal(res[0][0], res[1][0])
+
+
+def test_skip_in_batches(ddi):
+    """Batched solves (uneven sizes, mixed mask kinds, images that converge
+    at different sweeps and drop out of the tables, an image whose finest
+    blocks are not 64 rows high) equal the batch without skipping bit for
+    bit, in images and sweep counts; with timing the skipped blocks are
+    counted per image."""
+    C = 3
+    specs = [(540, 960, 0.04, "bernoulli"), (1081, 1923, 0.03, "clustered"),
+             (720, 1280, 0.08, "bernoulli"), (48, 200, 0.1, "bernoulli"),
+             (480, 640, 0.02, "clustered")]
+    data = [synth.make_workload(h, w, C, d, k, workload=78, index=i)
+            for i, (h, w, d, k) in enumerate(specs)]
+    # a tolerance every image reaches (the batch reports counters for
+    # converged images), after 3 to 10 sweeps
+    base = dict(BENCH, rel_tol=3e-4, max_sweeps=40)
+    say("skip in batches")
+    res = {}
+    for skip in (0, 1):
+        for timing in (0, 1):
+            prms = [ddi.default_params(skip_unchanged=skip, timing=timing, **base)
+                    for _ in specs]
+            with ddi.Batch([c.shape for _, c in data], C, params=prms) as b:
+                for rep in range(2):  # the second solve starts in the other buffer
+                    us, st, codes = b.solve([dev(f) for f, _ in data],
+                                            [dev(c) for _, c in data], allow_noconv=True)
+                    res[(skip, timing, rep)] = ([host(u) for u in us], st)
+            say("  skip", skip, "timing", timing, "sweeps", [s["sweeps"] for s in st],
+                "skipped", [s["skipped_blocks"] for s in st])
+    for key, (us, st) in res.items():
+        u0, s0 = res[(0, 0, key[2])]
+        assert [s["sweeps"] for s in st] == [s["sweeps"] for s in s0]
+        for a, b_ in zip(us, u0):
+            np.testing.assert_array_equal(a, b_)
+    st = res[(1, 1, 0)][1]
+    assert sum(s["skipped_blocks"] for s in st) > 0
+    assert sum(s["unwritten_blocks"] for s in st) > 0
+    assert st[3]["skipped_blocks"] == 0 and st[3]["unwritten_blocks"] == 0  # 48 rows
+    for s in res[(0, 1, 0)][1]:
+        assert s["skipped_blocks"] == 0 and s["unwritten_blocks"] == 0
