@@ -138,3 +138,39 @@ def test_krylov_method_needs_float32_storage():
     a = ddi.plan_footprint(540, 960, 3, ddi.default_params(levels=3))
     b = ddi.plan_footprint(540, 960, 3, ddi.default_params(levels=3, method=2, krylov_restart=4))
     assert b - a >= 9 * 3 * 540 * 960 * 4  # 2m + 1 = 9 finest-level vectors
+
+
+def _tiles_in_neighbour_owners(n, size, overlap):
+    """Along one axis: does every block's tile (the block and its one-pixel
+    halo, clamped) lie in pixels owned by the block or its two neighbours?
+    Computed from the oracle's block geometry (Sec. 4, eq. 10)."""
+    import oracle
+    org, s = oracle.block_origins(n, size, overlap)
+    lo, hi = oracle.owner_bounds(org, s, n)
+    nb = len(org)
+    for k, o in enumerate(org):
+        t0, t1 = max(o - 1, 0), min(o + s, n - 1)
+        if t0 < lo[max(k - 1, 0)] or t1 >= hi[min(k + 1, nb - 1)]:
+            return False
+    return True
+
+
+@pytest.mark.parametrize("h,w", [(2160, 3840), (700, 1000), (130, 4000), (64, 64), (65, 300)])
+def test_skip_flags_only_where_tiles_lie_in_the_3x3_neighbourhood(h, w):
+    """A plan keeps the unchanged-block flags of skip_unchanged (two int
+    arrays per block and channel) exactly when its finest level has 64-row
+    blocks and every block's tile lies in the owned pixels of its 3 x 3
+    neighbourhood, the condition under which a block whose neighbourhood
+    the previous sweep left unchanged may be skipped whole. The library's
+    decision is checked against the same condition computed from the
+    oracle's block geometry, over all overlaps."""
+    C = 3
+    for ov in range(0, 64, 3):
+        p = ddi.default_params(overlap=ov, levels=1)
+        p0 = ddi.default_params(overlap=ov, levels=1, skip_unchanged=0)
+        extra = ddi.plan_footprint(h, w, C, p) - ddi.plan_footprint(h, w, C, p0)
+        nblk = ddi.block_count(h, 64, ov) * ddi.block_count(w, 64, ov)
+        bh = min(64, h)
+        expect = (bh == 64 and _tiles_in_neighbour_owners(h, 64, ov)
+                  and _tiles_in_neighbour_owners(w, 64, ov))
+        assert extra == (2 * nblk * C * 4 if expect else 0), (h, w, ov)
