@@ -63,6 +63,11 @@ CASES = [
                                            final_residual=1)),
     # two channels, no local stop: blocks always run CG while r != 0
     (2, 300, 500, 0.1, "bernoulli", dict(levels=2, rel_tol=1e-6, max_sweeps=60)),
+    # four channels (the most a plan takes)
+    (4, 540, 960, 0.04, "clustered", dict(BENCH, rel_tol=1e-5, max_sweeps=40)),
+    # overlap 15 on a 3840-wide level: the last block's tile reaches two
+    # blocks back, so the plan keeps no flags and skips nothing
+    (3, 256, 3840, 0.04, "bernoulli", dict(BENCH, overlap=15, rel_tol=1e-5, max_sweeps=40)),
 ]
 
 
