@@ -488,7 +488,8 @@ int plan_enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0) {
                                &nwg, s));
     else
         DDI_HIP(launch_stats(L0.f, L0.c, P->h, P->w, C, P->part, &nwg, s));
-    DDI_HIP(launch_reduce(P->part, nwg, C + 2, C + 2, P->red, s));
+    // the statistics' column sums (P->part -> P->red) run in the transposed-
+    // mask launch below; nothing writes P->part before it
     for (int l = 1; l + 1 < L; ++l) {
         Level& a = P->lv[l];
         Level& b = P->lv[l + 1];
@@ -505,7 +506,9 @@ int plan_enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0) {
             ws[l] = P->lv[l].w;
         }
         // the same launch clears the stop-test control word of this solve
-        DDI_HIP(launch_mask_bits_levels(L, cs, hs, ws, mbs, s, P->ctl, 4));
+        // and sums the input statistics
+        DDI_HIP(launch_mask_bits_levels(L, cs, hs, ws, mbs, s, P->ctl, 4, P->part, nwg, C + 2,
+                                        C + 2, P->red));
     }
     const int top = L - 1;
     int cur = (top == 0) ? start0 : 0;

@@ -1538,9 +1538,23 @@ struct MaskBitsLevels {
     int h[kMaxLevels], w[kMaxLevels];
     int* clear;  // optional: nclear ints zeroed by the first workgroup
     int nclear;
+    // optional column sums (the k_reduce of the input statistics, folded
+    // into this launch): the extra z slice's workgroup j < ncols writes
+    // out[j] = sum_i part[i * stride + j] in k_reduce's order
+    const double* part;
+    double* out;
+    int nrows, stride, ncols;
 };
 
-__global__ __launch_bounds__(256) void k_mask_bits_levels(MaskBitsLevels L) {
+__global__ __launch_bounds__(256) void k_mask_bits_levels(MaskBitsLevels L, int nlev) {
+    if ((int)blockIdx.z == nlev) {  // the column-sum slice (uniform per workgroup)
+        const int j = blockIdx.x;
+        if (blockIdx.y != 0 || j >= L.ncols) return;
+        double acc[1] = {0.0};
+        for (int i = threadIdx.x; i < L.nrows; i += kTpb) acc[0] += L.part[(int64_t)i * L.stride + j];
+        block_reduce<1>(acc, L.out + j);
+        return;
+    }
     if (L.clear && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 &&
         (int)threadIdx.x < L.nclear)
         L.clear[threadIdx.x] = 0;
@@ -2617,11 +2631,19 @@ hipError_t launch_clear(double* p, int n, hipStream_t s) {
 
 hipError_t launch_mask_bits_levels(int n, const uint8_t* const* c, const int* h, const int* w,
                                   uint64_t* const* mbits, hipStream_t s, int* clear,
-                                  int nclear) {
+                                  int nclear, const double* part, int nrows, int stride,
+                                  int ncols, double* out) {
     if (n < 1 || n > kMaxLevels || nclear < 0 || nclear > 256) return hipErrorInvalidValue;
+    const bool sums = part && out && nrows > 0 && ncols > 0;
+    if (sums && (stride < ncols || ncols > 65535)) return hipErrorInvalidValue;
     MaskBitsLevels L;
     L.clear = nclear > 0 ? clear : nullptr;
     L.nclear = nclear;
+    L.part = part;
+    L.out = out;
+    L.nrows = sums ? nrows : 0;
+    L.stride = stride;
+    L.ncols = sums ? ncols : 0;
     int gx = 1, gy = 1;
     for (int i = 0; i < n; ++i) {
         L.c[i] = c[i];
@@ -2631,7 +2653,9 @@ hipError_t launch_mask_bits_levels(int n, const uint8_t* const* c, const int* h,
         gx = max(gx, (w[i] + 255) / 256);
         gy = max(gy, mask_bit_groups(h[i]));
     }
-    hipLaunchKernelGGL(k_mask_bits_levels, dim3(gx, gy, n), dim3(256), 0, s, L);
+    if (sums) gx = max(gx, ncols);
+    hipLaunchKernelGGL(k_mask_bits_levels, dim3(gx, gy, n + (sums ? 1 : 0)), dim3(256), 0, s, L,
+                       n);
     return hipGetLastError();
 }
 
