@@ -24,7 +24,9 @@
  *   - Pointers named f, c, u, r, ... are DEVICE pointers (HIP global memory,
  *     e.g. the data_ptr() of a torch tensor on a ROCm device). They remain
  *     owned by the caller; the library never frees them. Input and output
- *     buffers must not overlap.
+ *     buffers must not overlap: every call checks the address ranges on the
+ *     host and returns DDI_EINVAL when an output shares a byte with an
+ *     input (or, in a batch, with another image's buffers).
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     Work is enqueued on it; calls that return results on the host
  *     synchronise that stream.
@@ -268,9 +270,9 @@ int ddi_create(ddi_plan** out, int height, int width, int channels,
  * writing the result to u. f: channels x height x width float32; c: height x
  * width uint8; u: like f, fully written, with u = f bit for bit on the mask.
  * Synchronises the plan's stream (stop tests read float64 norms).
- * Errors: DDI_EINVAL (null pointer, mask byte > 1), DDI_ESINGULAR (empty
- * mask), DDI_ENOCONV (u then holds the last iterate and *st is filled),
- * DDI_EHIP. st may be NULL.
+ * Errors: DDI_EINVAL (null pointer, u overlapping f or c, mask byte > 1),
+ * DDI_ESINGULAR (empty mask), DDI_ENOCONV (u then holds the last iterate and
+ * *st is filled), DDI_EHIP. st may be NULL.
  */
 int ddi_solve(ddi_plan* plan, const float* f, const uint8_t* c, float* u,
               ddi_stats* st);

@@ -20,7 +20,8 @@ LIB = os.path.join(HERE, "libddi.so")
 SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "api.cpp"),
            os.path.join(CSRC, "batch.cpp"), os.path.join(CSRC, "mlcg.cpp"),
            os.path.join(CSRC, "krylov.cpp")]
-HEADERS = [os.path.join(CSRC, "internal.h"), os.path.join(ROOT, "include", "ddi.h")]
+HEADERS = [os.path.join(CSRC, "internal.h"), os.path.join(CSRC, "plan.h"),
+           os.path.join(ROOT, "include", "ddi.h")]
 
 
 def hipcc() -> str:

@@ -925,9 +925,15 @@ static int finish_solve(ddi_plan* P, ddi_stats* st) {
     return converged ? DDI_OK : DDI_ENOCONV;
 }
 
+// u (written) must not share memory with f or c (read throughout the solve).
+static bool solve_aliases(const ddi_plan* P, const float* f, const uint8_t* c, const float* u) {
+    const size_t nimg = (size_t)P->C * P->h * P->w * sizeof(float);
+    return overlaps(u, nimg, f, nimg) || overlaps(u, nimg, c, (size_t)P->h * P->w);
+}
+
 int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats* st) {
     if (!P || !f || !c || !u) return DDI_EINVAL;
-    if (P->pend.active) return DDI_EINVAL;
+    if (P->pend.active || solve_aliases(P, f, c, u)) return DDI_EINVAL;
     if (P->p.storage == 1 || P->p.method != 0) {
         Level& L0 = P->lv[0];
         L0.f = f;
@@ -947,7 +953,7 @@ int ddi_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u, ddi_stats
 }
 
 int ddi_solve_async(ddi_plan* P, const float* f, const uint8_t* c, float* u) {
-    if (!P || !f || !c || !u) return DDI_EINVAL;
+    if (!P || !f || !c || !u || solve_aliases(P, f, c, u)) return DDI_EINVAL;
     if (P->pend.active || P->p.storage != 0 || P->p.method != 0) return DDI_EINVAL;
     int e = begin_solve(P, f, c, u);
     if (e) P->pend.active = false;
@@ -999,6 +1005,10 @@ int ddi_residual(const float* f, const uint8_t* c, const float* u, int height, i
     int e = check_dims(height, width, channels);
     if (e) return e;
     if (!f || !c || !u) return DDI_EINVAL;
+    const size_t nimg = (size_t)channels * height * width * sizeof(float);
+    if (overlaps(r, nimg, f, nimg) || overlaps(r, nimg, u, nimg) ||
+        overlaps(r, nimg, c, (size_t)height * width))
+        return DDI_EINVAL;
     if ((e = check_device())) return e;
     hipStream_t s = (hipStream_t)stream;
     const size_t nwg = (size_t)residual_partials(height, width);
@@ -1020,6 +1030,15 @@ int ddi_coarsen(const float* f, const uint8_t* c, int height, int width, int cha
     int e = check_dims(height, width, channels);
     if (e) return e;
     if (!f || !c || !fc || !cc) return DDI_EINVAL;
+    {
+        const size_t nimg = (size_t)channels * height * width * sizeof(float);
+        const size_t ncs = (size_t)((height + 1) / 2) * ((width + 1) / 2);
+        const size_t hw = (size_t)height * width;
+        if (overlaps(fc, channels * ncs * sizeof(float), f, nimg) ||
+            overlaps(fc, channels * ncs * sizeof(float), c, hw) || overlaps(cc, ncs, f, nimg) ||
+            overlaps(cc, ncs, c, hw) || overlaps(fc, channels * ncs * sizeof(float), cc, ncs))
+            return DDI_EINVAL;
+    }
     if ((e = check_device())) return e;
     DDI_HIP(launch_coarsen(f, c, height, width, channels, fc, cc, nullptr, nullptr,
                            (hipStream_t)stream));
@@ -1032,6 +1051,12 @@ int ddi_prolong(const float* uc, int hc, int wc, const float* f, const uint8_t* 
     if (e) return e;
     if (!uc || !f || !c || !u) return DDI_EINVAL;
     if (hc != (height + 1) / 2 || wc != (width + 1) / 2) return DDI_EINVAL;
+    {
+        const size_t nimg = (size_t)channels * height * width * sizeof(float);
+        if (overlaps(u, nimg, uc, (size_t)channels * hc * wc * sizeof(float)) ||
+            overlaps(u, nimg, f, nimg) || overlaps(u, nimg, c, (size_t)height * width))
+            return DDI_EINVAL;
+    }
     if ((e = check_device())) return e;
     DDI_HIP(launch_prolong(uc, hc, wc, f, c, height, width, channels, u, (hipStream_t)stream));
     return DDI_OK;
@@ -1043,6 +1068,11 @@ int ddi_coarse_solve(const float* f, const uint8_t* c, int height, int width, in
     if (e) return e;
     if (!f || !c || !u || max_iter < 1 || !(tol >= 0.0)) return DDI_EINVAL;
     if ((int64_t)height * width > kCoarseMaxPixels) return DDI_EINVAL;
+    {
+        const size_t nimg = (size_t)channels * height * width * sizeof(float);
+        if (overlaps(u, nimg, f, nimg) || overlaps(u, nimg, c, (size_t)height * width))
+            return DDI_EINVAL;
+    }
     if ((e = check_device())) return e;
     DDI_HIP(launch_coarse_cg(f, c, height, width, channels, u, max_iter, tol,
                              (hipStream_t)stream));
@@ -1055,6 +1085,17 @@ int ddi_refine_residual(const float* f, const uint8_t* c, const float* u, const 
     int e = check_dims(height, width, channels);
     if (e) return e;
     if (!f || !c || !u || !rhs || (d && !u_next)) return DDI_EINVAL;
+    {
+        const size_t nimg = (size_t)channels * height * width * sizeof(float);
+        const size_t nb16 = nimg / 2, hw = (size_t)height * width;
+        const void* in[4] = {f, c, u, d};
+        const size_t nin[4] = {nimg, hw, nimg, nb16};
+        for (int i = 0; i < 4; ++i)
+            if (overlaps(rhs, nb16, in[i], nin[i]) ||
+                (d && overlaps(u_next, nimg, in[i], nin[i])))
+                return DDI_EINVAL;
+        if (overlaps(rhs, nb16, u_next, d ? nimg : 0)) return DDI_EINVAL;
+    }
     if ((e = check_device())) return e;
     hipStream_t s = (hipStream_t)stream;
     const size_t nwg = (size_t)residual_partials(height, width);
@@ -1076,7 +1117,13 @@ int ddi_correction_sweep(const uint16_t* d_in, const uint16_t* rhs, const uint8_
                          int overlap, float robin_alpha, int local_iters, void* stream) {
     int e = check_dims(height, width, channels);
     if (e) return e;
-    if (!rhs || !c || !d_out || d_in == d_out) return DDI_EINVAL;
+    if (!rhs || !c || !d_out) return DDI_EINVAL;
+    {
+        const size_t nb16 = (size_t)channels * height * width * sizeof(uint16_t);
+        if (overlaps(d_out, nb16, d_in, nb16) || overlaps(d_out, nb16, rhs, nb16) ||
+            overlaps(d_out, nb16, c, (size_t)height * width))
+            return DDI_EINVAL;
+    }
     if (block < 2 || block > DDI_MAX_BLOCK || overlap < 0 || overlap >= block) return DDI_EINVAL;
     if (!(robin_alpha > 0.f && robin_alpha <= 1.f) || local_iters < 1) return DDI_EINVAL;
     if ((e = check_device())) return e;
@@ -1098,7 +1145,12 @@ int ddi_oras_sweep(const float* u_in, const uint8_t* c, float* u_out, int height
                    double* rsq, void* stream) {
     int e = check_dims(height, width, channels);
     if (e) return e;
-    if (!u_in || !c || !u_out || u_in == u_out) return DDI_EINVAL;
+    if (!u_in || !c || !u_out) return DDI_EINVAL;
+    {
+        const size_t nimg = (size_t)channels * height * width * sizeof(float);
+        if (overlaps(u_out, nimg, u_in, nimg) || overlaps(u_out, nimg, c, (size_t)height * width))
+            return DDI_EINVAL;
+    }
     if (block < 2 || block > DDI_MAX_BLOCK || overlap < 0 || overlap >= block) return DDI_EINVAL;
     if (!(robin_alpha > 0.f && robin_alpha <= 1.f) || local_iters < 1) return DDI_EINVAL;
     if ((e = check_device())) return e;

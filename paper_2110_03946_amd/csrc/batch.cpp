@@ -665,6 +665,19 @@ int ddi_batch_solve(ddi_batch* B, const float* const* f, const uint8_t* const* c
     const int n = B->n, C = B->C;
     for (int i = 0; i < n; ++i)
         if (!f[i] || !c[i] || !u[i]) return DDI_EINVAL;
+    // every output must be disjoint from every input and from the other
+    // outputs: one launch reads and writes all images at once
+    for (int i = 0; i < n; ++i) {
+        const ddi_plan* Pi = B->plans[i];
+        const size_t ni = (size_t)C * Pi->h * Pi->w * sizeof(float);
+        for (int j = 0; j < n; ++j) {
+            const ddi_plan* Pj = B->plans[j];
+            const size_t nj = (size_t)C * Pj->h * Pj->w * sizeof(float);
+            if (overlaps(u[i], ni, f[j], nj) || overlaps(u[i], ni, c[j], (size_t)Pj->h * Pj->w) ||
+                (j != i && overlaps(u[i], ni, u[j], nj)))
+                return DDI_EINVAL;
+        }
+    }
     if (st) std::memset(st, 0, sizeof(*st) * n);
     std::vector<int> code(n, DDI_OK);
     hipStream_t s = B->s;

@@ -42,6 +42,14 @@ int level_count(int h, int w, int levels);
 // DDI_OK for 1 <= h, w; 1 <= channels <= 4; h * w <= 2^30.
 int check_dims(int h, int w, int channels);
 
+// True when the byte ranges [a, a + na) and [b, b + nb) share a byte (null
+// pointers never overlap): outputs of a call must not alias its inputs.
+inline bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    if (!a || !b || !na || !nb) return false;
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
 }  // namespace ddi
 
 #define DDI_HIP(call)                                  \

@@ -313,6 +313,65 @@ def test_error_paths(ddi):
         assert e.value.code == ddi.DDI_ENOCONV
 
 
+def test_aliased_buffers_rejected(ddi):
+    """An output sharing memory with an input (u with f or c; in a batch also
+    with another image's buffers) is DDI_EINVAL before any work is queued,
+    and the plan still solves afterwards."""
+    C, H, W = 2, 40, 56
+    f, c = workload(C, H, W, 0.05, wl=7, idx=3)
+    n = C * H * W
+    buf = torch.zeros(2 * n, dtype=torch.float32, device="cuda")
+    buf[:n] = dev(f).reshape(-1)
+    fd = buf[:n].view(C, H, W)
+    cd = dev(c)
+    cases = {"u is f": fd, "u starts inside f": buf[n // 2:n // 2 + n].view(C, H, W),
+             "u ends inside f": torch.zeros(2 * n, dtype=torch.float32, device="cuda")}
+    with ddi.Plan(H, W, C) as plan:
+        for name, u in cases.items():
+            if name == "u ends inside f":
+                # f placed in the upper half of a buffer whose lower part is u
+                u[n // 2:n // 2 + n] = fd.reshape(-1)
+                fo = u[n // 2:n // 2 + n].view(C, H, W)
+                uo = u[:n].view(C, H, W)
+                args = (fo, cd, uo)
+            else:
+                args = (fd, cd, u)
+            say("alias", name)
+            with pytest.raises(ddi.DDIError) as e:
+                plan.solve(*args)
+            assert e.value.code == ddi.DDI_EINVAL
+            with pytest.raises(ddi.DDIError) as e:
+                plan.solve_async(*args)
+            assert e.value.code == ddi.DDI_EINVAL
+        say("u overlapping c")
+        # c in the first bytes of a float32 buffer whose first n floats are u
+        fbuf = torch.zeros(n + H * W, dtype=torch.float32, device="cuda")
+        cview = fbuf.view(torch.uint8)[:H * W].view(H, W)
+        cview.copy_(cd)
+        with pytest.raises(ddi.DDIError) as e:
+            plan.solve(fd, cview, fbuf[:n].view(C, H, W))
+        assert e.value.code == ddi.DDI_EINVAL
+        # nothing was queued: a proper solve still works
+        u, _ = plan.solve(fd, cd)
+        ex = oracle.solve_exact(f.astype(np.float64), c)
+        assert np.abs(host(u) - ex).max() <= 0.5
+    say("batch: one image's output over another image's input")
+    f2, c2 = workload(C, 24, 32, 0.05, wl=7, idx=4)
+    with ddi.Batch([(H, W), (24, 32)], C) as b:
+        f2d = dev(f2)
+        u1 = torch.empty_like(f2d)
+        with pytest.raises(ddi.DDIError) as e:
+            b.solve([fd, f2d], [cd, dev(c2)], [torch.empty_like(fd), f2d])
+        assert e.value.code == ddi.DDI_EINVAL
+        with pytest.raises(ddi.DDIError) as e:
+            big = torch.empty(n + C * 24 * 32, dtype=torch.float32, device="cuda")
+            b.solve([fd, f2d], [cd, dev(c2)],
+                    [big[:n].view(C, H, W), big[n - 8:n - 8 + C * 24 * 32].view(C, 24, 32)])
+        assert e.value.code == ddi.DDI_EINVAL
+        us, _, _ = b.solve([fd, f2d], [cd, dev(c2)], [torch.empty_like(fd), u1])
+        assert np.abs(host(us[0]) - oracle.solve_exact(f.astype(np.float64), c)).max() <= 0.5
+
+
 @pytest.mark.slow
 def test_config1_4k_rgb_full_size(ddi):
     """4K RGB, 4 % Bernoulli shared mask, 64 x 64 blocks, overlap 4, four
