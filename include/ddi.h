@@ -54,9 +54,14 @@ extern "C" {
 #define DDI_ENOCONV    (-4)  /* max_sweeps reached before rel_tol */
 #define DDI_EHIP       (-5)  /* a HIP runtime call failed */
 #define DDI_ENODEV     (-6)  /* no usable gfx950 device */
+#define DDI_ESCRATCH   (-7)  /* ddi_oras_sweep_noalloc: the call needs more than
+                                DDI_NOALLOC_SCRATCH_BYTES of scratch */
 
 /* Largest block edge (pixels) the on-chip local solver supports. */
 #define DDI_MAX_BLOCK 64
+
+/* Fixed device scratch of ddi_oras_sweep_noalloc, per GPU (4 MiB). */
+#define DDI_NOALLOC_SCRATCH_BYTES (4u << 20)
 
 /* Largest coarsest level (pixels) of the float64 coarse solve. */
 #define DDI_COARSE_MAX_PIXELS 8192
@@ -405,6 +410,28 @@ int ddi_oras_sweep(const float* u_in, const uint8_t* c, float* u_out,
                    int height, int width, int channels, int block,
                    int overlap, float robin_alpha, int local_iters,
                    double* rsq, void* stream);
+
+/*
+ * ddi_oras_sweep for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops or harnesses that forbid hipMalloc). The
+ * same sweep, the same arguments and bit for bit the same u_out and rsq; it
+ * calls no hipMalloc or hipFree. Its scratch (the column-transposed mask
+ * bits, one float64 norm partial per block and channel, and their
+ * per-channel sums) is a fixed array of DDI_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends;
+ * ddi_noalloc_scratch_bytes reports what a call of these sizes needs
+ * (host only). Every call on one GPU shares that GPU's array and leaves its
+ * contents behind: calls that overlap in time on one GPU race (issue them on
+ * one stream, or order them). Synchronises `stream` only when rsq is given.
+ * Errors: DDI_EINVAL (as ddi_oras_sweep, or u_out overlapping u_in or c),
+ * DDI_ESCRATCH (the sizes need more than the fixed scratch), DDI_EHIP.
+ */
+int ddi_noalloc_scratch_bytes(int height, int width, int channels, int block,
+                              int overlap, size_t* bytes);
+int ddi_oras_sweep_noalloc(const float* u_in, const uint8_t* c, float* u_out,
+                           int height, int width, int channels, int block,
+                           int overlap, float robin_alpha, int local_iters,
+                           double* rsq, void* stream);
 
 /*
  * Float64 solve of A u = b (Sec. 2, eq. 6) on a small grid, the solver of

@@ -974,6 +974,7 @@ const char* ddi_strerror(int code) {
         case DDI_ENOCONV: return "no convergence within max_sweeps";
         case DDI_EHIP: return "HIP runtime error";
         case DDI_ENODEV: return "no gfx950 device";
+        case DDI_ESCRATCH: return "input too large for the fixed no-allocation scratch";
         default: return "unknown error";
     }
 }

@@ -26,7 +26,9 @@ DDI_ENOMEM = -3
 DDI_ENOCONV = -4
 DDI_EHIP = -5
 DDI_ENODEV = -6
+DDI_ESCRATCH = -7
 MAX_BLOCK = 64
+NOALLOC_SCRATCH_BYTES = 4 << 20
 COARSE_MAX_PIXELS = 8192
 
 
@@ -102,6 +104,8 @@ def lib():
             "ddi_coarsen": (i, [vp, vp, i, i, i, vp, vp, vp]),
             "ddi_prolong": (i, [vp, i, i, vp, vp, i, i, i, vp, vp]),
             "ddi_oras_sweep": (i, [vp, vp, vp, i, i, i, i, i, f, i, vp, vp]),
+            "ddi_oras_sweep_noalloc": (i, [vp, vp, vp, i, i, i, i, i, f, i, vp, vp]),
+            "ddi_noalloc_scratch_bytes": (i, [i, i, i, i, i, ctypes.POINTER(ctypes.c_size_t)]),
             "ddi_coarse_solve": (i, [vp, vp, i, i, i, vp, i, d, vp]),
             "ddi_plan_footprint": (i, [i, i, i, ctypes.POINTER(Params),
                                        ctypes.POINTER(ctypes.c_size_t)]),
@@ -485,3 +489,29 @@ def oras_sweep(u_in, c, block: int, overlap: int, alpha: float, k: int, u_out=No
                                 float(alpha), k, rsq.ctypes.data_as(ctypes.c_void_p),
                                 _stream(stream)), "ddi_oras_sweep")
     return u_out, rsq
+
+
+def noalloc_scratch_bytes(h: int, w: int, channels: int, block: int, overlap: int) -> int:
+    """Scratch bytes ddi_oras_sweep_noalloc needs for these sizes (host only)."""
+    n = ctypes.c_size_t(0)
+    _check(lib().ddi_noalloc_scratch_bytes(h, w, channels, block, overlap, ctypes.byref(n)),
+           "ddi_noalloc_scratch_bytes")
+    return n.value
+
+
+def oras_sweep_noalloc(u_in, c, block: int, overlap: int, alpha: float, k: int, u_out=None,
+                       stream=None, rsq: bool = True):
+    """ddi_oras_sweep without device allocation (fixed per-GPU scratch); returns
+    (u_out, per-channel ||r||^2 of u_in, or None when rsq is False)."""
+    torch = _torch()
+    u_in = _img(u_in, "u_in")
+    C, H, W = u_in.shape
+    c = _mask(c, (H, W))
+    if u_out is None:
+        u_out = torch.empty_like(u_in)
+    out = np.zeros(C, dtype=np.float64) if rsq else None
+    _check(lib().ddi_oras_sweep_noalloc(_ptr(u_in), _ptr(c), _ptr(u_out), H, W, C, block, overlap,
+                                        float(alpha), k,
+                                        out.ctypes.data_as(ctypes.c_void_p) if rsq else None,
+                                        _stream(stream)), "ddi_oras_sweep_noalloc")
+    return u_out, out
