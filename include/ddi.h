@@ -174,6 +174,17 @@ extern "C" {
  *                  every block's tile lies in its 3 x 3 neighbourhood
  *                  (overlap small against the block size); ignored
  *                  otherwise. 0: every sweep does all its work.
+ *   order_blocks   1: each finest-level ORAS sweep runs its blocks in the
+ *                  order of the local CG steps they needed in the sweep
+ *                  before (the first sweep: in the coarser level's last
+ *                  sweep, over the block's centre), most first, so that the
+ *                  blocks with long local solves start first and do not
+ *                  finish after the rest of the launch. A scheduling choice
+ *                  only: the iterates are bit for bit those of 0. Applies
+ *                  where the finest level has 64-row blocks and fewer than
+ *                  65536 blocks over its channels, at most 1024 per axis
+ *                  (float32 ORAS, storage = 0, method = 0); ignored
+ *                  otherwise.
  */
 typedef struct ddi_params {
     int block;
@@ -203,6 +214,7 @@ typedef struct ddi_params {
     int fuse_prolong;
     int krylov_restart;
     int skip_unchanged;
+    int order_blocks;
 } ddi_params;
 
 /*
@@ -253,7 +265,7 @@ typedef struct ddi_plan ddi_plan;
  * timing = 0, coarse_block = 0, coarse_overlap = -1, coarse_local_iters = 0,
  * local_tol = 0, use_graph = 0, coarse_solver = 0, coarse_cg_iters = 500,
  * coarse_cg_tol = 1e-10, storage = 0, inner_sweeps = 2, method = 0,
- * fuse_prolong = 1, krylov_restart = 8, skip_unchanged = 1. */
+ * fuse_prolong = 1, krylov_restart = 8, skip_unchanged = 1, order_blocks = 1. */
 int ddi_default_params(ddi_params* p);
 
 /* Check *p for one image size without touching the GPU (this includes the

@@ -82,6 +82,33 @@ bool use_skip(const ddi_params& prm, const SweepArgs& a0) {
     return prm.skip_unchanged == 1 && prm.storage == 0 && prm.method == 0 && sweep_skip_ok(a0);
 }
 
+// Level grids of a plan (level 0 = finest).
+static SweepArgs level_sweep(int h, int w, int C, const ddi_params& prm, int l) {
+    for (int i = 0; i < l; ++i) {
+        h = (h + 1) / 2;
+        w = (w + 1) / 2;
+    }
+    if (l == 0) return make_sweep(h, w, C, prm.block, prm.overlap, prm.robin_alpha, 1);
+    const int cb = prm.coarse_block ? prm.coarse_block : prm.block;
+    const int co = prm.coarse_overlap >= 0 ? prm.coarse_overlap : prm.overlap;
+    return make_sweep(h, w, C, cb, co, prm.robin_alpha, 1);
+}
+
+bool use_order(const ddi_params& prm, int h, int w, int C) {
+    // the first finest sweep's dispatch table comes from the level-2 sweep's
+    // CG steps and is built inside the level-1 sweep: three levels of 64-row
+    // blocks, levels 2 and 1 each running a sweep; the table's counting sort
+    // takes grids of < 2^16 blocks
+    if (prm.order_blocks != 1 || prm.storage != 0 || prm.method != 0) return false;
+    const int L = level_count(h, w, prm.levels);
+    if (L < 3 || prm.coarse_sweeps < 1) return false;
+    if (L == 3 && !(prm.coarse_solver == 0 && prm.coarsest_sweeps > 0)) return false;
+    const SweepArgs a0 = level_sweep(h, w, C, prm, 0);
+    return sweep_prolong_ok(a0) && sweep_prolong_ok(level_sweep(h, w, C, prm, 1)) &&
+           sweep_prolong_ok(level_sweep(h, w, C, prm, 2)) &&
+           (int64_t)sweep_partials(a0) * C < 65536 && a0.g.nby + a0.g.nbx <= kOrderMaxAxes;
+}
+
 size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm) {
     const int L = level_count(h, w, prm.levels);
     size_t bytes = 0, part_n = 0;
@@ -110,6 +137,9 @@ size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm) {
     {
         const SweepArgs a0 = make_sweep(h, w, C, prm.block, prm.overlap, prm.robin_alpha, 1);
         if (use_skip(prm, a0)) bytes += 2 * (size_t)sweep_partials(a0) * C * sizeof(int);
+        if (use_order(prm, h, w, C))
+            bytes += ((size_t)sweep_partials(a0) +
+                      (size_t)sweep_partials(level_sweep(h, w, C, prm, 2))) * C * sizeof(int);
     }
     if (prm.storage == 1) bytes += 3 * (size_t)C * h * w * sizeof(uint16_t);
     if (prm.method == 1)
@@ -182,6 +212,7 @@ int ddi_default_params(ddi_params* p) {
     p->fuse_prolong = 1;
     p->krylov_restart = 8;
     p->skip_unchanged = 1;
+    p->order_blocks = 1;
     return DDI_OK;
 }
 
@@ -215,6 +246,7 @@ int ddi_check_params(int height, int width, int channels, const ddi_params* p) {
     if (p->krylov_restart < 1 || p->krylov_restart > kKryMaxM) return DDI_EINVAL;
     if (p->fuse_prolong != 0 && p->fuse_prolong != 1) return DDI_EINVAL;
     if (p->skip_unchanged != 0 && p->skip_unchanged != 1) return DDI_EINVAL;
+    if (p->order_blocks != 0 && p->order_blocks != 1) return DDI_EINVAL;
     if (p->coarse_solver == 1) {
         int hl = height, wl = width;
         for (int l = 1; l < level_count(height, width, p->levels); ++l) {
@@ -248,6 +280,8 @@ int ddi_destroy(ddi_plan* plan) {
     if (plan->red) (void)hipFree(plan->red);
     if (plan->cgcnt) (void)hipFree(plan->cgcnt);
     if (plan->flg) (void)hipFree(plan->flg);
+    if (plan->keys2) (void)hipFree(plan->keys2);
+    if (plan->order) (void)hipFree(plan->order);
     if (plan->ctl) (void)hipFree(plan->ctl);
     if (plan->hctl) (void)hipHostFree(plan->hctl);
     if (plan->host) (void)hipHostFree(plan->host);
@@ -402,6 +436,15 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
             return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
         }
     }
+    if (use_order(prm, height, width, channels)) {
+        const size_t nfl = (size_t)sweep_partials(P->lv[0].sw) * channels;
+        const size_t nk = (size_t)sweep_partials(P->lv[2].sw) * channels;
+        if ((err = hipMalloc(&P->order, nfl * sizeof(int))) != hipSuccess ||
+            (err = hipMalloc(&P->keys2, nk * sizeof(int))) != hipSuccess) {
+            ddi_destroy(P);
+            return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
+        }
+    }
     if (prm.timing) {
         const size_t nc = 3 * (size_t)sweep_partials(P->lv[0].sw) * channels;
         if ((err = hipMalloc(&P->cgcnt, nc * sizeof(double))) != hipSuccess) {
@@ -519,6 +562,7 @@ int plan_enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0) {
         DDI_HIP(launch_init(P->lv[top].f, P->lv[top].c, P->lv[top].h, P->lv[top].w, C,
                             P->lv[top].u[cur], s));
     P->pro0_on = false;
+    P->order_on = false;
     // set: this level's first sweep prolongs from it (only when the level
     // has coarse_sweeps > 0 sweeps to fuse into)
     const ProSrc* from = nullptr;
@@ -527,13 +571,31 @@ int plan_enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0) {
         Level& lev = P->lv[l];
         const int n = (l == top) ? (prm.coarse_solver == 1 ? 0 : prm.coarsest_sweeps)
                                  : prm.coarse_sweeps;
+        // order_blocks: level 2 leaves its blocks' CG steps, and the first
+        // level-1 sweep turns them into the dispatch table of the finest
+        // level's first sweep in an extra workgroup
+        int* kout = (l == 2 && P->keys2) ? P->keys2 : nullptr;
+        OrderArgs job;
+        const OrderArgs* jp = nullptr;
+        if (l == 1 && P->order && n > 0) {
+            job.keys = P->keys2;
+            job.order = P->order;
+            job.g = L0.sw.g;
+            job.cg = P->lv[2].sw.g;
+            job.channels = C;
+            job.scale = 4;
+            jp = &job;
+            P->order_on = true;
+        }
         for (int i = 0; i < n; ++i) {
             if (i == 0 && from)
                 DDI_HIP(launch_sweep_prolong(*from, lev.mbits, lev.u[1 - cur], P->part, nullptr,
-                                             nullptr, lev.sw, s));
+                                             nullptr, lev.sw, s, kout, nullptr,
+                                             i == 0 ? jp : nullptr));
             else
                 DDI_HIP(launch_sweep(lev.u[cur], lev.mbits, lev.u[1 - cur], P->part, nullptr,
-                                     nullptr, lev.sw, s));
+                                     nullptr, lev.sw, s, nullptr, kout, nullptr,
+                                     i == 0 ? jp : nullptr));
             cur ^= 1;
         }
         from = nullptr;
@@ -574,10 +636,17 @@ static int enqueue_sweeps(ddi_plan* P, int from, int to, int start0, bool timing
     double* drel = reinterpret_cast<double*>(ctl + 4);
     for (int i = from; i < to; ++i) {
         const int c0 = start0 ^ (i & 1);
+        // the first sweep runs its blocks in the order built by level 1
+        const int* order = (i == 0 && P->order_on) ? P->order : nullptr;
         if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * i], s));
         if (i == 0 && P->pro0_on)
             DDI_HIP(launch_sweep_prolong(P->pro0, L0.mbits, L0.u[c0 ^ 1], P->part,
-                                         timing ? P->cgcnt : nullptr, ctl, L0.sw, s));
+                                         timing ? P->cgcnt : nullptr, ctl, L0.sw, s, nullptr,
+                                         order));
+        else if (i == 0 && order)
+            DDI_HIP(launch_sweep(L0.u[c0], L0.mbits, L0.u[c0 ^ 1], P->part,
+                                 timing ? P->cgcnt : nullptr, ctl, L0.sw, s, nullptr,
+                                 P->flg ? P->flg + (i & 1) * nb * P->C : nullptr, order));
         else if (P->flg) {
             // sweep i writes the flags of parity i & 1 and reads those of the
             // sweep before (from the third sweep on: the first sweep's

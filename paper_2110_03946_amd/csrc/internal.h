@@ -154,27 +154,45 @@ struct ReduceJob {
 // lanes are columns, rows live in registers).
 constexpr int kMaxBlock = 64;
 
+// Dispatch-table job of a sweep launch (order_run): sort the blocks of grid
+// g (channels x g.nby x g.nbx, channel-major) by the CG steps `keys` of the
+// blocks of a coarser grid cg (scale = fine / coarse pixel size) over their
+// centres, most first, stably, into order[]. A sweep launch that carries a
+// job runs it in one extra workgroup beside its blocks.
+constexpr int kOrderMaxAxes = 2048;  // g.nby + g.nbx of a dispatch-table job
+struct OrderArgs {
+    const int* keys = nullptr;
+    int* order = nullptr;
+    BlockGrid g{}, cg{};
+    int channels = 0, scale = 0;
+};
+
 // One ORAS sweep u_in -> u_out. `mbits` is the column-transposed mask of
 // launch_mask_bits for the same level. When cg_steps is non-null, block b
 // of channel ch adds the number of CG steps it ran to cg_steps[b * C + ch].
 // When ctl is non-null and ctl[0] != 0 the sweep does nothing.
-// Unchanged-block flags (only where sweep_skip_ok): fout (may be null)
-// receives per block (index ch * blocks + b) 1 if the sweep left the block's
-// owned pixels unchanged (no CG step), else 0. fin (may be null) holds the
-// flags of the previous sweep on the same level, whose input was u_out and
-// whose output is u_in: a block that this sweep would leave unchanged and
-// that the previous sweep left unchanged skips its write-back (u_out holds
-// the values already), and a block whose 3 x 3 neighbourhood the previous
-// sweep left unchanged is skipped whole (its partial keeps the previous
-// value, which is its residual norm again). The result is bit for bit that
-// of the sweep without flags. With cg_steps, planes 1 and 2 of cg_steps
+// Block keys (only where sweep_prolong_ok, i.e. 64-row blocks): fout (may
+// be null) receives per block (index ch * blocks + b) the CG steps the block
+// ran; 0 means the sweep left its owned pixels unchanged. fin (may be null;
+// only where sweep_skip_ok) holds the keys of the previous sweep on the
+// same level, whose input was u_out and whose output is u_in: a block that
+// this sweep would leave unchanged and that the previous sweep left
+// unchanged skips its write-back (u_out holds the values already), and a
+// block whose 3 x 3 neighbourhood the previous sweep left unchanged is
+// skipped whole (its partial keeps the previous value, which is its residual
+// norm again). The result is bit for bit that of the sweep without keys.
+// order (may be null; 64-row blocks): a dispatch table (OrderArgs) built
+// before this launch; workgroup i runs block order[i]. job (may be null;
+// 64-row blocks, a table of < 2^16 blocks): a dispatch table for a later
+// sweep, built by this launch. With cg_steps, planes 1 and 2 of cg_steps
 // (offsets blocks * C and 2 * blocks * C) count the blocks skipped whole and
 // those whose write-back was skipped.
 hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
                         double* partial, double* cg_steps, const int* ctl, const SweepArgs& a,
-                        hipStream_t s, const int* fin = nullptr, int* fout = nullptr);
+                        hipStream_t s, const int* fin = nullptr, int* fout = nullptr,
+                        const int* order = nullptr, const OrderArgs* job = nullptr);
 
-// True when a sweep of `a` can use unchanged-block flags: full 64-row
+// True when a sweep of `a` can use unchanged-block keys: full 64-row
 // blocks, each tile inside the owned pixels of its block and its 8
 // neighbours.
 bool sweep_skip_ok(const SweepArgs& a);
@@ -190,7 +208,8 @@ bool sweep_prolong_ok(const SweepArgs& a);
 // exact in float64 (coarse values within a factor 2^26 of their neighbours).
 hipError_t launch_sweep_prolong(const ProSrc& src, const uint64_t* mbits, float* uout,
                                 double* partial, double* cg_steps, const int* ctl,
-                                const SweepArgs& a, hipStream_t s);
+                                const SweepArgs& a, hipStream_t s, int* fout = nullptr,
+                                const int* order = nullptr, const OrderArgs* job = nullptr);
 
 // Device stop test after finest-level sweep n (see k_decide): reduces the
 // sweep's partials, stores max_k ||r_k||^2/||b_k||^2 in rel[0] and, when

@@ -513,6 +513,9 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
 // matvec, and to add their halves of p.q and r.r (wave 0's half first, so
 // both waves hold bitwise equal scalars and take the same branches).
 constexpr int kSplitRows = 32;
+// Floor of the split sweep's local CG: it stops once r.r or p.Ap is at most
+// this (a residual of 1e-15 grey levels per block).
+constexpr float kCgFloor = 1e-30f;
 // LDS floats of a split sweep: the 66 x 66 tile, then the exchange area
 // (two p rows, then the per-wave scalars).
 constexpr int kSplitLds = (2 * kSplitRows + 2) * kTileW + 2 * 64 + 8;
@@ -777,8 +780,8 @@ __device__ __forceinline__ void tile2_store(const Tile2& T, const SweepArgs& a,
 // of the tile.
 // keep: the previous sweep left this block's owned pixels unchanged, so the
 // output buffer already holds the input's values there; a block that then
-// runs no CG step skips its write-back. fout (may be null) receives 1 for a
-// block whose output equals its input on its owned pixels (no CG step).
+// runs no CG step skips its write-back. fout (may be null) receives the CG
+// steps the block ran (0: its output equals its input on its owned pixels).
 template <bool CORR, bool QL, bool F32 = false>
 __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
                                                const void* __restrict__ rhs,
@@ -801,11 +804,19 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
     double* xd = reinterpret_cast<double*>(xs + 4);
 
     // ---- residual of this wave's rows, owned norm ----
+    // The Laplacian as a sum of neighbour differences: near the fixed point
+    // the residual is tiny against the grey values, and differences of
+    // neighbours keep it accurate where (sum of neighbours) - 4 u would
+    // cancel. Each row's contribution to the owned norm is weighted by a
+    // wave-uniform 0/1 factor (one fused multiply-add with a scalar operand
+    // instead of a select and an add).
     float r[RPW], w[RPW];
     float rho_l0 = 0.f, rho_l1 = 0.f, own_l = 0.f;
     const int ry0 = k.y0 + RPW * wi;
     {
-        const int ylo = k.oylo - ry0, yhi = k.oyhi - ry0;
+        // owned rows of this wave as a uniform bit mask
+        const int ylo = max(k.oylo - ry0, 0), yhi = min(k.oyhi - ry0, RPW);
+        const uint32_t ownrows = yhi > ylo ? (uint32_t)(((1ull << (yhi - ylo)) - 1) << ylo) : 0u;
         const float* col = lds + lane + CO + RPW * wi * TW;
         float uup = col[0];
         float uy = col[TW];
@@ -832,7 +843,8 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
             w[y] = uy;
             const float rq = ry * ry;
             if (y & 1) rho_l1 += rq; else rho_l0 += rq;
-            if (y >= ylo && y < yhi) own_l += rq;  // wave-uniform test
+            const uint32_t wrow = ((ownrows >> y) & 1u) ? 0x3f800000u : 0u;  // 1.f or 0
+            own_l = __builtin_fmaf(rq, __uint_as_float(wrow), own_l);
             uup = uy;
             uy = udn;
         }
@@ -863,7 +875,10 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
     float4* qs = reinterpret_cast<float4*>(lds) + wi * (RPW / 4) * 64;
 #pragma unroll
     for (int y = 0; y < RPW; ++y) p[y] = r[y];
-    const float rho_stop = a.local_tol2 * (float)(g.bh * g.bw);
+    // a floor on the local residual and on p.Ap: below it the block's
+    // correction is far under a float32 ulp of any grey value, and the
+    // reciprocals of the CG scalars stay finite
+    const float rho_stop = fmaxf(a.local_tol2 * (float)(g.bh * g.bw), kCgFloor);
     uint32_t mb[RPW / 4];
 #pragma unroll
     for (int j = 0; j < RPW / 4; ++j) mb[j] = mask_bytes(mw, j);
@@ -897,11 +912,14 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
         if (lane == 0) xs[2 + wi] = pqw;
         __syncthreads();
         const float pq = xs[2] + xs[3];
-        if (!(pq > 0.f)) {
+        if (!(pq > kCgFloor)) {
             ++it;
             break;
         }
-        const float alpha = rho / pq;
+        // the CG scalars through one reciprocal (about 1 ulp): a tiny
+        // perturbation of the step lengths, off the critical path of the
+        // exact quotient's scaling and fix-up sequence
+        const float alpha = rho * __builtin_amdgcn_rcpf(pq);
         float rr0 = 0.f, rr1 = 0.f;
         float4 qn;
         if constexpr (QL) qn = qs[lane];
@@ -925,14 +943,14 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
         if (lane == 0) xs[wi] = rrw;
         __syncthreads();
         const float rr = xs[0] + xs[1];
-        const float beta = rr / rho;
+        const float beta = rr * __builtin_amdgcn_rcpf(rho);
         rho = rr;
 #pragma unroll
         for (int y = 0; y < RPW; ++y) p[y] = r[y] + beta * p[y];
     }
 
     if (cg_steps && wi == 0 && lane == 0) cg_steps[(int64_t)k.b * a.channels + k.ch] += (double)it;
-    if (fout && wi == 0 && lane == 0) fout[lb] = it == 0 ? 1 : 0;
+    if (fout && wi == 0 && lane == 0) fout[lb] = it;
     if (keep && it == 0) {  // output already equals the input here
         // timing counters: plane 2 counts blocks whose write-back was skipped
         if (cg_steps && wi == 0 && lane == 0)
@@ -966,13 +984,15 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
 
 // One split block (tile loaded, stored, computed). PRO: the input iterate
 // is the prolongation of pro (uin_v unused).
-// fin (may be null): the previous sweep's flags (1 = block left unchanged,
-// see sweep2_compute), fout those of this sweep. A block whose tile lies in
-// blocks that the previous sweep all left unchanged has the same input as
-// then, so the same residual and again no CG step: it keeps its partial and
-// its output (which already holds these values) and exits. Each tile lies
-// in the owned pixels of its own block and its 8 neighbours (the host
-// passes fin only for grids where this holds).
+// Workgroup position pos runs logical block pos, or with a dispatch table
+// (order_run) the block of entry pos.
+// fin (may be null): the CG steps of the previous sweep's blocks (0 = block
+// left unchanged, see sweep2_compute), fout those of this sweep. A block
+// whose tile lies in blocks that the previous sweep all left unchanged has
+// the same input as then, so the same residual and again no CG step: it
+// keeps its partial and its output (which already holds these values) and
+// exits. Each tile lies in the owned pixels of its own block and its 8
+// neighbours (the host passes fin only for grids where this holds).
 template <bool CORR, bool QL, bool PRO = false, bool F32 = false>
 __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
                                             const void* __restrict__ rhs,
@@ -981,15 +1001,17 @@ __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
                                             double* __restrict__ partial,
                                             double* __restrict__ cg_steps,
                                             const int* __restrict__ ctl, const SweepArgs& a,
-                                            int lb, float* __restrict__ lds,
+                                            int pos, float* __restrict__ lds,
                                             const ProSrc* pro = nullptr,
                                             const int* __restrict__ fin = nullptr,
-                                            int* __restrict__ fout = nullptr) {
-    const Blk k = blk_geo(a, lb);
-    // the control word and the flags are loaded together (uniform loads):
-    // read by both waves, so both take the same decisions
+                                            int* __restrict__ fout = nullptr,
+                                            const int* __restrict__ order = nullptr) {
+    // the control word, the table entry and the keys are uniform loads, read
+    // by both waves, so both take the same decisions
     const int stop = ctl ? ctl[0] : 0;
+    const int lb = order ? order[pos] : pos;
     bool keep = false, same = false;
+    const Blk k = blk_geo(a, lb);
     if (fin) {
         const int nbx = a.g.nbx, nby = a.g.nby;
         const int by = k.b / nbx, bx = k.b - by * nbx;
@@ -997,15 +1019,15 @@ __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
         const int r0 = max(by - 1, 0) * nbx, r1 = by * nbx, r2 = min(by + 1, nby - 1) * nbx;
         const int c0 = max(bx - 1, 0), c2 = min(bx + 1, nbx - 1);
         const int own = F[r1 + bx];
-        const int nb = (F[r0 + c0] & F[r0 + bx] & F[r0 + c2]) & (F[r1 + c0] & F[r1 + c2]) &
-                       (F[r2 + c0] & F[r2 + bx] & F[r2 + c2]);
-        keep = own != 0;
-        same = (own & nb) != 0;
+        const int nb = (F[r0 + c0] | F[r0 + bx] | F[r0 + c2]) | (F[r1 + c0] | F[r1 + c2]) |
+                       (F[r2 + c0] | F[r2 + bx] | F[r2 + c2]);
+        keep = own == 0;
+        same = (own | nb) == 0;
     }
     if (stop != 0) return;
     if (same) {
         if (threadIdx.x == 0) {
-            if (fout) fout[lb] = 1;
+            if (fout) fout[lb] = 0;
             // timing counters: plane 1 counts blocks skipped whole
             if (cg_steps)
                 cg_steps[(int64_t)a.g.nby * a.g.nbx * a.channels + (int64_t)k.b * a.channels +
@@ -1037,6 +1059,134 @@ __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
     sweep2_compute<CORR, QL, F32>(k, mw, rhs, uout_v, partial, cg_steps, a, lds, fout, lb, keep);
 }
 
+// ---------------------------------------------------------------------------
+// Dispatch order of a sweep (blocks with the longest local solves first)
+// ---------------------------------------------------------------------------
+//
+// One workgroup of NT threads sorts the blocks of a grid into kOrderBuckets
+// buckets by a key per block, stably (a counting sort): thread t owns the
+// t-th contiguous run of the logical block order, counts its blocks per
+// bucket in registers, a workgroup-wide exclusive scan of those counts (four
+// 16-bit counters packed per 64-bit word) gives every thread its first rank
+// in each bucket, and the thread then writes its run's blocks to
+// consecutive ranks. Buckets run from the most CG steps down to none. The
+// key of a block is that of the block of a coarser grid over its centre.
+// Equal buckets keep their logical order, so consecutive workgroups still
+// cover neighbouring blocks. sh: LDS for the coarse keys and two axis
+// tables (cap ints); wsum: NT / 64 words of LDS.
+constexpr int kOrderBuckets = 8;
+static_assert(kOrderMaxAxes < kSplitLds, "axis tables of a dispatch table fit in a sweep's LDS");
+
+// Bucket of a block whose coarse block ran `key` CG steps (0 = first).
+__device__ __forceinline__ int order_bucket_of(int key) {
+    return key >= 12 ? 0 : key >= 8 ? 1 : key >= 5 ? 2 : key >= 3 ? 3 : 6 - min(max(key, 0), 2);
+}
+
+// Exclusive scan of v over the workgroup (threads in order); *total gets
+// the workgroup sum.
+template <int NT>
+__device__ __forceinline__ uint64_t order_scan(uint64_t v, uint64_t* wsum, uint64_t* total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint64_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    uint64_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+        const uint64_t t = wsum[w];
+        if (w < wv) before += t;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return before + x - v;
+}
+
+template <int NT>
+__device__ void order_run(const OrderArgs& A, int* __restrict__ sh, int cap,
+                          uint64_t* __restrict__ wsum) {
+    const BlockGrid& g = A.g;
+    const BlockGrid& c = A.cg;
+    const int tid = threadIdx.x;
+    const int nblk = g.nby * g.nbx, n = nblk * A.channels;
+    const int nk = c.nby * c.nbx * A.channels;
+    // coarse block row / column over each fine block's centre
+    int* cby_of = sh;
+    int* cbx_of = sh + g.nby;
+    for (int y = tid; y < g.nby; y += NT)
+        cby_of[y] = min(((block_origin(y, g.sy, g.h, g.bh) + g.bh / 2) / A.scale) / c.sy,
+                        c.nby - 1);
+    for (int x = tid; x < g.nbx; x += NT)
+        cbx_of[x] = min(((block_origin(x, g.sx, g.w, g.bw) + g.bw / 2) / A.scale) / c.sx,
+                        c.nbx - 1);
+    const int* K = A.keys;
+    int* sk = sh + g.nby + g.nbx;
+    if (nk <= cap - g.nby - g.nbx) {
+        for (int i = tid; i < nk; i += NT) sk[i] = A.keys[i];
+        K = sk;
+    }
+    __syncthreads();
+    const int per = (n + NT - 1) / NT;
+    const int lo = min(tid * per, n), hi = min(lo + per, n);
+    const int ch0 = lo / nblk, by0 = (lo - ch0 * nblk) / g.nbx, bx0 = lo - ch0 * nblk - by0 * g.nbx;
+    auto bucket = [&](int ch, int by, int bx) {
+        return order_bucket_of(K[(ch * c.nby + cby_of[by]) * c.nbx + cbx_of[bx]]);
+    };
+    uint64_t c03 = 0, c47 = 0;
+    {
+        int ch = ch0, by = by0, bx = bx0;
+        for (int i = lo; i < hi; ++i) {
+            const int bk = bucket(ch, by, bx);
+            if (bk < 4) c03 += 1ull << (16 * bk); else c47 += 1ull << (16 * (bk - 4));
+            if (++bx == g.nbx) {
+                bx = 0;
+                if (++by == g.nby) { by = 0; ++ch; }
+            }
+        }
+    }
+    uint64_t t03, t47;
+    const uint64_t r03 = order_scan<NT>(c03, wsum, &t03);
+    const uint64_t r47 = order_scan<NT>(c47, wsum, &t47);
+    int rank[kOrderBuckets];
+    {
+        int base = 0;
+#pragma unroll
+        for (int k = 0; k < kOrderBuckets; ++k) {
+            const uint64_t tw = k < 4 ? t03 : t47, rw = k < 4 ? r03 : r47;
+            const int sh16 = 16 * (k & 3);
+            rank[k] = base + (int)((rw >> sh16) & 0xffff);
+            base += (int)((tw >> sh16) & 0xffff);
+        }
+    }
+    int ch = ch0, by = by0, bx = bx0;
+    for (int i = lo; i < hi; ++i) {
+        const int bk = bucket(ch, by, bx);
+        int r = 0;
+#pragma unroll
+        for (int k = 0; k < kOrderBuckets; ++k)
+            if (bk == k) r = rank[k]++;
+        A.order[r] = i;
+        if (++bx == g.nbx) {
+            bx = 0;
+            if (++by == g.nby) { by = 0; ++ch; }
+        }
+    }
+}
+
+// The extra last workgroup of a sweep launch that carries an order job
+// builds the dispatch table of a later sweep instead of running a block.
+__device__ __forceinline__ bool order_job(const OrderArgs& job, float* __restrict__ lds) {
+    if (!job.order || blockIdx.x != gridDim.x - 1) return false;
+    __shared__ uint64_t wsum[2];
+    order_run<128>(job, reinterpret_cast<int*>(lds), kSplitLds, wsum);
+    return true;
+}
+
 #ifndef DDI_SPLIT_QL
 #define DDI_SPLIT_QL 1
 #endif
@@ -1052,10 +1202,14 @@ __global__ __launch_bounds__(128, DDI_SPLIT_WAVES) void k_sweep2(const void* __r
                                                 double* __restrict__ cg_steps,
                                                 const int* __restrict__ ctl, SweepArgs a,
                                                 const int* __restrict__ fin,
-                                                int* __restrict__ fout) {
+                                                int* __restrict__ fout,
+                                                const int* __restrict__ order, OrderArgs job) {
     __shared__ __attribute__((aligned(16))) float lds[kSplitLds];
+    if (order_job(job, lds)) return;
+    const int nwg = gridDim.x - (job.order ? 1 : 0);
     sweep2_body<CORR, DDI_SPLIT_QL>(uin, rhs, mbits, uout, partial, cg_steps, ctl, a,
-                                    xcd_remap(blockIdx.x, gridDim.x), lds, nullptr, fin, fout);
+                                    xcd_remap(blockIdx.x, nwg), lds, nullptr, fin, fout,
+                                    order);
 }
 
 // k_sweep2 whose input iterate is the bilinear prolongation of a coarser
@@ -1065,10 +1219,16 @@ __global__ __launch_bounds__(128, DDI_SPLIT_WAVES) void k_sweep2_pro(ProSrc pro,
                                                     float* __restrict__ uout,
                                                     double* __restrict__ partial,
                                                     double* __restrict__ cg_steps,
-                                                    const int* __restrict__ ctl, SweepArgs a) {
+                                                    const int* __restrict__ ctl, SweepArgs a,
+                                                    int* __restrict__ fout,
+                                                    const int* __restrict__ order,
+                                                    OrderArgs job) {
     __shared__ __attribute__((aligned(16))) float lds[kSplitLds];
+    if (order_job(job, lds)) return;
+    const int nwg = gridDim.x - (job.order ? 1 : 0);
     sweep2_body<false, DDI_SPLIT_QL, true>(nullptr, nullptr, mbits, uout, partial, cg_steps, ctl,
-                                           a, xcd_remap(blockIdx.x, gridDim.x), lds, &pro);
+                                           a, xcd_remap(blockIdx.x, nwg), lds, &pro, nullptr,
+                                           fout, order);
 }
 
 
@@ -2423,11 +2583,13 @@ template <int RPW, bool QLDS, bool MBITS>
 static hipError_t sweep_rpw(const float* uin, const uint64_t* mbits, float* uout,
                             double* partial, double* cg_steps, const int* ctl,
                             const SweepArgs& a, hipStream_t s, const int* fin = nullptr,
-                            int* fout = nullptr) {
+                            int* fout = nullptr, const int* order = nullptr,
+                            const OrderArgs* job = nullptr) {
     const int grid = a.g.nby * a.g.nbx * a.channels;
     if (use_split(a)) {
-        hipLaunchKernelGGL((k_sweep2<false>), dim3(grid), dim3(128), 0, s, uin, nullptr, mbits,
-                           uout, partial, cg_steps, ctl, a, fin, fout);
+        const OrderArgs j = job ? *job : OrderArgs{};
+        hipLaunchKernelGGL((k_sweep2<false>), dim3(grid + (job ? 1 : 0)), dim3(128), 0, s, uin,
+                           nullptr, mbits, uout, partial, cg_steps, ctl, a, fin, fout, order, j);
         return hipGetLastError();
     }
     if (a.g.bh == RPW)
@@ -2447,7 +2609,8 @@ static hipError_t sweep_corr_rpw(const uint16_t* din, const uint16_t* rhs,
     const int grid = a.g.nby * a.g.nbx * a.channels;
     if (use_split(a)) {
         hipLaunchKernelGGL((k_sweep2<true>), dim3(grid), dim3(128), 0, s, din, rhs, mbits, dout,
-                           partial, cg_steps, ctl, a, (const int*)nullptr, (int*)nullptr);
+                           partial, cg_steps, ctl, a, (const int*)nullptr, (int*)nullptr,
+                           (const int*)nullptr, OrderArgs{});
         return hipGetLastError();
     }
     if (a.g.bh == RPW)
@@ -2573,15 +2736,26 @@ hipError_t launch_sweep_corr(const uint16_t* din, const uint16_t* rhs, const uin
     return sweep_corr_rpw<8, false, false>(din, rhs, mbits, dout, partial, cg_steps, ctl, a, s);
 }
 
+static bool order_job_ok(const OrderArgs* job) {
+    // the axis tables live in the sweep's LDS; counts are 16-bit fields
+    return !job || (job->order && job->keys && job->scale >= 1 &&
+                    (int64_t)job->g.nby * job->g.nbx * job->channels < 65536 &&
+                    job->g.nby + job->g.nbx <= kOrderMaxAxes && job->cg.sy >= 1 &&
+                    job->cg.sx >= 1);
+}
+
 hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
                         double* partial, double* cg_steps, const int* ctl, const SweepArgs& a,
-                        hipStream_t s, const int* fin, int* fout) {
+                        hipStream_t s, const int* fin, int* fout, const int* order,
+                        const OrderArgs* job) {
     const int bh = a.g.bh;
     if (a.g.bw < 1 || a.g.bw > kMaxBlock || bh < 1 || bh > kMaxBlock) return hipErrorInvalidValue;
-    if ((fin || fout) && !(use_split(a) && skip_grid_ok(a.g))) return hipErrorInvalidValue;
+    if ((fout || order || job) && !use_split(a)) return hipErrorInvalidValue;
+    if (fin && !(use_split(a) && skip_grid_ok(a.g))) return hipErrorInvalidValue;
+    if (!order_job_ok(job)) return hipErrorInvalidValue;
     if (bh > 32)
         return sweep_rpw<64, true, true>(uin, mbits, uout, partial, cg_steps, ctl, a, s, fin,
-                                         fout);
+                                         fout, order, job);
     if (bh > 16) return sweep_rpw<32, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
     if (bh > 8) return sweep_rpw<16, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
     return sweep_rpw<8, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
@@ -2593,13 +2767,15 @@ bool sweep_skip_ok(const SweepArgs& a) { return use_split(a) && skip_grid_ok(a.g
 
 hipError_t launch_sweep_prolong(const ProSrc& src, const uint64_t* mbits, float* uout,
                                 double* partial, double* cg_steps, const int* ctl,
-                                const SweepArgs& a, hipStream_t s) {
+                                const SweepArgs& a, hipStream_t s, int* fout,
+                                const int* order, const OrderArgs* job) {
     if (!use_split(a) || a.g.bw < 1 || a.g.bw > kMaxBlock || !src.uc || !src.f || !src.c ||
-        src.hc != (a.g.h + 1) / 2 || src.wc != (a.g.w + 1) / 2)
+        src.hc != (a.g.h + 1) / 2 || src.wc != (a.g.w + 1) / 2 || !order_job_ok(job))
         return hipErrorInvalidValue;
     const int grid = a.g.nby * a.g.nbx * a.channels;
-    hipLaunchKernelGGL(k_sweep2_pro, dim3(grid), dim3(128), 0, s, src, mbits, uout, partial,
-                       cg_steps, ctl, a);
+    const OrderArgs j = job ? *job : OrderArgs{};
+    hipLaunchKernelGGL(k_sweep2_pro, dim3(grid + (job ? 1 : 0)), dim3(128), 0, s, src, mbits,
+                       uout, partial, cg_steps, ctl, a, fout, order, j);
     return hipGetLastError();
 }
 

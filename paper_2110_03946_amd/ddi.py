@@ -46,7 +46,7 @@ class Params(ctypes.Structure):
                 ("coarse_cg_tol", ctypes.c_double), ("storage", ctypes.c_int),
                 ("inner_sweeps", ctypes.c_int), ("method", ctypes.c_int),
                 ("fuse_prolong", ctypes.c_int), ("krylov_restart", ctypes.c_int),
-                ("skip_unchanged", ctypes.c_int)]
+                ("skip_unchanged", ctypes.c_int), ("order_blocks", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

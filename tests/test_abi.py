@@ -109,7 +109,8 @@ def test_plan_footprint():
     level, plus a zero row group) and small partial buffers; bfloat16
     storage adds three 2-byte planes. The unchanged-block flags of the
     finest level (skip_unchanged) are two int arrays per block and
-    channel."""
+    channel; the dispatch order (order_blocks) one more (the table of the
+    first finest sweep) plus one per level-2 block and channel (its keys)."""
     p = ddi.default_params()
     b = ddi.plan_footprint(2160, 3840, 3, p)
     n = 2160 * 3840
@@ -118,9 +119,14 @@ def test_plan_footprint():
     exp += sum(8 * ((h + 63) // 64 + 1) * w for h, w in sizes)
     assert exp < b < exp + 2e6
     nblk = ddi.block_count(2160, 64, 4) * ddi.block_count(3840, 64, 4)
+    nblk2 = ddi.block_count(540, 64, 4) * ddi.block_count(960, 64, 4)
+    p.order_blocks = 0
+    b1 = ddi.plan_footprint(2160, 3840, 3, p)
+    assert b - b1 == (nblk + nblk2) * 3 * 4
     p.skip_unchanged = 0
     b0 = ddi.plan_footprint(2160, 3840, 3, p)
-    assert b - b0 == 2 * nblk * 3 * 4
+    assert b1 - b0 == 2 * nblk * 3 * 4
+    p.order_blocks = 1  # ignored with bfloat16 storage
     p.storage = 1
     assert ddi.plan_footprint(2160, 3840, 3, p) - b0 == 3 * 3 * n * 2
     p.skip_unchanged = 1  # ignored with bfloat16 storage
