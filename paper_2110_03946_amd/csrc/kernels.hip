@@ -513,6 +513,10 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
 // matvec, and to add their halves of p.q and r.r (wave 0's half first, so
 // both waves hold bitwise equal scalars and take the same branches).
 constexpr int kSplitRows = 32;
+// Word 3 of a raw buffer resource on gfx950 (32-bit data, no swizzle) and a
+// vector offset that its range check rejects (the load returns 0).
+constexpr int kBufferDword3 = 0x00020000;
+constexpr uint32_t kBufferOutside = 0x80000000u;
 // Floor of the split sweep's local CG: it stops once r.r or p.Ap is at most
 // this (a residual of 1e-15 grey levels per block).
 constexpr float kCgFloor = 1e-30f;
@@ -633,70 +637,87 @@ __device__ __forceinline__ void tile2_load(Tile2& T, const Blk& k, const SweepAr
     T.mhi = (uint32_t)(bits >> 32);
 }
 
-// Bilinear prolongation (Sec. 4, cell-centred) of one fine pixel from the
-// coarse plane: fine row y lies between coarse rows (y - 1) >> 1 and the
-// next, weight 3/4 on the second for even y, 1/4 for odd y (likewise in x);
-// indices clamped to the coarse grid, where both weights then fall on the
-// same value, which float64 sums back exactly. Each coarse row is
-// interpolated in x first, then the two rows in y, in float64, and rounded
-// to float32 once.
-__device__ __forceinline__ double pro_lerp(double a, double b, double t) {
-    return (1.0 - t) * a + t * b;
+// Bilinear prolongation (Sec. 4; cell-centred, the reading this build
+// takes of the paper's coarse-to-fine step): fine pixel y sits at coarse
+// coordinate y/2 - 1/4, so along each axis it mixes the coarse sample y >> 1
+// with weight 3/4 and that sample's neighbour on the fine pixel's side with
+// weight 1/4, the neighbour index clamped to the coarse grid (where both
+// weights fall on one sample, which the mix returns exactly). Columns first,
+// then rows. Each mix is one rounding of the exact weighted sum of two
+// float32 values: the 1/4 product is exact and the 3/4 one is fused.
+__device__ __forceinline__ float pro_mix(float near, float far) {
+    return __builtin_fmaf(0.75f, near, 0.25f * far);
+}
+// Nearer and farther coarse sample of fine index y on an axis of nc samples.
+__device__ __forceinline__ int pro_far(int y, int nc) {
+    return (y & 1) ? min((y >> 1) + 1, nc - 1) : max((y >> 1) - 1, 0);
 }
 __device__ __forceinline__ float pro_pixel(const ProSrc& S, const float* __restrict__ Uc,
                                            int y, int x) {
-    const int r0 = min(max((y - 1) >> 1, 0), S.hc - 1), r1 = min(max(((y - 1) >> 1) + 1, 0), S.hc - 1);
-    const int c0 = min(max((x - 1) >> 1, 0), S.wc - 1), c1 = min(max(((x - 1) >> 1) + 1, 0), S.wc - 1);
-    const double ay = (y & 1) ? 0.25 : 0.75, ax = (x & 1) ? 0.25 : 0.75;
-    const uint32_t o0 = (uint32_t)r0 * (uint32_t)S.wc, o1 = (uint32_t)r1 * (uint32_t)S.wc;
-    const double h0 = pro_lerp(at32(Uc, o0 + c0), at32(Uc, o0 + c1), ax);
-    const double h1 = pro_lerp(at32(Uc, o1 + c0), at32(Uc, o1 + c1), ax);
-    return (float)pro_lerp(h0, h1, ay);
+    const int rn = y >> 1, rf = pro_far(y, S.hc), cn = x >> 1, cf = pro_far(x, S.wc);
+    const float* Rn = Uc + (uint32_t)rn * (uint32_t)S.wc;
+    const float* Rf = Uc + (uint32_t)rf * (uint32_t)S.wc;
+    return pro_mix(pro_mix(Rn[cn], Rn[cf]), pro_mix(Rf[cn], Rf[cf]));
 }
 
 // tile2_load for a first sweep: the tile of the prolonged iterate, built
 // from the coarse plane and f. The wave's 33 rows ybase .. ybase + 32 need
-// coarse rows F0 .. F0 + 17 (F0 = (ybase - 1) >> 1); fine row ybase + j
-// uses rows F0 + ((j + Q) >> 1) and the next, Q = (ybase - 1) & 1, so the
-// 18 x-interpolated coarse rows are shared by the fine rows. Image rows
-// outside the image (tile rows 0 and 65 at the border) are computed
-// clamped and then replaced by their reflection.
+// coarse rows F0 .. F0 + 17 (F0 = (ybase - 1) >> 1): fine row ybase + j
+// takes coarse rows F0 + (s >> 1) (nearer) and the one before or after it
+// (s = 1 + Q + j, Q = (ybase - 1) & 1), so the 18 column-mixed coarse rows
+// are shared by the fine rows. known: bit j set where row j of this lane is
+// a known pixel (its value is f). Every load is a uniform row base plus the
+// lane's column. Image rows outside the image (tile rows 0 and 65 at the
+// border) are computed clamped and then replaced by their reflection.
 template <int Q>
 __device__ __forceinline__ void tile2_prolong_rows(Tile2& T, const ProSrc& S,
                                                    const float* __restrict__ Uc,
                                                    const float* __restrict__ F, int ybase,
                                                    int hmax, uint32_t xc, uint32_t Wd,
-                                                   const bool* known) {
+                                                   uint32_t klo, uint32_t khi) {
     constexpr int RPW = kSplitRows;
     constexpr int NQ = RPW / 2 + 2;
     const int F0 = (ybase - 1) >> 1;
-    const int X = (int)xc;
-    const uint32_t c0 = min(max((X - 1) >> 1, 0), S.wc - 1);
-    const uint32_t c1 = min(max(((X - 1) >> 1) + 1, 0), S.wc - 1);
-    const double ax = (X & 1) ? 0.25 : 0.75;
-    // all loads first: f where known, then the coarse pairs
+    // Buffer loads: the row offset is a scalar operand and the lane's column
+    // the vector offset, so a row costs no vector instruction; a lane that
+    // is not known in a row of f gets an offset past the plane, which the
+    // buffer's range check turns into 0 without a memory access.
+    const uint32_t fbytes = Wd * (uint32_t)(hmax + 1) * 4u;
+    const __amdgpu_buffer_rsrc_t rf =
+        __builtin_amdgcn_make_buffer_rsrc((void*)F, (short)0, (int)fbytes, kBufferDword3);
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)Uc, (short)0, (int)((uint32_t)S.hc * (uint32_t)S.wc * 4u), kBufferDword3);
+    const uint32_t xb = xc * 4u, cnb = (xc >> 1) * 4u, cfb = (uint32_t)pro_far((int)xc, S.wc) * 4u;
+    // all loads first: f (0 where not known), then the coarse pairs
     float fv[RPW + 1];
+    int sel[RPW + 1];
 #pragma unroll
     for (int j = 0; j < RPW + 1; ++j) {
-        const uint32_t y = (uint32_t)min(max(ybase + j, 0), hmax);
-        fv[j] = known[j] ? at32(F, y * Wd + xc) : 0.f;
+        const int y = (j == 0 || j == RPW) ? min(max(ybase + j, 0), hmax) : ybase + j;
+        sel[j] = j < 32 ? __builtin_amdgcn_sbfe((int)klo, j, 1)
+                        : __builtin_amdgcn_sbfe((int)khi, j - 32, 1);
+        const uint32_t off = (xb & (uint32_t)sel[j]) | (kBufferOutside & ~(uint32_t)sel[j]);
+        fv[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                              rf, (int)off, (int)((uint32_t)y * Wd * 4u), 0));
     }
-    float q0[NQ], q1[NQ];
+    float qn[NQ], qf[NQ];
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-        const uint32_t o = (uint32_t)min(max(F0 + i, 0), S.hc - 1) * (uint32_t)S.wc;
-        q0[i] = at32(Uc, o + c0);
-        q1[i] = at32(Uc, o + c1);
+        const int so = (int)((uint32_t)min(max(F0 + i, 0), S.hc - 1) * (uint32_t)S.wc * 4u);
+        qn[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)cnb, so, 0));
+        qf[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)cfb, so, 0));
     }
-    double hq[NQ];
+    float hq[NQ];
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) hq[i] = pro_lerp(q0[i], q1[i], ax);
+    for (int i = 0; i < NQ; ++i) hq[i] = pro_mix(qn[i], qf[i]);
 #pragma unroll
     for (int j = 0; j < RPW + 1; ++j) {
-        const int m = (j + Q) >> 1;
-        const double ay = ((j + Q) & 1) ? 0.75 : 0.25;
-        const float v = (float)pro_lerp(hq[m], hq[m + 1], ay);
-        T.col[j] = known[j] ? fv[j] : v;
+        const int sj = 1 + Q + j;
+        const int in = sj >> 1, ifar = (sj & 1) ? in + 1 : in - 1;
+        const float v = pro_mix(hq[in], hq[ifar]);
+        // known rows take f
+        T.col[j] = __uint_as_float((__float_as_uint(fv[j]) & (uint32_t)sel[j]) |
+                                   (__float_as_uint(v) & ~(uint32_t)sel[j]));
     }
 }
 
@@ -727,19 +748,21 @@ __device__ __forceinline__ void tile2_load_prolong(Tile2& T, const Blk& k, const
     const int ybase = k.y0 - 1 + wi * (RPW + 1);
     const int yh = wi == 0 ? k.y0 - 1 : k.y0 + 2 * RPW;
     const bool hin = wi == 0 ? k.has_top : k.has_bot;
-    const bool hknown = hin && at32(S.c, (uint32_t)min(max(yh, 0), g.h - 1) * Wd + xc) != 0;
-    bool known[RPW + 1];
-#pragma unroll
-    for (int j = 0; j < RPW + 1; ++j) {
-        if (wi == 0)
-            known[j] = j == 0 ? hknown : ((T.mlo >> (j - 1)) & 1u) == 0;
-        else
-            known[j] = j == RPW ? hknown : ((T.mhi >> j) & 1u) == 0;
+    const uint32_t hknown =
+        (hin && at32(S.c, (uint32_t)min(max(yh, 0), g.h - 1) * Wd + xc) != 0) ? 1u : 0u;
+    // bit j of (klo, khi): tile row j of this wave is known
+    uint32_t klo, khi;
+    if (wi == 0) {
+        klo = (~T.mlo << 1) | hknown;
+        khi = (~T.mlo) >> 31;
+    } else {
+        klo = ~T.mhi;
+        khi = hknown;
     }
     if ((ybase - 1) & 1)
-        tile2_prolong_rows<1>(T, S, Uc, F, ybase, g.h - 1, xc, Wd, known);
+        tile2_prolong_rows<1>(T, S, Uc, F, ybase, g.h - 1, xc, Wd, klo, khi);
     else
-        tile2_prolong_rows<0>(T, S, Uc, F, ybase, g.h - 1, xc, Wd, known);
+        tile2_prolong_rows<0>(T, S, Uc, F, ybase, g.h - 1, xc, Wd, klo, khi);
     // reflecting border: the clamped tile row repeats its neighbour
     if (wi == 0 && !k.has_top) T.col[0] = T.col[1];
     if (wi == 1 && !k.has_bot) T.col[RPW] = T.col[RPW - 1];
@@ -1547,12 +1570,13 @@ __global__ __launch_bounds__(kTpb) void k_coarsen4_batch(const LevelJob* __restr
 
 // Prolongation for widths divisible by 4: a thread writes fine pixels
 // (y, 4t .. 4t+3) of all channels with one u32 mask load, float4 loads of f
-// where the mask is set, and float4 stores. Fine x = 2J sits at coarse
-// column J - 1/4 and x = 2J + 1 at J + 1/4, so the four pixels read coarse
-// columns 2t - 1 .. 2t + 2 (clamped) of two coarse rows: one float2 (2t,
-// 2t + 1: in range and 8-byte aligned since the coarse width is even) and
-// two scalars per row and channel. Every load is issued before the first
-// result is computed. Same float64 bilinear expression as k_prolong.
+// where the mask is set, and float4 stores. Fine columns 4t .. 4t+3 mix the
+// coarse columns (2t, 2t-1), (2t, 2t+1), (2t+1, 2t), (2t+1, 2t+2) (nearer
+// first, clamped), so a thread reads coarse columns 2t - 1 .. 2t + 2 of the
+// two coarse rows of fine row y: one float2 (2t, 2t + 1: in range and 8-byte
+// aligned since the coarse width is even) and two scalars per row and
+// channel. Every load is issued before the first result is computed. The
+// same pro_mix expression as the fused first sweep and k_prolong.
 template <int NC>
 __device__ __forceinline__ void prolong4_body(const float* __restrict__ uc, int hc, int wc,
                                               const float* __restrict__ f,
@@ -1563,32 +1587,24 @@ __device__ __forceinline__ void prolong4_body(const float* __restrict__ uc, int 
     const int64_t n = (int64_t)h * w, ncs = (int64_t)hc * wc;
     const int64_t i = (int64_t)y * w + 4 * t;
     const uint32_t m = *reinterpret_cast<const uint32_t*>(c + i);
-    // coarse rows (r0, r1) and the weight of r1
-    const int I = y >> 1;
-    int r0, r1;
-    double ay;
-    if ((y & 1) == 0) {
-        r0 = max(I - 1, 0); r1 = I; ay = I > 0 ? 0.75 : 0.0;
-        if (I == 0) r1 = 0;
-    } else {
-        r0 = I; r1 = min(I + 1, hc - 1); ay = I + 1 < hc ? 0.25 : 0.0;
-    }
+    // nearer and farther coarse rows of fine row y
+    const int rn = y >> 1, rf = pro_far(y, hc);
     const int J0 = 2 * t;
     const int jl = max(J0 - 1, 0), jr = min(J0 + 2, wc - 1);
     // ---- all loads: the coarse values first (unconditional), then f
     // where the mask is set; 32-bit element offsets inside a plane ----
-    float2 m0[NC], m1[NC];
-    float l0[NC], l1[NC], e0[NC], e1[NC];
-    const uint32_t o0 = (uint32_t)r0 * (uint32_t)wc, o1 = (uint32_t)r1 * (uint32_t)wc;
+    float2 mn[NC], mf[NC];
+    float ln[NC], lf[NC], en[NC], ef[NC];
+    const uint32_t on = (uint32_t)rn * (uint32_t)wc, of = (uint32_t)rf * (uint32_t)wc;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         const float* C = uc + k * ncs;
-        m0[k] = *reinterpret_cast<const float2*>(C + (o0 + J0));
-        m1[k] = *reinterpret_cast<const float2*>(C + (o1 + J0));
-        l0[k] = C[o0 + jl];
-        l1[k] = C[o1 + jl];
-        e0[k] = C[o0 + jr];
-        e1[k] = C[o1 + jr];
+        mn[k] = *reinterpret_cast<const float2*>(C + (on + J0));
+        mf[k] = *reinterpret_cast<const float2*>(C + (of + J0));
+        ln[k] = C[on + jl];
+        lf[k] = C[of + jl];
+        en[k] = C[on + jr];
+        ef[k] = C[of + jr];
     }
     float4 fk[NC];
 #pragma unroll
@@ -1597,42 +1613,18 @@ __device__ __forceinline__ void prolong4_body(const float* __restrict__ uc, int 
 #pragma unroll
         for (int k = 0; k < NC; ++k) fk[k] = *reinterpret_cast<const float4*>(f + k * n + i);
     }
-    // per fine pixel b: first coarse column (index into q0/q1) and weight of
-    // the second
-    double ax[4];
-    int c0[4];
-    // x = 4t   -> coarse J0 - 1/4: (J0 - 1, J0), weight 0.75 (0 if J0 == 0)
-    c0[0] = 0; ax[0] = J0 > 0 ? 0.75 : 0.0;
-    // x = 4t+1 -> J0 + 1/4: (J0, J0 + 1), weight 0.25 (0 if J0 + 1 == wc)
-    c0[1] = 1; ax[1] = J0 + 1 < wc ? 0.25 : 0.0;
-    // x = 4t+2 -> J0 + 1 - 1/4: (J0, J0 + 1), weight 0.75
-    c0[2] = 1; ax[2] = 0.75;
-    // x = 4t+3 -> J0 + 1 + 1/4: (J0 + 1, J0 + 2), weight 0.25 (0 at the border)
-    c0[3] = 2; ax[3] = J0 + 2 < wc ? 0.25 : 0.0;
-    if (J0 == 0) c0[0] = 1;  // clamped: coordinate 0 -> column J0 only
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-        // interpolate the four coarse columns in y first, then in x. With
-        // weights in {0, 1/4, 3/4, 1}, float64 holds these sums of float32
-        // values exactly unless their magnitudes differ by more than about
-        // 2^26, so the order does not matter for grey-level data; the
-        // result is rounded to float32 once
-        const double q0[4] = {l0[k], m0[k].x, m0[k].y, e0[k]};
-        const double q1[4] = {l1[k], m1[k].x, m1[k].y, e1[k]};
-        double yv[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) yv[j] = (1.0 - ay) * q0[j] + ay * q1[j];
-        float o[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int a0 = c0[b], a1 = min(c0[b] + 1, 3);
-            o[b] = (float)((1.0 - ax[b]) * yv[a0] + ax[b] * yv[a1]);
-        }
+        // columns first (each coarse row), then rows
+        const float o0 = pro_mix(pro_mix(mn[k].x, ln[k]), pro_mix(mf[k].x, lf[k]));
+        const float o1 = pro_mix(pro_mix(mn[k].x, mn[k].y), pro_mix(mf[k].x, mf[k].y));
+        const float o2 = pro_mix(pro_mix(mn[k].y, mn[k].x), pro_mix(mf[k].y, mf[k].x));
+        const float o3 = pro_mix(pro_mix(mn[k].y, en[k]), pro_mix(mf[k].y, ef[k]));
         float4 out;
-        out.x = (m & 0xffu) ? fk[k].x : o[0];
-        out.y = (m & 0xff00u) ? fk[k].y : o[1];
-        out.z = (m & 0xff0000u) ? fk[k].z : o[2];
-        out.w = (m & 0xff000000u) ? fk[k].w : o[3];
+        out.x = (m & 0xffu) ? fk[k].x : o0;
+        out.y = (m & 0xff00u) ? fk[k].y : o1;
+        out.z = (m & 0xff0000u) ? fk[k].z : o2;
+        out.w = (m & 0xff000000u) ? fk[k].w : o3;
         *reinterpret_cast<float4*>(u + k * n + i) = out;
     }
 }
@@ -1746,10 +1738,10 @@ __global__ __launch_bounds__(kTpb) void k_init(const float* __restrict__ f,
     for (int k = 0; k < channels; ++k) u[k * n + i] = known ? f[k * n + i] : 0.f;
 }
 
-// One thread per coarse cell (I, J) writes the fine pixels 2I + a, 2J + b.
-// Fine pixel y = 2I sits at coarse coordinate I - 1/4 and y = 2I + 1 at
-// I + 1/4 (clamped to the coarse grid), so each output mixes the cell with
-// its neighbour on that side with weights 3/4 and 1/4 per axis.
+// One thread per coarse cell (I, J) writes the fine pixels 2I + a, 2J + b:
+// along each axis the nearer coarse sample is the cell itself and the
+// farther its neighbour on the fine pixel's side (clamped), mixed by
+// pro_mix, columns first.
 __global__ __launch_bounds__(kTpb) void k_prolong(const float* __restrict__ uc, int hc, int wc,
                                                   const float* __restrict__ f,
                                                   const uint8_t* __restrict__ c, int h, int w,
@@ -1762,7 +1754,7 @@ __global__ __launch_bounds__(kTpb) void k_prolong(const float* __restrict__ uc, 
     const int Jm = max(J - 1, 0), Jp = min(J + 1, wc - 1);
     for (int k = 0; k < channels; ++k) {
         const float* C = uc + k * nc;
-        double q[3][3];
+        float q[3][3];
         const int rr[3] = {Im, I, Ip}, cc[3] = {Jm, J, Jp};
 #pragma unroll
         for (int a2 = 0; a2 < 3; ++a2)
@@ -1772,26 +1764,16 @@ __global__ __launch_bounds__(kTpb) void k_prolong(const float* __restrict__ uc, 
         for (int a2 = 0; a2 < 2; ++a2) {
             const int y = 2 * I + a2;
             if (y >= h) break;
-            // coarse rows used by fine row y and the weight of the second
-            const int r0 = (a2 == 0) ? 0 : 1, r1 = (a2 == 0) ? 1 : 2;
-            const bool ey = (a2 == 0) ? (I > 0) : (I + 1 < hc);
-            const double ay = ey ? ((a2 == 0) ? 0.75 : 0.25) : 0.0;
+            const int rf = a2 == 0 ? 0 : 2;  // farther row: above for even y
 #pragma unroll
             for (int b2 = 0; b2 < 2; ++b2) {
                 const int x = 2 * J + b2;
                 if (x >= w) break;
-                const int c0 = (b2 == 0) ? 0 : 1, c1 = (b2 == 0) ? 1 : 2;
-                const bool ex = (b2 == 0) ? (J > 0) : (J + 1 < wc);
-                const double ax = ex ? ((b2 == 0) ? 0.75 : 0.25) : 0.0;
+                const int cf = b2 == 0 ? 0 : 2;
                 const int64_t i = (int64_t)y * w + x;
-                float out;
-                if (c[i] != 0) {
-                    out = f[k * n + i];
-                } else {
-                    const double v = (1.0 - ay) * ((1.0 - ax) * q[r0][c0] + ax * q[r0][c1]) +
-                                     ay * ((1.0 - ax) * q[r1][c0] + ax * q[r1][c1]);
-                    out = (float)v;
-                }
+                const float out = c[i] != 0 ? f[k * n + i]
+                                            : pro_mix(pro_mix(q[1][1], q[1][cf]),
+                                                      pro_mix(q[rf][1], q[rf][cf]));
                 u[k * n + i] = out;
             }
         }

@@ -6,8 +6,16 @@ Tolerances (grey levels, values in [0, 255]):
                 sums of them twice more -> 1e-4 absolute.
   coarsen       bit-exact: the kernel sums <= 4 float32 values in float64
                 (exact) and divides once, as the float64 oracle does.
-  prolong       float64 bilinear weights on both sides, one float32
-                rounding -> 1 float32 ulp (1.6e-5 at 255).
+  prolong       bilinear weights 3/4 and 1/4 per axis. The kernel mixes in
+                float32, columns then rows, each mix one rounding of the
+                exact weighted sum (the 1/4 product is exact, the 3/4 one
+                fused): its result is within 0.5 ulp of the result plus
+                0.5 ulp of the row values it mixes, i.e. within 1.6e-5 of
+                the exact value for grey values below 256; the float64
+                oracle is within 0.5 ulp (7.6e-6). The two float32 results
+                differ by at most 2.3e-5 in exact terms, which in a float32
+                binade below 256 is at most one ulp of 1.5e-5 (two of 7.6e-6
+                below 128) -> 2e-5 absolute.
   ORAS sweep    k float32 CG steps vs float64 ones: 2e-3 absolute (the
                 local corrections are at most a few hundred grey levels and
                 CG on these well-conditioned blocks loses no more than a few
