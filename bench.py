@@ -32,30 +32,39 @@ Inputs are synthetic (paper_2110_03946_amd.synth) and already resident in
 HBM when the timed region starts.
 
 The timed region keeps several frames in flight (4k and precision: four
-plans, batch: three batch plans), each on a stream of its own picked so that
-no two share a hardware queue: one frame's latency-bound kernels run beside
-another's sweeps, and the host's wait for a stop test never idles the GPU.
+plans, each solving a seeded frame of its own; batch: three batch plans),
+each on a stream of its own picked so that no two share a hardware queue:
+one frame's latency-bound kernels run beside another's sweeps, and the
+host's wait for a stop test never idles the GPU. A step of the 4k and
+precision workloads is one frame on every plan (four frames).
 
 Prints one JSON line. Besides the driver's fields it carries
-  roofline      the finest-level ORAS sweep (the dominant kernel): its
-                average duration from HIP events bracketing every such
-                launch on its plan's stream during the timed region (so
-                while it shares the GPU with the other frames), the
-                algorithmic float32 work per launch, and the peak it is
-                held against; `isolated` gives the same kernels timed in
-                synchronous solves one frame at a time;
-  cpu_baseline  the float64 CPU oracle (4k: the same frame; batch: a sample
-                of the images, scaled to frames of the batch's mix);
-  max_err_grey  max |u - u_oracle| on the 0-255 scale (batch: over the
-                sample);
+  roofline      the dominant kernel, the second finest-level ORAS sweep
+                (one full outer iteration: every block runs and writes):
+                its algorithmic bytes (float32 iterate read with the tile
+                overlap re-read, written once, mask bits) over its own
+                kernel duration, recorded by the launch at the kernel's
+                start and end in synchronous solves with nothing else on
+                the GPU; the later sweeps (which skip blocks), the fused
+                first sweep and the same kernel in flight are sub-keys;
+  cpu_baseline  the float64 CPU oracle on the first timed frame, all host
+                threads and (single_core) one thread;
+  max_err_grey  max |u - u_oracle| on the 0-255 scale over every plan's own
+                timed result (batch: one image per autotuned class; serve:
+                one served result per size);
   p50_ms/p99_ms 4k and precision: latency of one frame solved on its own
                 (wall clock of a synchronous solve on a plan without timing
                 events, after the timed region); batch: of a batched solve
-                in flight.
+                in flight;
+  batch, precision, serve
+                compact runs of those workloads (the 4k workload with
+                --legs), each with its own value, error and comparison
+                with the plain single-image path.
 
-Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 5] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu]
                        [--workload 4k|batch|precision|serve|ablation|psnr|scaling]
                        [--frames-in-flight 4] [--batches-in-flight 3]
+                       [--legs batch,precision,serve]
 """
 from __future__ import annotations
 
@@ -194,19 +203,6 @@ def summarize_trace(path: str) -> str:
     return "\n".join(out)
 
 
-def cpu_baseline(f, c, u_gpu):
-    import oracle
-    t0 = time.perf_counter()
-    ex, info = oracle.solve_exact(f.astype(np.float64), c, return_info=True)
-    t = time.perf_counter() - t0
-    diff = np.abs(u_gpu.astype(np.float64) - ex)
-    per_ch = [float(diff[k].max()) for k in range(diff.shape[0])]
-    return {"value": 1.0 / t, "unit": "frames/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": "the full 3840x2160x3 frame: float64 CG on the reduced system to "
-                      f"relative residual 1e-12 per channel ({[i['iters'] for i in info]} "
-                      f"iterations), {t:.1f} s"}, max(per_ch), per_ch
-
-
 def precision_params() -> dict:
     """Parameters of the mixed-precision workload: bfloat16 correction
     storage with float32 refinement steps of 2 correction sweeps, float64
@@ -270,62 +266,106 @@ def concurrent_streams(n: int, candidates: int = 24) -> list:
     return chosen
 
 
-def run_frame(args, workload: str):
+def gen_workers() -> int:
+    """Worker processes for input generation: the host's cores, at most 16."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def overlap_factor(p: dict) -> float:
+    """(S / (S - o))^2: each block reads its S x S tile while owning a
+    (S - o) x (S - o) core, so a full sweep reads every pixel this often."""
+    return (p["block"] / (p["block"] - p["overlap"])) ** 2
+
+
+def full_sweep_bytes(p: dict, h: int = H, w: int = W, ch: int = C) -> float:
+    """Algorithmic HBM bytes of one full finest-level ORAS sweep (every
+    block runs and writes): float32 iterate read with the tile overlap
+    re-read, float32 iterate written once (Boolean partition of unity), and
+    the transposed mask (one bit per pixel, shared by the channels)."""
+    return ch * h * w * (4 * overlap_factor(p) + 4) + h * w / 8
+
+
+def oracle_check(frames, outs):
+    """Max |u - u_oracle| over frames (grey levels) and per channel, and the
+    oracle's wall time and CG iterations on the first frame."""
+    import oracle
+    worst, per_ch, t_first, iters = 0.0, None, None, None
+    for k, ((f, c), u) in enumerate(zip(frames, outs)):
+        t0 = time.perf_counter()
+        ex, info = oracle.solve_exact(f.astype(np.float64), c, return_info=True)
+        t = time.perf_counter() - t0
+        if k == 0:
+            t_first, iters = t, [i["iters"] for i in info]
+        d = np.abs(u.astype(np.float64) - ex)
+        ch = [float(d[i].max()) for i in range(d.shape[0])]
+        per_ch = ch if per_ch is None else [max(x, y) for x, y in zip(per_ch, ch)]
+        worst = max(worst, max(ch))
+    return worst, per_ch, t_first, iters
+
+
+def oracle_one_core(h: int, w: int, density: float, wl: int, idx: int) -> float:
+    """Seconds the float64 oracle takes on channel 0 of a frame with one
+    OpenMP thread (a child process regenerates the frame from its seed)."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r)\n"
+            "from paper_2110_03946_amd import synth\nimport oracle\n"
+            "f, c = synth.make_workload(%d, %d, 1, %r, 'bernoulli', workload=%d, index=%d)\n"
+            "assert oracle.threads() == 1\n"
+            "t = time.perf_counter(); oracle.solve_exact(f[0].astype('float64'), c)\n"
+            "print(time.perf_counter() - t)\n") % (ROOT, h, w, density, wl, idx)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         check=True)
+    return float(out.stdout.strip().splitlines()[-1])
+
+
+def run_frame(args, workload: str) -> dict:
     """One 4K RGB frame per step: the float32 path (4k) or the mixed-precision
-    path (precision)."""
+    path (precision). Every plan in flight solves a frame of its own."""
     import torch
     from paper_2110_03946_amd import ddi, synth
     precision = workload == "precision"
     density = PRECISION_DENSITY if precision else DENSITY
-    f_np, c_np = synth.make_workload(H, W, C, density, "bernoulli", workload=3 if precision else 1)
-    f = torch.from_numpy(f_np).cuda()
-    c = torch.from_numpy(c_np).cuda()
-    u = torch.empty_like(f)
-    prm = precision_params() if precision else solver_params()
-    # several plans, each with a frame in flight on a stream of its own
-    # (float32 path): one frame's latency-bound kernels (coarse levels,
-    # stop tests, reductions) and the load phases of its sweeps run beside
-    # the other frames' sweeps, and the host's wait for one plan's stop test
-    # never leaves the GPU idle
+    wl = 3 if precision else 1
     nplans = args.frames_in_flight
+    print(f"[bench] {workload}: generating {nplans} frames", file=sys.stderr, flush=True)
+    frames = synth.make_workloads([(H, W, C, density, "bernoulli", wl, k) for k in range(nplans)],
+                                  workers=gen_workers())
+    fs = [torch.from_numpy(f).cuda() for f, _ in frames]
+    cs = [torch.from_numpy(c).cuda() for _, c in frames]
+    us = [torch.empty_like(f) for f in fs]
+    prm = precision_params() if precision else solver_params()
+    # several plans, each with a frame of its own in flight on a stream of
+    # its own: one frame's latency-bound kernels (coarse levels, stop tests,
+    # reductions) and the load phases of its sweeps run beside the other
+    # frames' sweeps, and the host's wait for one plan's stop test never
+    # leaves the GPU idle
     streams = concurrent_streams(nplans) if nplans > 1 else [None]
     if len(streams) < nplans:
         print(f"[bench] only {len(streams)} concurrent streams found", file=sys.stderr)
         streams = [streams[i % len(streams)] for i in range(nplans)]
     plans = [ddi.Plan(H, W, C, timing=1, stream=s, **prm) for s in streams]
-    us = [u] + [torch.empty_like(f) for _ in range(nplans - 1)]
     plan = plans[0]
-
     for _ in range(args.warmup):
-        for p, uu in zip(plans, us):
-            p.solve(f, c, uu)
+        for p, f, c, u in zip(plans, fs, cs, us):
+            p.solve(f, c, u)
     torch.cuda.synchronize()
     sweeps_per_solve, rels = [], []
-    acc = {"timed": dict.fromkeys(["sweep_ms", "nsweeps", "steps", "refs", "first_ms",
-                                   "first_steps", "nfirst", "skipped", "unwritten"], 0.0)}
-    acc["isolated"] = dict(acc["timed"])
+    inflight = {"ms": [], "nsweeps": []}
 
-    def account(st, a):
-        # float32 storage: the first finest-level sweep of each solve is a
-        # different kernel (it also computes the prolongation), accounted
-        # on its own; the rest are the steady-state sweep kernel
-        a["sweep_ms"] += st["sweep_ms"] - st["first_sweep_ms"]
-        a["steps"] += st["cg_steps"] - st["first_cg_steps"]
-        a["nsweeps"] += st["sweeps"] - (0 if precision else 1)
-        a["first_ms"] += st["first_sweep_ms"]
-        a["first_steps"] += st["first_cg_steps"]
-        a["nfirst"] += 0 if precision else 1
-        a["refs"] += st["refinements"]
-        a["skipped"] += st["skipped_blocks"]
-        a["unwritten"] += st["unwritten_blocks"]
+    def account(st, times):
+        sweeps_per_solve.append(st["sweeps"])
+        rels.append(st["rel_residual"])
+        if times and len(times) > 1:
+            inflight["ms"].append(times[1])
 
+    # a step is one frame on every plan in flight (nplans frames)
+    nframes = args.steps * nplans
     t0 = time.perf_counter()
     if nplans == 1:
-        for _ in range(args.steps):
-            _, st = plan.solve(f, c, u)
-            account(st, acc["timed"])
-            sweeps_per_solve.append(st["sweeps"])
-            rels.append(st["rel_residual"])
+        for _ in range(nframes):
+            _, st = plan.solve(fs[0], cs[0], us[0])
+            account(st, plan.sweep_times() if not precision else None)
     elif precision:
         # the refinement loop has no asynchronous entry point: one host
         # thread per plan drives synchronous solves (the library call
@@ -336,12 +376,10 @@ def run_frame(args, workload: str):
 
         def worker(k):
             try:
-                for _ in range(k, args.steps, nplans):
-                    _, st = plans[k].solve(f, c, us[k])
+                for _ in range(args.steps):
+                    _, st = plans[k].solve(fs[k], cs[k], us[k])
                     with lock:
-                        account(st, acc["timed"])
-                        sweeps_per_solve.append(st["sweeps"])
-                        rels.append(st["rel_residual"])
+                        account(st, None)
             except Exception as e:  # re-raised in the main thread
                 errors.append(e)
 
@@ -353,24 +391,32 @@ def run_frame(args, workload: str):
         if errors:
             raise errors[0]
     else:
-        for i in range(min(nplans, args.steps)):
-            plans[i].solve_async(f, c, us[i])
-        for i in range(args.steps):
+        for i in range(nplans):
+            plans[i].solve_async(fs[i], cs[i], us[i])
+        for i in range(nframes):
             k = i % nplans
             _, st = plans[k].wait()
-            account(st, acc["timed"])
-            sweeps_per_solve.append(st["sweeps"])
-            rels.append(st["rel_residual"])
-            if i + nplans < args.steps:
-                plans[k].solve_async(f, c, us[k])
+            account(st, plans[k].sweep_times())
+            if i + nplans < nframes:
+                plans[k].solve_async(fs[k], cs[k], us[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    fps = args.steps / elapsed
-    # the kernels' launch durations with the GPU to themselves: synchronous
-    # solves, one frame at a time, on a timed plan
+    fps = nframes / elapsed
+    outs = [u.cpu().numpy() for u in us]  # each plan's own last timed result
+    # the kernels with the GPU to themselves: synchronous solves, one frame
+    # at a time, on a timed plan; the sweep launches record their kernels'
+    # own start and end (no dispatch gap in the bracket)
+    iso = {"t": [], "steps": 0.0, "first_steps": 0.0, "skipped": 0.0, "unwritten": 0.0,
+           "refs": 0, "sweeps": 0}
     for _ in range(20):
-        _, st = plan.solve(f, c, u)
-        account(st, acc["isolated"])
+        _, st = plan.solve(fs[0], cs[0], us[0])
+        iso["t"].append(plan.sweep_times())
+        iso["steps"] += st["cg_steps"] - st["first_cg_steps"]
+        iso["first_steps"] += st["first_cg_steps"]
+        iso["skipped"] += st["skipped_blocks"]
+        iso["unwritten"] += st["unwritten_blocks"]
+        iso["refs"] += st["refinements"]
+        iso["sweeps"] += st["sweeps"]
     for p in plans[1:]:
         p.close()
     # latency of one frame on its own (no other frame queued): wall clock
@@ -378,86 +424,23 @@ def run_frame(args, workload: str):
     lat = []
     with ddi.Plan(H, W, C, **prm) as lat_plan:
         for _ in range(3):
-            lat_plan.solve(f, c, u)
+            lat_plan.solve(fs[0], cs[0], us[0])
         for _ in range(max(10, min(args.steps, 100))):
             ts = time.perf_counter()
-            lat_plan.solve(f, c, u)
+            lat_plan.solve(fs[0], cs[0], us[0])
             lat.append((time.perf_counter() - ts) * 1e3)
     sync_fps = 1e3 / float(np.mean(lat))
-    a = acc["timed"]
-    sweep_ms, nsweeps, steps, refs = a["sweep_ms"], int(a["nsweeps"]), a["steps"], int(a["refs"])
-    first_ms, first_steps, nfirst = a["first_ms"], a["first_steps"], int(a["nfirst"])
-
-    flops, bytes_ = sweep_work(prm, nsweeps, steps, skipped=a["skipped"],
-                               unwritten=a["unwritten"])
+    nb = ddi.block_count(H, prm["block"], prm["overlap"]) * ddi.block_count(W, prm["block"],
+                                                                               prm["overlap"])
     if precision:
-        bytes_ = correction_bytes(prm["inner_sweeps"], refs)
-    roofline = roofline_of(flops, bytes_, sweep_ms, nsweeps)
-    roofline.update({"traffic": None if precision else measured_traffic(),
-                     "kernel": ("k_sweep2<true> (finest-level correction sweep, bf16)"
-                                if precision else "k_sweep2<false> (finest-level ORAS sweep)"),
-                     "cg_steps_per_block_sweep": round(
-                         steps / max(nsweeps, 1) /
-                         (ddi.block_count(H, prm["block"], prm["overlap"]) *
-                          ddi.block_count(W, prm["block"], prm["overlap"]) * C), 2),
-                     # blocks of the steady sweeps skipped whole / without
-                     # their write-back (the previous sweep left them unchanged)
-                     "skipped_block_frac": round(
-                         a["skipped"] / max(nsweeps, 1) /
-                         (ddi.block_count(H, prm["block"], prm["overlap"]) *
-                          ddi.block_count(W, prm["block"], prm["overlap"]) * C), 4),
-                     "unwritten_block_frac": round(
-                         a["unwritten"] / max(nsweeps, 1) /
-                         (ddi.block_count(H, prm["block"], prm["overlap"]) *
-                          ddi.block_count(W, prm["block"], prm["overlap"]) * C), 4)})
-    if not precision and nfirst:
-        # the first sweep of a solve: prolongation fused into the tile load
-        # (algorithmic bytes: the level-1 iterate and f on the known pixels
-        # read, the transposed mask, u written) plus the same local solves
-        fl1, _ = sweep_work(prm, nfirst, first_steps)
-        nknown = int(c_np.sum())
-        fb1 = nfirst * (C * H * W * 4 + C * ((H + 1) // 2) * ((W + 1) // 2) * 4 + C * nknown * 4 +
-                        H * W // 8)
-        r1 = roofline_of(fl1, fb1, first_ms, nfirst)
-        roofline["first_sweep"] = {
-            "kernel": "k_sweep2_pro (first finest-level sweep, bilinear prolongation in the "
-                      "tile load)",
-            "avg_launch_us": r1["avg_launch_us"], "valu_tflops": r1["valu_tflops"],
-            "valu_frac": r1["valu_frac"], "hbm_gbs": r1["hbm_gbs"],
-            "cg_steps_per_block_sweep": round(
-                first_steps / nfirst / (ddi.block_count(H, prm["block"], prm["overlap"]) *
-                                        ddi.block_count(W, prm["block"], prm["overlap"]) * C),
-                2)}
-    # launches in the timed region share the GPU with the other frames in
-    # flight; synchronous solves one frame at a time give the same kernels alone
-    roofline["frames_sharing_gpu"] = nplans
-    if not precision and nfirst:
-        # the finest sweeps' algorithmic bytes over the timed region's wall
-        # clock: what the overlapping launches of all frames sustain together
-        agg = (bytes_ + fb1) / elapsed / 1e9
-        roofline["finest_sweeps_wall_gbs"] = round(agg, 1)
-        roofline["finest_sweeps_wall_frac"] = round(agg / HBM_PEAK_GBS, 4)
-    b = acc["isolated"]
-    if b["nsweeps"]:
-        fi, bi = sweep_work(prm, int(b["nsweeps"]), b["steps"], skipped=b["skipped"],
-                            unwritten=b["unwritten"])
-        if precision:
-            bi = correction_bytes(prm["inner_sweeps"], int(b["refs"]))
-        ri = roofline_of(fi, bi, b["sweep_ms"], int(b["nsweeps"]))
-        roofline["isolated"] = {k: ri[k] for k in ("avg_launch_us", "hbm_gbs", "hbm_frac",
-                                                    "valu_tflops", "valu_frac")}
-        if b["nfirst"]:
-            roofline["isolated"]["first_sweep_avg_launch_us"] = round(
-                b["first_ms"] / b["nfirst"] * 1e3, 2)
-
-    u_np = u.cpu().numpy()
-    if precision:
+        roofline = precision_roofline(prm, iso)
         desc = ("4K RGB 3840x2160x3, 3% Bernoulli mask shared by the channels; bf16 storage of "
                 "the correction and its right-hand side with f32 arithmetic, f32 iterative "
                 "refinement (2 correction sweeps per step), f64 residual norm and f64 solve of "
-                "the coarsest level (6 levels: 120x68)")
+                "the coarsest level")
         dtype = "bf16 storage / f32 compute"
     else:
+        roofline = frame_roofline(prm, iso, inflight, nb, frames[0][1])
         desc = ("4K RGB 3840x2160x3 f32, 4% Bernoulli mask shared by the channels, multilevel "
                 "ORAS (64x64 blocks, overlap 4, 4 levels: coarsest 1/8), CG local solves")
         dtype = "f32"
@@ -465,7 +448,10 @@ def run_frame(args, workload: str):
            "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
-           "config": {"workload": desc, **prm},
+           "config": {"workload": desc, "frames": f"{nplans} distinct seeded frames, one per "
+                                                   "plan in flight",
+                      "step": f"one frame on each of the {nplans} plans ({nplans} frames)",
+                      **prm},
            "p50_ms": round(float(np.percentile(lat, 50)), 3),
            "p99_ms": round(float(np.percentile(lat, 99)), 3),
            "frames_in_flight": nplans,
@@ -474,14 +460,108 @@ def run_frame(args, workload: str):
            "rel_residual_max": max(rels),
            "roofline": roofline}
     if precision:
-        out["refinements_per_solve"] = round(refs / args.steps, 2)
+        out["refinements_per_solve"] = round(iso["refs"] / 20, 2)
     if not args.no_cpu:
-        cb, err, per_ch = cpu_baseline(f_np, c_np, u_np)
-        out["cpu_baseline"] = cb
+        print(f"[bench] {workload}: oracle on the {nplans} timed frames", file=sys.stderr,
+              flush=True)
+        err, per_ch, t_first, iters = oracle_check(frames, outs)
         out["max_err_grey"] = round(err, 4)
         out["max_err_grey_per_channel"] = [round(e, 4) for e in per_ch]
-    print(json.dumps(out), flush=True)
-    plan.close()
+        out["max_err_frames"] = nplans
+        if not precision:
+            import oracle
+            t1 = oracle_one_core(H, W, density, wl, 0)
+            out["cpu_baseline"] = {
+                "value": round(1.0 / t_first, 4), "unit": "frames/s", "cores": oracle.threads(),
+                "kind": "oracle",
+                "sample": "the first timed 3840x2160x3 frame: float64 CG on the reduced system "
+                          f"to relative residual 1e-12 per channel ({iters} iterations), "
+                          f"{t_first:.1f} s",
+                "single_core": {"value": round(1.0 / (3 * t1), 4), "unit": "frames/s",
+                                "cores": 1,
+                                "sample": f"channel 0 of that frame on one thread, {t1:.1f} s, "
+                                          "times 3 channels"}}
+    return out
+
+
+def frame_roofline(prm, iso, inflight, nb, c0) -> dict:
+    """Roofline of the dominant kernel from its own launch durations (sweep
+    launches record the kernel's start and end), alone on the GPU: the
+    second finest sweep, one full outer ORAS iteration in which every block
+    runs and writes (the third sweep skips blocks the second left
+    unchanged and is reported apart)."""
+    full_ms = float(np.mean([x[1] for x in iso["t"]]))
+    first_ms = float(np.mean([x[0] for x in iso["t"]]))
+    later = [v for x in iso["t"] for v in x[2:]]
+    bfull = full_sweep_bytes(prm)
+    gbs = bfull / (full_ms / 1e3) / 1e9
+    # the first sweep: level-1 iterate read, f on the known pixels, the
+    # transposed mask, u written
+    hc, wc = (H + 1) // 2, (W + 1) // 2
+    bfirst = C * H * W * 4 + C * hc * wc * 4 + C * int(c0.sum()) * 4 + H * W / 8
+    r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+         "kernel": "k_sweep2<false>: second finest-level ORAS sweep (one full outer iteration: "
+                   "all 6912 blocks of 64x64 run and write)",
+         "avg_launch_us": round(full_ms * 1e3, 2),
+         "bytes_per_launch": round(bfull),
+         "bytes_model": "C*H*W*(4*(S/(S-o))^2 + 4) + H*W/8: iterate read with the tile "
+                        "overlap re-read (S=64, o=4: 1.138), iterate written once, mask bits",
+         "timing": "kernel start/end recorded by the launch (hipExtLaunchKernel events), 20 "
+                   "synchronous solves, nothing else on the GPU"}
+    if later:
+        # later sweeps skip blocks: credit only the blocks that run, and
+        # the writes they do not skip
+        n_later = len(later)
+        own = H * W / nb
+        # per block and channel: a whole skip saves its tile read, its write
+        # and its share of the mask bits; a skipped write-back its write
+        b_later = (n_later * bfull - iso["skipped"] * own * (4 * overlap_factor(prm) + 4)
+                   - iso["skipped"] * own / 8 / C - iso["unwritten"] * own * 4)
+        ms_later = float(np.sum(later))
+        r["later_sweeps"] = {
+            "avg_launch_us": round(ms_later / n_later * 1e3, 2),
+            "achieved": round(b_later / (ms_later / 1e3) / 1e9, 1),
+            "skipped_block_frac": round(iso["skipped"] / (n_later * nb * C), 4),
+            "unwritten_block_frac": round(iso["unwritten"] / (n_later * nb * C), 4),
+            "bytes_model": "the full-sweep bytes less the blocks skipped whole (their reads, "
+                           "writes and mask bits) and the write-backs skipped"}
+    r["first_sweep"] = {
+        "kernel": "k_sweep2_pro: first finest sweep, bilinear prolongation in the tile load",
+        "avg_launch_us": round(first_ms * 1e3, 2),
+        "achieved": round(bfirst / (first_ms / 1e3) / 1e9, 1),
+        "bytes_per_launch": round(bfirst),
+        "cg_steps_per_block": round(iso["first_steps"] / 20 / (nb * C), 2)}
+    steady_steps = iso["steps"] / 20
+    r["cg_steps_per_block_steady_sweeps"] = round(steady_steps / (nb * C) /
+                                                  max(1, iso["sweeps"] / 20 - 1), 2)
+    if inflight["ms"]:
+        ms = float(np.mean(inflight["ms"]))
+        r["in_flight"] = {"avg_launch_us": round(ms * 1e3, 2),
+                          "achieved": round(bfull / (ms / 1e3) / 1e9, 1),
+                          "note": "the same second sweep during the timed region, sharing the "
+                                  "GPU with the other frames in flight"}
+    r["valu_peak_basis"] = ("78.6 TFLOP/s float32 without packed instructions: 256 CU x 4 SIMD x "
+                            "16 lanes x 2 flop (FMA) x 2.4 GHz; packed FP32 is disabled in this "
+                            "build")
+    return r
+
+
+def precision_roofline(prm, iso) -> dict:
+    """Correction sweeps of the mixed-precision path (k_sweep2<true>):
+    bfloat16 right-hand side read, correction written (and read, except in
+    a step's first sweep), transposed mask."""
+    ms = [v for x in iso["t"] for v in x]
+    if not ms:
+        return None
+    m = prm["inner_sweeps"]
+    per_step = sum(C * H * W * (4 if j == 0 else 6) + H * W / 8 for j in range(m))
+    bytes_ = per_step * iso["refs"]
+    gbs = bytes_ / (float(np.sum(ms)) / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_sweep2<true> (finest-level correction sweep, bf16 storage)",
+            "avg_launch_us": round(float(np.mean(ms)) * 1e3, 2)}
 
 
 SERVE_RATE, SERVE_SECONDS = 120.0, 30.0
@@ -650,19 +730,30 @@ def run_scaling(args):
     print(json.dumps(out), flush=True)
 
 
-def run_serve(args):
+def run_serve(args) -> dict:
     """Poisson stream of mixed-resolution requests through the serving loop
     (slot pools under an HBM budget, graph replays, results copied back to
     host memory), then the same requests all at once (saturation), then the
-    plain single-image path on them."""
+    plain single-image path on them. The first served result of every
+    (size, frame) pair is kept and one per size is checked against the
+    float64 oracle."""
     import torch
     from paper_2110_03946_amd import serve
     reqs, pool_dens = serve.poisson_stream(SERVE_RATE, args.serve_seconds)
-    print(f"[bench] {len(reqs)} requests; generating the frame pool", file=sys.stderr, flush=True)
-    pool = serve.frame_pool(pool_dens)
-    srv = serve.Server(budget_bytes=args.serve_budget_gb << 30)
+    print(f"[bench] serve: {len(reqs)} requests; generating the frame pool", file=sys.stderr,
+          flush=True)
+    pool, host_pool = serve.frame_pool(pool_dens, workers=gen_workers(), keep_host=True)
+    kept = {}
+
+    def on_result(req, u):
+        key = (req.size, req.frame)
+        if key not in kept:
+            kept[key] = u.numpy().copy()
+
+    srv = serve.Server(budget_bytes=args.serve_budget_gb << 30, on_result=on_result)
     srv.warmup(pool)
-    print("[bench] serving the stream in real time", file=sys.stderr, flush=True)
+    kept.clear()
+    print("[bench] serve: the stream in real time", file=sys.stderr, flush=True)
     rt = srv.run(reqs, pool, realtime=True).summary()
     print("[bench] saturation", file=sys.stderr, flush=True)
     sat_reqs, _ = serve.poisson_stream(SERVE_RATE, args.serve_seconds)
@@ -680,7 +771,18 @@ def run_serve(args):
                                   "HIP-graph replays, results copied to host memory"},
            "p50_ms": rt["p50_ms"], "p99_ms": rt["p99_ms"], "realtime": rt, "saturation": sat,
            "plain_single_image_path": plain, "roofline": None}
-    print(json.dumps(out), flush=True)
+    if not args.no_cpu:
+        import oracle
+        err, checked = 0.0, []
+        for size in sorted({k[0] for k in kept}):
+            k = min(kk for kk in kept if kk[0] == size)
+            f, c = host_pool[k[0]][k[1]]
+            ex = oracle.solve_exact(f.astype(np.float64), c)
+            err = max(err, float(np.abs(kept[k].astype(np.float64) - ex).max()))
+            checked.append(f"{size[1]}x{size[0]}")
+        out["max_err_grey"] = round(err, 4)
+        out["max_err_checked"] = f"one served result per size ({', '.join(checked)})"
+    return out
 
 
 BATCH_N, BATCH_SEED = 48, 2
@@ -688,15 +790,25 @@ BATCHES_IN_FLIGHT = 3
 METRIC_BATCH = "batched uneven RGB frames/s at ≤0.5 grey-level err vs FP64"
 
 
-def run_batch(args):
+def batch_class(s: dict) -> str:
+    """Autotuner class of a batch image: size, mask kind, density bucket."""
+    from paper_2110_03946_amd import autotune
+    lo, hi = next((b for b in autotune.DENSITY_BUCKETS if b[0] <= s["density"] <= b[1]),
+                  autotune.DENSITY_BUCKETS[-1])
+    return f'{s["h"]}x{s["w"]}/{s["kind"]}/{lo:.2f}-{hi:.2f}'
+
+
+def run_batch(args) -> dict:
     """48 uneven RGB images in one batched solve per step (autotuned
-    parameters per image class), beside the plain single-image path."""
+    parameters per image class), beside the plain single-image path on the
+    same images; the result of one image per class is checked against the
+    float64 oracle."""
     import torch
     from paper_2110_03946_amd import ddi, synth
     specs = synth.batch_specs(BATCH_N, BATCH_SEED)
-    print(f"[bench] generating {len(specs)} images", file=sys.stderr, flush=True)
-    data = [synth.make_workload(s["h"], s["w"], C, s["density"], s["kind"], workload=BATCH_SEED,
-                                index=s["index"]) for s in specs]
+    print(f"[bench] batch: generating {len(specs)} images", file=sys.stderr, flush=True)
+    data = synth.make_workloads([(s["h"], s["w"], C, s["density"], s["kind"], BATCH_SEED,
+                                  s["index"]) for s in specs], workers=gen_workers())
     fs = [torch.from_numpy(f).cuda() for f, _ in data]
     cs = [torch.from_numpy(c).cuda() for _, c in data]
     us = [torch.empty_like(f) for f in fs]
@@ -817,44 +929,55 @@ def run_batch(args):
            "sweeps_per_image": [min(sweeps), max(sweeps)],
            "roofline": roofline}
     if not args.no_cpu:
+        # one image of every autotuned class (size x mask kind x density
+        # bucket) present in the batch, against the float64 oracle
         import oracle
         seen, sample = set(), []
-        for i, s in enumerate(specs):
-            if (s["h"], s["w"]) not in seen:
-                seen.add((s["h"], s["w"]))
+        for i, sp in enumerate(specs):
+            k = batch_class(sp)
+            if k not in seen:
+                seen.add(k)
                 sample.append(i)
+        print(f"[bench] batch: oracle on {len(sample)} images (one per class)", file=sys.stderr,
+              flush=True)
         t = 0.0
-        err = 0.0
+        err, per_class = 0.0, {}
         for i in sample:
             f, c = data[i]
             t0 = time.perf_counter()
             ex = oracle.solve_exact(f.astype(np.float64), c)
             t += time.perf_counter() - t0
-            err = max(err, float(np.abs(us[i].cpu().numpy().astype(np.float64) - ex).max()))
+            e = float(np.abs(us[i].cpu().numpy().astype(np.float64) - ex).max())
+            per_class[batch_class(specs[i])] = round(e, 4)
+            err = max(err, e)
         spix = sum(specs[i]["h"] * specs[i]["w"] for i in sample)
         out["cpu_baseline"] = {
             "value": round(spix / t / (npix / len(specs)), 4), "unit": "frames/s",
             "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"images {sample} (one per size, {spix / 1e6:.1f} Mpx, {t:.1f} s): float64 "
-                      "CG to relative residual 1e-12; pixel rate scaled to frames of the "
-                      "batch's mean size"}
+            "sample": f"{len(sample)} images, one per autotuned class ({spix / 1e6:.1f} Mpx, "
+                      f"{t:.1f} s): float64 CG to relative residual 1e-12; pixel rate scaled "
+                      "to frames of the batch's mean size"}
         out["max_err_grey"] = round(err, 4)
+        out["max_err_grey_per_class"] = per_class
     b.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--frames-in-flight", type=int, default=FRAMES_IN_FLIGHT,
                     help="4k and precision workloads: plans (one stream each) with a frame in flight")
     ap.add_argument("--batches-in-flight", type=int, default=BATCHES_IN_FLIGHT,
                     help="batch workload: batch plans (one stream and host thread each)")
     ap.add_argument("--workload", choices=["4k", "batch", "precision", "serve", "ablation", "psnr",
                                            "scaling"], default="4k")
+    ap.add_argument("--legs", default="batch,precision,serve",
+                    help="4k workload: compact runs of these workloads added to the line as "
+                         "keys (comma list; empty for none)")
     ap.add_argument("--serve-seconds", type=float, default=SERVE_SECONDS)
     ap.add_argument("--serve-budget-gb", type=int, default=16)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -881,17 +1004,17 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": 4 * n}), flush=True)
         return
-    from paper_2110_03946_amd import build, ddi, synth
+    from paper_2110_03946_amd import build
     if not os.path.exists(build.LIB):
         build.build()
     if not torch.cuda.is_available():
         print("no GPU", file=sys.stderr)
         sys.exit(1)
     if args.workload == "batch":
-        run_batch(args)
+        print(json.dumps(run_batch(args)), flush=True)
         return
     if args.workload == "serve":
-        run_serve(args)
+        print(json.dumps(run_serve(args)), flush=True)
         return
     if args.workload == "ablation":
         run_ablation(args)
@@ -902,8 +1025,33 @@ def main():
     if args.workload == "scaling":
         run_scaling(args)
         return
+    if args.workload == "precision":
+        print(json.dumps(run_frame(args, "precision")), flush=True)
+        return
 
-    run_frame(args, args.workload)
+    out = run_frame(args, "4k")
+    # compact runs of the other workloads, each against the plain
+    # single-image path on the same GPU where it has one
+    legs = [x for x in args.legs.split(",") if x]
+    for leg in legs:
+        t0 = time.perf_counter()
+        sub = argparse.Namespace(**vars(args))
+        if leg == "batch":
+            sub.steps, sub.warmup = 6, 1
+            r = run_batch(sub)
+        elif leg == "precision":
+            sub.steps, sub.warmup = 20, 2
+            r = run_frame(sub, "precision")
+        elif leg == "serve":
+            sub.serve_seconds = 5.0
+            r = run_serve(sub)
+        else:
+            raise SystemExit(f"unknown leg {leg!r}")
+        r["leg_wall_s"] = round(time.perf_counter() - t0, 1)
+        out[leg] = r
+        print(f"[bench] leg {leg}: {r['value']} {r['unit']} ({r['leg_wall_s']} s)",
+              file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

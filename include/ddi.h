@@ -368,6 +368,13 @@ const char* ddi_strerror(int code);
  * (0 if none). */
 int ddi_last_hip_error(void);
 
+/* With timing = 1: the device time of each finest-level ORAS sweep of the
+ * plan's last float32 solve (storage = 0, method = 0), from events that the
+ * sweep launch itself records at the kernel's start and end: ms[i] for
+ * sweep i < n, *count (may be NULL) = sweeps of that solve (0 without
+ * timing). Host only. */
+int ddi_sweep_times(const ddi_plan* plan, double* ms, int n, int* count);
+
 /* Geometry of the block grid the solver uses on an n-pixel axis: number of
  * blocks, and origin / owned range [lo, hi) of block k (k < count). Host
  * only; lets callers and tests check the partition of unity (eq. 10). */

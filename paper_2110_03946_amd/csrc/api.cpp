@@ -638,15 +638,18 @@ static int enqueue_sweeps(ddi_plan* P, int from, int to, int start0, bool timing
         const int c0 = start0 ^ (i & 1);
         // the first sweep runs its blocks in the order built by level 1
         const int* order = (i == 0 && P->order_on) ? P->order : nullptr;
-        if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * i], s));
+        // with timing, the launch records the kernel's own start and end
+        hipEvent_t ev0 = timing ? P->sweep_ev[2 * i] : nullptr;
+        hipEvent_t ev1 = timing ? P->sweep_ev[2 * i + 1] : nullptr;
         if (i == 0 && P->pro0_on)
             DDI_HIP(launch_sweep_prolong(P->pro0, L0.mbits, L0.u[c0 ^ 1], P->part,
                                          timing ? P->cgcnt : nullptr, ctl, L0.sw, s, nullptr,
-                                         order));
+                                         order, nullptr, ev0, ev1));
         else if (i == 0 && order)
             DDI_HIP(launch_sweep(L0.u[c0], L0.mbits, L0.u[c0 ^ 1], P->part,
                                  timing ? P->cgcnt : nullptr, ctl, L0.sw, s, nullptr,
-                                 P->flg ? P->flg + (i & 1) * nb * P->C : nullptr, order));
+                                 P->flg ? P->flg + (i & 1) * nb * P->C : nullptr, order, nullptr,
+                                 ev0, ev1));
         else if (P->flg) {
             // sweep i writes the flags of parity i & 1 and reads those of the
             // sweep before (from the third sweep on: the first sweep's
@@ -655,12 +658,12 @@ static int enqueue_sweeps(ddi_plan* P, int from, int to, int start0, bool timing
             DDI_HIP(launch_sweep(L0.u[c0], L0.mbits, L0.u[c0 ^ 1], P->part,
                                  timing ? P->cgcnt : nullptr, ctl, L0.sw, s,
                                  i >= 2 ? P->flg + ((i - 1) & 1) * nfl : nullptr,
-                                 P->flg + (i & 1) * nfl));
+                                 P->flg + (i & 1) * nfl, nullptr, nullptr, ev0, ev1));
         } else {
             DDI_HIP(launch_sweep(L0.u[c0], L0.mbits, L0.u[c0 ^ 1], P->part,
-                                 timing ? P->cgcnt : nullptr, ctl, L0.sw, s));
+                                 timing ? P->cgcnt : nullptr, ctl, L0.sw, s, nullptr, nullptr,
+                                 nullptr, nullptr, ev0, ev1));
         }
-        if (timing) DDI_HIP(hipEventRecord(P->sweep_ev[2 * i + 1], s));
         if (timing && i == 0)  // the first sweep's CG steps on their own
             DDI_HIP(launch_reduce(P->cgcnt, nb, P->C, P->C, P->red + 3 * P->C + 2, s));
         if (is_check(prm, i + 1) || i + 1 == prm.max_sweeps)
@@ -973,10 +976,12 @@ static int finish_solve(ddi_plan* P, ddi_stats* st) {
     float ms = 0.f;
     DDI_HIP(hipEventElapsedTime(&ms, P->e0, end));
     double sweep_ms = 0.0, first_ms = 0.0;
+    P->sweep_ms.clear();
     for (int i = 0; q.timing && i < sweeps; ++i) {
         float t = 0.f;
         DDI_HIP(hipEventElapsedTime(&t, P->sweep_ev[2 * i], P->sweep_ev[2 * i + 1]));
         sweep_ms += t;
+        P->sweep_ms.push_back(t);
         if (i == 0) first_ms = t;
     }
     if (st) {
@@ -1049,6 +1054,14 @@ const char* ddi_strerror(int code) {
 }
 
 int ddi_last_hip_error(void) { return g_last_hip; }
+
+int ddi_sweep_times(const ddi_plan* P, double* ms, int n, int* count) {
+    if (!P || n < 0 || (n > 0 && !ms)) return DDI_EINVAL;
+    const int m = (int)P->sweep_ms.size();
+    for (int i = 0; i < std::min(n, m); ++i) ms[i] = P->sweep_ms[i];
+    if (count) *count = m;
+    return DDI_OK;
+}
 
 int ddi_block_count(int n, int block, int overlap) {
     if (n < 1 || block < 1 || overlap < 0 || overlap >= block) return DDI_EINVAL;

@@ -187,10 +187,13 @@ struct OrderArgs {
 // sweep, built by this launch. With cg_steps, planes 1 and 2 of cg_steps
 // (offsets blocks * C and 2 * blocks * C) count the blocks skipped whole and
 // those whose write-back was skipped.
+// ev0, ev1 (both or neither): timing events recorded by the launch itself
+// at the kernel's start and end.
 hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
                         double* partial, double* cg_steps, const int* ctl, const SweepArgs& a,
                         hipStream_t s, const int* fin = nullptr, int* fout = nullptr,
-                        const int* order = nullptr, const OrderArgs* job = nullptr);
+                        const int* order = nullptr, const OrderArgs* job = nullptr,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // True when a sweep of `a` can use unchanged-block keys: full 64-row
 // blocks, each tile inside the owned pixels of its block and its 8
@@ -209,7 +212,8 @@ bool sweep_prolong_ok(const SweepArgs& a);
 hipError_t launch_sweep_prolong(const ProSrc& src, const uint64_t* mbits, float* uout,
                                 double* partial, double* cg_steps, const int* ctl,
                                 const SweepArgs& a, hipStream_t s, int* fout = nullptr,
-                                const int* order = nullptr, const OrderArgs* job = nullptr);
+                                const int* order = nullptr, const OrderArgs* job = nullptr,
+                                hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Device stop test after finest-level sweep n (see k_decide): reduces the
 // sweep's partials, stores max_k ||r_k||^2/||b_k||^2 in rel[0] and, when

@@ -17,6 +17,8 @@
 // All reductions run in a fixed order, so results are bitwise reproducible.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 namespace ddi {
@@ -2561,26 +2563,38 @@ static bool skip_grid_ok(const BlockGrid& g) {
 }
 
 
+// A launch, or with timing events (ev0, ev1 non-null) a launch whose
+// dispatch packet records the kernel's own start and end in them (no
+// dispatch gap inside the bracket).
+template <class K, class... Args>
+static hipError_t launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t ev0,
+                               hipEvent_t ev1, Args... args) {
+    if (ev0 && ev1)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, ev0, ev1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    return hipGetLastError();
+}
+
 template <int RPW, bool QLDS, bool MBITS>
 static hipError_t sweep_rpw(const float* uin, const uint64_t* mbits, float* uout,
                             double* partial, double* cg_steps, const int* ctl,
                             const SweepArgs& a, hipStream_t s, const int* fin = nullptr,
                             int* fout = nullptr, const int* order = nullptr,
-                            const OrderArgs* job = nullptr) {
+                            const OrderArgs* job = nullptr, hipEvent_t ev0 = nullptr,
+                            hipEvent_t ev1 = nullptr) {
     const int grid = a.g.nby * a.g.nbx * a.channels;
     if (use_split(a)) {
         const OrderArgs j = job ? *job : OrderArgs{};
-        hipLaunchKernelGGL((k_sweep2<false>), dim3(grid + (job ? 1 : 0)), dim3(128), 0, s, uin,
-                           nullptr, mbits, uout, partial, cg_steps, ctl, a, fin, fout, order, j);
-        return hipGetLastError();
+        return launch_timed(k_sweep2<false>, dim3(grid + (job ? 1 : 0)), dim3(128), s, ev0, ev1,
+                            (const void*)uin, (const uint16_t*)nullptr, mbits, (void*)uout,
+                            partial, cg_steps, ctl, a, fin, fout, order, j);
     }
     if (a.g.bh == RPW)
-        hipLaunchKernelGGL((k_sweep<RPW, false, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
-                           uin, mbits, uout, partial, cg_steps, ctl, a);
-    else
-        hipLaunchKernelGGL((k_sweep<RPW, true, QLDS, MBITS>), dim3(grid), dim3(64), 0, s,
-                           uin, mbits, uout, partial, cg_steps, ctl, a);
-    return hipGetLastError();
+        return launch_timed(k_sweep<RPW, false, QLDS, MBITS>, dim3(grid), dim3(64), s, ev0, ev1,
+                            uin, mbits, uout, partial, cg_steps, ctl, a);
+    return launch_timed(k_sweep<RPW, true, QLDS, MBITS>, dim3(grid), dim3(64), s, ev0, ev1, uin,
+                        mbits, uout, partial, cg_steps, ctl, a);
 }
 
 template <int RPW, bool QLDS, bool MBITS>
@@ -2729,7 +2743,7 @@ static bool order_job_ok(const OrderArgs* job) {
 hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
                         double* partial, double* cg_steps, const int* ctl, const SweepArgs& a,
                         hipStream_t s, const int* fin, int* fout, const int* order,
-                        const OrderArgs* job) {
+                        const OrderArgs* job, hipEvent_t ev0, hipEvent_t ev1) {
     const int bh = a.g.bh;
     if (a.g.bw < 1 || a.g.bw > kMaxBlock || bh < 1 || bh > kMaxBlock) return hipErrorInvalidValue;
     if ((fout || order || job) && !use_split(a)) return hipErrorInvalidValue;
@@ -2737,10 +2751,15 @@ hipError_t launch_sweep(const float* uin, const uint64_t* mbits, float* uout,
     if (!order_job_ok(job)) return hipErrorInvalidValue;
     if (bh > 32)
         return sweep_rpw<64, true, true>(uin, mbits, uout, partial, cg_steps, ctl, a, s, fin,
-                                         fout, order, job);
-    if (bh > 16) return sweep_rpw<32, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
-    if (bh > 8) return sweep_rpw<16, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
-    return sweep_rpw<8, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s);
+                                         fout, order, job, ev0, ev1);
+    if (bh > 16)
+        return sweep_rpw<32, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s, nullptr,
+                                           nullptr, nullptr, nullptr, ev0, ev1);
+    if (bh > 8)
+        return sweep_rpw<16, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s, nullptr,
+                                           nullptr, nullptr, nullptr, ev0, ev1);
+    return sweep_rpw<8, false, false>(uin, mbits, uout, partial, cg_steps, ctl, a, s, nullptr,
+                                      nullptr, nullptr, nullptr, ev0, ev1);
 }
 
 bool sweep_prolong_ok(const SweepArgs& a) { return use_split(a); }
@@ -2750,15 +2769,15 @@ bool sweep_skip_ok(const SweepArgs& a) { return use_split(a) && skip_grid_ok(a.g
 hipError_t launch_sweep_prolong(const ProSrc& src, const uint64_t* mbits, float* uout,
                                 double* partial, double* cg_steps, const int* ctl,
                                 const SweepArgs& a, hipStream_t s, int* fout,
-                                const int* order, const OrderArgs* job) {
+                                const int* order, const OrderArgs* job, hipEvent_t ev0,
+                                hipEvent_t ev1) {
     if (!use_split(a) || a.g.bw < 1 || a.g.bw > kMaxBlock || !src.uc || !src.f || !src.c ||
         src.hc != (a.g.h + 1) / 2 || src.wc != (a.g.w + 1) / 2 || !order_job_ok(job))
         return hipErrorInvalidValue;
     const int grid = a.g.nby * a.g.nbx * a.channels;
     const OrderArgs j = job ? *job : OrderArgs{};
-    hipLaunchKernelGGL(k_sweep2_pro, dim3(grid + (job ? 1 : 0)), dim3(128), 0, s, src, mbits,
-                       uout, partial, cg_steps, ctl, a, fout, order, j);
-    return hipGetLastError();
+    return launch_timed(k_sweep2_pro, dim3(grid + (job ? 1 : 0)), dim3(128), s, ev0, ev1, src,
+                        mbits, uout, partial, cg_steps, ctl, a, fout, order, j);
 }
 
 hipError_t launch_decide(const double* partial, int nb, int channels, const double* stats,

@@ -96,6 +96,7 @@ struct ddi_plan {
     };
     Pending pend;
     std::vector<hipEvent_t> sweep_ev;  // 2 per finest-level sweep (timing)
+    std::vector<double> sweep_ms;      // device ms of each finest sweep, last solve
     int last_sweeps = -1;              // finest-level sweeps of the previous solve
     // graph mode: a plan-owned stream, and the instantiated graph of the
     // solve's first batch with the key it was captured for

@@ -98,6 +98,7 @@ def lib():
             "ddi_solve_wait": (i, [vp, ctypes.POINTER(Stats)]),
             "ddi_strerror": (ctypes.c_char_p, [i]),
             "ddi_last_hip_error": (i, []),
+            "ddi_sweep_times": (i, [vp, ctypes.POINTER(d), i, ip]),
             "ddi_block_count": (i, [i, i, i]),
             "ddi_block_range": (i, [i, i, i, i, ip, ip, ip]),
             "ddi_residual": (i, [vp, vp, vp, i, i, i, vp, vp, vp]),
@@ -270,6 +271,14 @@ class Plan:
         if rc != DDI_OK and not (allow_noconv and rc == DDI_ENOCONV):
             raise DDIError(rc, "ddi_solve_wait")
         return u, st.as_dict()
+
+    def sweep_times(self) -> list:
+        """Device ms of each finest-level sweep of the last solve (timing = 1)."""
+        n = ctypes.c_int(0)
+        _check(lib().ddi_sweep_times(self._h, None, 0, ctypes.byref(n)), "ddi_sweep_times")
+        buf = (ctypes.c_double * max(n.value, 1))()
+        _check(lib().ddi_sweep_times(self._h, buf, n.value, ctypes.byref(n)), "ddi_sweep_times")
+        return list(buf[:n.value])
 
     def device_bytes(self) -> int:
         n = ctypes.c_size_t()

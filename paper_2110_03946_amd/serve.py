@@ -72,17 +72,24 @@ def poisson_stream(rate: float, duration: float, seed: int = 4, mix=SERVE_MIX,
     return out, pool_dens
 
 
-def frame_pool(pool_dens, channels: int = 3, workload: int = 4):
-    """Device-resident input frames: {(h, w): [(f, c), ...]}."""
+def frame_pool(pool_dens, channels: int = 3, workload: int = 4, workers: int = 0,
+               keep_host: bool = False):
+    """Device-resident input frames: {(h, w): [(f, c), ...]} (generated in
+    `workers` processes when > 1); with keep_host also the host copies, as
+    a second dict of the same shape."""
     import torch
-    pool = {}
+    args = [(h, w, channels, float(d), "bernoulli", workload, 1000 * (h // 10) + k)
+            for (h, w), dens in pool_dens.items() for k, d in enumerate(dens)]
+    data = iter(synth.make_workloads(args, workers=workers))
+    pool, host = {}, {}
     for (h, w), dens in pool_dens.items():
-        pool[(h, w)] = []
-        for k, d in enumerate(dens):
-            f, c = synth.make_workload(h, w, channels, float(d), "bernoulli", workload=workload,
-                                       index=1000 * (h // 10) + k)
+        pool[(h, w)], host[(h, w)] = [], []
+        for _ in dens:
+            f, c = next(data)
             pool[(h, w)].append((torch.from_numpy(f).cuda(), torch.from_numpy(c).cuda()))
-    return pool
+            if keep_host:
+                host[(h, w)].append((f, c))
+    return (pool, host) if keep_host else pool
 
 
 @dataclass

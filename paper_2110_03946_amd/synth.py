@@ -36,8 +36,8 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["make_image", "make_mask", "make_workload", "image_seed", "mask_seed",
-           "batch_specs", "BATCH_SIZES"]
+__all__ = ["make_image", "make_mask", "make_workload", "make_workloads", "image_seed",
+           "mask_seed", "batch_specs", "BATCH_SIZES"]
 
 
 def image_seed(workload: int, index: int = 0) -> int:
@@ -110,6 +110,25 @@ def make_workload(h: int, w: int, channels: int, density: float,
     f = make_image(h, w, channels, image_seed(workload, index))
     c = make_mask(h, w, density, kind, mask_seed(workload, index))
     return f, c
+
+
+def _workload_args(a):
+    return make_workload(*a)
+
+
+def make_workloads(args, workers: int = 0):
+    """make_workload for each argument tuple of `args` (h, w, channels,
+    density, kind, workload, index), in worker processes started fresh
+    (spawn: they import numpy and this module only) when workers > 1;
+    the results are identical to sequential calls."""
+    args = [tuple(a) for a in args]
+    if workers <= 1 or len(args) <= 1:
+        return [make_workload(*a) for a in args]
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=min(workers, len(args)),
+                             mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_workload_args, args))
 
 
 # (height, width) of the batch recipe
