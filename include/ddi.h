@@ -175,11 +175,13 @@ extern "C" {
  *                  (overlap small against the block size); ignored
  *                  otherwise. 0: every sweep does all its work.
  *   order_blocks   1: each finest-level ORAS sweep runs its blocks in the
- *                  order of the local CG steps they needed in the sweep
- *                  before (the first sweep: in the coarser level's last
- *                  sweep, over the block's centre), most first, so that the
- *                  blocks with long local solves start first and do not
- *                  finish after the rest of the launch. A scheduling choice
+ *                  order of the local CG steps that the sweep of the level
+ *                  two below the finest needed over the block's centre,
+ *                  most first, so that the blocks with long local solves
+ *                  start first and do not finish after the rest of the
+ *                  launch (where the coarse level found the error large,
+ *                  the later finest sweeps also need most steps). A
+ *                  scheduling choice
  *                  only: the iterates are bit for bit those of 0. Applies
  *                  where the finest level has 64-row blocks and fewer than
  *                  65536 blocks over its channels, at most 1024 per axis

@@ -95,7 +95,7 @@ static SweepArgs level_sweep(int h, int w, int C, const ddi_params& prm, int l) 
 }
 
 bool use_order(const ddi_params& prm, int h, int w, int C) {
-    // the first finest sweep's dispatch table comes from the level-2 sweep's
+    // the finest sweeps' dispatch table comes from the level-2 sweep's
     // CG steps and is built inside the level-1 sweep: three levels of 64-row
     // blocks, levels 2 and 1 each running a sweep; the table's counting sort
     // takes grids of < 2^16 blocks
@@ -636,8 +636,10 @@ static int enqueue_sweeps(ddi_plan* P, int from, int to, int start0, bool timing
     double* drel = reinterpret_cast<double*>(ctl + 4);
     for (int i = from; i < to; ++i) {
         const int c0 = start0 ^ (i & 1);
-        // the first sweep runs its blocks in the order built by level 1
-        const int* order = (i == 0 && P->order_on) ? P->order : nullptr;
+        // every sweep runs its blocks in the order built by level 1: the
+        // blocks the coarse level found heavy stay the ones that take most
+        // CG steps in the later sweeps too, so they start first in each
+        const int* order = P->order_on ? P->order : nullptr;
         // with timing, the launch records the kernel's own start and end
         hipEvent_t ev0 = timing ? P->sweep_ev[2 * i] : nullptr;
         hipEvent_t ev1 = timing ? P->sweep_ev[2 * i + 1] : nullptr;
@@ -658,7 +660,7 @@ static int enqueue_sweeps(ddi_plan* P, int from, int to, int start0, bool timing
             DDI_HIP(launch_sweep(L0.u[c0], L0.mbits, L0.u[c0 ^ 1], P->part,
                                  timing ? P->cgcnt : nullptr, ctl, L0.sw, s,
                                  i >= 2 ? P->flg + ((i - 1) & 1) * nfl : nullptr,
-                                 P->flg + (i & 1) * nfl, nullptr, nullptr, ev0, ev1));
+                                 P->flg + (i & 1) * nfl, order, nullptr, ev0, ev1));
         } else {
             DDI_HIP(launch_sweep(L0.u[c0], L0.mbits, L0.u[c0 ^ 1], P->part,
                                  timing ? P->cgcnt : nullptr, ctl, L0.sw, s, nullptr, nullptr,

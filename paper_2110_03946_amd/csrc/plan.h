@@ -37,7 +37,7 @@ size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm);
 // Finest-level sweeps of this plan use unchanged-block flags
 // (skip_unchanged, float32 ORAS, a grid where launch_sweep accepts them).
 bool use_skip(const ddi_params& prm, const SweepArgs& a0);
-// The finest level's first sweep of this plan runs its blocks in the order
+// The finest level's sweeps of this plan run their blocks in the order
 // of the CG steps of the level-2 blocks over them (order_blocks).
 bool use_order(const ddi_params& prm, int h, int w, int C);
 // Levels a plan builds for h x w: `levels`, fewer once a level is 1 x 1.
@@ -79,7 +79,7 @@ struct ddi_plan {
                              // parity); null: no skipping
     int* keys2 = nullptr;    // order_blocks: CG steps per level-2 block of its
                              // last sweep, and the dispatch table of the
-    int* order = nullptr;    // finest level's first sweep built from them
+    int* order = nullptr;    // finest level's sweeps built from them
     bool order_on = false;   // the solve being enqueued built that table
     int* ctl = nullptr;      // device stop test: done, sweeps, error, -, rel (double)
     void* hctl = nullptr;    // pinned mirror of ctl
