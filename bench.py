@@ -461,6 +461,8 @@ def run_frame(args, workload: str) -> dict:
            "roofline": roofline}
     if precision:
         out["refinements_per_solve"] = round(iso["refs"] / 20, 2)
+    else:
+        out["coarsest_level"] = coarse_comparison(fs[0], cs[0], prm)
     if not args.no_cpu:
         print(f"[bench] {workload}: oracle on the {nplans} timed frames", file=sys.stderr,
               flush=True)
@@ -481,6 +483,64 @@ def run_frame(args, workload: str) -> dict:
                                 "cores": 1,
                                 "sample": f"channel 0 of that frame on one thread, {t1:.1f} s, "
                                           "times 3 channels"}}
+    return out
+
+
+def coarse_comparison(f0, c0, prm: dict, reps: int = 20) -> dict:
+    """The coarsest level of the 4K frame (1/8: 480 x 270 x 3) solved the two
+    ways a plan offers: one float32 ORAS sweep from u = c ? f : 0 (what the
+    benchmark plan runs there, coarse_solver = 0) and float64 conjugate
+    gradients on a grid of workgroups (coarse_solver = 1, relative residual
+    1e-10); then the whole 4K solve with each."""
+    import torch
+    from paper_2110_03946_amd import ddi
+    f, c = f0, c0
+    for _ in range(prm["levels"] - 1):
+        f, c = ddi.coarsen(f, c)
+    nc, hc, wc = f.shape
+    work = torch.empty(ddi.coarse_grid_bytes(hc, wc, nc), dtype=torch.uint8, device="cuda")
+    u64, u32 = torch.empty_like(f), torch.empty_like(f)
+    start = torch.where(c.bool(), f, torch.zeros_like(f))
+    sweep = dict(block=prm["block"], overlap=prm["overlap"], alpha=prm["robin_alpha"],
+                 k=prm["coarse_local_iters"])
+    _, steps = ddi.coarse_solve_grid(f, c, max_iter=500, tol=1e-10, u=u64, work=work,
+                                     steps=True)
+    ddi.oras_sweep_noalloc(start, c, u_out=u32, rsq=False, **sweep)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        ddi.coarse_solve_grid(f, c, max_iter=500, tol=1e-10, u=u64, work=work)
+    ev[1].record()
+    ev[2].record()
+    for _ in range(reps):
+        ddi.oras_sweep_noalloc(start, c, u_out=u32, rsq=False, **sweep)
+    ev[3].record()
+    torch.cuda.synchronize()
+    unk = ~c.bool()
+    dev32 = float((u32 - u64).abs()[:, unk].max()) if bool(unk.any()) else 0.0
+    out = {"level": f"{wc}x{hc}x{nc}", "known_frac": round(float(c.float().mean()), 4),
+           "f64_grid_cg_us": round(ev[0].elapsed_time(ev[1]) / reps * 1e3, 1),
+           "f64_grid_cg_steps": steps,
+           "f32_oras_sweep_us": round(ev[2].elapsed_time(ev[3]) / reps * 1e3, 1),
+           "f32_sweep_max_dev_from_f64_grey": round(dev32, 3),
+           "timing": "CUDA events around back-to-back calls on one stream"}
+    # the whole solve with each coarsest-level solver (synchronous, no timing
+    # events)
+    u = torch.empty_like(f0)
+    for cs_ in (0, 1):
+        q = dict(prm, coarse_solver=cs_)
+        lat, sw = [], []
+        with ddi.Plan(f0.shape[1], f0.shape[2], f0.shape[0], **q) as pl:
+            for _ in range(3):
+                pl.solve(f0, c0, u)
+            for _ in range(reps):
+                ts = time.perf_counter()
+                _, st = pl.solve(f0, c0, u)
+                lat.append((time.perf_counter() - ts) * 1e3)
+                sw.append(st["sweeps"])
+        out[f"solve_coarse_solver_{cs_}"] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                                             "sweeps": sorted(set(sw))}
     return out
 
 

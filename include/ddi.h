@@ -56,6 +56,10 @@ extern "C" {
 #define DDI_ENODEV     (-6)  /* no usable gfx950 device */
 #define DDI_ESCRATCH   (-7)  /* ddi_oras_sweep_noalloc: the call needs more than
                                 DDI_NOALLOC_SCRATCH_BYTES of scratch */
+#define DDI_ESTALL     (-8)  /* a grid-wide wait of the float64 coarse solve on
+                                many workgroups exceeded its bound (its
+                                workgroups were not all resident); the result
+                                is not valid */
 
 /* Largest block edge (pixels) the on-chip local solver supports. */
 #define DDI_MAX_BLOCK 64
@@ -63,7 +67,9 @@ extern "C" {
 /* Fixed device scratch of ddi_oras_sweep_noalloc, per GPU (4 MiB). */
 #define DDI_NOALLOC_SCRATCH_BYTES (4u << 20)
 
-/* Largest coarsest level (pixels) of the float64 coarse solve. */
+/* Largest level (pixels) of the one-workgroup-per-channel float64 coarse
+ * solve (ddi_coarse_solve); larger coarsest levels of coarse_solver = 1 use
+ * the grid solve (ddi_coarse_solve_grid). */
 #define DDI_COARSE_MAX_PIXELS 8192
 
 /*
@@ -108,9 +114,10 @@ extern "C" {
  *                  the same f, c and u pointers (ignored with timing = 1).
  *   coarse_solver  0: coarsest_sweeps ORAS sweeps on the coarsest level;
  *                  1: solve the coarsest level in float64 by conjugate
- *                  gradients (one workgroup per channel; the coarsest level
- *                  must have at most DDI_COARSE_MAX_PIXELS pixels -- add
- *                  levels for large images).
+ *                  gradients: one workgroup per channel when the level has
+ *                  at most DDI_COARSE_MAX_PIXELS pixels, else the grid
+ *                  solve of ddi_coarse_solve_grid (many workgroups, grid
+ *                  barriers; the plan holds its workspace).
  *   coarse_cg_iters cap on CG steps of coarse_solver = 1, >= 1.
  *   coarse_cg_tol  coarse_solver = 1 stops once ||b - A u||_2 <= tol ||b||_2
  *                  on the coarsest level (float64), >= 0.
@@ -350,8 +357,8 @@ int ddi_batch_create(ddi_batch** out, int n, const int* heights,
 /*
  * Inpaint all images: f[i], c[i], u[i] are device pointers laid out as for
  * ddi_solve (host arrays of n pointers). st (n entries) and status (n codes:
- * DDI_OK, DDI_EINVAL for a mask byte > 1, DDI_ESINGULAR, DDI_ENOCONV) may
- * be NULL; st[i].ms and st[i].sweep_ms are those of the whole batch.
+ * DDI_OK, DDI_EINVAL for a mask byte > 1, DDI_ESINGULAR, DDI_ENOCONV,
+ * DDI_ESTALL) may be NULL; st[i].ms and st[i].sweep_ms are those of the whole batch.
  * Returns DDI_OK when every image converged, else the first image's error
  * code in order (or DDI_EHIP / DDI_EINVAL for the call itself). Synchronises
  * the stream.
@@ -464,6 +471,39 @@ int ddi_oras_sweep_noalloc(const float* u_in, const uint8_t* c, float* u_out,
 int ddi_coarse_solve(const float* f, const uint8_t* c, int height, int width,
                      int channels, float* u, int max_iter, double tol,
                      void* stream);
+
+/*
+ * The same float64 solve on a level of any size (height * width <= 2^30):
+ * the conjugate gradients of ddi_coarse_solve, with the vectors in the
+ * caller's workspace and `workgroups` workgroups (1..256; 0 = a default from
+ * the size) that stay resident for the whole solve and meet at two grid
+ * barriers per step. The per-channel partial sums of each dot product are
+ * added in a fixed order, so the result does not depend on timing; it
+ * differs from ddi_coarse_solve's only by the order of those sums.
+ *   work, work_bytes  device workspace of at least ddi_coarse_grid_bytes
+ *                     bytes, 256-byte aligned, not overlapping f, c or u;
+ *                     owned by the caller, overwritten by the call (calls
+ *                     that share one workspace must not overlap in time).
+ *   steps             NULL: the call is asynchronous on `stream`. Else the
+ *                     call waits for the stream and stores the CG steps each
+ *                     channel took in steps[0..channels).
+ * Errors: DDI_EINVAL (sizes, tolerances, pointers, a short or misaligned
+ * workspace, u overlapping an input); DDI_ESTALL (only with steps given) if
+ * a barrier wait exceeded its bound, when not every workgroup could run.
+ */
+int ddi_coarse_grid_bytes(int height, int width, int channels, size_t* bytes);
+/*
+ * Test hook of the DDI_ESTALL path: later grid solves of this process bound
+ * each barrier wait by `polls` polls instead of the default (about two
+ * seconds' worth); 0 makes every wait that does not end at once a stall, so
+ * a solve on two or more workgroups reports DDI_ESTALL while every
+ * workgroup still ends. polls < 0 restores the default.
+ */
+int ddi_coarse_grid_debug_spin_limit(long polls);
+int ddi_coarse_solve_grid(const float* f, const uint8_t* c, int height, int width,
+                          int channels, float* u, int max_iter, double tol,
+                          int workgroups, void* work, size_t work_bytes,
+                          int* steps, void* stream);
 
 /*
  * The two steps of the mixed-precision refinement (storage = 1), exposed

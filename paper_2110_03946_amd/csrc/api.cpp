@@ -109,6 +109,23 @@ bool use_order(const ddi_params& prm, int h, int w, int C) {
            (int64_t)sweep_partials(a0) * C < 65536 && a0.g.nby + a0.g.nbx <= kOrderMaxAxes;
 }
 
+// Size of the coarsest level a plan builds for h x w.
+static void coarsest_dims(const ddi_params& prm, int h, int w, int* hl, int* wl) {
+    *hl = h;
+    *wl = w;
+    for (int l = 1; l < level_count(h, w, prm.levels); ++l) {
+        *hl = (*hl + 1) / 2;
+        *wl = (*wl + 1) / 2;
+    }
+}
+
+bool use_coarse_grid(const ddi_params& prm, int h, int w) {
+    if (prm.coarse_solver != 1) return false;
+    int hl, wl;
+    coarsest_dims(prm, h, w, &hl, &wl);
+    return (int64_t)hl * wl > kCoarseMaxPixels;
+}
+
 size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm) {
     const int L = level_count(h, w, prm.levels);
     size_t bytes = 0, part_n = 0;
@@ -142,6 +159,11 @@ size_t plan_device_bytes(int h, int w, int C, const ddi_params& prm) {
                       (size_t)sweep_partials(level_sweep(h, w, C, prm, 2))) * C * sizeof(int);
     }
     if (prm.storage == 1) bytes += 3 * (size_t)C * h * w * sizeof(uint16_t);
+    if (use_coarse_grid(prm, h, w)) {
+        int hl, wl;
+        coarsest_dims(prm, h, w, &hl, &wl);
+        bytes += coarse_grid_bytes(hl, wl, C);
+    }
     if (prm.method == 1)
         bytes += 4 * (size_t)C * h * w * sizeof(float) + (3 * (size_t)C + L * ((size_t)C + 2)) *
                                                              sizeof(double);
@@ -247,14 +269,6 @@ int ddi_check_params(int height, int width, int channels, const ddi_params* p) {
     if (p->fuse_prolong != 0 && p->fuse_prolong != 1) return DDI_EINVAL;
     if (p->skip_unchanged != 0 && p->skip_unchanged != 1) return DDI_EINVAL;
     if (p->order_blocks != 0 && p->order_blocks != 1) return DDI_EINVAL;
-    if (p->coarse_solver == 1) {
-        int hl = height, wl = width;
-        for (int l = 1; l < level_count(height, width, p->levels); ++l) {
-            hl = (hl + 1) / 2;
-            wl = (wl + 1) / 2;
-        }
-        if ((int64_t)hl * wl > DDI_COARSE_MAX_PIXELS) return DDI_EINVAL;
-    }
     return DDI_OK;
 }
 
@@ -280,6 +294,7 @@ int ddi_destroy(ddi_plan* plan) {
     if (plan->red) (void)hipFree(plan->red);
     if (plan->cgcnt) (void)hipFree(plan->cgcnt);
     if (plan->flg) (void)hipFree(plan->flg);
+    if (plan->cgw) (void)hipFree(plan->cgw);
     if (plan->keys2) (void)hipFree(plan->keys2);
     if (plan->order) (void)hipFree(plan->order);
     if (plan->ctl) (void)hipFree(plan->ctl);
@@ -445,6 +460,14 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
             return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
         }
     }
+    if (use_coarse_grid(prm, height, width)) {
+        const Level& top = P->lv.back();
+        if ((err = hipMalloc(&P->cgw, coarse_grid_bytes(top.h, top.w, channels))) !=
+            hipSuccess) {
+            ddi_destroy(P);
+            return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
+        }
+    }
     if (prm.timing) {
         const size_t nc = 3 * (size_t)sweep_partials(P->lv[0].sw) * channels;
         if ((err = hipMalloc(&P->cgcnt, nc * sizeof(double))) != hipSuccess) {
@@ -555,7 +578,12 @@ int plan_enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0) {
     }
     const int top = L - 1;
     int cur = (top == 0) ? start0 : 0;
-    if (prm.coarse_solver == 1)
+    if (prm.coarse_solver == 1 && P->cgw) {
+        const Level& t = P->lv[top];
+        DDI_HIP(launch_coarse_cg_grid(t.f, t.c, t.h, t.w, C, t.u[cur], prm.coarse_cg_iters,
+                                      prm.coarse_cg_tol, coarse_grid_workgroups(t.h, t.w, C),
+                                      P->cgw, P->ctl, s));
+    } else if (prm.coarse_solver == 1)
         DDI_HIP(launch_coarse_cg(P->lv[top].f, P->lv[top].c, P->lv[top].h, P->lv[top].w, C,
                                  P->lv[top].u[cur], prm.coarse_cg_iters, prm.coarse_cg_tol, s));
     else
@@ -736,6 +764,7 @@ static int solve_refine(ddi_plan* P, const float* f, const uint8_t* c, float* u,
         const int* hc = reinterpret_cast<const int*>(P->hctl);
         if (hc[2] == 1) return DDI_EINVAL;
         if (hc[2] == 2) return DDI_ESINGULAR;
+        if (hc[2] == 3) return DDI_ESTALL;
         double rel2;
         std::memcpy(&rel2, hc + 4, sizeof(rel2));
         rel = std::sqrt(rel2);
@@ -920,6 +949,7 @@ static int finish_solve(ddi_plan* P, ddi_stats* st) {
         validated = done_upto > 0;
         if (hc[2] == 1) return DDI_EINVAL;
         if (hc[2] == 2) return DDI_ESINGULAR;
+        if (hc[2] == 3) return DDI_ESTALL;
         if (done_upto > 0) {
             double rel2;
             std::memcpy(&rel2, hc + 4, sizeof(rel2));
@@ -1051,6 +1081,7 @@ const char* ddi_strerror(int code) {
         case DDI_EHIP: return "HIP runtime error";
         case DDI_ENODEV: return "no gfx950 device";
         case DDI_ESCRATCH: return "input too large for the fixed no-allocation scratch";
+        case DDI_ESTALL: return "a grid barrier of the float64 coarse solve timed out";
         default: return "unknown error";
     }
 }
@@ -1161,6 +1192,54 @@ int ddi_coarse_solve(const float* f, const uint8_t* c, int height, int width, in
     if ((e = check_device())) return e;
     DDI_HIP(launch_coarse_cg(f, c, height, width, channels, u, max_iter, tol,
                              (hipStream_t)stream));
+    return DDI_OK;
+}
+
+int ddi_coarse_grid_bytes(int height, int width, int channels, size_t* bytes) {
+    if (!bytes) return DDI_EINVAL;
+    const int e = check_dims(height, width, channels);
+    if (e) return e;
+    *bytes = coarse_grid_bytes(height, width, channels);
+    return DDI_OK;
+}
+
+int ddi_coarse_grid_debug_spin_limit(long polls) {
+    set_coarse_grid_spin_limit(polls);
+    return DDI_OK;
+}
+
+int ddi_coarse_solve_grid(const float* f, const uint8_t* c, int height, int width, int channels,
+                          float* u, int max_iter, double tol, int workgroups, void* work,
+                          size_t work_bytes, int* steps, void* stream) {
+    int e = check_dims(height, width, channels);
+    if (e) return e;
+    if (!f || !c || !u || !work || max_iter < 1 || !(tol >= 0.0)) return DDI_EINVAL;
+    if (workgroups < 0 || workgroups > kGridCgMaxWg) return DDI_EINVAL;
+    const size_t need = coarse_grid_bytes(height, width, channels);
+    if (work_bytes < need || ((uintptr_t)work & 255) != 0) return DDI_EINVAL;
+    {
+        const size_t nimg = (size_t)channels * height * width * sizeof(float);
+        const size_t nc = (size_t)height * width;
+        if (overlaps(u, nimg, f, nimg) || overlaps(u, nimg, c, nc) ||
+            overlaps(work, need, f, nimg) || overlaps(work, need, c, nc) ||
+            overlaps(work, need, u, nimg))
+            return DDI_EINVAL;
+    }
+    if ((e = check_device())) return e;
+    hipStream_t s = (hipStream_t)stream;
+    const int g = workgroups ? workgroups : coarse_grid_workgroups(height, width, channels);
+    DDI_HIP(launch_coarse_cg_grid(f, c, height, width, channels, u, max_iter, tol, g, work,
+                                  nullptr, s));
+    if (steps) {
+        int hs[4 + 1] = {};
+        DDI_HIP(hipMemcpyAsync(hs, coarse_grid_status(work), sizeof(int), hipMemcpyDeviceToHost,
+                               s));
+        DDI_HIP(hipMemcpyAsync(hs + 1, coarse_grid_steps(work), 4 * sizeof(int),
+                               hipMemcpyDeviceToHost, s));
+        DDI_HIP(hipStreamSynchronize(s));
+        if (hs[0] != 0) return DDI_ESTALL;
+        for (int k = 0; k < channels; ++k) steps[k] = hs[1 + k];
+    }
     return DDI_OK;
 }
 

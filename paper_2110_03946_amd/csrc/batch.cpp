@@ -119,8 +119,8 @@ hipError_t run_sweeps(const std::vector<SweepLaunch>& ls, hipStream_t s) {
 // uploaded before the first launch is enqueued).
 struct Front {
     struct Step {
-        enum Kind { Coarsen, CoarsenOne, StatsOne, Reduce, MaskBits, Init, CoarseCg, Sweep,
-                    Prolong, ProlongOne } kind;
+        enum Kind { Coarsen, CoarsenOne, StatsOne, Reduce, MaskBits, Init, CoarseCg,
+                    CoarseGrid, Sweep, Prolong, ProlongOne } kind;
         const void* jobs = nullptr;
         int njobs = 0, total_wg = 0;
         std::vector<SweepLaunch> sweeps;
@@ -247,12 +247,23 @@ void build_front(ddi_batch* B, const std::vector<int>& start0, Arena& A, Front& 
     {
         std::vector<LevelJob> jobs;
         std::vector<CoarseJob> cg;
+        std::vector<Front::Step> grid;
         int wg = 0;
         for (int i = 0; i < n; ++i) {
             ddi_plan* P = B->plans[i];
             const int top = (int)P->lv.size() - 1;
             cur[i] = top == 0 ? start0[i] : 0;
             const Level& lev = P->lv[top];
+            if (P->p.coarse_solver == 1 && P->cgw) {
+                // a coarsest level too large for one workgroup: its own
+                // grid solve
+                Front::Step st;
+                st.kind = Front::Step::CoarseGrid;
+                st.img = i;
+                st.dst = cur[i];
+                grid.push_back(st);
+                continue;
+            }
             if (P->p.coarse_solver == 1) {
                 CoarseJob j{};
                 j.f = lev.f;
@@ -290,6 +301,7 @@ void build_front(ddi_batch* B, const std::vector<int>& start0, Arena& A, Front& 
             st.njobs = (int)cg.size();
             F.steps.push_back(st);
         }
+        for (const Front::Step& st : grid) F.steps.push_back(st);
     }
 
     // coarse levels, coarsest first: sweeps, then prolongation one level down
@@ -417,6 +429,15 @@ int enqueue_front(ddi_batch* B, const Front& F) {
             case Front::Step::CoarseCg:
                 e = launch_coarse_cg_batch((const CoarseJob*)st.jobs, st.njobs, C, s);
                 break;
+            case Front::Step::CoarseGrid: {
+                ddi_plan* P = B->plans[st.img];
+                const Level& t = P->lv.back();
+                e = launch_coarse_cg_grid(t.f, t.c, t.h, t.w, C, t.u[st.dst],
+                                          P->p.coarse_cg_iters, P->p.coarse_cg_tol,
+                                          coarse_grid_workgroups(t.h, t.w, C), P->cgw,
+                                          B->ctl + (size_t)st.img * kCtlInts, s);
+                break;
+            }
             case Front::Step::Sweep:
                 e = run_sweeps(st.sweeps, s);
                 break;
@@ -711,8 +732,10 @@ int ddi_batch_solve(ddi_batch* B, const float* const* f, const uint8_t* const* c
     build_fine(B, act, start0, A, T, true);
     int e = upload(B, A);
     if (e) return e;
-    if ((e = enqueue_front(B, F))) return e;
+    // the control words first: the front's float64 grid solves report a
+    // stalled barrier there
     DDI_HIP(launch_clear_int(B->ctl, n * kCtlInts, s));
+    if ((e = enqueue_front(B, F))) return e;
 
     int done_upto = 0;
     bool first_batch = true;
@@ -741,7 +764,7 @@ int ddi_batch_solve(ddi_batch* B, const float* const* f, const uint8_t* const* c
             std::memcpy(&rel2, hc + 4, sizeof(rel2));
             rel[i] = std::sqrt(rel2);
             if (hc[2] != 0) {
-                code[i] = hc[2] == 1 ? DDI_EINVAL : DDI_ESINGULAR;
+                code[i] = hc[2] == 1 ? DDI_EINVAL : hc[2] == 2 ? DDI_ESINGULAR : DDI_ESTALL;
                 sweeps[i] = hc[1];
             } else if (hc[0] != 0) {
                 sweeps[i] = hc[1];

@@ -374,6 +374,29 @@ hipError_t launch_coarse_cg(const float* f, const uint8_t* c, int h, int w, int 
                             float* u, int max_iter, double tol, hipStream_t s);
 hipError_t launch_coarse_cg_batch(const CoarseJob* jobs, int njobs, int channels, hipStream_t s);
 
+// The same float64 CG on a level of any size, run by `wgs` workgroups
+// (1..kGridCgMaxWg) that stay resident for the whole solve and meet at grid
+// barriers. work: coarse_grid_bytes(h, w, channels) bytes, 256-byte aligned,
+// owned by the caller (control words, partial sums, five float64 vectors);
+// the launcher clears its control words first. A barrier that waits longer
+// than its bound (about a second: workgroups that never became resident)
+// ends the solve on every workgroup and leaves a nonzero status word
+// (coarse_grid_status); with ctl given it also sets ctl[2] = 3 and ctl[0] =
+// 1, so that the plan's later sweeps and stop tests do nothing.
+constexpr int kGridCgMaxWg = 256;
+size_t coarse_grid_bytes(int h, int w, int channels);
+int coarse_grid_workgroups(int h, int w, int channels);
+// Device addresses inside `work`: the barrier status (int, 0 = ok) and the
+// CG steps taken per channel (int[4]).
+const int* coarse_grid_status(const void* work);
+// Bound of every later grid-solve barrier wait, in polls (test hook; < 0:
+// the default).
+void set_coarse_grid_spin_limit(long polls);
+const int* coarse_grid_steps(const void* work);
+hipError_t launch_coarse_cg_grid(const float* f, const uint8_t* c, int h, int w, int channels,
+                                 float* u, int max_iter, double tol, int wgs, void* work,
+                                 int* ctl, hipStream_t s);
+
 // ---- global conjugate gradients (multilevel-CG comparator) ----
 // Partial rows of these kernels: residual_partials(h, w). All skip their
 // work once ctl[0] != 0.

@@ -90,6 +90,7 @@ int solve_krylov(ddi_plan* P, ddi_stats* st) {
             checked = true;
         }
         const int* hc = reinterpret_cast<const int*>(P->hctl);
+        if (hc[2] == 3) return DDI_ESTALL;  // the float64 coarse grid solve stalled
         double rel2;
         std::memcpy(&rel2, hc + 4, sizeof(rel2));
         rel = std::sqrt(rel2);

@@ -40,6 +40,9 @@ bool use_skip(const ddi_params& prm, const SweepArgs& a0);
 // The finest level's sweeps of this plan run their blocks in the order
 // of the CG steps of the level-2 blocks over them (order_blocks).
 bool use_order(const ddi_params& prm, int h, int w, int C);
+// coarse_solver = 1 on a coarsest level too large for one workgroup: the
+// solve runs on a grid of workgroups (launch_coarse_cg_grid).
+bool use_coarse_grid(const ddi_params& prm, int h, int w);
 // Levels a plan builds for h x w: `levels`, fewer once a level is 1 x 1.
 int level_count(int h, int w, int levels);
 // DDI_OK for 1 <= h, w; 1 <= channels <= 4; h * w <= 2^30.
@@ -77,6 +80,8 @@ struct ddi_plan {
     int* flg = nullptr;      // block keys (CG steps) of the finest level for the
                              // skips of the batched solve, two arrays (sweep
                              // parity); null: no skipping
+    void* cgw = nullptr;     // coarse_solver = 1 on a coarsest level over
+                             // kCoarseMaxPixels: the grid solve's workspace
     int* keys2 = nullptr;    // order_blocks: CG steps per level-2 block of its
                              // last sweep, and the dispatch table of the
     int* order = nullptr;    // finest level's sweeps built from them

@@ -27,6 +27,7 @@ DDI_ENOCONV = -4
 DDI_EHIP = -5
 DDI_ENODEV = -6
 DDI_ESCRATCH = -7
+DDI_ESTALL = -8
 MAX_BLOCK = 64
 NOALLOC_SCRATCH_BYTES = 4 << 20
 COARSE_MAX_PIXELS = 8192
@@ -108,6 +109,10 @@ def lib():
             "ddi_oras_sweep_noalloc": (i, [vp, vp, vp, i, i, i, i, i, f, i, vp, vp]),
             "ddi_noalloc_scratch_bytes": (i, [i, i, i, i, i, ctypes.POINTER(ctypes.c_size_t)]),
             "ddi_coarse_solve": (i, [vp, vp, i, i, i, vp, i, d, vp]),
+            "ddi_coarse_grid_bytes": (i, [i, i, i, ctypes.POINTER(ctypes.c_size_t)]),
+            "ddi_coarse_grid_debug_spin_limit": (i, [ctypes.c_long]),
+            "ddi_coarse_solve_grid": (i, [vp, vp, i, i, i, vp, i, d, i, vp, ctypes.c_size_t, vp,
+                                          vp]),
             "ddi_plan_footprint": (i, [i, i, i, ctypes.POINTER(Params),
                                        ctypes.POINTER(ctypes.c_size_t)]),
             "ddi_plan_bytes": (i, [vp, ctypes.POINTER(ctypes.c_size_t)]),
@@ -435,6 +440,40 @@ def coarse_solve(f, c, max_iter: int = 500, tol: float = 1e-10, u=None, stream=N
     _check(lib().ddi_coarse_solve(_ptr(f), _ptr(c), H, W, C, _ptr(u), max_iter, float(tol),
                                   _stream(stream)), "ddi_coarse_solve")
     return u
+
+
+def coarse_grid_bytes(h: int, w: int, channels: int) -> int:
+    """Workspace bytes of coarse_solve_grid for an h x w x channels level."""
+    n = ctypes.c_size_t()
+    _check(lib().ddi_coarse_grid_bytes(h, w, channels, ctypes.byref(n)), "ddi_coarse_grid_bytes")
+    return n.value
+
+
+def coarse_solve_grid(f, c, max_iter: int = 500, tol: float = 1e-10, workgroups: int = 0,
+                      u=None, work=None, steps: bool = False, stream=None):
+    """Float64 CG solve of a level of any size on a grid of workgroups.
+
+    work: a uint8 device tensor of at least coarse_grid_bytes bytes (one is
+    allocated when None). Returns u, or (u, CG steps per channel) with
+    steps=True, which waits for the stream."""
+    torch = _torch()
+    f = _img(f, "f")
+    C, H, W = f.shape
+    c = _mask(c, (H, W))
+    if u is None:
+        u = torch.empty_like(f)
+    need = coarse_grid_bytes(H, W, C)
+    if work is None:
+        work = torch.empty(need, dtype=torch.uint8, device=f.device)
+    if not (isinstance(work, torch.Tensor) and work.is_cuda and work.dtype == torch.uint8 and
+            work.is_contiguous()):
+        raise TypeError("work must be a contiguous uint8 tensor on the GPU")
+    st = (ctypes.c_int * 4)() if steps else None
+    _check(lib().ddi_coarse_solve_grid(_ptr(f), _ptr(c), H, W, C, _ptr(u), max_iter, float(tol),
+                                       workgroups, _ptr(work), work.numel(),
+                                       ctypes.cast(st, ctypes.c_void_p) if steps else None,
+                                       _stream(stream)), "ddi_coarse_solve_grid")
+    return (u, list(st)[:C]) if steps else u
 
 
 def _bf16(t, name, channels=None, hw=None):

@@ -51,18 +51,42 @@ def test_binding_structs_match_header():
     assert [f for f, _ in ddi.Stats._fields_] == _header_struct_fields("ddi_stats")
 
 
-def test_coarse_solver_size_limit():
-    """The float64 coarsest-level solve takes at most 8192 pixels: 4K needs
-    6 levels (120 x 68) for it."""
+def test_coarse_solver_any_size():
+    """The float64 coarsest-level solve takes any size: up to 8192 pixels in
+    one workgroup per channel, above that on a grid of workgroups whose
+    workspace the plan holds (4K with 4 levels: a 480 x 270 coarsest
+    level)."""
     p = ddi.default_params(coarse_solver=1, levels=4)
-    assert ddi.check_params(2160, 3840, 3, p) == ddi.DDI_EINVAL
-    p.levels = 6
     assert ddi.check_params(2160, 3840, 3, p) == ddi.DDI_OK
+    b1 = ddi.plan_footprint(2160, 3840, 3, p)
+    b0 = ddi.plan_footprint(2160, 3840, 3, ddi.default_params(coarse_solver=0, levels=4))
+    assert b1 - b0 == ddi.coarse_grid_bytes(270, 480, 3)
+    # 6 levels: a 120 x 68 coarsest level, one workgroup per channel, no
+    # workspace
+    p6 = ddi.default_params(coarse_solver=1, levels=6)
+    assert ddi.plan_footprint(2160, 3840, 3, p6) == \
+        ddi.plan_footprint(2160, 3840, 3, ddi.default_params(coarse_solver=0, levels=6))
     p = ddi.default_params(coarse_solver=1, levels=1)
-    assert ddi.check_params(64, 128, 1, p) == ddi.DDI_OK
-    assert ddi.check_params(64, 129, 1, p) == ddi.DDI_EINVAL
+    assert ddi.check_params(64, 129, 1, p) == ddi.DDI_OK
     p = ddi.default_params(coarse_cg_iters=0)
     assert ddi.check_params(64, 64, 1, p) == ddi.DDI_EINVAL
+
+
+def test_coarse_grid_workspace_layout():
+    """Control words (256 B), three partial tables of 256 workgroups x 4
+    channels (float64), the unknown counts of 256 workgroups, the pixel of
+    each unknown and the number of each pixel (int), four neighbours per
+    unknown (int), five float64 vectors per unknown and channel; each part
+    256-byte aligned."""
+    r = lambda n: (n + 255) // 256 * 256
+    for h, w, C in [(1, 1, 1), (270, 480, 3), (5, 7, 4), (8192, 3, 2)]:
+        n = h * w
+        assert ddi.coarse_grid_bytes(h, w, C) == (256 + r(3 * 256 * 4 * 8) + r(256 * 4) +
+                                                  2 * r(n * 4) + r(n * 16) + 5 * r(n * C * 8))
+    with pytest.raises(ddi.DDIError):
+        ddi.coarse_grid_bytes(0, 5, 1)
+    with pytest.raises(ddi.DDIError):
+        ddi.coarse_grid_bytes(5, 5, 5)
 
 
 @pytest.mark.parametrize("h,w,ch", [(0, 5, 1), (5, 0, 1), (5, 5, 0), (5, 5, 5)])
