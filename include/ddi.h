@@ -370,6 +370,24 @@ int ddi_batch_solve(ddi_batch* b, const float* const* f,
 /* Release the batch plan. NULL is a no-op. */
 int ddi_batch_destroy(ddi_batch* b);
 
+/*
+ * Host self-check of the kernels' index arithmetic. Replays every global-
+ * memory offset that the kernels of a float32 ORAS plan for height x width
+ * x channels with parameters p (NULL: defaults) read or write -- the
+ * transposed mask bits, both coarsening kernels, every level's sweeps (with
+ * the first sweep of a level that builds its tile from the coarser level),
+ * both prolongation kernels and the column-walking kernels -- computed by
+ * the functions the kernels themselves use, over every thread of every
+ * launch, and checks each offset against the buffer it addresses. No GPU is
+ * used. *checked (may be NULL) receives the number of offsets checked,
+ * *violations (may be NULL) the number outside their buffer, first (may be
+ * NULL, first_len bytes) a description of the first such offset.
+ * Errors: those of ddi_check_params.
+ */
+int ddi_selfcheck_access(int height, int width, int channels, const ddi_params* p,
+                         long long* checked, long long* violations, char* first,
+                         int first_len);
+
 /* Text for an error code (static storage). */
 const char* ddi_strerror(int code);
 

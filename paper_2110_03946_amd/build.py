@@ -19,8 +19,10 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddi.so")
 SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "api.cpp"),
            os.path.join(CSRC, "batch.cpp"), os.path.join(CSRC, "mlcg.cpp"),
-           os.path.join(CSRC, "krylov.cpp"), os.path.join(CSRC, "noalloc.hip")]
+           os.path.join(CSRC, "krylov.cpp"), os.path.join(CSRC, "noalloc.hip"),
+           os.path.join(CSRC, "replay.cpp")]
 HEADERS = [os.path.join(CSRC, "internal.h"), os.path.join(CSRC, "plan.h"),
+           os.path.join(CSRC, "access.h"),
            os.path.join(ROOT, "include", "ddi.h")]
 
 

@@ -83,7 +83,7 @@ bool use_skip(const ddi_params& prm, const SweepArgs& a0) {
 }
 
 // Level grids of a plan (level 0 = finest).
-static SweepArgs level_sweep(int h, int w, int C, const ddi_params& prm, int l) {
+SweepArgs level_sweep(int h, int w, int C, const ddi_params& prm, int l) {
     for (int i = 0; i < l; ++i) {
         h = (h + 1) / 2;
         w = (w + 1) / 2;

@@ -20,6 +20,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "access.h"
 #include "internal.h"
 
 namespace ddi {
@@ -63,36 +64,6 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     return x;
-}
-
-// Workgroups are handed to the 8 XCDs of the chip round-robin (workgroup i
-// runs on XCD i mod 8). Renumber them so that each XCD works through runs
-// of kXcdChunk consecutive blocks of the logical order (XCD j takes runs j,
-// j + 8, j + 16, ...): horizontal neighbours, which share halo and overlap
-// cache lines, meet in the same L2, while costly regions of the image are
-// still spread over all XCDs. A tail shorter than 8 runs keeps its order.
-constexpr int kXcds = 8;
-#ifndef DDI_XCD_CHUNK
-#define DDI_XCD_CHUNK 16
-#endif
-constexpr int kXcdChunk = DDI_XCD_CHUNK;
-
-// Workgroup b of n -> logical index: XCD j (= b mod 8) takes one
-// contiguous band of the logical order, so that row-streaming kernels whose
-// neighbouring rows share reads (prolongation: four fine rows read each
-// coarse row) fetch them into one L2 only. A tail shorter than 8 keeps its
-// order.
-__device__ __forceinline__ int xcd_band(int b, int n) {
-    const int full = n - n % kXcds;
-    if (b >= full) return b;
-    return (b % kXcds) * (full / kXcds) + b / kXcds;
-}
-
-__device__ __forceinline__ int xcd_remap(int b, int n) {
-    const int full = n - n % (kXcds * kXcdChunk);
-    if (b >= full) return b;
-    const int j = b % kXcds, i = b / kXcds;
-    return (j + kXcds * (i / kXcdChunk)) * kXcdChunk + i % kXcdChunk;
 }
 
 // q where bit `bit` of `bits` is set, +0 elsewhere: a sign-extended bit
@@ -233,16 +204,9 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
 
     const int lane = threadIdx.x;
     const BlockGrid g = a.g;
-    const int nblk = g.nby * g.nbx;
-    const int ch = lb / nblk;
-    const int b = lb - ch * nblk;
-    const int by = b / g.nbx;
-    const int bx = b - by * g.nbx;
-    const int y0 = block_origin(by, g.sy, g.h, g.bh);
-    const int x0 = block_origin(bx, g.sx, g.w, g.bw);
-    int oylo, oyhi, oxlo, oxhi;
-    owner_range(by, g.nby, g.sy, g.h, g.bh, &oylo, &oyhi);
-    owner_range(bx, g.nbx, g.sx, g.w, g.bw, &oxlo, &oxhi);
+    const Blk kb = blk_geo(g, lb);
+    const int ch = kb.ch, b = kb.b, y0 = kb.y0, x0 = kb.x0;
+    const int oylo = kb.oylo, oyhi = kb.oyhi, oxlo = kb.oxlo, oxhi = kb.oxhi;
 
     const float* __restrict__ U = CORR ? nullptr : (const float*)uin_v + ch * a.cpitch;
     const uint16_t* __restrict__ U16 =
@@ -264,36 +228,34 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
     // 32-bit element indices into one channel plane (planes hold < 2^30
     // pixels), so each load is one scalar base plus a vector offset.
     auto stage = [&](auto ld) {
-        const uint32_t xc = on ? x : x0;
+        const uint32_t xc = tile_col(kb, g, lane);
         const uint32_t Wd = g.w;
         float col[RPW + 2];
         if constexpr (!RAGGED) {
             // rows y0 .. y0+RPW-1 lie in the image; only the two halo rows
             // can fall outside it (then they copy the border row)
-            uint32_t off = (uint32_t)y0 * Wd + xc;
-            col[0] = ld(has_top ? off - Wd : off);
+            const Tile2Rows tr = tile1_rows(kb, RPW, Wd, xc);
+            uint32_t off = tr.mid0;
+            col[0] = ld(tr.first);
 #pragma unroll
             for (int t = 1; t <= RPW; ++t) {
                 col[t] = ld(off);
                 if (t < RPW) off += Wd;
             }
-            col[RPW + 1] = ld(has_bot ? off + Wd : off);
+            col[RPW + 1] = ld(tr.last);
         } else {
 #pragma unroll
-            for (int t = 0; t < RPW + 2; ++t) {
-                const uint32_t yy = min(max(y0 + t - 1, 0), g.h - 1);
-                col[t] = ld(yy * Wd + xc);
-            }
+            for (int t = 0; t < RPW + 2; ++t) col[t] = ld(tile_row(kb, g, t) * Wd + xc);
         }
         // halo columns: lane l fetches row l - 1 (and rows 63, 64 in a
         // second pass for lanes 0, 1)
-        const uint32_t xl = max(x0 - 1, 0), xr = min(x0 + g.bw, g.w - 1);
+        const uint32_t xl = halo_left(kb), xr = halo_right(kb, g);
         const int t1 = lane, t2 = 64 + lane;
-        const uint32_t r1 = (uint32_t)min(max(y0 + t1 - 1, 0), g.h - 1) * (uint32_t)g.w;
+        const uint32_t r1 = tile_row(kb, g, t1) * (uint32_t)g.w;
         const float hl1 = ld(r1 + xl), hr1 = ld(r1 + xr);
         float hl2 = 0.f, hr2 = 0.f;
         if (t2 < RPW + 2) {
-            const uint32_t r2 = (uint32_t)min(max(y0 + t2 - 1, 0), g.h - 1) * (uint32_t)g.w;
+            const uint32_t r2 = tile_row(kb, g, t2) * (uint32_t)g.w;
             hl2 = ld(r2 + xl);
             hr2 = ld(r2 + xr);
         }
@@ -326,10 +288,10 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
     // unknown-pixel bits of this column: bit y <-> row y0 + y
     uint32_t mlo = 0u, mhi = 0u;
     if (on) {
-        const int gy = y0 >> 6, sh = y0 & 63;
-        const uint64_t* mb = mbits + (uint32_t)gy * (uint32_t)g.w + (uint32_t)x;
-        uint64_t bits = mb[0] >> sh;
-        if (sh) bits |= mb[g.w] << (64 - sh);
+        const MaskWords mw = mask_words(kb, (uint32_t)g.w, x);
+        const uint64_t* mb = mbits + mw.w0;
+        uint64_t bits = mb[0] >> mw.sh;
+        if (mw.sh) bits |= mb[g.w] << (64 - mw.sh);
         if (nrows < 64) bits &= (1ull << (nrows & 63)) - 1ull;
         mlo = (uint32_t)bits;
         mhi = (uint32_t)(bits >> 32);
@@ -482,7 +444,7 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
 
     // ---- restricted prolongation: u_out = u_in + v on owned pixels (eq. 9)
     if (on && x >= oxlo && x < oxhi) {
-        uint32_t off = (uint32_t)y0 * (uint32_t)g.w + (uint32_t)x;
+        uint32_t off = out_base(y0, (uint32_t)g.w, x);
         if constexpr (!CORR || F32) {
             float* __restrict__ UO = (float*)uout_v + ch * a.cpitch;
 #pragma unroll
@@ -515,7 +477,6 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
 // times in LDS: to swap the boundary rows of p (row 31 <-> row 32) for the
 // matvec, and to add their halves of p.q and r.r (wave 0's half first, so
 // both waves hold bitwise equal scalars and take the same branches).
-constexpr int kSplitRows = 32;
 // Word 3 of a raw buffer resource on gfx950 (32-bit data, no swizzle) and a
 // vector offset that its range check rejects (the load returns 0).
 constexpr int kBufferDword3 = 0x00020000;
@@ -526,31 +487,6 @@ constexpr float kCgFloor = 1e-30f;
 // LDS floats of a split sweep: the 66 x 66 tile, then the exchange area
 // (two p rows, then the per-wave scalars).
 constexpr int kSplitLds = (2 * kSplitRows + 2) * kTileW + 2 * 64 + 8;
-
-// Geometry of one block of the grid (logical index lb, channel-major).
-struct Blk {
-    int ch, b, y0, x0, oylo, oyhi, oxlo, oxhi;
-    bool has_top, has_bot, has_left, has_right;
-};
-
-__device__ __forceinline__ Blk blk_geo(const SweepArgs& a, int lb) {
-    const BlockGrid& g = a.g;
-    Blk k;
-    const int nblk = g.nby * g.nbx;
-    k.ch = lb / nblk;
-    k.b = lb - k.ch * nblk;
-    const int by = k.b / g.nbx;
-    const int bx = k.b - by * g.nbx;
-    k.y0 = block_origin(by, g.sy, g.h, g.bh);
-    k.x0 = block_origin(bx, g.sx, g.w, g.bw);
-    owner_range(by, g.nby, g.sy, g.h, g.bh, &k.oylo, &k.oyhi);
-    owner_range(bx, g.nbx, g.sx, g.w, g.bw, &k.oxlo, &k.oxhi);
-    k.has_top = k.y0 > 0;
-    k.has_bot = k.y0 + g.bh < g.h;
-    k.has_left = k.x0 > 0;
-    k.has_right = k.x0 + g.bw < g.w;
-    return k;
-}
 
 // This wave's share of a split block's tile, held in registers between the
 // loads and the LDS stores: tile rows 33 wi .. 33 wi + 32 of its column
@@ -607,34 +543,32 @@ __device__ __forceinline__ void tile2_load(Tile2& T, const Blk& k, const SweepAr
     const int wi = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool on = lane < g.bw;
     const int x = k.x0 + lane;
-    const uint32_t xc = on ? x : k.x0;
+    const uint32_t xc = tile_col(k, g, lane);
     const uint32_t Wd = g.w;
     // tile row t0 + j = image row y0 - 1 + t0 + j; only tile rows 0 and 65
     // (first of wave 0, last of wave 1) can lie outside the image
-    const int t0 = wi * (RPW + 1);
-    const int yfirst = (wi == 0 && !k.has_top) ? k.y0 : k.y0 - 1 + t0;
-    const int ylast = (wi == 1 && !k.has_bot) ? k.y0 + 2 * RPW - 1 : k.y0 - 1 + t0 + RPW;
-    T.col[0] = ld((uint32_t)yfirst * Wd + xc);
+    const Tile2Rows tr = tile2_rows(k, wi, Wd, xc);
+    T.col[0] = ld(tr.first);
     // byte offsets: one add per row
     const uint32_t bstride = Wd * 4u;
-    uint32_t boff = ((uint32_t)(k.y0 + t0) * Wd + xc) * 4u;
+    uint32_t boff = tr.mid0 * 4u;
 #pragma unroll
     for (int j = 1; j < RPW; ++j) {
         T.col[j] = ld.bytes(boff);
         boff += bstride;
     }
-    T.col[RPW] = ld((uint32_t)ylast * Wd + xc);
-    const uint32_t xl = max(k.x0 - 1, 0), xr = min(k.x0 + g.bw, g.w - 1);
+    T.col[RPW] = ld(tr.last);
+    const uint32_t xl = halo_left(k), xr = halo_right(k, g);
     const int th = wi == 0 ? lane : 64 + lane;
-    const uint32_t r1 = (uint32_t)min(max(k.y0 + min(th, 2 * RPW + 1) - 1, 0), g.h - 1) * Wd;
+    const uint32_t r1 = tile_row(k, g, min(th, 2 * RPW + 1)) * Wd;
     T.hl = ld(r1 + xl);
     T.hr = ld(r1 + xr);
     uint64_t bits = 0;
     if (on) {
-        const int gy = k.y0 >> 6, sh = k.y0 & 63;
-        const uint64_t* mb = mbits + (uint32_t)gy * Wd + (uint32_t)x;
-        bits = mb[0] >> sh;
-        if (sh) bits |= mb[g.w] << (64 - sh);
+        const MaskWords mw = mask_words(k, Wd, x);
+        const uint64_t* mb = mbits + mw.w0;
+        bits = mb[0] >> mw.sh;
+        if (mw.sh) bits |= mb[g.w] << (64 - mw.sh);
     }
     T.mlo = (uint32_t)bits;
     T.mhi = (uint32_t)(bits >> 32);
@@ -651,16 +585,11 @@ __device__ __forceinline__ void tile2_load(Tile2& T, const Blk& k, const SweepAr
 __device__ __forceinline__ float pro_mix(float near, float far) {
     return __builtin_fmaf(0.75f, near, 0.25f * far);
 }
-// Nearer and farther coarse sample of fine index y on an axis of nc samples.
-__device__ __forceinline__ int pro_far(int y, int nc) {
-    return (y & 1) ? min((y >> 1) + 1, nc - 1) : max((y >> 1) - 1, 0);
-}
+// The prolonged value of fine pixel (y, x) from the coarse plane Uc.
 __device__ __forceinline__ float pro_pixel(const ProSrc& S, const float* __restrict__ Uc,
                                            int y, int x) {
-    const int rn = y >> 1, rf = pro_far(y, S.hc), cn = x >> 1, cf = pro_far(x, S.wc);
-    const float* Rn = Uc + (uint32_t)rn * (uint32_t)S.wc;
-    const float* Rf = Uc + (uint32_t)rf * (uint32_t)S.wc;
-    return pro_mix(pro_mix(Rn[cn], Rn[cf]), pro_mix(Rf[cn], Rf[cf]));
+    const ProCell p = pro_cell(y, x, S.hc, S.wc);
+    return pro_mix(pro_mix(Uc[p.nn], Uc[p.nf]), pro_mix(Uc[p.fn], Uc[p.ff]));
 }
 
 // tile2_load for a first sweep: the tile of the prolonged iterate, built
@@ -675,12 +604,12 @@ __device__ __forceinline__ float pro_pixel(const ProSrc& S, const float* __restr
 template <int Q>
 __device__ __forceinline__ void tile2_prolong_rows(Tile2& T, const ProSrc& S,
                                                    const float* __restrict__ Uc,
-                                                   const float* __restrict__ F, int ybase,
-                                                   int hmax, uint32_t xc, uint32_t Wd,
+                                                   const float* __restrict__ F,
+                                                   const ProRows& P, uint32_t xc, uint32_t Wd,
                                                    uint32_t klo, uint32_t khi) {
     constexpr int RPW = kSplitRows;
     constexpr int NQ = RPW / 2 + 2;
-    const int F0 = (ybase - 1) >> 1;
+    const int hmax = P.hmax;
     // Buffer loads: the row offset is a scalar operand and the lane's column
     // the vector offset, so a row costs no vector instruction; a lane that
     // is not known in a row of f gets an offset past the plane, which the
@@ -696,7 +625,7 @@ __device__ __forceinline__ void tile2_prolong_rows(Tile2& T, const ProSrc& S,
     int sel[RPW + 1];
 #pragma unroll
     for (int j = 0; j < RPW + 1; ++j) {
-        const int y = (j == 0 || j == RPW) ? min(max(ybase + j, 0), hmax) : ybase + j;
+        const int y = pro_frow(P, j);
         sel[j] = j < 32 ? __builtin_amdgcn_sbfe((int)klo, j, 1)
                         : __builtin_amdgcn_sbfe((int)khi, j - 32, 1);
         const uint32_t off = (xb & (uint32_t)sel[j]) | (kBufferOutside & ~(uint32_t)sel[j]);
@@ -706,7 +635,7 @@ __device__ __forceinline__ void tile2_prolong_rows(Tile2& T, const ProSrc& S,
     float qn[NQ], qf[NQ];
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-        const int so = (int)((uint32_t)min(max(F0 + i, 0), S.hc - 1) * (uint32_t)S.wc * 4u);
+        const int so = (int)((uint32_t)pro_crow(P, i, S.hc) * (uint32_t)S.wc * 4u);
         qn[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)cnb, so, 0));
         qf[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)cfb, so, 0));
     }
@@ -733,26 +662,23 @@ __device__ __forceinline__ void tile2_load_prolong(Tile2& T, const Blk& k, const
     const int wi = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool on = lane < g.bw;
     const int x = k.x0 + lane;
-    const uint32_t xc = on ? x : k.x0;
+    const uint32_t xc = tile_col(k, g, lane);
     const uint32_t Wd = g.w;
     const float* __restrict__ Uc = S.uc + (int64_t)k.ch * S.hc * S.wc;
     const float* __restrict__ F = S.f + k.ch * a.cpitch;
     uint64_t bits = 0;
     if (on) {
-        const int gy = k.y0 >> 6, sh = k.y0 & 63;
-        const uint64_t* mb = mbits + (uint32_t)gy * Wd + (uint32_t)x;
-        bits = mb[0] >> sh;
-        if (sh) bits |= mb[g.w] << (64 - sh);
+        const MaskWords mw = mask_words(k, Wd, x);
+        const uint64_t* mb = mbits + mw.w0;
+        bits = mb[0] >> mw.sh;
+        if (mw.sh) bits |= mb[g.w] << (64 - mw.sh);
     }
     T.mlo = (uint32_t)bits;
     T.mhi = (uint32_t)(bits >> 32);
     // known pixels of this wave's 33 rows: the block's bits, and the mask
     // byte for the halo row (above the block for wave 0, below for wave 1)
-    const int ybase = k.y0 - 1 + wi * (RPW + 1);
-    const int yh = wi == 0 ? k.y0 - 1 : k.y0 + 2 * RPW;
-    const bool hin = wi == 0 ? k.has_top : k.has_bot;
-    const uint32_t hknown =
-        (hin && at32(S.c, (uint32_t)min(max(yh, 0), g.h - 1) * Wd + xc) != 0) ? 1u : 0u;
+    const ProRows P = pro_rows(k, g, wi, xc);
+    const uint32_t hknown = (P.hin && at32(S.c, P.hrow) != 0) ? 1u : 0u;
     // bit j of (klo, khi): tile row j of this wave is known
     uint32_t klo, khi;
     if (wi == 0) {
@@ -762,17 +688,17 @@ __device__ __forceinline__ void tile2_load_prolong(Tile2& T, const Blk& k, const
         klo = ~T.mhi;
         khi = hknown;
     }
-    if ((ybase - 1) & 1)
-        tile2_prolong_rows<1>(T, S, Uc, F, ybase, g.h - 1, xc, Wd, klo, khi);
+    if ((P.ybase - 1) & 1)
+        tile2_prolong_rows<1>(T, S, Uc, F, P, xc, Wd, klo, khi);
     else
-        tile2_prolong_rows<0>(T, S, Uc, F, ybase, g.h - 1, xc, Wd, klo, khi);
+        tile2_prolong_rows<0>(T, S, Uc, F, P, xc, Wd, klo, khi);
     // reflecting border: the clamped tile row repeats its neighbour
     if (wi == 0 && !k.has_top) T.col[0] = T.col[1];
     if (wi == 1 && !k.has_bot) T.col[RPW] = T.col[RPW - 1];
     // halo columns: one pixel each per lane th (tile row th)
-    const int xl = max(k.x0 - 1, 0), xr = min(k.x0 + g.bw, g.w - 1);
+    const int xl = (int)halo_left(k), xr = (int)halo_right(k, g);
     const int th = wi == 0 ? lane : 64 + lane;
-    const int r1 = min(max(k.y0 + min(th, 2 * RPW + 1) - 1, 0), g.h - 1);
+    const int r1 = (int)tile_row(k, g, min(th, 2 * RPW + 1));
     const uint32_t ro = (uint32_t)r1 * Wd;
     const bool kl = at32(S.c, ro + xl) != 0, kr = at32(S.c, ro + xr) != 0;
     const float fl = kl ? at32(F, ro + xl) : 0.f;
@@ -989,7 +915,7 @@ __device__ __forceinline__ void sweep2_compute(const Blk& k, uint32_t mw,
     // wave-uniform, the column test per lane ----
     if (on && x >= k.oxlo && x < k.oxhi) {
         const int ylo = k.oylo - ry0, yhi = k.oyhi - ry0;
-        uint32_t off = (uint32_t)ry0 * (uint32_t)g.w + (uint32_t)x;
+        uint32_t off = out_base(ry0, (uint32_t)g.w, x);
         if constexpr (!CORR || F32) {
             float* __restrict__ UO = (float*)uout_v + k.ch * a.cpitch;
 #pragma unroll
@@ -1037,16 +963,14 @@ __device__ __forceinline__ void sweep2_body(const void* __restrict__ uin_v,
     const int stop = ctl ? ctl[0] : 0;
     const int lb = order ? order[pos] : pos;
     bool keep = false, same = false;
-    const Blk k = blk_geo(a, lb);
+    const Blk k = blk_geo(a.g, lb);
     if (fin) {
-        const int nbx = a.g.nbx, nby = a.g.nby;
-        const int by = k.b / nbx, bx = k.b - by * nbx;
-        const int* F = fin + (int64_t)k.ch * nby * nbx;
-        const int r0 = max(by - 1, 0) * nbx, r1 = by * nbx, r2 = min(by + 1, nby - 1) * nbx;
-        const int c0 = max(bx - 1, 0), c2 = min(bx + 1, nbx - 1);
-        const int own = F[r1 + bx];
-        const int nb = (F[r0 + c0] | F[r0 + bx] | F[r0 + c2]) | (F[r1 + c0] | F[r1 + c2]) |
-                       (F[r2 + c0] | F[r2 + bx] | F[r2 + c2]);
+        const int* F = fin + (int64_t)k.ch * a.g.nby * a.g.nbx;
+        int cell[9];
+        flag_cells(k, a.g, cell);
+        const int own = F[cell[0]];
+        const int nb = (F[cell[1]] | F[cell[2]] | F[cell[3]]) | (F[cell[4]] | F[cell[5]]) |
+                       (F[cell[6]] | F[cell[7]] | F[cell[8]]);
         keep = own == 0;
         same = (own | nb) == 0;
     }
@@ -1504,7 +1428,7 @@ __device__ __forceinline__ void coarsen4_body(const float* __restrict__ f,
             for (int a2 = 0; a2 < 2; ++a2) {
                 const int y = 2 * I + a2;
                 if (y < h) {
-                    const int64_t i = (int64_t)y * w + 4 * t;
+                    const int64_t i = coarsen4_in(y, w, t);
                     m[a2] = *reinterpret_cast<const uint32_t*>(c + i);
 #pragma unroll
                     for (int k = 0; k < NC; ++k)
@@ -1536,7 +1460,7 @@ __device__ __forceinline__ void coarsen4_body(const float* __restrict__ f,
                     st[NC + 1] += cv > 1 ? 1.0 : 0.0;
                 }
             }
-            const int64_t o = (int64_t)I * wc + 2 * t;
+            const int64_t o = coarsen4_out(I, wc, t);
             *reinterpret_cast<uint16_t*>(cc + o) =
                 (uint16_t)((cnt[0] > 0 ? 1 : 0) | ((cnt[1] > 0 ? 1 : 0) << 8));
 #pragma unroll
@@ -1588,17 +1512,16 @@ __device__ __forceinline__ void prolong4_body(const float* __restrict__ uc, int 
     const int t = bx * kTpb + threadIdx.x;
     if (4 * t >= w) return;
     const int64_t n = (int64_t)h * w, ncs = (int64_t)hc * wc;
-    const int64_t i = (int64_t)y * w + 4 * t;
+    const Pro4Addr pa = prolong4_addr(y, t, w, hc, wc);
+    const int64_t i = pa.fine;
     const uint32_t m = *reinterpret_cast<const uint32_t*>(c + i);
     // nearer and farther coarse rows of fine row y
-    const int rn = y >> 1, rf = pro_far(y, hc);
-    const int J0 = 2 * t;
-    const int jl = max(J0 - 1, 0), jr = min(J0 + 2, wc - 1);
+    const int J0 = pa.J0, jl = pa.jl, jr = pa.jr;
     // ---- all loads: the coarse values first (unconditional), then f
     // where the mask is set; 32-bit element offsets inside a plane ----
     float2 mn[NC], mf[NC];
     float ln[NC], lf[NC], en[NC], ef[NC];
-    const uint32_t on = (uint32_t)rn * (uint32_t)wc, of = (uint32_t)rf * (uint32_t)wc;
+    const uint32_t on = pa.rn, of = pa.rf;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         const float* C = uc + k * ncs;
@@ -1794,29 +1717,8 @@ __global__ __launch_bounds__(kTpb) void k_prolong(const float* __restrict__ uc, 
 // 0: the reflecting boundary. One float64 partial per workgroup and
 // channel, in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int kWalkRows = 16;
-constexpr int kWalkWaves = 4;
-
-struct Walk {
-    int lane, x, y0, y1;
-    uint32_t xc, xe;  // clamped column, and the edge column lanes 0 / 63 read
-    bool inb, edge;
-};
-
 __device__ __forceinline__ Walk walk_geom(int h, int w) {
-    Walk k;
-    k.lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    k.x = (blockIdx.x * kWalkWaves + wv) * 64 + k.lane;
-    k.inb = k.x < w;
-    k.xc = k.inb ? k.x : w - 1;
-    k.edge = k.lane == 0 || k.lane == 63;
-    // from the clamped column, so that lane 0 of a wave lying wholly right of
-    // the image still reads inside the row (its values are not used)
-    k.xe = k.lane == 0 ? (uint32_t)max((int)k.xc - 1, 0) : (uint32_t)min(k.x + 1, w - 1);
-    k.y0 = blockIdx.y * kWalkRows;
-    k.y1 = min(k.y0 + kWalkRows, h);
-    return k;
+    return walk_at(h, w, blockIdx.x, blockIdx.y, threadIdx.x);
 }
 
 // Sum of acc over the workgroup into partial[wg][ch] (fixed order).
@@ -1864,17 +1766,17 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_residual_walk(
     uint32_t cm[R];
 #pragma unroll
     for (int t = 0; t < R + 2; ++t)
-        v[t] = val((uint32_t)min(max(k.y0 - 1 + t, 0), h - 1) * W + k.xc);
+        v[t] = val(walk_vrow(k, h, t) * W + k.xc);
 #pragma unroll
     for (int t = 0; t < R; ++t) {
-        const uint32_t row = (uint32_t)min(k.y0 + t, h - 1) * W;
+        const uint32_t row = walk_row(k, h, t) * W;
         cm[t] = at32(c, row + k.xc);
         e[t] = k.edge ? val(row + k.xe) : 0.f;
     }
     float fv[R];
 #pragma unroll
     for (int t = 0; t < R; ++t)
-        fv[t] = cm[t] ? at32(F, (uint32_t)min(k.y0 + t, h - 1) * W + k.xc) : 0.f;
+        fv[t] = cm[t] ? at32(F, walk_row(k, h, t) * W + k.xc) : 0.f;
     const int nr = k.y1 - k.y0;
     double acc = 0.0;
 #pragma unroll
@@ -1888,7 +1790,7 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_residual_walk(
         const float ry = cm[t] ? fv[t] - cur
                                : ((v[t] - cur) + (v[t + 2] - cur)) + ((lft - cur) + (rgt - cur));
         if (k.inb && t < nr) {
-            const uint32_t i = (uint32_t)(k.y0 + t) * W + k.xc;
+            const uint32_t i = walk_out(k, W, t);
             acc += (double)ry * (double)ry;
             if (r) put32(r + ch * n, i, ry);
             if (rhs) put32(rhs + ch * n, i, f_to_bf16(ry));
@@ -2031,10 +1933,10 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_cg_dir_matvec(
     uint32_t cm[R];
 #pragma unroll
     for (int t = 0; t < R + 2; ++t)
-        v[t] = pn((uint32_t)min(max(k.y0 - 1 + t, 0), h - 1) * W + k.xc);
+        v[t] = pn(walk_vrow(k, h, t) * W + k.xc);
 #pragma unroll
     for (int t = 0; t < R; ++t) {
-        const uint32_t row = (uint32_t)min(k.y0 + t, h - 1) * W;
+        const uint32_t row = walk_row(k, h, t) * W;
         cm[t] = at32(c, row + k.xc);
         e[t] = k.edge ? pn(row + k.xe) : 0.f;
     }
@@ -2051,7 +1953,7 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_cg_dir_matvec(
         const float qv =
             cm[t] == 0 ? ((cur - v[t]) + (cur - v[t + 2])) + ((cur - lft) + (cur - rgt)) : 0.f;
         if (k.inb && t < nr) {
-            const uint32_t i = (uint32_t)(k.y0 + t) * W + k.xc;
+            const uint32_t i = walk_out(k, W, t);
             put32(pout + ch * n, i, cur);
             put32(q + ch * n, i, qv);
             acc += (double)cur * (double)qv;
@@ -2083,7 +1985,7 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_cg_update(
         float xs[R], rs[R], ps[R], qs[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-            const uint32_t i = (uint32_t)min(k.y0 + t, h - 1) * W + k.xc;
+            const uint32_t i = walk_row(k, h, t) * W + k.xc;
             xs[t] = at32(X, i);
             rs[t] = at32(RR, i);
             ps[t] = at32(P, i);
@@ -2092,7 +1994,7 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_cg_update(
 #pragma unroll
         for (int t = 0; t < R; ++t) {
             if (t < nr) {
-                const uint32_t i = (uint32_t)(k.y0 + t) * W + k.xc;
+                const uint32_t i = walk_out(k, W, t);
                 put32(X, i, xs[t] + a * ps[t]);
                 const float rv = rs[t] - a * qs[t];
                 put32(RR, i, rv);
@@ -2198,10 +2100,10 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_kry_matvec_dots(
     uint32_t cm[R];
 #pragma unroll
     for (int t = 0; t < R + 2; ++t)
-        v[t] = at32(Z, (uint32_t)min(max(k.y0 - 1 + t, 0), h - 1) * W + k.xc);
+        v[t] = at32(Z, walk_vrow(k, h, t) * W + k.xc);
 #pragma unroll
     for (int t = 0; t < R; ++t) {
-        const uint32_t row = (uint32_t)min(k.y0 + t, h - 1) * W;
+        const uint32_t row = walk_row(k, h, t) * W;
         cm[t] = at32(c, row + k.xc);
         e[t] = k.edge ? at32(Z, row + k.xe) : 0.f;
     }
@@ -2218,7 +2120,7 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_kry_matvec_dots(
         const float q =
             cm[t] == 0 ? ((cur - v[t]) + (cur - v[t + 2])) + ((cur - lft) + (cur - rgt)) : 0.f;
         wv[t] = q;
-        if (k.inb && t < nr) put32(wout + ch * n, (uint32_t)(k.y0 + t) * W + k.xc, q);
+        if (k.inb && t < nr) put32(wout + ch * n, walk_out(k, W, t), q);
     }
     const int64_t wg = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     for (int i = 0; i < nv; ++i) {
@@ -2227,7 +2129,7 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_kry_matvec_dots(
         if (k.inb) {
 #pragma unroll
             for (int t = 0; t < R; ++t)
-                if (t < nr) acc += (double)wv[t] * (double)at32(Vi, (uint32_t)(k.y0 + t) * W + k.xc);
+                if (t < nr) acc += (double)wv[t] * (double)at32(Vi, walk_out(k, W, t));
         }
         walk_sum_to(acc, partial + (wg * nv + i) * channels + ch);
     }
@@ -2251,18 +2153,18 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_kry_orth(
     if (k.inb) {
         float x[R];
 #pragma unroll
-        for (int t = 0; t < R; ++t) x[t] = at32(Wp, (uint32_t)min(k.y0 + t, h - 1) * W + k.xc);
+        for (int t = 0; t < R; ++t) x[t] = at32(Wp, walk_row(k, h, t) * W + k.xc);
         for (int i = 0; i < nv; ++i) {
             const float hi = (float)hcol[i * channels + ch];
             const float* __restrict__ Vi = V + i * vstride + ch * n;
 #pragma unroll
             for (int t = 0; t < R; ++t)
-                x[t] -= hi * at32(Vi, (uint32_t)min(k.y0 + t, h - 1) * W + k.xc);
+                x[t] -= hi * at32(Vi, walk_row(k, h, t) * W + k.xc);
         }
 #pragma unroll
         for (int t = 0; t < R; ++t) {
             if (t < nr) {
-                put32(Wp, (uint32_t)(k.y0 + t) * W + k.xc, x[t]);
+                put32(Wp, walk_out(k, W, t), x[t]);
                 acc += (double)x[t] * (double)x[t];
             }
         }
@@ -3324,8 +3226,7 @@ hipError_t launch_prolong(const float* uc, int hc, int wc, const float* f, const
 }
 
 static dim3 walk_grid(int h, int w, int channels) {
-    return dim3((w + 64 * kWalkWaves - 1) / (64 * kWalkWaves), (h + kWalkRows - 1) / kWalkRows,
-                channels);
+    return dim3(walk_groups_x(w), walk_groups_y(h), channels);
 }
 
 int residual_partials(int h, int w) {

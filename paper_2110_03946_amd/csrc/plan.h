@@ -40,6 +40,8 @@ bool use_skip(const ddi_params& prm, const SweepArgs& a0);
 // The finest level's sweeps of this plan run their blocks in the order
 // of the CG steps of the level-2 blocks over them (order_blocks).
 bool use_order(const ddi_params& prm, int h, int w, int C);
+// Sweep geometry of level l (0 = finest) of a plan for h x w x C.
+SweepArgs level_sweep(int h, int w, int C, const ddi_params& prm, int l);
 // coarse_solver = 1 on a coarsest level too large for one workgroup: the
 // solve runs on a grid of workgroups (launch_coarse_cg_grid).
 bool use_coarse_grid(const ddi_params& prm, int h, int w);

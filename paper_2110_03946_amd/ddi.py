@@ -110,6 +110,8 @@ def lib():
             "ddi_noalloc_scratch_bytes": (i, [i, i, i, i, i, ctypes.POINTER(ctypes.c_size_t)]),
             "ddi_coarse_solve": (i, [vp, vp, i, i, i, vp, i, d, vp]),
             "ddi_coarse_grid_bytes": (i, [i, i, i, ctypes.POINTER(ctypes.c_size_t)]),
+            "ddi_selfcheck_access": (i, [i, i, i, vp, ctypes.POINTER(ctypes.c_longlong),
+                                         ctypes.POINTER(ctypes.c_longlong), ctypes.c_char_p, i]),
             "ddi_coarse_grid_debug_spin_limit": (i, [ctypes.c_long]),
             "ddi_coarse_solve_grid": (i, [vp, vp, i, i, i, vp, i, d, i, vp, ctypes.c_size_t, vp,
                                           vp]),
@@ -440,6 +442,17 @@ def coarse_solve(f, c, max_iter: int = 500, tol: float = 1e-10, u=None, stream=N
     _check(lib().ddi_coarse_solve(_ptr(f), _ptr(c), H, W, C, _ptr(u), max_iter, float(tol),
                                   _stream(stream)), "ddi_coarse_solve")
     return u
+
+
+def selfcheck_access(h: int, w: int, channels: int, p: Params | None = None):
+    """Host replay of every global-memory offset of a plan's kernels (no GPU):
+    returns (offsets checked, offsets outside their buffer, first of those)."""
+    checked, bad = ctypes.c_longlong(0), ctypes.c_longlong(0)
+    buf = ctypes.create_string_buffer(512)
+    _check(lib().ddi_selfcheck_access(h, w, channels, ctypes.byref(p) if p is not None else None,
+                                      ctypes.byref(checked), ctypes.byref(bad), buf, 512),
+           "ddi_selfcheck_access")
+    return checked.value, bad.value, buf.value.decode()
 
 
 def coarse_grid_bytes(h: int, w: int, channels: int) -> int:

@@ -204,3 +204,39 @@ def test_skip_flags_only_where_tiles_lie_in_the_3x3_neighbourhood(h, w):
         expect = (bh == 64 and _tiles_in_neighbour_owners(h, 64, ov)
                   and _tiles_in_neighbour_owners(w, 64, ov))
         assert extra == (2 * nblk * C * 4 if expect else 0), (h, w, ov)
+
+
+# Parameter sets of the access replay: the default (two-wave 64-row blocks on
+# every level that has them), one-wave blocks of 32, 16 and 8 rows, ragged
+# blocks (40 rows), no overlap, one and six levels.
+REPLAY_PARAMS = [dict(), dict(block=32, overlap=2), dict(block=16, overlap=3, levels=3),
+                 dict(block=8, overlap=1, levels=2), dict(block=40, overlap=6, levels=3),
+                 dict(block=64, overlap=0), dict(levels=1), dict(levels=6, coarse_block=32)]
+
+
+@pytest.mark.parametrize("h", [1, 5, 65, 129])
+@pytest.mark.parametrize("w", [1, 3, 47, 63, 64, 65, 70])
+def test_kernel_offsets_in_bounds(h, w):
+    """Every global-memory offset of every thread of every launch a plan
+    makes (mask bits, coarsening, the sweeps of all levels with the first
+    sweep built from the coarser level, prolongation, the walking stencil
+    kernels), from the kernels' own index functions, lies in its buffer: odd
+    and edge widths and heights, 1-4 channels, several block shapes."""
+    for C in (1, 2, 3, 4):
+        for prm in REPLAY_PARAMS:
+            p = ddi.default_params(**prm)
+            if ddi.check_params(h, w, C, p) != ddi.DDI_OK:
+                continue
+            checked, bad, first = ddi.selfcheck_access(h, w, C, p)
+            assert checked > 0
+            assert bad == 0, (h, w, C, prm, first)
+
+
+def test_kernel_offsets_in_bounds_4k():
+    """The 4K RGB benchmark plan (3840 x 2160 x 3, four levels): about 3e8
+    offsets, none outside its buffer; more channels, more offsets."""
+    c3, bad, first = ddi.selfcheck_access(2160, 3840, 3)
+    assert bad == 0, first
+    assert c3 > 2e8
+    c1, bad1, _ = ddi.selfcheck_access(2160, 3840, 1)
+    assert bad1 == 0 and c1 < c3
