@@ -168,8 +168,9 @@ def roofline_of(flops: float, bytes_: float, sweep_ms: float, launches: int) -> 
 
 
 def measured_traffic():
-    """HBM bytes per finest-level sweep launch from the committed rocprofv3
-    counter summary, or None when the kernels changed since it was taken."""
+    """HBM bytes of the second finest-level sweep launch (the kernel the
+    roofline describes) from the committed rocprofv3 counter summary, or
+    None when the kernels changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_sweep2_4k_rgb_traffic.json")
     src = os.path.join(ROOT, "paper_2110_03946_amd", "csrc", "kernels.hip")
