@@ -345,9 +345,11 @@ typedef struct ddi_batch ddi_batch;
  * Create a batch plan for n images; image i is heights[i] x widths[i] with
  * `channels` channels (shared by all). p is NULL (defaults), one params
  * struct (n_params = 1) or one per image (n_params = n), e.g. picked per
- * size by a tuner. min_sweeps, max_sweeps, check_every and timing must be
- * equal across images (the finest-level sweeps run in lock step); use_graph
- * is ignored. Allocates every device buffer once.
+ * size by a tuner. max_sweeps, check_every and timing must be equal across
+ * images (the finest-level sweeps run in lock step); min_sweeps may differ:
+ * the stop tests run after sweep m, m + check_every, ... (m the smallest
+ * min_sweeps), and an image's test passes only from its own min_sweeps on.
+ * use_graph is ignored. Allocates every device buffer once.
  * Errors: DDI_EINVAL, DDI_ENOMEM, DDI_ENODEV, DDI_EHIP.
  */
 int ddi_batch_create(ddi_batch** out, int n, const int* heights,

@@ -534,6 +534,7 @@ void build_fine(ddi_batch* B, const std::vector<int>& act, const std::vector<int
             j.rel = reinterpret_cast<double*>(B->ctl + (size_t)i * kCtlInts + 4);
             j.tol2 = t == 0 ? P->p.rel_tol * P->p.rel_tol : -1.0;
             j.nb = sweep_partials(P->lv[0].sw);
+            j.min_n = P->p.min_sweeps;
             jobs.push_back(j);
         }
         T.decide[t] = A.put(jobs);
@@ -606,8 +607,8 @@ int ddi_batch_create(ddi_batch** out, int n, const int* heights, const int* widt
         if (e) return e;
         // batches run float32 ORAS
         if (prm[i].storage != 0 || prm[i].method != 0) return DDI_EINVAL;
-        if (prm[i].min_sweeps != prm[0].min_sweeps || prm[i].max_sweeps != prm[0].max_sweeps ||
-            prm[i].check_every != prm[0].check_every || prm[i].timing != prm[0].timing)
+        if (prm[i].max_sweeps != prm[0].max_sweeps || prm[i].check_every != prm[0].check_every ||
+            prm[i].timing != prm[0].timing)
             return DDI_EINVAL;
     }
     int e = check_device();
@@ -617,7 +618,10 @@ int ddi_batch_create(ddi_batch** out, int n, const int* heights, const int* widt
     B->n = n;
     B->C = channels;
     B->s = (hipStream_t)stream;
+    // the stop tests start with the smallest min_sweeps; each image's test
+    // passes only from its own on
     B->min_sweeps = prm[0].min_sweeps;
+    for (int i = 1; i < n; ++i) B->min_sweeps = std::min(B->min_sweeps, prm[i].min_sweeps);
     B->max_sweeps = prm[0].max_sweeps;
     B->check_every = prm[0].check_every;
     B->timing = prm[0].timing != 0;

@@ -139,6 +139,7 @@ struct DecideJob {
     double* rel;
     double tol2;  // squared tolerance, < 0: never passes
     int nb;       // sweep partial rows (blocks)
+    int min_n;    // the image's min_sweeps: an earlier test never passes
 };
 
 // One image's column sums in a batched reduction.

@@ -1835,7 +1835,7 @@ template <int NC>
 __device__ __forceinline__ void decide_body(const double* __restrict__ partial, int nb,
                                             const double* __restrict__ stats,
                                             int* __restrict__ ctl, double* __restrict__ rel,
-                                            double tol2, int n) {
+                                            double tol2, int n, int min_n) {
     if (ctl[0] != 0) return;  // an earlier test passed: sweep n did not run
     __shared__ double sm[kDecideTpb / 64][NC];
     double v[NC];
@@ -1870,7 +1870,7 @@ __device__ __forceinline__ void decide_body(const double* __restrict__ partial, 
             ctl[2] = err;
             ctl[1] = n;
             ctl[0] = 1;
-        } else if (worst <= tol2) {
+        } else if (worst <= tol2 && n >= min_n) {
             ctl[1] = n;
             ctl[0] = 1;
         }
@@ -1883,16 +1883,16 @@ __global__ __launch_bounds__(kDecideTpb) void k_decide(const double* __restrict_
                                                        int* __restrict__ ctl,
                                                        double* __restrict__ rel, double tol2,
                                                        int n) {
-    decide_body<NC>(partial, nb, stats, ctl, rel, tol2, n);
+    decide_body<NC>(partial, nb, stats, ctl, rel, tol2, n, 0);
 }
 
 // One stop test per image after finest-level sweep n: workgroup j tests
-// job j.
+// job j; an image's test passes only from its own min_sweeps on.
 template <int NC>
 __global__ __launch_bounds__(kDecideTpb) void k_decide_batch(const DecideJob* __restrict__ jobs,
                                                              int n) {
     const DecideJob& J = jobs[blockIdx.x];
-    decide_body<NC>(J.partial, J.nb, J.stats, J.ctl, J.rel, J.tol2, n);
+    decide_body<NC>(J.partial, J.nb, J.stats, J.ctl, J.rel, J.tol2, n, J.min_n);
 }
 
 __global__ void k_clear_int(int* __restrict__ p, int n) {

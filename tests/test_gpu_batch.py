@@ -184,3 +184,24 @@ def test_batch_recipe_sample_vs_oracle(ddi):
             "sweeps", st[i]["sweeps"])
         assert err <= 0.5, i
         np.testing.assert_array_equal(u[:, c == 1], f[:, c == 1])
+
+
+def test_batch_per_image_min_sweeps(ddi):
+    """Images with different min_sweeps (a per-class sweep floor) share one
+    batch: the stop tests start at the smallest, an image's test passes only
+    from its own floor on, and each image equals its single-image solve bit
+    for bit (same sweep count)."""
+    C = 3
+    data = inputs(MIXED[:4], C, wl=8)
+    floors = [1, 3, 5, 2]
+    prms = [ddi.default_params(**dict(SMALL_PRM, rel_tol=1e-2, min_sweeps=m)) for m in floors]
+    say("batch per-image min_sweeps", floors)
+    with ddi.Batch([c.shape for _, c in data], C, params=prms) as b:
+        us, st, codes = b.solve([dev(f) for f, _ in data], [dev(c) for _, c in data])
+    assert codes == [0] * len(data)
+    ref = single_solves(ddi, data, C, prms)
+    for i, (u_t, s, (u_ref, s_ref), m) in enumerate(zip(us, st, ref, floors)):
+        assert s["sweeps"] == s_ref["sweeps"] and s["sweeps"] >= m, (i, s["sweeps"], m)
+        np.testing.assert_array_equal(host(u_t), u_ref)
+    # a loose tolerance every image meets early: each stops at its own floor
+    assert [s["sweeps"] for s in st][1:3] == [3, 5]
