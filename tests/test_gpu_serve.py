@@ -61,3 +61,34 @@ def test_serve_results_and_admission(serve, graph, realtime):
             exact[key] = oracle.solve_exact(f.cpu().numpy().astype(np.float64), c.cpu().numpy())
         u = got[r.rid].numpy()
         assert np.abs(u - exact[key]).max() <= 0.5, r
+
+
+def test_serve_hd_requests(serve):
+    """720p and 1080p RGB requests through the serving loop with the tuned
+    table (graph replays, results copied to host memory): every result within
+    0.5 grey levels of the exact solution of its frame."""
+    mix = {(720, 1280): 0.5, (1080, 1920): 0.5}
+    reqs, dens = serve.poisson_stream(60.0, 0.4, seed=11, mix=mix, frames_per_size=1)
+    pool = serve.frame_pool(dens, channels=3, workload=41)
+    got = {}
+
+    def keep(req, out):
+        got[req.rid] = out.clone() if not out.is_cuda else out.cpu()
+
+    srv = serve.Server(channels=3, budget_bytes=4 << 30, mix=mix, use_graph=True,
+                       on_result=keep, max_slots=2)
+    say("serve hd", len(reqs), "requests", srv.stats.slots)
+    srv.warmup(pool)
+    st = srv.run(reqs, pool, realtime=True)
+    srv.close()
+    say("  ", st.summary())
+    assert len(got) == len(reqs) >= 10
+    assert st.used_bytes <= st.budget_bytes
+    exact = {}
+    for r in reqs:
+        f, c = pool[r.size][r.frame]
+        key = (r.size, r.frame)
+        if key not in exact:
+            exact[key] = oracle.solve_exact(f.cpu().numpy().astype(np.float64), c.cpu().numpy())
+        err = float(np.abs(got[r.rid].numpy() - exact[key]).max())
+        assert err <= 0.5, (r.size, err)
