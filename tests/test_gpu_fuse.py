@@ -1,12 +1,15 @@
 """Prolongation fused into the first sweep of a level (fuse_prolong = 1)
-against the separate prolongation kernel (fuse_prolong = 0).
+against the separate prolongation kernel (fuse_prolong = 0), and one fused
+sweep against the oracle.
 
-The fused tile load evaluates the same bilinear formula in float64 and
-rounds once, so for grey-level data (every interpolation sum exact in
-float64) both paths give the same iterates: the solves must agree bit for
-bit, in the returned image and in the statistics. The separate path is
-itself pinned to the oracle's prolongation and sweep; the full solves are
-also checked against the oracle's exact solution.
+The fused tile load and the separate prolongation kernels evaluate the same
+float32 mix (3/4 of the nearer and 1/4 of the farther sample, columns then
+rows, one rounding each), so both paths give the same iterates: the solves
+must agree bit for bit, in the returned image and in the statistics. The
+separate path is itself pinned to the oracle's prolongation and sweep; the
+full solves are also checked against the oracle's exact solution, and one
+fused first sweep at 1920 x 1080 x 3 against the oracle's prolongation and
+sweep on sampled blocks.
 """
 import numpy as np
 import pytest
@@ -149,3 +152,45 @@ def test_fused_prolongation_in_batches(ddi):
         assert s1 == s0
         for a, b_ in zip(u1, u0):
             np.testing.assert_array_equal(a, b_)
+
+
+def test_fused_first_sweep_vs_oracle_1080p(ddi):
+    """One fused first finest sweep at 1920 x 1080 x 3, against the oracle
+    on sampled blocks (the four corners and four inside). The plan has two
+    levels and solves level 1 in float64 (the grid solve: 540 x 960 pixels),
+    then runs exactly one finest sweep, whose tile is the prolongation of
+    that solution built in the tile load. The oracle takes its own level 1
+    (coarsen, exact float64 solve), fine_start and one oras_step.
+
+    Tolerance 3e-3: the sweep's 2e-3 (float32 against float64 CG) plus the
+    difference of the two starts, which is the prolongation's 2e-5 and the
+    float64 coarse solve's 1e-4 carried through one local solve."""
+    C, H, W = 3, 1080, 1920
+    f, c = synth.make_workload(H, W, C, 0.04, "bernoulli", workload=15, index=0)
+    p = dict(levels=2, coarse_solver=1, coarse_cg_tol=1e-10, coarse_cg_iters=20000,
+             block=64, overlap=4, robin_alpha=0.25, local_iters=16, local_tol=0.0,
+             min_sweeps=1, max_sweeps=1, rel_tol=0.0, final_residual=0)
+    say("fused first sweep vs oracle", C, H, W)
+    with ddi.Plan(H, W, C, **p) as plan:
+        u_t, st = plan.solve(dev(f), dev(c), allow_noconv=True)
+    out = host(u_t)
+    assert st["sweeps"] == 1
+    fd = f.astype(np.float64)
+    fc, cc = oracle.coarsen(fd, c)
+    start = oracle.fine_start(oracle.solve_exact(fc, cc), fd, c)
+    oy, bh = oracle.block_origins(H, 64, 4)
+    ox, bw = oracle.block_origins(W, 64, 4)
+    ly, hy = oracle.owner_bounds(oy, bh, H)
+    lx, hx = oracle.owner_bounds(ox, bw, W)
+    nby, nbx = len(oy), len(ox)
+    rng = np.random.default_rng(15)
+    picks = [(0, 0), (nby - 1, nbx - 1), (0, nbx - 1), (nby - 1, 0)]
+    picks += [(int(rng.integers(nby)), int(rng.integers(nbx))) for _ in range(4)]
+    for i, (by, bx) in enumerate(picks):
+        ch = i % C
+        ref, _ = oracle.oras_step(start[ch], fd[ch], c, 64, 4, 0.25, 16, blocks=[(by, bx)])
+        sl = (slice(ly[by], hy[by]), slice(lx[bx], hx[bx]))
+        err = float(np.abs(out[ch][sl] - ref[sl]).max())
+        say("  block", by, bx, "ch", ch, "dev", err)
+        assert err <= 3e-3, (by, bx, err)
+    np.testing.assert_array_equal(out[:, c == 1], f[:, c == 1])
