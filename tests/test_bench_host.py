@@ -39,3 +39,20 @@ def test_summarize_trace(tmp_path):
     assert float(big[5]) == 59.0 and float(big[6]) == 60.0  # min, max
     assert int(cells[("ddi::k_sweep2<false>", 120)][3]) == 1
     assert ("ddi::k_decide<3>", 1) in cells
+
+
+def test_psnr_against_worked_values():
+    """PSNR = 10 log10(255^2 / MSE) over all pixels and channels: a uniform
+    error of 1 grey level is 48.13 dB, of 255 is 0 dB; identical images give
+    infinity; the MSE averages over every element."""
+    import math
+    import torch
+    sys.path.insert(0, ROOT)
+    import bench
+    a = torch.zeros((3, 4, 5))
+    assert bench.psnr(a, a) == float("inf")
+    assert abs(bench.psnr(a, a + 1.0) - 20 * math.log10(255.0)) < 1e-9
+    assert abs(bench.psnr(a, a + 255.0)) < 1e-9
+    b = a.clone()
+    b[0, 0, 0] = 60.0  # MSE = 3600 / 60 = 60
+    assert abs(bench.psnr(a, b) - 10 * math.log10(255.0 ** 2 / 60.0)) < 1e-9
