@@ -169,19 +169,31 @@ def roofline_of(flops: float, bytes_: float, sweep_ms: float, launches: int) -> 
     return r
 
 
+SWEEP_SOURCES = ("sweep.hip", "device.h", "access.h", "internal.h")
+
+
+def sweep_sources_sha256() -> str:
+    """SHA-256 over the sources the finest-level sweep kernel is compiled
+    from, in a fixed order."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in SWEEP_SOURCES:
+        data = open(os.path.join(ROOT, "paper_2110_03946_amd", "csrc", name), "rb").read()
+        h.update(name.encode() + b"\0" + str(len(data)).encode() + b"\0" + data)
+    return h.hexdigest()
+
+
 def measured_traffic():
     """HBM bytes of the second finest-level sweep launch (the kernel the
     roofline describes) from the committed rocprofv3 counter summary, or
-    None when the kernels changed since it was taken."""
-    import hashlib
+    None when the sweep's sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "k_sweep2_4k_rgb_traffic.json")
-    src = os.path.join(ROOT, "paper_2110_03946_amd", "csrc", "kernels.hip")
     try:
         d = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = sweep_sources_sha256()
     except (OSError, ValueError):
         return None
-    return d["hbm_bytes_per_launch"] if d.get("kernels_hip_sha256") == sha else None
+    return d["hbm_bytes_per_launch"] if d.get("sweep_sources_sha256") == sha else None
 
 
 def summarize_trace(path: str) -> str:

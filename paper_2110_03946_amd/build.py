@@ -12,17 +12,17 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddi.so")
-SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "api.cpp"),
-           os.path.join(CSRC, "batch.cpp"), os.path.join(CSRC, "mlcg.cpp"),
-           os.path.join(CSRC, "krylov.cpp"), os.path.join(CSRC, "noalloc.hip"),
-           os.path.join(CSRC, "replay.cpp")]
+SOURCES = [os.path.join(CSRC, n) for n in
+           ("sweep.hip", "levels.hip", "outer.hip", "coarse.hip", "noalloc.hip",
+            "api.cpp", "batch.cpp", "mlcg.cpp", "krylov.cpp", "replay.cpp")]
 HEADERS = [os.path.join(CSRC, "internal.h"), os.path.join(CSRC, "plan.h"),
-           os.path.join(CSRC, "access.h"),
+           os.path.join(CSRC, "access.h"), os.path.join(CSRC, "device.h"),
            os.path.join(ROOT, "include", "ddi.h")]
 
 
@@ -39,9 +39,7 @@ def flags():
             "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + flags() + ["-shared", "-o", tmp] + SOURCES
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -51,7 +49,20 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{err}")
     if verbose and err.strip():
         print(err)
-    os.replace(tmp, LIB)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source to an object (in parallel, at most 8 at a time)
+    and link them into libddi.so, replaced only once the link succeeded."""
+    from concurrent.futures import ThreadPoolExecutor
+    with tempfile.TemporaryDirectory(prefix="ddi_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(s) + ".o") for s in SOURCES]
+        cmds = [[hipcc()] + flags() + ["-c", s, "-o", o] for s, o in zip(SOURCES, objs)]
+        with ThreadPoolExecutor(max_workers=min(8, len(cmds))) as ex:
+            list(ex.map(lambda c: _run(c, verbose), cmds))
+        tmp = LIB + ".tmp"
+        _run([hipcc(), "--offload-arch=gfx950", "-fPIC", "-shared", "-o", tmp] + objs, verbose)
+        os.replace(tmp, LIB)
     return LIB
 
 

@@ -1,6 +1,7 @@
 // Solver driver and C ABI (include/ddi.h) of the multilevel ORAS inpainting
 // library. Host code only: it owns the device buffers of a plan and
-// enqueues the kernels of kernels.hip on the plan's stream.
+// enqueues the kernels (sweep.hip, levels.hip, outer.hip, coarse.hip) on the
+// plan's stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -1,5 +1,6 @@
-// Internal declarations shared by the kernels (kernels.hip) and the solver
-// driver / C ABI (api.cpp). Not part of the public interface.
+// Internal declarations shared by the kernels (sweep.hip, levels.hip,
+// outer.hip, coarse.hip) and the solver driver / C ABI (api.cpp, batch.cpp,
+// mlcg.cpp, krylov.cpp). Not part of the public interface.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -149,7 +150,7 @@ struct ReduceJob {
     int nrows, stride;
 };
 
-// ---- launchers (kernels.hip); all asynchronous on `s` ----
+// ---- launchers (the .hip kernel files); all asynchronous on `s` ----
 
 // Largest block edge the sweep kernel holds on chip (one wave64 per block:
 // lanes are columns, rows live in registers).
