@@ -225,10 +225,10 @@ void replay_sweep(Replay& R, const SweepArgs& a, bool pro) {
                     const int64_t r1 = (int64_t)tile_row(k, g, std::min(th, 2 * kSplitRows + 1)) * W;
                     R.at("k_sweep2", "halo left", r1 + halo_left(k), n);
                     R.at("k_sweep2", "halo right", r1 + halo_right(k, g), n);
-                    if (on) {
-                        const MaskWords mw = mask_words(k, W, x);
+                    {  // every lane, idle lanes at the last column
+                        const MaskWords mw = mask_words(k, W, std::min(x, w - 1));
                         R.at("k_sweep2", "mask word", mw.w0, nm);
-                        if (mw.sh) R.at("k_sweep2", "second mask word", (int64_t)mw.w0 + W, nm);
+                        R.at("k_sweep2", "second mask word", (int64_t)mw.w0 + W, nm);
                     }
                     const int ry0 = k.y0 + kSplitRows * wi;
                     if (on && x >= k.oxlo && x < k.oxhi)
@@ -295,7 +295,7 @@ void replay_sweep(Replay& R, const SweepArgs& a, bool pro) {
             if (on) {
                 const MaskWords mw = mask_words(k, W, x);
                 R.at("k_sweep", "mask word", mw.w0, nm);
-                if (mw.sh) R.at("k_sweep", "second mask word", (int64_t)mw.w0 + W, nm);
+                R.at("k_sweep", "second mask word", (int64_t)mw.w0 + W, nm);
             }
             if (on && x >= k.oxlo && x < k.oxhi)
                 for (int y = 0; y < rpw; ++y)

@@ -41,6 +41,25 @@ namespace {
 // do not fit v, r, p and q in 256 VGPRs).
 constexpr int kTileW = kMaxBlock + 2;
 
+// The two mask words holding a block column's 64 unknown-pixel bits, and
+// the bits themselves (bit y <-> row y0 + y). Both words are always loaded
+// (the transposed mask has one all-zero group row past the last, so the
+// second exists) and combined without a branch: the loads issue together
+// with the tile's, and the bits cost no extra memory round trip whatever
+// y0 % 64 is.
+struct BlockWords {
+    uint64_t lo, hi;
+    int sh;
+};
+__device__ __forceinline__ BlockWords block_words(const uint64_t* __restrict__ mbits,
+                                                  const MaskWords& mw, uint32_t W) {
+    return {mbits[mw.w0], mbits[mw.w0 + W], mw.sh};
+}
+__device__ __forceinline__ uint64_t block_bits(const BlockWords& b) {
+    // (hi << 1) << (63 - sh): hi << (64 - sh) without the undefined shift by 64
+    return (b.lo >> b.sh) | ((b.hi << 1) << (63 - b.sh));
+}
+
 // The sweep of logical block lb (channel-major over the block grid) of one
 // image, with the block's tile in `lds` ((RPW + 2) x kTileW floats).
 //
@@ -154,10 +173,7 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
     // unknown-pixel bits of this column: bit y <-> row y0 + y
     uint32_t mlo = 0u, mhi = 0u;
     if (on) {
-        const MaskWords mw = mask_words(kb, (uint32_t)g.w, x);
-        const uint64_t* mb = mbits + mw.w0;
-        uint64_t bits = mb[0] >> mw.sh;
-        if (mw.sh) bits |= mb[g.w] << (64 - mw.sh);
+        uint64_t bits = block_bits(block_words(mbits, mask_words(kb, (uint32_t)g.w, x), (uint32_t)g.w));
         if (nrows < 64) bits &= (1ull << (nrows & 63)) - 1ull;
         mlo = (uint32_t)bits;
         mhi = (uint32_t)(bits >> 32);
@@ -401,6 +417,9 @@ __device__ __forceinline__ void tile2_load(Tile2& T, const Blk& k, const SweepAr
     const uint32_t Wd = g.w;
     // tile row t0 + j = image row y0 - 1 + t0 + j; only tile rows 0 and 65
     // (first of wave 0, last of wave 1) can lie outside the image
+    // the mask words first, combined after the tile loads are issued (idle
+    // lanes read the last column's words and drop them)
+    const BlockWords bw = block_words(mbits, mask_words(k, Wd, min(x, g.w - 1)), Wd);
     const Tile2Rows tr = tile2_rows(k, wi, Wd, xc);
     T.col[0] = ld(tr.first);
     // byte offsets: one add per row
@@ -417,13 +436,7 @@ __device__ __forceinline__ void tile2_load(Tile2& T, const Blk& k, const SweepAr
     const uint32_t r1 = tile_row(k, g, min(th, 2 * RPW + 1)) * Wd;
     T.hl = ld(r1 + xl);
     T.hr = ld(r1 + xr);
-    uint64_t bits = 0;
-    if (on) {
-        const MaskWords mw = mask_words(k, Wd, x);
-        const uint64_t* mb = mbits + mw.w0;
-        bits = mb[0] >> mw.sh;
-        if (mw.sh) bits |= mb[g.w] << (64 - mw.sh);
-    }
+    const uint64_t bits = on ? block_bits(bw) : 0ull;
     T.mlo = (uint32_t)bits;
     T.mhi = (uint32_t)(bits >> 32);
 }
@@ -509,13 +522,8 @@ __device__ __forceinline__ void tile2_load_prolong(Tile2& T, const Blk& k, const
     const uint32_t Wd = g.w;
     const float* __restrict__ Uc = S.uc + (int64_t)k.ch * S.hc * S.wc;
     const float* __restrict__ F = S.f + k.ch * a.cpitch;
-    uint64_t bits = 0;
-    if (on) {
-        const MaskWords mw = mask_words(k, Wd, x);
-        const uint64_t* mb = mbits + mw.w0;
-        bits = mb[0] >> mw.sh;
-        if (mw.sh) bits |= mb[g.w] << (64 - mw.sh);
-    }
+    const BlockWords bw = block_words(mbits, mask_words(k, Wd, min(x, g.w - 1)), Wd);
+    const uint64_t bits = on ? block_bits(bw) : 0ull;
     T.mlo = (uint32_t)bits;
     T.mhi = (uint32_t)(bits >> 32);
     // known pixels of this wave's 33 rows: the block's bits, and the mask
