@@ -926,11 +926,16 @@ __device__ void order_run(const OrderArgs& A, int* __restrict__ sh, int cap,
         cbx_of[x] = min(((block_origin(x, g.sx, g.w, g.bw) + g.bw / 2) / A.scale) / c.sx,
                         c.nbx - 1);
     const int* K = A.keys;
-    int* sk = sh + g.nby + g.nbx;
-    if (nk <= cap - g.nby - g.nbx) {
+    int used = g.nby + g.nbx;
+    int* sk = sh + used;
+    if (nk <= cap - used) {
         for (int i = tid; i < nk; i += NT) sk[i] = A.keys[i];
         K = sk;
+        used += nk;
     }
+    // the count pass leaves each block's bucket here for the write pass
+    // (one byte per block, where the LDS holds them)
+    uint8_t* bks = n <= 4 * (cap - used) ? reinterpret_cast<uint8_t*>(sh + used) : nullptr;
     __syncthreads();
     const int per = (n + NT - 1) / NT;
     const int lo = min(tid * per, n), hi = min(lo + per, n);
@@ -938,11 +943,15 @@ __device__ void order_run(const OrderArgs& A, int* __restrict__ sh, int cap,
     auto bucket = [&](int ch, int by, int bx) {
         return order_bucket_of(K[(ch * c.nby + cby_of[by]) * c.nbx + cbx_of[bx]]);
     };
+    // the bucket lookups of consecutive blocks are independent: unrolled,
+    // their LDS latencies overlap
     uint64_t c03 = 0, c47 = 0;
     {
         int ch = ch0, by = by0, bx = bx0;
+#pragma unroll 4
         for (int i = lo; i < hi; ++i) {
             const int bk = bucket(ch, by, bx);
+            if (bks) bks[i] = (uint8_t)bk;
             if (bk < 4) c03 += 1ull << (16 * bk); else c47 += 1ull << (16 * (bk - 4));
             if (++bx == g.nbx) {
                 bx = 0;
@@ -965,8 +974,9 @@ __device__ void order_run(const OrderArgs& A, int* __restrict__ sh, int cap,
         }
     }
     int ch = ch0, by = by0, bx = bx0;
+#pragma unroll 4
     for (int i = lo; i < hi; ++i) {
-        const int bk = bucket(ch, by, bx);
+        const int bk = bks ? (int)bks[i] : bucket(ch, by, bx);
         int r = 0;
 #pragma unroll
         for (int k = 0; k < kOrderBuckets; ++k)
