@@ -109,8 +109,14 @@ def test_correction_sweep_parity(ddi, C, H, W, S, o, alpha, k, start):
         assert np.all(out[ch][c == 1] == 0.0)
 
 
+def _bench_precision():
+    import bench
+    return bench.precision_params()
+
+
 @pytest.mark.parametrize("C,H,W,d,kind,prm", [
     (3, 2160, 3840, 0.03, "bernoulli", dict()),
+    (3, 2160, 3840, 0.03, "bernoulli", "bench"),
     (3, 1080, 1920, 0.03, "clustered", dict(levels=5, local_iters=24, local_tol=0.0005,
                                             coarse_sweeps=2, coarse_local_iters=16)),
     (1, 200, 300, 0.05, "bernoulli", dict(levels=3, block=32)),
@@ -119,6 +125,8 @@ def test_correction_sweep_parity(ddi, C, H, W, S, o, alpha, k, start):
 def test_precision_variant_solve(ddi, C, H, W, d, kind, prm):
     """storage = 1 reaches the same fixed point: within 0.5 grey levels in
     every channel, u = f on the mask."""
+    if prm == "bench":  # the benchmark's parameters on a frame it does not time
+        prm = _bench_precision()
     f, c = synth.make_workload(H, W, C, d, kind, workload=31, index=H)
     say("storage=1 solve", C, H, W, d, kind, prm)
     p = dict(dict(levels=4, local_iters=16, robin_alpha=0.25, coarse_sweeps=1, coarsest_sweeps=1,
