@@ -37,8 +37,9 @@ each on a stream of its own picked so that no two share a hardware queue:
 one frame's latency-bound kernels run beside another's sweeps, and the
 host's wait for a stop test never idles the GPU. A step of the 4k and
 precision workloads is one frame on every plan (four frames). The timed
-plans carry no timing events; the per-sweep durations come from separate
-passes on plans that record them.
+plans (and batch plans) carry no timing events; the per-sweep durations
+come from separate passes on plans that record them (batch: batched solves
+one at a time).
 
 Prints one JSON line. Besides the driver's fields it carries
   roofline      the dominant kernel, the second finest-level ORAS sweep
@@ -918,7 +919,7 @@ def run_batch(args) -> dict:
     us = [torch.empty_like(f) for f in fs]
     prms = batch_params(specs)
     for p in prms:
-        p.timing = 1
+        p.timing = 0  # the timed batches run as a caller would (no timing events)
         p.final_residual = 0
     sizes = [(s["h"], s["w"]) for s in specs]
     # several batched solves in flight, each batch plan on a stream of its
@@ -938,7 +939,6 @@ def run_batch(args) -> dict:
             bb.solve(fs, cs, uu)
     torch.cuda.synchronize()
     lat, sweeps = [], []
-    acc = {"sweep_ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0}
     lock = threading.Lock()
     errors = []
 
@@ -948,19 +948,8 @@ def run_batch(args) -> dict:
                 ts = time.perf_counter()
                 _, st, _ = bs[k].solve(fs, cs, uss[k])
                 dt = (time.perf_counter() - ts) * 1e3
-                fl = by = 0.0
-                for (h, w), p, x in zip(sizes, prms, st):
-                    a, bb = sweep_work(p.as_dict(), x["sweeps"], x["cg_steps"], h, w,
-                                       skipped=x["skipped_blocks"],
-                                       unwritten=x["unwritten_blocks"])
-                    fl += a
-                    by += bb
                 with lock:
                     lat.append(dt)
-                    acc["sweep_ms"] += st[0]["sweep_ms"]
-                    acc["launches"] += max(x["sweeps"] for x in st)
-                    acc["flops"] += fl
-                    acc["bytes"] += by
                     sweeps[:] = [x["sweeps"] for x in st]
         except Exception as e:  # re-raised in the main thread
             errors.append(e)
@@ -976,7 +965,25 @@ def run_batch(args) -> dict:
     if errors:
         raise errors[0]
     fps = args.steps * len(specs) / elapsed
-    sweep_ms, launches, flops, bytes_ = acc["sweep_ms"], acc["launches"], acc["flops"], acc["bytes"]
+    # the finest batched sweeps' durations and CG steps (roofline), outside
+    # the timed region: batched solves one at a time on a plan with timing
+    # events
+    tprms = [ddi.Params.from_buffer_copy(p) for p in prms]
+    for p in tprms:
+        p.timing = 1
+    sweep_ms = flops = bytes_ = 0.0
+    launches = 0
+    with ddi.Batch(sizes, C, params=tprms) as bt:
+        bt.solve(fs, cs, uss[-1])
+        for _ in range(5):
+            _, st, _ = bt.solve(fs, cs, uss[-1])
+            for (h, w), p, x in zip(sizes, tprms, st):
+                a, bb = sweep_work(p.as_dict(), x["sweeps"], x["cg_steps"], h, w,
+                                   skipped=x["skipped_blocks"], unwritten=x["unwritten_blocks"])
+                flops += a
+                bytes_ += bb
+            sweep_ms += st[0]["sweep_ms"]
+            launches += max(x["sweeps"] for x in st)
     # one batch at a time: the latency of a batched solve on its own
     lat1 = []
     for _ in range(max(3, min(args.steps // 2, 10))):
