@@ -708,22 +708,45 @@ int ddi_batch_solve(ddi_batch* B, const float* const* f, const uint8_t* const* c
     hipStream_t s = B->s;
 
     // start buffers: as many sweeps as each image needed last time
-    std::vector<int> start0(n), sweeps(n, 0), act;
+    std::vector<int> start0(n), sweeps(n, 0), act, expect(n);
     std::vector<double> rel(n, INFINITY);
     std::vector<char> converged(n, 0), validated(n, 0);
-    int expect_max = 0;
     for (int i = 0; i < n; ++i) {
         ddi_plan* P = B->plans[i];
         Level& L0 = P->lv[0];
         L0.f = f[i];
         L0.c = c[i];
         L0.u[0] = u[i];
-        const int expect = P->last_sweeps >= 0 ? P->last_sweeps : std::max(B->min_sweeps, 1);
-        start0[i] = std::min(expect, B->max_sweeps) & 1;
-        expect_max = std::max(expect_max, expect);
+        expect[i] = P->last_sweeps >= 0 ? P->last_sweeps : std::max(B->min_sweeps, 1);
+        start0[i] = std::min(expect[i], B->max_sweeps) & 1;
         act.push_back(i);
     }
-    int first = std::min(B->max_sweeps, std::max(expect_max, B->min_sweeps));
+    // the first batch of finest sweeps: as many as the images holding three
+    // quarters of the pixels needed last time. The images expected to need
+    // more continue after one host check in tables of their own, so the
+    // launches of the longest-running images do not carry the blocks of
+    // every converged image (each such block still costs a dispatch).
+    int first;
+    {
+        std::vector<std::pair<int, double>> ep;
+        double total = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double px = (double)B->plans[i]->h * B->plans[i]->w;
+            ep.push_back({expect[i], px});
+            total += px;
+        }
+        std::sort(ep.begin(), ep.end());
+        double acc = 0.0;
+        int n75 = ep.back().first;
+        for (const auto& e : ep) {
+            acc += e.second;
+            if (acc >= 0.75 * total) {
+                n75 = e.first;
+                break;
+            }
+        }
+        first = std::min(B->max_sweeps, std::max(n75, B->min_sweeps));
+    }
 
     DDI_HIP(hipEventRecord(B->e0, s));
     Arena A;
@@ -744,7 +767,15 @@ int ddi_batch_solve(ddi_batch* B, const float* const* f, const uint8_t* const* c
     int done_upto = 0;
     bool first_batch = true;
     while (done_upto < B->max_sweeps) {
-        const int upto = next_upto(B, done_upto, first_batch ? first : 0);
+        // later batches: up to the largest count the running images needed
+        // last time, then two sweeps per check
+        int want = first;
+        if (!first_batch) {
+            want = 0;
+            for (int i : act) want = std::max(want, expect[i]);
+            if (want <= done_upto) want = 0;
+        }
+        const int upto = next_upto(B, done_upto, want);
         if (!first_batch) {
             // rebuild the finest-level tables for the images still running
             Arena R;
