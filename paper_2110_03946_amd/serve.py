@@ -17,8 +17,15 @@ Admission by HBM footprint: the slots are carved out of a device-memory
 budget (plan bytes from ddi_plan_footprint plus the slot's f, c, u), in
 proportion to the expected share of each class. A request is admitted when
 a slot of its class is free; otherwise it waits in its class queue. A slot
-is busy from the solve until its result has been copied to host memory on
-a separate copy stream, which overlaps with the next solves.
+is busy from the solve until its result has been copied to host memory.
+
+Concurrency: the slots are spread over a few lanes, each a compute stream,
+a copy stream and a host thread of its own. The dispatcher (the thread
+that calls run) hands an admitted request to its slot's lane; the lane
+copies the frame into the slot, solves (the library call releases the
+interpreter lock) and starts the copy of the result to host memory on its
+copy stream. Solves of different lanes run on the GPU at the same time, so
+one frame's latency-bound coarse levels overlap another's sweeps.
 
 Latency = time from a request's arrival to its result in host memory; the
 completion times come from HIP events on the copy stream.
@@ -26,6 +33,8 @@ completion times come from HIP events on the copy stream.
 from __future__ import annotations
 
 import collections
+import queue
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -101,9 +110,54 @@ class Slot:
     u: object
     host: object            # pinned host buffer for the result
     bytes: int
+    lane: object = None
     busy: bool = False
     req: Request = None
-    ev_done: object = None
+    ev_done: object = None  # set by the lane once the result copy is enqueued
+
+
+class Lane:
+    """A compute stream, a copy stream and a host thread that runs the
+    solves of its slots in the order they were handed over."""
+
+    def __init__(self, torch, download: bool):
+        self.torch = torch
+        self.download = download
+        self.stream = torch.cuda.Stream()  # default priority
+        self.copy = torch.cuda.Stream()
+        self.q = queue.Queue()
+        self.error = None
+        self.thread = threading.Thread(target=self._work, daemon=True)
+        self.thread.start()
+
+    def _work(self):
+        torch = self.torch
+        while True:
+            item = self.q.get()
+            if item is None:
+                return
+            s, f, c = item
+            try:
+                with torch.cuda.stream(self.stream):
+                    s.f.copy_(f)
+                    s.c.copy_(c)
+                s.plan.solve(s.f, s.c, s.u)  # synchronises the slot's streams
+                ev = torch.cuda.Event(enable_timing=True)
+                if self.download:
+                    self.copy.wait_stream(self.stream)
+                    with torch.cuda.stream(self.copy):
+                        s.host.copy_(s.u, non_blocking=True)
+                        ev.record(self.copy)
+                else:
+                    ev.record(self.stream)
+                s.ev_done = ev
+            except Exception as e:  # re-raised by the dispatcher
+                self.error = e
+                return
+
+    def close(self):
+        self.q.put(None)
+        self.thread.join()
 
 
 @dataclass
@@ -132,7 +186,7 @@ class Server:
 
     def __init__(self, channels: int = 3, budget_bytes: int = 16 << 30, mix=SERVE_MIX,
                  use_graph: bool = True, download: bool = True, table=None, max_slots: int = 8,
-                 on_result=None):
+                 on_result=None, lanes: int = 4):
         import torch
         self.torch = torch
         self.C = channels
@@ -140,7 +194,7 @@ class Server:
         self.on_result = on_result  # called as on_result(request, host or device result)
         self.table = table or autotune.load_table()
         self.stream = torch.cuda.current_stream()
-        self.copy_stream = torch.cuda.Stream()  # default priority
+        self.lanes = [Lane(torch, download) for _ in range(max(1, lanes))]
         buckets = autotune.DENSITY_BUCKETS
         classes = [(h, w, lo, hi) for (h, w) in mix for lo, hi in buckets]
         share = {k: mix[k[:2]] / len(buckets) for k in classes}
@@ -172,15 +226,20 @@ class Server:
             counts[k] += 1
             used += foot[k]
         self.slots = {k: [] for k in classes}
+        nslot = 0
         for k, n in counts.items():
             h, w = k[:2]
             for _ in range(n):
+                # consecutive slots of a class on different lanes
+                lane = self.lanes[nslot % len(self.lanes)]
+                nslot += 1
                 f = torch.empty((channels, h, w), dtype=torch.float32, device="cuda")
                 c = torch.zeros((h, w), dtype=torch.uint8, device="cuda")
                 u = torch.empty_like(f)
                 host = torch.empty((channels, h, w), dtype=torch.float32, pin_memory=True)
-                plan = ddi.Plan(h, w, channels, params=ddi.Params.from_buffer_copy(self.params[k]))
-                self.slots[k].append(Slot(k, plan, f, c, u, host, foot[k]))
+                plan = ddi.Plan(h, w, channels, params=ddi.Params.from_buffer_copy(self.params[k]),
+                                stream=lane.stream)
+                self.slots[k].append(Slot(k, plan, f, c, u, host, foot[k], lane))
         self.stats = ServeStats(slots=counts, budget_bytes=budget_bytes, used_bytes=used)
 
     def class_of(self, req: Request) -> tuple:
@@ -193,21 +252,33 @@ class Server:
         return (h, w, lo, hi)
 
     def close(self):
+        for lane in self.lanes:
+            lane.close()
+        self.torch.cuda.synchronize()
         for lst in self.slots.values():
             for s in lst:
                 s.plan.close()
 
+    def _check_lanes(self):
+        for lane in self.lanes:
+            if lane.error is not None:
+                raise lane.error
+
     # -- the loop -------------------------------------------------------
 
     def _retire(self, t_ref_event, block: bool = False):
-        """Free the slots whose results have reached host memory."""
+        """Free the slots whose results have reached host memory (block:
+        wait for every busy slot)."""
         for lst in self.slots.values():
             for s in lst:
                 if not s.busy:
                     continue
                 if block:
+                    while s.ev_done is None:
+                        self._check_lanes()
+                        time.sleep(5e-5)
                     s.ev_done.synchronize()
-                elif not s.ev_done.query():
+                elif s.ev_done is None or not s.ev_done.query():
                     continue
                 s.req.done = t_ref_event.elapsed_time(s.ev_done) / 1e3
                 self.stats.latencies_ms.append((s.req.done - s.req.arrival) * 1e3)
@@ -217,20 +288,10 @@ class Server:
                 s.req = None
 
     def _dispatch(self, s: Slot, req: Request, pool):
-        torch = self.torch
+        """Hand an admitted request to its slot's lane."""
         f, c = pool[req.size][req.frame]
-        s.f.copy_(f)
-        s.c.copy_(c)
-        s.plan.solve(s.f, s.c, s.u)  # synchronises the compute stream
-        ev = torch.cuda.Event(enable_timing=True)
-        if self.download:
-            self.copy_stream.wait_stream(self.stream)
-            with torch.cuda.stream(self.copy_stream):
-                s.host.copy_(s.u, non_blocking=True)
-                ev.record(self.copy_stream)
-        else:
-            ev.record(self.stream)
-        s.busy, s.req, s.ev_done = True, req, ev
+        s.busy, s.req, s.ev_done = True, req, None
+        s.lane.q.put((s, f, c))
 
     def warmup(self, pool):
         """One solve on every slot (captures its graphs), outside any stream."""
@@ -238,11 +299,14 @@ class Server:
             for s in lst:
                 k = 0
                 self._dispatch(s, Request(-1, 0.0, (h, w), 0.5 * (lo + hi), k), pool)
-        self.torch.cuda.synchronize()
         for lst in self.slots.values():
             for s in lst:
+                while s.ev_done is None:
+                    self._check_lanes()
+                    time.sleep(1e-4)
                 s.ev_done.synchronize()
                 s.busy, s.req = False, None
+        self.torch.cuda.synchronize()
 
     def run(self, requests, pool, realtime: bool = True) -> ServeStats:
         """Serve `requests` (sorted by arrival). realtime: arrivals follow
@@ -270,6 +334,7 @@ class Server:
                 queues[requests[nxt].cls].append(requests[nxt])
                 nxt += 1
             self.stats.max_queue = max(self.stats.max_queue, sum(len(q) for q in queues.values()))
+            self._check_lanes()
             self._retire(t_ref)
             # oldest admissible request first
             best = None
