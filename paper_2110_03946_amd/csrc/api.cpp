@@ -572,10 +572,15 @@ int plan_enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0) {
             hs[l] = P->lv[l].h;
             ws[l] = P->lv[l].w;
         }
-        // the same launch clears the stop-test control word of this solve
-        // and sums the input statistics
+        // the same launch clears the stop-test control word of this solve,
+        // sums the input statistics and, unless the coarsest level is solved
+        // in float64, makes its initial guess u = c ? f : 0
+        const int top = L - 1;
+        const int cur = (top == 0) ? start0 : 0;
+        const Level& t = P->lv[top];
+        const InitJob ini{t.f, t.c, t.u[cur], (int64_t)t.h * t.w, C};
         DDI_HIP(launch_mask_bits_levels(L, cs, hs, ws, mbs, s, P->ctl, 4, P->part, nwg, C + 2,
-                                        C + 2, P->red));
+                                        C + 2, P->red, prm.coarse_solver == 1 ? nullptr : &ini));
     }
     const int top = L - 1;
     int cur = (top == 0) ? start0 : 0;
@@ -587,9 +592,7 @@ int plan_enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0) {
     } else if (prm.coarse_solver == 1)
         DDI_HIP(launch_coarse_cg(P->lv[top].f, P->lv[top].c, P->lv[top].h, P->lv[top].w, C,
                                  P->lv[top].u[cur], prm.coarse_cg_iters, prm.coarse_cg_tol, s));
-    else
-        DDI_HIP(launch_init(P->lv[top].f, P->lv[top].c, P->lv[top].h, P->lv[top].w, C,
-                            P->lv[top].u[cur], s));
+    // (otherwise the initial guess came with the transposed masks)
     P->pro0_on = false;
     P->order_on = false;
     // set: this level's first sweep prolongs from it (only when the level

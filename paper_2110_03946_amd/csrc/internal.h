@@ -236,15 +236,26 @@ hipError_t launch_mask_bits(const uint8_t* c, int h, int w, uint64_t* mbits, hip
 // Largest number of levels a plan holds.
 constexpr int kMaxLevels = 16;
 
-// The transposed masks of n levels in one launch; optionally also zeroes
-// clear[0 .. nclear) (nclear <= 256), e.g. a solve's control word, and
-// writes the column sums out[j] = sum_i part[i * stride + j] for j < ncols
-// bit for bit as launch_reduce does (e.g. the input statistics).
+// The initial guess u = c ? f : 0 of one level (n pixels, channel planes
+// n apart).
+struct InitJob {
+    const float* f;
+    const uint8_t* c;
+    float* u;
+    int64_t n;
+    int channels;
+};
 hipError_t launch_mask_bits_levels(int n, const uint8_t* const* c, const int* h, const int* w,
                                    uint64_t* const* mbits, hipStream_t s,
                                    int* clear = nullptr, int nclear = 0,
                                    const double* part = nullptr, int nrows = 0, int stride = 0,
-                                   int ncols = 0, double* out = nullptr);
+                                   int ncols = 0, double* out = nullptr,
+                                   const InitJob* init = nullptr);
+// (above) The transposed masks of n levels in one launch; optionally also
+// zeroes clear[0 .. nclear) (nclear <= 256), e.g. a solve's control word,
+// writes the column sums out[j] = sum_i part[i * stride + j] for j < ncols
+// bit for bit as launch_reduce does (e.g. the input statistics), and makes
+// the initial guess of `init` bit for bit as launch_init does.
 
 // p[0..n) = 0.
 hipError_t launch_clear(double* p, int n, hipStream_t s);

@@ -342,9 +342,26 @@ struct MaskBitsLevels {
     const double* part;
     double* out;
     int nrows, stride, ncols;
+    // optional initial guess u = c ? f : 0 of one level (the k_init of the
+    // coarsest level, folded into this launch): a further z slice
+    const float* init_f;
+    const uint8_t* init_c;
+    float* init_u;
+    int64_t init_n;
+    int init_ch;
 };
 
 __global__ __launch_bounds__(256) void k_mask_bits_levels(MaskBitsLevels L, int nlev) {
+    if ((int)blockIdx.z == nlev + (L.ncols > 0 ? 1 : 0)) {  // the initial-guess slice
+        const int64_t nth = (int64_t)gridDim.x * gridDim.y * 256;
+        for (int64_t i = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 256 + threadIdx.x;
+             i < L.init_n; i += nth) {
+            const bool known = L.init_c[i] != 0;
+            for (int k = 0; k < L.init_ch; ++k)
+                L.init_u[k * L.init_n + i] = known ? L.init_f[k * L.init_n + i] : 0.f;
+        }
+        return;
+    }
     if ((int)blockIdx.z == nlev) {  // the column-sum slice (uniform per workgroup)
         const int j = blockIdx.x;
         if (blockIdx.y != 0 || j >= L.ncols) return;
@@ -620,10 +637,12 @@ hipError_t launch_clear(double* p, int n, hipStream_t s) {
 hipError_t launch_mask_bits_levels(int n, const uint8_t* const* c, const int* h, const int* w,
                                   uint64_t* const* mbits, hipStream_t s, int* clear,
                                   int nclear, const double* part, int nrows, int stride,
-                                  int ncols, double* out) {
+                                  int ncols, double* out, const InitJob* init) {
     if (n < 1 || n > kMaxLevels || nclear < 0 || nclear > 256) return hipErrorInvalidValue;
     const bool sums = part && out && nrows > 0 && ncols > 0;
     if (sums && (stride < ncols || ncols > 65535)) return hipErrorInvalidValue;
+    const bool ini = init && init->f && init->c && init->u && init->n > 0 && init->channels > 0;
+    if (init && !ini) return hipErrorInvalidValue;
     MaskBitsLevels L;
     L.clear = nclear > 0 ? clear : nullptr;
     L.nclear = nclear;
@@ -632,6 +651,11 @@ hipError_t launch_mask_bits_levels(int n, const uint8_t* const* c, const int* h,
     L.nrows = sums ? nrows : 0;
     L.stride = stride;
     L.ncols = sums ? ncols : 0;
+    L.init_f = ini ? init->f : nullptr;
+    L.init_c = ini ? init->c : nullptr;
+    L.init_u = ini ? init->u : nullptr;
+    L.init_n = ini ? init->n : 0;
+    L.init_ch = ini ? init->channels : 0;
     int gx = 1, gy = 1;
     for (int i = 0; i < n; ++i) {
         L.c[i] = c[i];
@@ -642,8 +666,8 @@ hipError_t launch_mask_bits_levels(int n, const uint8_t* const* c, const int* h,
         gy = max(gy, mask_bit_groups(h[i]));
     }
     if (sums) gx = max(gx, ncols);
-    hipLaunchKernelGGL(k_mask_bits_levels, dim3(gx, gy, n + (sums ? 1 : 0)), dim3(256), 0, s, L,
-                       n);
+    hipLaunchKernelGGL(k_mask_bits_levels, dim3(gx, gy, n + (sums ? 1 : 0) + (ini ? 1 : 0)),
+                       dim3(256), 0, s, L, n);
     return hipGetLastError();
 }
 
