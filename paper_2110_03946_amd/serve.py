@@ -186,7 +186,7 @@ class Server:
 
     def __init__(self, channels: int = 3, budget_bytes: int = 16 << 30, mix=SERVE_MIX,
                  use_graph: bool = True, download: bool = True, table=None, max_slots: int = 8,
-                 on_result=None, lanes: int = 4):
+                 on_result=None, lanes: int = 3):
         import torch
         self.torch = torch
         self.C = channels
