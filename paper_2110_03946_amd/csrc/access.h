@@ -276,6 +276,12 @@ DDI_HD uint32_t walk_out(const Walk& k, uint32_t W, int t) {
 DDI_HD int64_t coarsen4_in(int y, int w, int t) { return (int64_t)y * w + 4 * t; }
 DDI_HD int64_t coarsen4_out(int I, int wc, int t) { return (int64_t)I * wc + 2 * t; }
 
+// k_coarsen2x (two levels in one launch): thread t reads columns 8t .. 8t + 7
+// of the finer level's rows, writes columns 4t .. 4t + 3 of the middle
+// level's rows and columns 2t, 2t + 1 of the coarsest (coarsen4_out).
+DDI_HD int64_t coarsen8_in(int y, int w, int t) { return (int64_t)y * w + 8 * t; }
+DDI_HD int64_t coarsen8_mid(int Y, int wm, int t) { return (int64_t)Y * wm + 4 * t; }
+
 // k_prolong4: thread t of fine row y writes fine columns 4t .. 4t + 3 (one
 // float4 per channel) from coarse columns 2t - 1 .. 2t + 2 (clamped; 2t and
 // 2t + 1 as one float2) of the nearer and the farther coarse row.

@@ -557,10 +557,21 @@ int plan_enqueue_front(ddi_plan* P, int start0, hipStream_t s, bool fuse_l0) {
         DDI_HIP(launch_stats(L0.f, L0.c, P->h, P->w, C, P->part, &nwg, s));
     // the statistics' column sums (P->part -> P->red) run in the transposed-
     // mask launch below; nothing writes P->part before it
-    for (int l = 1; l + 1 < L; ++l) {
+    // the coarser levels two at a time where the widths allow it (one launch
+    // makes both, bit for bit as two would)
+    for (int l = 1; l + 1 < L;) {
         Level& a = P->lv[l];
         Level& b = P->lv[l + 1];
+        if (l + 2 < L) {
+            Level& d = P->lv[l + 2];
+            if (coarsen2_ok(a.f, a.c, b.fown, b.cown, d.fown, d.cown, a.w)) {
+                DDI_HIP(launch_coarsen2(a.f, a.c, a.h, a.w, C, b.fown, b.cown, d.fown, d.cown, s));
+                l += 2;
+                continue;
+            }
+        }
         DDI_HIP(launch_coarsen(a.f, a.c, a.h, a.w, C, b.fown, b.cown, nullptr, nullptr, s));
+        ++l;
     }
     {
         const uint8_t* cs[kMaxLevels];

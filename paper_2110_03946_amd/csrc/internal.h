@@ -267,6 +267,14 @@ hipError_t launch_clear(double* p, int n, hipStream_t s);
 hipError_t launch_coarsen(const float* f, const uint8_t* c, int h, int w,
                           int channels, float* fc, uint8_t* cc,
                           double* stats, int* nwg, hipStream_t s);
+// Two levels at once (h x w -> middle -> coarsest, each as launch_coarsen
+// would make it, bit for bit) when coarsen2_ok: widths divisible by 8 and
+// aligned buffers. No statistics.
+bool coarsen2_ok(const float* f, const uint8_t* c, const float* fm, const uint8_t* cm,
+                 const float* fc, const uint8_t* cc, int w);
+int coarsen2_grid(int h, int w, int* gx, int* rows);
+hipError_t launch_coarsen2(const float* f, const uint8_t* c, int h, int w, int channels,
+                           float* fm, uint8_t* cm, float* fc, uint8_t* cc, hipStream_t s);
 
 // Workgroups (statistics partial rows) launch_coarsen uses for h x w,
 // whichever path it takes.

@@ -205,6 +205,138 @@ __global__ __launch_bounds__(kTpb) void k_coarsen4(const float* __restrict__ f,
                       gridDim.x);
 }
 
+// Two levels of coarsening in one launch (level a -> a + 1 -> a + 2), for
+// widths divisible by 8: a thread makes the coarse pixels (I, 2t) and
+// (I, 2t + 1) of level a + 2 from rows 2I, 2I + 1 and columns 4t .. 4t + 3
+// of level a + 1, which it makes itself (and writes) from rows 4I .. 4I + 3
+// and columns 8t .. 8t + 7 of level a. Each level takes the arithmetic of
+// k_coarsen4 (float64 sum of <= 4 known values, one rounding to float32),
+// so the two levels equal two k_coarsen4 launches bit for bit.
+template <int NC>
+__device__ __forceinline__ void coarsen2x_body(const float* __restrict__ f,
+                                               const uint8_t* __restrict__ c, int h, int w,
+                                               float* __restrict__ fm, uint8_t* __restrict__ cm,
+                                               int hm, int wm, float* __restrict__ fc,
+                                               uint8_t* __restrict__ cc, int hc, int wc,
+                                               int rows, int bx, int by) {
+    const int t = bx * kTpb + threadIdx.x;
+    if (8 * t >= w) return;
+    const int64_t n = (int64_t)h * w, nm = (int64_t)hm * wm, ncs = (int64_t)hc * wc;
+    for (int I = by * rows; I < min(hc, (by + 1) * rows); ++I) {
+        float mv[2][4][NC];
+        int mk[2][4];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int Y = 2 * I + r;  // row of level a + 1
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                mk[r][j] = 0;
+#pragma unroll
+                for (int k = 0; k < NC; ++k) mv[r][j][k] = 0.f;
+            }
+            if (Y >= hm) continue;
+            uint2 m[2] = {make_uint2(0u, 0u), make_uint2(0u, 0u)};
+            float4 fv[2][2][NC];
+#pragma unroll
+            for (int a2 = 0; a2 < 2; ++a2) {
+                const int y = 2 * Y + a2;
+#pragma unroll
+                for (int k = 0; k < NC; ++k)
+                    fv[a2][0][k] = fv[a2][1][k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (y < h) {
+                    const int64_t i = coarsen8_in(y, w, t);
+                    m[a2] = *reinterpret_cast<const uint2*>(c + i);
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+                        if (m[a2].x) fv[a2][0][k] = *reinterpret_cast<const float4*>(f + k * n + i);
+                        if (m[a2].y)
+                            fv[a2][1][k] = *reinterpret_cast<const float4*>(f + k * n + i + 4);
+                    }
+                }
+            }
+            double sm[4][NC];
+            int cnt[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) sm[j][k] = 0.0;
+#pragma unroll
+            for (int a2 = 0; a2 < 2; ++a2) {
+#pragma unroll
+                for (int b2 = 0; b2 < 8; ++b2) {
+                    const uint32_t word = b2 < 4 ? m[a2].x : m[a2].y;
+                    const uint32_t cv = (word >> (8 * (b2 & 3))) & 0xffu;
+                    const int J = b2 >> 1;
+                    if (cv != 0) {
+                        ++cnt[J];
+#pragma unroll
+                        for (int k = 0; k < NC; ++k) {
+                            const float4 q = fv[a2][b2 >> 2][k];
+                            const int e = b2 & 3;
+                            sm[J][k] += e == 0 ? q.x : e == 1 ? q.y : e == 2 ? q.z : q.w;
+                        }
+                    }
+                }
+            }
+            const int64_t o = coarsen8_mid(Y, wm, t);
+            *reinterpret_cast<uint32_t*>(cm + o) =
+                (uint32_t)(cnt[0] > 0 ? 1 : 0) | ((uint32_t)(cnt[1] > 0 ? 1 : 0) << 8) |
+                ((uint32_t)(cnt[2] > 0 ? 1 : 0) << 16) | ((uint32_t)(cnt[3] > 0 ? 1 : 0) << 24);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                float v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    v[j] = cnt[j] > 0 ? (float)(sm[j][k] / (double)cnt[j]) : 0.f;
+                    mv[r][j][k] = v[j];
+                }
+                *reinterpret_cast<float4*>(fm + k * nm + o) = make_float4(v[0], v[1], v[2], v[3]);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) mk[r][j] = cnt[j] > 0 ? 1 : 0;
+        }
+        // level a + 2 from the level a + 1 values just made
+        double s2[2][NC];
+        int c2[2] = {0, 0};
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int k = 0; k < NC; ++k) s2[j][k] = 0.0;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+#pragma unroll
+            for (int b2 = 0; b2 < 4; ++b2) {
+                if (mk[r][b2]) {
+                    ++c2[b2 >> 1];
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) s2[b2 >> 1][k] += mv[r][b2][k];
+                }
+            }
+        }
+        const int64_t o2 = coarsen4_out(I, wc, t);
+        *reinterpret_cast<uint16_t*>(cc + o2) =
+            (uint16_t)((c2[0] > 0 ? 1 : 0) | ((c2[1] > 0 ? 1 : 0) << 8));
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            float2 out;
+            out.x = c2[0] > 0 ? (float)(s2[0][k] / (double)c2[0]) : 0.f;
+            out.y = c2[1] > 0 ? (float)(s2[1][k] / (double)c2[1]) : 0.f;
+            *reinterpret_cast<float2*>(fc + k * ncs + o2) = out;
+        }
+    }
+}
+
+template <int NC>
+__global__ __launch_bounds__(kTpb) void k_coarsen2x(const float* __restrict__ f,
+                                                    const uint8_t* __restrict__ c, int h, int w,
+                                                    float* __restrict__ fm,
+                                                    uint8_t* __restrict__ cm, int hm, int wm,
+                                                    float* __restrict__ fc,
+                                                    uint8_t* __restrict__ cc, int hc, int wc,
+                                                    int rows) {
+    coarsen2x_body<NC>(f, c, h, w, fm, cm, hm, wm, fc, cc, hc, wc, rows, blockIdx.x, blockIdx.y);
+}
+
 template <int NC>
 __global__ __launch_bounds__(kTpb) void k_coarsen4_batch(const LevelJob* __restrict__ jobs,
                                                          int njobs) {
@@ -718,6 +850,39 @@ hipError_t launch_coarsen(const float* f, const uint8_t* c, int h, int w, int ch
     case NC:                                                                               \
         hipLaunchKernelGGL(k_coarsen<NC>, dim3(grid), dim3(kTpb), 0, s, f, c, h, w, fc, cc, \
                            hc, wc, stats);                                                 \
+        break;
+        DDI_CASE(1) DDI_CASE(2) DDI_CASE(3) DDI_CASE(4)
+#undef DDI_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+bool coarsen2_ok(const float* f, const uint8_t* c, const float* fm, const uint8_t* cm,
+                 const float* fc, const uint8_t* cc, int w) {
+    return w % 8 == 0 && aligned(f, 16) && aligned(c, 8) && aligned(fm, 16) && aligned(cm, 4) &&
+           aligned(fc, 8) && aligned(cc, 2);
+}
+
+int coarsen2_grid(int h, int w, int* gx, int* rows) {
+    const int hm = (h + 1) / 2, hc = (hm + 1) / 2;
+    *gx = (w / 8 + kTpb - 1) / kTpb;
+    *rows = coarsen4_rows(hc, *gx);
+    return *gx * ((hc + *rows - 1) / *rows);
+}
+
+hipError_t launch_coarsen2(const float* f, const uint8_t* c, int h, int w, int channels,
+                           float* fm, uint8_t* cm, float* fc, uint8_t* cc, hipStream_t s) {
+    if (!coarsen2_ok(f, c, fm, cm, fc, cc, w)) return hipErrorInvalidValue;
+    const int hm = (h + 1) / 2, wm = w / 2, hc = (hm + 1) / 2, wc = wm / 2;
+    int gx = 0, rows = 0;
+    const int ng = coarsen2_grid(h, w, &gx, &rows);
+    const dim3 grid(gx, ng / gx);
+    switch (channels) {
+#define DDI_CASE(NC)                                                                          \
+    case NC:                                                                                  \
+        hipLaunchKernelGGL(k_coarsen2x<NC>, grid, dim3(kTpb), 0, s, f, c, h, w, fm, cm, hm, wm, \
+                           fc, cc, hc, wc, rows);                                             \
         break;
         DDI_CASE(1) DDI_CASE(2) DDI_CASE(3) DDI_CASE(4)
 #undef DDI_CASE

@@ -98,6 +98,39 @@ void replay_coarsen(Replay& R, int h, int w) {
         }
 }
 
+// Two levels of coarsening in one launch (k_coarsen2x): h x w -> middle ->
+// coarsest, for widths divisible by 8.
+void replay_coarsen2(Replay& R, int h, int w) {
+    const int hm = (h + 1) / 2, wm = w / 2, hc = (hm + 1) / 2, wc = wm / 2;
+    const int64_t n = (int64_t)h * w, nm = (int64_t)hm * wm, nc = (int64_t)hc * wc;
+    int gx = 0, rows = 0;
+    const int ng = coarsen2_grid(h, w, &gx, &rows);
+    const int gy = ng / gx;
+    R.check("k_coarsen2x", "grid covers the coarsest rows", (int64_t)gy * rows >= hc);
+    for (int by = 0; by < gy; ++by)
+        for (int bx = 0; bx < gx; ++bx)
+            for (int tid = 0; tid < 256; ++tid) {
+                const int t = bx * 256 + tid;
+                if (8 * t >= w) continue;
+                for (int I = by * rows; I < std::min(hc, (by + 1) * rows); ++I) {
+                    for (int r = 0; r < 2; ++r) {
+                        const int Y = 2 * I + r;
+                        if (Y >= hm) continue;
+                        for (int a2 = 0; a2 < 2; ++a2) {
+                            const int y = 2 * Y + a2;
+                            if (y >= h) continue;
+                            R.at("k_coarsen2x", "c (8 bytes)", coarsen8_in(y, w, t), n, 8);
+                            R.at("k_coarsen2x", "f (2 float4)", coarsen8_in(y, w, t), n, 8);
+                        }
+                        R.at("k_coarsen2x", "middle c (4 bytes) / f (float4)",
+                             coarsen8_mid(Y, wm, t), nm, 4);
+                    }
+                    R.at("k_coarsen2x", "coarsest c (2 bytes) / f (float2)", coarsen4_out(I, wc, t),
+                         nc, 2);
+                }
+            }
+}
+
 // Prolongation hc x wc -> h x w: both variants.
 void replay_prolong(Replay& R, int h, int w) {
     const int hc = (h + 1) / 2, wc = (w + 1) / 2;
@@ -333,6 +366,7 @@ extern "C" int ddi_selfcheck_access(int height, int width, int channels, const d
             replay_coarsen(R, h, w);
             replay_prolong(R, h, w);
         }
+        if (l >= 1 && l + 2 < L && w % 8 == 0) replay_coarsen2(R, h, w);
         h = (h + 1) / 2;
         w = (w + 1) / 2;
     }
