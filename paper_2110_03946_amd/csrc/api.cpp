@@ -403,6 +403,13 @@ int ddi_create(ddi_plan** out, int height, int width, int channels, const ddi_pa
         ddi_destroy(P);
         return err == hipErrorOutOfMemory ? DDI_ENOMEM : hip_fail(err);
     }
+    // the stop test writes the control words' host copy itself (pinned
+    // memory the device can address); without that address, a copy after it
+    void* dm = nullptr;
+    if (hipHostGetDevicePointer(&dm, P->hctl, 0) == hipSuccess && dm)
+        P->dmirror = static_cast<int*>(dm);
+    else
+        (void)hipGetLastError();
     if (prm.storage == 1) {
         const size_t nv = (size_t)channels * height * width * sizeof(uint16_t);
         if ((err = hipMalloc(&P->r16, nv)) != hipSuccess ||
@@ -713,7 +720,8 @@ static int enqueue_sweeps(ddi_plan* P, int from, int to, int start0, bool timing
             DDI_HIP(launch_reduce(P->cgcnt, nb, P->C, P->C, P->red + 3 * P->C + 2, s));
         if (is_check(prm, i + 1) || i + 1 == prm.max_sweeps)
             DDI_HIP(launch_decide(P->part, nb, P->C, P->red, ctl, drel,
-                                  is_check(prm, i + 1) ? prm.rel_tol : -1.0, i + 1, s));
+                                  is_check(prm, i + 1) ? prm.rel_tol : -1.0, i + 1, s,
+                                  P->dmirror));
     }
     return DDI_OK;
 }
@@ -914,6 +922,8 @@ static int begin_solve(ddi_plan* P, const float* f, const uint8_t* c, float* u) 
         if (e) return e;
         q.done_upto = batch;
     }
+    // every path that ran sweeps ended with a stop test that wrote the mirror
+    q.mirrored = batch > 0 && P->dmirror != nullptr;
     q.active = true;
     return enqueue_check(P);
 }
@@ -931,8 +941,10 @@ static int enqueue_check(ddi_plan* P) {
         DDI_HIP(hipMemcpyAsync(P->host + 2 * C + 2, P->red + 2 * C + 2, 4 * C * sizeof(double),
                                hipMemcpyDeviceToHost, s));
     }
-    DDI_HIP(hipMemcpyAsync(P->hctl, P->ctl, 4 * sizeof(int) + sizeof(double),
-                           hipMemcpyDeviceToHost, s));
+    if (!P->pend.mirrored)
+        DDI_HIP(hipMemcpyAsync(P->hctl, P->ctl, 4 * sizeof(int) + sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    P->pend.mirrored = false;
     DDI_HIP(hipEventRecord(P->ev_ctl, s));
     return DDI_OK;
 }
@@ -982,6 +994,7 @@ static int finish_solve(ddi_plan* P, ddi_stats* st) {
         int e = enqueue_sweeps(P, done_upto, upto, q.start0, q.timing, s);
         if (e) return e;
         done_upto = upto;
+        q.mirrored = P->dmirror != nullptr;
         if ((e = enqueue_check(P))) return e;
     }
     int cur = q.start0 ^ (sweeps & 1);

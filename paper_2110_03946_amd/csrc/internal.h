@@ -220,9 +220,12 @@ hipError_t launch_sweep_prolong(const ProSrc& src, const uint64_t* mbits, float*
 // Device stop test after finest-level sweep n (see k_decide): reduces the
 // sweep's partials, stores max_k ||r_k||^2/||b_k||^2 in rel[0] and, when
 // the test passes or the input statistics are invalid (ctl[2] = 1 bad mask
-// byte, 2 empty mask), sets ctl[0] and records n in ctl[1].
+// byte, 2 empty mask), sets ctl[0] and records n in ctl[1]. mirror (may be
+// null): device-visible host memory that receives ctl[0 .. 4) and then the
+// 8 bytes of rel[0] at the end, whatever the outcome.
 hipError_t launch_decide(const double* partial, int nb, int channels, const double* stats,
-                         int* ctl, double* rel, double tol, int n, hipStream_t s);
+                         int* ctl, double* rel, double tol, int n, hipStream_t s,
+                         int* mirror = nullptr);
 
 // p[0..n) = 0 for ints.
 hipError_t launch_clear_int(int* p, int n, hipStream_t s);

@@ -715,13 +715,23 @@ __device__ __forceinline__ void decide_body(const double* __restrict__ partial, 
     }
 }
 
+// mirror (may be null): host-mapped memory that receives ctl[0 .. 4) and
+// then rel[0], written by the thread that decides, so the host reads the
+// outcome without a copy launch.
 template <int NC>
 __global__ __launch_bounds__(kDecideTpb) void k_decide(const double* __restrict__ partial, int nb,
                                                        const double* __restrict__ stats,
                                                        int* __restrict__ ctl,
                                                        double* __restrict__ rel, double tol2,
-                                                       int n) {
+                                                       int n, int* __restrict__ mirror) {
     decide_body<NC>(partial, nb, stats, ctl, rel, tol2, n, 0);
+    if (mirror && threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mirror[j] = ctl[j];
+        const long long bits = __double_as_longlong(rel[0]);
+        mirror[4] = static_cast<int>(bits);
+        mirror[5] = static_cast<int>(bits >> 32);
+    }
 }
 
 // One stop test per image after finest-level sweep n: workgroup j tests
@@ -741,13 +751,13 @@ __global__ void k_clear_int(int* __restrict__ p, int n) {
 }  // namespace
 
 hipError_t launch_decide(const double* partial, int nb, int channels, const double* stats,
-                         int* ctl, double* rel, double tol, int n, hipStream_t s) {
+                         int* ctl, double* rel, double tol, int n, hipStream_t s, int* mirror) {
     const double tol2 = tol < 0.0 ? -1.0 : tol * tol;  // negative: never passes
     switch (channels) {
 #define DDI_CASE(NC)                                                                          \
     case NC:                                                                                  \
         hipLaunchKernelGGL(k_decide<NC>, dim3(1), dim3(kDecideTpb), 0, s, partial, nb, stats, \
-                           ctl, rel, tol2, n);                                                \
+                           ctl, rel, tol2, n, mirror);                                        \
         break;
         DDI_CASE(1) DDI_CASE(2) DDI_CASE(3) DDI_CASE(4)
 #undef DDI_CASE

@@ -90,6 +90,7 @@ struct ddi_plan {
     bool order_on = false;   // the solve being enqueued built that table
     int* ctl = nullptr;      // device stop test: done, sweeps, error, -, rel (double)
     void* hctl = nullptr;    // pinned mirror of ctl
+    int* dmirror = nullptr;  // hctl as the device sees it (k_decide writes it), or null
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipEvent_t ev_ctl = nullptr;  // after the control-word read-back of a batch
     // a solve enqueued by ddi_solve_async and not yet waited for
@@ -100,6 +101,9 @@ struct ddi_plan {
         float* u = nullptr;
         hipStream_t s = nullptr;
         int start0 = 0, done_upto = 0;
+        // the work enqueued since the last check ends with a stop test that
+        // writes the host mirror of the control words (no copy needed)
+        bool mirrored = false;
     };
     Pending pend;
     std::vector<hipEvent_t> sweep_ev;  // 2 per finest-level sweep (timing)
