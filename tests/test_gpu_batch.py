@@ -89,6 +89,30 @@ def test_batch_bitwise_equals_single(ddi, C):
             np.testing.assert_array_equal(host(u1), host(u2))
 
 
+# Deeper pyramids whose level-1 widths are multiples of 8: the single-image
+# solve makes levels 2-3 (and 4-5 with six levels) from level 1 in one
+# launch, the batch one level per launch, so bit-equal results check that the
+# two-level launch equals two one-level ones (ragged heights at every level).
+DEEP = [(200, 256, 0.05, "bernoulli"), (131, 208, 0.06, "clustered"), (77, 160, 0.04, "bernoulli")]
+
+
+@pytest.mark.parametrize("C,levels", [(1, 6), (3, 5), (2, 4)])
+def test_batch_equals_single_deep_pyramid(ddi, C, levels):
+    data = inputs(DEEP, C, wl=9)
+    prm = {**SMALL_PRM, "levels": levels}
+    say("batch deep pyramid", C, levels, [s[:2] for s in DEEP])
+    with ddi.Batch([c.shape for _, c in data], C, params=ddi.default_params(**prm)) as b:
+        us, st, codes = b.solve([dev(f) for f, _ in data], [dev(c) for _, c in data])
+    assert codes == [0] * len(data)
+    ref = single_solves(ddi, data, C, [ddi.default_params(**prm)] * len(data))
+    for i, ((f, c), u_t, s, (u_ref, s_ref)) in enumerate(zip(data, us, st, ref)):
+        u = host(u_t)
+        assert s["sweeps"] == s_ref["sweeps"], i
+        np.testing.assert_array_equal(u, u_ref, err_msg=f"image {i}")
+        ex = oracle.solve_exact(f.astype(np.float64), c)
+        assert np.abs(u - ex).max() <= 0.5, i
+
+
 def test_batch_per_image_params(ddi):
     """Per-image parameters: several sweep instances (block heights) share
     each launch."""
