@@ -272,9 +272,9 @@ void replay_sweep(Replay& R, const SweepArgs& a, bool pro) {
                     if (!pro) continue;
                     // the first sweep's tile from the coarser level
                     const ProRows P = pro_rows(k, g, wi, xc);
-                    if (P.hin) R.at("k_sweep2_pro", "halo row mask byte", P.hrow, n);
+                    R.at("k_sweep2_pro", "halo row mask byte", P.hrow, n);  // loaded always
                     for (int j = 0; j <= kSplitRows; ++j)
-                        R.at("k_sweep2_pro", "f of a known row",
+                        R.at("k_sweep2_pro", "f (every row)",
                              (int64_t)pro_frow(P, j) * W + xc, n);
                     const int64_t cn = xc >> 1, cf = pro_far((int)xc, wc);
                     for (int i = 0; i < kSplitRows / 2 + 2; ++i) {

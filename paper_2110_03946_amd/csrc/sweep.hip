@@ -359,10 +359,8 @@ __device__ __forceinline__ void sweep_body(const void* __restrict__ uin_v,
 // times in LDS: to swap the boundary rows of p (row 31 <-> row 32) for the
 // matvec, and to add their halves of p.q and r.r (wave 0's half first, so
 // both waves hold bitwise equal scalars and take the same branches).
-// Word 3 of a raw buffer resource on gfx950 (32-bit data, no swizzle) and a
-// vector offset that its range check rejects (the load returns 0).
+// Word 3 of a raw buffer resource on gfx950 (32-bit data, no swizzle).
 constexpr int kBufferDword3 = 0x00020000;
-constexpr uint32_t kBufferOutside = 0x80000000u;
 // Floor of the split sweep's local CG: it stops once r.r or p.Ap is at most
 // this (a residual of 1e-15 grey levels per block).
 constexpr float kCgFloor = 1e-30f;
@@ -453,40 +451,40 @@ __device__ __forceinline__ float pro_pixel(const ProSrc& S, const float* __restr
 // coarse rows F0 .. F0 + 17 (F0 = (ybase - 1) >> 1): fine row ybase + j
 // takes coarse rows F0 + (s >> 1) (nearer) and the one before or after it
 // (s = 1 + Q + j, Q = (ybase - 1) & 1), so the 18 column-mixed coarse rows
-// are shared by the fine rows. known: bit j set where row j of this lane is
-// a known pixel (its value is f). Every load is a uniform row base plus the
-// lane's column. Image rows outside the image (tile rows 0 and 65 at the
+// are shared by the fine rows. Row j of a lane takes f where that pixel is
+// known: the block's mask bits bw, and the mask byte hbyte for the halo row
+// (above the block for wave 0, below for wave 1). Every load is a uniform
+// row base plus the lane's column. f is loaded in every row, known or not:
+// nearly every 128-byte line of f holds a known pixel at 4 % density, and
+// the loads then go out with the coarse ones, before the mask words are
+// waited for. Image rows outside the image (tile rows 0 and 65 at the
 // border) are computed clamped and then replaced by their reflection.
 template <int Q>
 __device__ __forceinline__ void tile2_prolong_rows(Tile2& T, const ProSrc& S,
                                                    const float* __restrict__ Uc,
                                                    const float* __restrict__ F,
                                                    const ProRows& P, uint32_t xc, uint32_t Wd,
-                                                   uint32_t klo, uint32_t khi) {
+                                                   const BlockWords& bw, uint32_t hbyte, bool on,
+                                                   int wi) {
     constexpr int RPW = kSplitRows;
     constexpr int NQ = RPW / 2 + 2;
     const int hmax = P.hmax;
     // Buffer loads: the row offset is a scalar operand and the lane's column
-    // the vector offset, so a row costs no vector instruction; a lane that
-    // is not known in a row of f gets an offset past the plane, which the
-    // buffer's range check turns into 0 without a memory access.
+    // the vector offset, so a row costs no vector instruction.
     const uint32_t fbytes = Wd * (uint32_t)(hmax + 1) * 4u;
     const __amdgpu_buffer_rsrc_t rf =
         __builtin_amdgcn_make_buffer_rsrc((void*)F, (short)0, (int)fbytes, kBufferDword3);
     const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
         (void*)Uc, (short)0, (int)((uint32_t)S.hc * (uint32_t)S.wc * 4u), kBufferDword3);
     const uint32_t xb = xc * 4u, cnb = (xc >> 1) * 4u, cfb = (uint32_t)pro_far((int)xc, S.wc) * 4u;
-    // all loads first: f (0 where not known), then the coarse pairs
+    // all loads first: f, then the coarse pairs
     float fv[RPW + 1];
     int sel[RPW + 1];
 #pragma unroll
     for (int j = 0; j < RPW + 1; ++j) {
         const int y = pro_frow(P, j);
-        sel[j] = j < 32 ? __builtin_amdgcn_sbfe((int)klo, j, 1)
-                        : __builtin_amdgcn_sbfe((int)khi, j - 32, 1);
-        const uint32_t off = (xb & (uint32_t)sel[j]) | (kBufferOutside & ~(uint32_t)sel[j]);
         fv[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                              rf, (int)off, (int)((uint32_t)y * Wd * 4u), 0));
+                                              rf, (int)xb, (int)((uint32_t)y * Wd * 4u), 0));
     }
     float qn[NQ], qf[NQ];
 #pragma unroll
@@ -495,6 +493,24 @@ __device__ __forceinline__ void tile2_prolong_rows(Tile2& T, const ProSrc& S,
         qn[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)cnb, so, 0));
         qf[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)cfb, so, 0));
     }
+    // the mask words and the halo byte are consumed only after every load
+    // of the tile is issued
+    const uint64_t bits = on ? block_bits(bw) : 0ull;
+    T.mlo = (uint32_t)bits;
+    T.mhi = (uint32_t)(bits >> 32);
+    const uint32_t hknown = (P.hin & (hbyte != 0)) ? 1u : 0u;
+    uint32_t klo, khi;
+    if (wi == 0) {
+        klo = (~T.mlo << 1) | hknown;
+        khi = (~T.mlo) >> 31;
+    } else {
+        klo = ~T.mhi;
+        khi = hknown;
+    }
+#pragma unroll
+    for (int j = 0; j < RPW + 1; ++j)
+        sel[j] = j < 32 ? __builtin_amdgcn_sbfe((int)klo, j, 1)
+                        : __builtin_amdgcn_sbfe((int)khi, j - 32, 1);
     float hq[NQ];
 #pragma unroll
     for (int i = 0; i < NQ; ++i) hq[i] = pro_mix(qn[i], qf[i]);
@@ -523,26 +539,14 @@ __device__ __forceinline__ void tile2_load_prolong(Tile2& T, const Blk& k, const
     const float* __restrict__ Uc = S.uc + (int64_t)k.ch * S.hc * S.wc;
     const float* __restrict__ F = S.f + k.ch * a.cpitch;
     const BlockWords bw = block_words(mbits, mask_words(k, Wd, min(x, g.w - 1)), Wd);
-    const uint64_t bits = on ? block_bits(bw) : 0ull;
-    T.mlo = (uint32_t)bits;
-    T.mhi = (uint32_t)(bits >> 32);
     // known pixels of this wave's 33 rows: the block's bits, and the mask
     // byte for the halo row (above the block for wave 0, below for wave 1)
     const ProRows P = pro_rows(k, g, wi, xc);
-    const uint32_t hknown = (P.hin && at32(S.c, P.hrow) != 0) ? 1u : 0u;
-    // bit j of (klo, khi): tile row j of this wave is known
-    uint32_t klo, khi;
-    if (wi == 0) {
-        klo = (~T.mlo << 1) | hknown;
-        khi = (~T.mlo) >> 31;
-    } else {
-        klo = ~T.mhi;
-        khi = hknown;
-    }
+    const uint32_t hbyte = at32(S.c, P.hrow);  // clamped: always in the plane
     if ((P.ybase - 1) & 1)
-        tile2_prolong_rows<1>(T, S, Uc, F, P, xc, Wd, klo, khi);
+        tile2_prolong_rows<1>(T, S, Uc, F, P, xc, Wd, bw, hbyte, on, wi);
     else
-        tile2_prolong_rows<0>(T, S, Uc, F, P, xc, Wd, klo, khi);
+        tile2_prolong_rows<0>(T, S, Uc, F, P, xc, Wd, bw, hbyte, on, wi);
     // reflecting border: the clamped tile row repeats its neighbour
     if (wi == 0 && !k.has_top) T.col[0] = T.col[1];
     if (wi == 1 && !k.has_bot) T.col[RPW] = T.col[RPW - 1];
@@ -552,8 +556,8 @@ __device__ __forceinline__ void tile2_load_prolong(Tile2& T, const Blk& k, const
     const int r1 = (int)tile_row(k, g, min(th, 2 * RPW + 1));
     const uint32_t ro = (uint32_t)r1 * Wd;
     const bool kl = at32(S.c, ro + xl) != 0, kr = at32(S.c, ro + xr) != 0;
-    const float fl = kl ? at32(F, ro + xl) : 0.f;
-    const float fr = kr ? at32(F, ro + xr) : 0.f;
+    const float fl = at32(F, ro + xl);
+    const float fr = at32(F, ro + xr);
     const float pl = pro_pixel(S, Uc, r1, xl), pr = pro_pixel(S, Uc, r1, xr);
     T.hl = kl ? fl : pl;
     T.hr = kr ? fr : pr;
