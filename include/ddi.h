@@ -398,10 +398,11 @@ const char* ddi_strerror(int code);
 int ddi_last_hip_error(void);
 
 /* With timing = 1: the device time of each finest-level ORAS sweep of the
- * plan's last float32 solve (storage = 0, method = 0), from events that the
- * sweep launch itself records at the kernel's start and end: ms[i] for
- * sweep i < n, *count (may be NULL) = sweeps of that solve (0 without
- * timing). Host only. */
+ * plan's last solve: ms[i] for sweep i < n, *count (may be NULL) = sweeps
+ * of that solve (0 without timing). Float32 solves (storage = 0, method =
+ * 0): from events that the sweep launch itself records at the kernel's
+ * start and end. Mixed precision (storage = 1): the correction sweeps in
+ * order, from events recorded on the stream around each launch. Host only. */
 int ddi_sweep_times(const ddi_plan* plan, double* ms, int n, int* count);
 
 /* Geometry of the block grid the solver uses on an n-pixel axis: number of

@@ -813,10 +813,12 @@ static int solve_refine(ddi_plan* P, const float* f, const uint8_t* c, float* u,
     float ms = 0.f;
     DDI_HIP(hipEventElapsedTime(&ms, P->e0, P->e1));
     double sweep_ms = 0.0, nsteps = 0.0;
+    P->sweep_ms.clear();
     for (int i = 0; timing && i < k_end * m; ++i) {
         float t = 0.f;
         DDI_HIP(hipEventElapsedTime(&t, P->sweep_ev[2 * i], P->sweep_ev[2 * i + 1]));
         sweep_ms += t;
+        P->sweep_ms.push_back(t);  // the correction sweeps, in order
     }
     for (int k = 0; timing && k < C; ++k) nsteps += P->host[2 * C + 2 + k];
     if (st) {

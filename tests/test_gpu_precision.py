@@ -170,3 +170,21 @@ def test_precision_variant_errors(ddi):
         assert st["converged"] == 0 and st["refinements"] == 3
     with pytest.raises(ddi.DDIError):
         ddi.Batch([(40, 48)], 1, params=ddi.default_params(storage=1))
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_sweep_times_per_sweep(ddi, storage):
+    """With timing = 1 the plan reports one device time per finest-level
+    sweep of the last solve (the correction sweeps for storage = 1), and
+    they add up to the solve's sweep time."""
+    f, c = synth.make_workload(256, 384, 3, 0.04, "bernoulli", workload=33)
+    say("sweep times", storage)
+    p = dict(levels=3, block=32, local_iters=12, rel_tol=1e-4, min_sweeps=2, max_sweeps=40,
+             storage=storage, inner_sweeps=2, timing=1)
+    with ddi.Plan(256, 384, 3, **p) as plan:
+        plan.solve(dev(f), dev(c))
+        _, st = plan.solve(dev(f), dev(c))
+        t = plan.sweep_times()
+    assert len(t) == st["sweeps"] >= 2
+    assert all(x > 0.0 for x in t)
+    assert abs(sum(t) - st["sweep_ms"]) <= 1e-6 + 1e-6 * st["sweep_ms"]
