@@ -534,7 +534,9 @@ int ddi_coarse_solve_grid(const float* f, const uint8_t* c, int height, int widt
  * ddi_refine_residual: u_next = u + d in float32 (d may be NULL: then u_next
  * is not written and u itself is used), rhs = bfloat16(b - A u_next) of
  * eq. 7 rounded to nearest even, rsq (host, channels doubles, may be NULL)
- * = sum of (b - A u_next)^2 per channel in float64.
+ * = sum of (b - A u_next)^2 per channel in float64. Requires u = f and
+ * d = 0 on the mask, as the refinement keeps them: the residual is then 0
+ * there, the stencil takes the known values from u, and f is not read.
  *
  * ddi_correction_sweep: one ORAS iteration (Sec. 3, eqs. 7-9) on the
  * refinement equation A d = rhs with d = 0 on the mask: the block residual

@@ -385,7 +385,8 @@ hipError_t launch_sweep_corr(const uint16_t* din, const uint16_t* rhs, const uin
 
 // unext = u + d (skipped when d == nullptr), rhs = bfloat16(b - A unext),
 // float64 partials of ||b - A unext||^2 laid out as launch_residual's (same
-// workgroup count). Does nothing once ctl[0] != 0.
+// workgroup count). Requires u = f and d = 0 on the mask (f is not read).
+// Does nothing once ctl[0] != 0.
 hipError_t launch_refine_residual(const float* f, const uint8_t* c, const float* u,
                                   const uint16_t* d, int h, int w, int channels, float* unext,
                                   uint16_t* rhs, double* partial, const int* ctl, int* nwg,

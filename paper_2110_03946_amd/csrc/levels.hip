@@ -579,7 +579,10 @@ __global__ __launch_bounds__(kTpb) void k_prolong(const float* __restrict__ uc, 
 // bfloat16: the refinement update). Outputs, each optional: r (float32),
 // rhs (bfloat16 of r), vout (v; with ucopy semantics for d == nullptr),
 // and the float64 partials of ||r||^2. Skipped once ctl[0] is set.
-template <bool REF>
+// FIXED: v equals f on the mask (the refinement keeps u = f and d = 0
+// there), so r is 0 there and f is not read: on an unknown pixel the
+// stencil takes its known neighbours' values from v.
+template <bool REF, bool FIXED = false>
 __global__ __launch_bounds__(64 * kWalkWaves) void k_residual_walk(
     const float* __restrict__ f, const uint8_t* __restrict__ c, const float* __restrict__ u,
     const uint16_t* __restrict__ d, int h, int w, int channels, float* __restrict__ r,
@@ -614,8 +617,12 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_residual_walk(
     }
     float fv[R];
 #pragma unroll
-    for (int t = 0; t < R; ++t)
-        fv[t] = cm[t] ? at32(F, walk_row(k, h, t) * W + k.xc) : 0.f;
+    for (int t = 0; t < R; ++t) {
+        if constexpr (FIXED)
+            fv[t] = 0.f;
+        else
+            fv[t] = cm[t] ? at32(F, walk_row(k, h, t) * W + k.xc) : 0.f;
+    }
     const int nr = k.y1 - k.y0;
     double acc = 0.0;
 #pragma unroll
@@ -626,7 +633,7 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_residual_walk(
         if (k.lane == 63) rgt = e[t];
         if (k.x == 0) lft = cur;
         if (k.x + 1 >= w) rgt = cur;
-        const float ry = cm[t] ? fv[t] - cur
+        const float ry = cm[t] ? (FIXED ? 0.f : fv[t] - cur)
                                : ((v[t] - cur) + (v[t + 2] - cur)) + ((lft - cur) + (rgt - cur));
         if (k.inb && t < nr) {
             const uint32_t i = walk_out(k, W, t);
@@ -1060,12 +1067,13 @@ hipError_t launch_refine_residual(const float* f, const uint8_t* c, const float*
                                   hipStream_t s) {
     const dim3 grid = walk_grid(h, w, channels);
     if (nwg) *nwg = (int)(grid.x * grid.y);
+    // u = f and d = 0 on the mask (the caller's precondition): f is not read
     if (d)
-        hipLaunchKernelGGL(k_residual_walk<true>, grid, dim3(64 * kWalkWaves), 0, s, f, c, u, d,
-                           h, w, channels, nullptr, rhs, unext, partial, ctl);
+        hipLaunchKernelGGL((k_residual_walk<true, true>), grid, dim3(64 * kWalkWaves), 0, s, f, c,
+                           u, d, h, w, channels, nullptr, rhs, unext, partial, ctl);
     else
-        hipLaunchKernelGGL(k_residual_walk<false>, grid, dim3(64 * kWalkWaves), 0, s, f, c, u,
-                           nullptr, h, w, channels, nullptr, rhs, nullptr, partial, ctl);
+        hipLaunchKernelGGL((k_residual_walk<false, true>), grid, dim3(64 * kWalkWaves), 0, s, f,
+                           c, u, nullptr, h, w, channels, nullptr, rhs, nullptr, partial, ctl);
     return hipGetLastError();
 }
 
