@@ -538,6 +538,12 @@ int ddi_coarse_solve_grid(const float* f, const uint8_t* c, int height, int widt
  * d = 0 on the mask, as the refinement keeps them: the residual is then 0
  * there, the stencil takes the known values from u, and f is not read.
  *
+ * ddi_refine_start: the first residual of the refinement built with the
+ * coarse-to-fine start (Sec. 4): u = c ? f : the bilinear interpolation of
+ * the coarse grid uc (channels x hc x wc, hc = ceil(height/2), wc =
+ * ceil(width/2)), bit for bit what ddi_prolong writes, and rhs and rsq as
+ * ddi_refine_residual gives for that u (0 on the mask).
+ *
  * ddi_correction_sweep: one ORAS iteration (Sec. 3, eqs. 7-9) on the
  * refinement equation A d = rhs with d = 0 on the mask: the block residual
  * rhs - A d_in (float32), k local CG steps, d_out = d_in + owned
@@ -546,6 +552,9 @@ int ddi_coarse_solve_grid(const float* f, const uint8_t* c, int height, int widt
 int ddi_refine_residual(const float* f, const uint8_t* c, const float* u,
                         const uint16_t* d, int height, int width, int channels,
                         float* u_next, uint16_t* rhs, double* rsq, void* stream);
+int ddi_refine_start(const float* uc, int hc, int wc, const float* f,
+                     const uint8_t* c, int height, int width, int channels,
+                     float* u, uint16_t* rhs, double* rsq, void* stream);
 int ddi_correction_sweep(const uint16_t* d_in, const uint16_t* rhs,
                          const uint8_t* c, uint16_t* d_out, int height,
                          int width, int channels, int block, int overlap,

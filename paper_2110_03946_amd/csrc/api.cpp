@@ -726,8 +726,9 @@ static int enqueue_sweeps(ddi_plan* P, int from, int to, int start0, bool timing
     return DDI_OK;
 }
 
-// storage = 1: the coarse-to-fine start, then refinement steps k = 0, 1,
-// ...: r_k = b - A u_k (bfloat16, float64 norm, device stop test), then
+// storage = 1: the coarse-to-fine start (built by the first residual pass
+// where the finest level's start can be fused), then refinement steps k =
+// 0, 1, ...: r_k = b - A u_k (bfloat16, float64 norm, device stop test), then
 // inner_sweeps correction sweeps on A d = r_k from d = 0 (bfloat16), and
 // u_{k+1} = u_k + d fused into the next residual pass. u_k lives in buffer
 // start0 ^ (k & 1) of the finest level; steps are enqueued ahead in batches
@@ -743,7 +744,9 @@ static int solve_refine(ddi_plan* P, const float* f, const uint8_t* c, float* u,
     DDI_HIP(hipEventRecord(P->e0, s));
     const int expect = P->last_sweeps >= 0 ? P->last_sweeps : std::max(prm.min_sweeps, 1);
     const int start0 = std::min(expect, kmax) & 1;
-    int e = enqueue_front(P, start0, s, false);  // also clears the control word
+    // also clears the control word; where the finest level's start can be
+    // fused (P->pro0_on), the first residual pass builds it
+    int e = enqueue_front(P, start0, s, true);
     if (e) return e;
     int* ctl = P->ctl;
     double* drel = reinterpret_cast<double*>(ctl + 4);
@@ -753,9 +756,13 @@ static int solve_refine(ddi_plan* P, const float* f, const uint8_t* c, float* u,
             const int a = start0 ^ (k & 1);
             const float* usrc = k == 0 ? L0.u[start0] : L0.u[a ^ 1];
             const uint16_t* dk = k == 0 ? nullptr : P->d16[(m - 1) & 1];
-            DDI_HIP(launch_refine_residual(f, c, usrc, dk, P->h, P->w, C,
-                                           k == 0 ? nullptr : L0.u[a], P->r16, P->part, ctl,
-                                           nullptr, s));
+            if (k == 0 && P->pro0_on)
+                DDI_HIP(launch_start_residual(P->pro0, P->h, P->w, C, L0.u[start0], P->r16,
+                                              P->part, ctl, nullptr, s));
+            else
+                DDI_HIP(launch_refine_residual(f, c, usrc, dk, P->h, P->w, C,
+                                               k == 0 ? nullptr : L0.u[a], P->r16, P->part, ctl,
+                                               nullptr, s));
             const bool chk = is_check(prm, k);
             if (chk || k == kmax)
                 DDI_HIP(launch_decide(P->part, nres, C, P->red, ctl, drel, chk ? prm.rel_tol : -1.0,
@@ -1299,6 +1306,39 @@ int ddi_refine_residual(const float* f, const uint8_t* c, const float* u, const 
     int n = 0;
     DDI_HIP(launch_refine_residual(f, c, u, d, height, width, channels, u_next, rhs,
                                    (double*)part.p, nullptr, &n, s));
+    DDI_HIP(launch_reduce((double*)part.p, n, channels, channels, (double*)red.p, s));
+    if (rsq)
+        DDI_HIP(hipMemcpyAsync(rsq, red.p, channels * sizeof(double), hipMemcpyDeviceToHost, s));
+    DDI_HIP(hipStreamSynchronize(s));
+    return DDI_OK;
+}
+
+int ddi_refine_start(const float* uc, int hc, int wc, const float* f, const uint8_t* c,
+                     int height, int width, int channels, float* u, uint16_t* rhs, double* rsq,
+                     void* stream) {
+    int e = check_dims(height, width, channels);
+    if (e) return e;
+    if (!uc || !f || !c || !u || !rhs) return DDI_EINVAL;
+    if (hc != (height + 1) / 2 || wc != (width + 1) / 2) return DDI_EINVAL;
+    {
+        const size_t nimg = (size_t)channels * height * width * sizeof(float);
+        const size_t nb16 = nimg / 2, hw = (size_t)height * width;
+        const void* in[3] = {uc, f, c};
+        const size_t nin[3] = {(size_t)channels * hc * wc * sizeof(float), nimg, hw};
+        for (int i = 0; i < 3; ++i)
+            if (overlaps(u, nimg, in[i], nin[i]) || overlaps(rhs, nb16, in[i], nin[i]))
+                return DDI_EINVAL;
+        if (overlaps(rhs, nb16, u, nimg)) return DDI_EINVAL;
+    }
+    if ((e = check_device())) return e;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nwg = (size_t)residual_partials(height, width);
+    Scratch part, red;
+    DDI_HIP(hipMalloc(&part.p, nwg * channels * sizeof(double)));
+    DDI_HIP(hipMalloc(&red.p, channels * sizeof(double)));
+    int n = 0;
+    DDI_HIP(launch_start_residual(ProSrc{uc, hc, wc, f, c}, height, width, channels, u, rhs,
+                                  (double*)part.p, nullptr, &n, s));
     DDI_HIP(launch_reduce((double*)part.p, n, channels, channels, (double*)red.p, s));
     if (rsq)
         DDI_HIP(hipMemcpyAsync(rsq, red.p, channels * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -383,6 +383,14 @@ hipError_t launch_sweep_corr(const uint16_t* din, const uint16_t* rhs, const uin
                              uint16_t* dout, double* partial, double* cg_steps, const int* ctl,
                              const SweepArgs& a, hipStream_t s);
 
+// The first refinement residual fused with the coarse-to-fine start: vout
+// = c ? f : the bilinear prolongation of S.uc (bit for bit launch_prolong's),
+// rhs = bfloat16(b - A vout), float64 partials as launch_residual's. S.hc
+// and S.wc must be ceil(h / 2) and ceil(w / 2). Does nothing once ctl[0] != 0.
+hipError_t launch_start_residual(const ProSrc& S, int h, int w, int channels, float* vout,
+                                 uint16_t* rhs, double* partial, const int* ctl, int* nwg,
+                                 hipStream_t s);
+
 // unext = u + d (skipped when d == nullptr), rhs = bfloat16(b - A unext),
 // float64 partials of ||b - A unext||^2 laid out as launch_residual's (same
 // workgroup count). Requires u = f and d = 0 on the mask (f is not read).

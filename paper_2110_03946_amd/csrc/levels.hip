@@ -646,6 +646,91 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_residual_walk(
     walk_partial(acc, partial, channels);
 }
 
+// The first residual of the refinement fused with the coarse-to-fine start
+// (Sec. 4): v = c ? f : the bilinear prolongation of the coarse plane, with
+// the arithmetic of k_prolong4 (each coarse row mixed in x, then the nearer
+// and farther row mixed in y), written to vout; rhs = bfloat16(b - A v),
+// 0 on the mask (v = f there), and the float64 partials of ||b - A v||^2
+// laid out as k_residual_walk's. The walk's kWalkRows + 2 rows y0 - 1 + t
+// share kWalkRows / 2 + 2 coarse rows, from y0 / 2 - 1 on: row t takes
+// index (t + 1) / 2 as the nearer row and the one after it (t even: odd
+// fine row) or before it as the farther. The outside column of an edge
+// lane (x - 1 for lane 0, x + 1 for lane 63, used only inside the image)
+// takes the lane's two coarse columns with the roles of nearer and farther
+// swapped. Skipped once ctl[0] is set.
+__global__ __launch_bounds__(64 * kWalkWaves) void k_start_residual_walk(
+    ProSrc S, int h, int w, uint16_t* __restrict__ rhs, float* __restrict__ vout,
+    double* __restrict__ partial, const int* __restrict__ ctl) {
+    constexpr int R = kWalkRows;
+    constexpr int NQ = R / 2 + 2;
+    if (ctl && ctl[0] != 0) return;
+    const Walk k = walk_geom(h, w);
+    const int ch = blockIdx.z;
+    const int64_t n = (int64_t)h * w;
+    const uint32_t W = w;
+    const float* __restrict__ F = S.f + ch * n;
+    const float* __restrict__ Uc = S.uc + (int64_t)ch * S.hc * S.wc;
+    const uint32_t cn = k.xc >> 1, cf = (uint32_t)pro_far((int)k.xc, S.wc);
+    const int cb = (k.y0 >> 1) - 1;
+    // the loads that wait for nothing: mask bytes and coarse rows
+    uint32_t cm[R + 2], ce[R];
+#pragma unroll
+    for (int t = 0; t < R + 2; ++t) cm[t] = at32(S.c, walk_vrow(k, h, t) * W + k.xc);
+#pragma unroll
+    for (int t = 0; t < R; ++t) ce[t] = k.edge ? at32(S.c, walk_row(k, h, t) * W + k.xe) : 0u;
+    float qn[NQ], qf[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const uint32_t row = (uint32_t)min(max(cb + i, 0), S.hc - 1) * (uint32_t)S.wc;
+        qn[i] = at32(Uc, row + cn);
+        qf[i] = at32(Uc, row + cf);
+    }
+    // f where the mask is set
+    float fv[R + 2], fe[R];
+#pragma unroll
+    for (int t = 0; t < R + 2; ++t) fv[t] = cm[t] ? at32(F, walk_vrow(k, h, t) * W + k.xc) : 0.f;
+#pragma unroll
+    for (int t = 0; t < R; ++t) fe[t] = ce[t] ? at32(F, walk_row(k, h, t) * W + k.xe) : 0.f;
+    float hq[NQ], he[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        hq[i] = pro_mix(qn[i], qf[i]);
+        he[i] = pro_mix(qf[i], qn[i]);
+    }
+    float v[R + 2], e[R];
+#pragma unroll
+    for (int t = 0; t < R + 2; ++t) {
+        const int ni = (t + 1) / 2, fi = (t & 1) ? ni - 1 : ni + 1;
+        v[t] = cm[t] ? fv[t] : pro_mix(hq[ni], hq[fi]);
+        if (t >= 1 && k.y0 - 1 + t > h - 1) v[t] = v[t - 1];  // the clamp of walk_vrow
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const int ni = (t + 2) / 2, fi = ((t + 1) & 1) ? ni - 1 : ni + 1;
+        e[t] = ce[t] ? fe[t] : pro_mix(he[ni], he[fi]);
+    }
+    const int nr = k.y1 - k.y0;
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const float cur = v[t + 1];
+        float lft = from_left(cur), rgt = from_right(cur);
+        if (k.lane == 0) lft = e[t];
+        if (k.lane == 63) rgt = e[t];
+        if (k.x == 0) lft = cur;
+        if (k.x + 1 >= w) rgt = cur;
+        const float ry = cm[t + 1] ? 0.f
+                                   : ((v[t] - cur) + (v[t + 2] - cur)) + ((lft - cur) + (rgt - cur));
+        if (k.inb && t < nr) {
+            const uint32_t i = walk_out(k, W, t);
+            acc += (double)ry * (double)ry;
+            put32(rhs + ch * n, i, f_to_bf16(ry));
+            put32(vout + ch * n, i, cur);
+        }
+    }
+    walk_partial(acc, partial, gridDim.z);
+}
+
 __global__ __launch_bounds__(kTpb) void k_reduce(double* __restrict__ partial, int nrows,
                                                  int stride, double* __restrict__ out, int zero) {
     const int j = blockIdx.x;
@@ -1058,6 +1143,17 @@ hipError_t launch_mask_bits_batch(const LevelJob* jobs, int njobs, int total_wg,
 hipError_t launch_reduce_batch(const ReduceJob* jobs, int njobs, int ncols, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_reduce_batch, dim3(njobs * ncols), dim3(kTpb), 0, s, jobs, ncols);
+    return hipGetLastError();
+}
+
+hipError_t launch_start_residual(const ProSrc& S, int h, int w, int channels, float* vout,
+                                 uint16_t* rhs, double* partial, const int* ctl, int* nwg,
+                                 hipStream_t s) {
+    if (S.hc != (h + 1) / 2 || S.wc != (w + 1) / 2) return hipErrorInvalidValue;
+    const dim3 grid = walk_grid(h, w, channels);
+    if (nwg) *nwg = (int)(grid.x * grid.y);
+    hipLaunchKernelGGL(k_start_residual_walk, grid, dim3(64 * kWalkWaves), 0, s, S, h, w, rhs,
+                       vout, partial, ctl);
     return hipGetLastError();
 }
 

@@ -200,6 +200,44 @@ void replay_walk(Replay& R, int h, int w) {
             }
 }
 
+// The first refinement residual built with the coarse-to-fine start, over
+// an h x w level whose coarser level is ceil(h/2) x ceil(w/2): its coarse
+// rows and columns, and the index rules it relies on (the coarse rows of
+// each in-image fine row, and an edge lane's outside column taking the
+// lane's coarse columns swapped).
+void replay_start_walk(Replay& R, int h, int w) {
+    const int hc = (h + 1) / 2, wc = (w + 1) / 2;
+    const int64_t nc = (int64_t)hc * wc;
+    constexpr int NQ = kWalkRows / 2 + 2;
+    for (int by = 0; by < walk_groups_y(h); ++by)
+        for (int bx = 0; bx < walk_groups_x(w); ++bx)
+            for (int tid = 0; tid < 64 * kWalkWaves; ++tid) {
+                const Walk k = walk_at(h, w, bx, by, tid);
+                const int cn = (int)k.xc >> 1, cf = pro_far((int)k.xc, wc);
+                const int cb = (k.y0 >> 1) - 1;
+                auto crow = [&](int i) { return std::min(std::max(cb + i, 0), hc - 1); };
+                for (int i = 0; i < NQ; ++i) {
+                    R.at("k_start_residual_walk", "coarse row, nearer column",
+                         (int64_t)crow(i) * wc + cn, nc);
+                    R.at("k_start_residual_walk", "coarse row, farther column",
+                         (int64_t)crow(i) * wc + cf, nc);
+                }
+                for (int t = 0; t < kWalkRows + 2; ++t) {
+                    const int y = k.y0 - 1 + t;
+                    if (y < 0 || y >= h) continue;
+                    const int ni = (t + 1) / 2, fi = (t & 1) ? ni - 1 : ni + 1;
+                    R.check("k_start_residual_walk", "nearer coarse row of a fine row",
+                            crow(ni) == (y >> 1));
+                    R.check("k_start_residual_walk", "farther coarse row of a fine row",
+                            crow(fi) == pro_far(y, hc));
+                }
+                const bool used = k.inb && ((k.lane == 0 && k.x > 0) || (k.lane == 63 && k.x + 1 < w));
+                if (used)
+                    R.check("k_start_residual_walk", "edge column: the lane's coarse columns swapped",
+                            ((int)k.xe >> 1) == cf && pro_far((int)k.xe, wc) == cn);
+            }
+}
+
 // Block data the sweeps index per block: partials, timing counters, flags.
 void replay_block_data(Replay& R, const char* kernel, const SweepArgs& a, const Blk& k, int lb) {
     const int nb = sweep_partials(a), C = a.channels;
@@ -362,6 +400,7 @@ extern "C" int ddi_selfcheck_access(int height, int width, int channels, const d
         // sweep may build the tile from it
         replay_sweep(R, a, l + 1 < L && sweep_prolong_ok(a));
         replay_walk(R, h, w);
+        if (l == 0 && L > 1) replay_start_walk(R, h, w);
         if (l + 1 < L) {
             replay_coarsen(R, h, w);
             replay_prolong(R, h, w);

@@ -119,6 +119,7 @@ def lib():
                                        ctypes.POINTER(ctypes.c_size_t)]),
             "ddi_plan_bytes": (i, [vp, ctypes.POINTER(ctypes.c_size_t)]),
             "ddi_refine_residual": (i, [vp, vp, vp, vp, i, i, i, vp, vp, vp, vp]),
+            "ddi_refine_start": (i, [vp, i, i, vp, vp, i, i, i, vp, vp, vp, vp]),
             "ddi_correction_sweep": (i, [vp, vp, vp, vp, i, i, i, i, i, f, i, vp]),
             "ddi_batch_create": (i, [ctypes.POINTER(vp), i, ip, ip, i, ctypes.POINTER(Params),
                                      i, vp]),
@@ -519,6 +520,24 @@ def refine_residual(f, c, u, d=None, stream=None):
                                      rsq.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
            "ddi_refine_residual")
     return un, rhs, rsq
+
+
+def refine_start(uc, f, c, stream=None):
+    """First refinement residual built with the coarse-to-fine start from the
+    coarse grid uc: returns (u, rhs bfloat16, per-channel ||r||^2)."""
+    torch = _torch()
+    f = _img(f, "f")
+    C, H, W = f.shape
+    c = _mask(c, (H, W))
+    uc = _img(uc, "uc", C, ((H + 1) // 2, (W + 1) // 2))
+    u = torch.empty_like(f)
+    rhs = torch.empty((C, H, W), dtype=torch.bfloat16, device=f.device)
+    rsq = np.zeros(C, dtype=np.float64)
+    _check(lib().ddi_refine_start(_ptr(uc), uc.shape[1], uc.shape[2], _ptr(f), _ptr(c), H, W, C,
+                                  _ptr(u), _ptr(rhs), rsq.ctypes.data_as(ctypes.c_void_p),
+                                  _stream(stream)),
+           "ddi_refine_start")
+    return u, rhs, rsq
 
 
 def correction_sweep(d_in, rhs, c, block: int, overlap: int, alpha: float, k: int, stream=None):

@@ -86,6 +86,26 @@ def test_refine_residual_parity(ddi, C, H, W, with_d):
     np.testing.assert_allclose(rsq, (r64 ** 2).reshape(C, -1).sum(1), rtol=1e-5, atol=1e-6)
 
 
+@pytest.mark.parametrize("C,H,W", [(1, 1, 1), (1, 2, 3), (1, 17, 5), (3, 67, 131), (2, 64, 64),
+                                   (1, 130, 1), (3, 33, 200), (3, 1079, 1921), (3, 2160, 3840)])
+def test_refine_start_bit_exact(ddi, C, H, W):
+    """The first refinement residual built with the coarse-to-fine start
+    equals the prolongation followed by the refinement residual, bit for bit
+    (iterate, right-hand side and norms); odd sizes clamp the last coarse
+    row and column."""
+    f, c, _, _ = case(C, H, W, seed=H + 2 * W)
+    hc, wc = (H + 1) // 2, (W + 1) // 2
+    uc = np.random.default_rng(H * W + 5).uniform(0, 255, (C, hc, wc)).astype(np.float32)
+    say("refine start", C, H, W)
+    u_ref = ddi.prolong(dev(uc), dev(f), dev(c))
+    _, rhs_ref, rsq_ref = ddi.refine_residual(dev(f), dev(c), u_ref)
+    u, rhs, rsq = ddi.refine_start(dev(uc), dev(f), dev(c))
+    np.testing.assert_array_equal(host(u), host(u_ref))
+    torch.cuda.synchronize()
+    assert torch.equal(rhs.view(torch.int16), rhs_ref.view(torch.int16))
+    np.testing.assert_array_equal(rsq, rsq_ref)
+
+
 SWEEP_CASES = [(1, 64, 64, 64, 4, 0.25, 8), (3, 67, 131, 32, 4, 0.5, 6), (2, 100, 75, 24, 6, 1.0, 5),
                (1, 130, 70, 64, 4, 0.25, 12), (1, 20, 200, 16, 2, 0.3, 4), (1, 7, 9, 8, 2, 0.5, 3)]
 
