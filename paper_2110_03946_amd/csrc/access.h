@@ -224,7 +224,7 @@ DDI_HD int pro_crow(const ProRows& P, int i, int hc) { return min(max(P.F0 + i, 
 
 // A workgroup is kWalkWaves waves side by side, each covering 64
 // consecutive columns of a band of kWalkRows rows.
-constexpr int kWalkRows = 16;
+constexpr int kWalkRows = 8;
 constexpr int kWalkWaves = 4;
 
 // Launch grid of a walk over h x w: workgroup columns and row bands.
