@@ -56,3 +56,24 @@ def test_psnr_against_worked_values():
     b = a.clone()
     b[0, 0, 0] = 60.0  # MSE = 3600 / 60 = 60
     assert abs(bench.psnr(a, b) - 10 * math.log10(255.0 ** 2 / 60.0)) < 1e-9
+
+
+def test_precision_roofline_bound_by_intensity():
+    """The mixed-precision leg's roofline: flops from the residual of every
+    block plus the CG steps run, bytes from the correction-sweep model,
+    bound chosen against the 9.8 flops/byte ridge; None without timings."""
+    import bench
+    prm = bench.precision_params()
+    assert bench.precision_roofline(prm, {"t": [], "steps": 0.0, "refs": 0}) is None
+    # 2 solves x 2 steps x 2 sweeps, 100 us each
+    m = prm["inner_sweeps"]
+    iso = {"t": [[0.1] * (2 * m)] * 2, "refs": 4}
+    nblk = 64 * 36 * 3
+    few = bench.precision_roofline(prm, dict(iso, steps=0.0))
+    many = bench.precision_roofline(prm, dict(iso, steps=8.0 * nblk * len(iso["t"]) * 2 * m))
+    assert few["bound"] == "hbm" and many["bound"] == "alu"
+    assert few["avg_launch_us"] == 100.0
+    bytes_ = bench.correction_bytes(m, 1) * 4
+    assert abs(few["hbm_gbs"] - bytes_ / (0.1 * 8 * 1e-3) / 1e9) < 0.1
+    flops = 64 * 64 * (8 * nblk * (bench.FLOPS_RESIDUAL + 1))
+    assert abs(few["valu_tflops"] - flops / (0.8e-3) / 1e12) < 1e-3
